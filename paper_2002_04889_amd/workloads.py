@@ -1,0 +1,340 @@
+"""Seeded synthetic inputs: meshes, bathymetry and initial states.
+
+This module holds input recipes only.  It generates triangle meshes, samples
+a bathymetry at cell centroids and evaluates initial conditions.  It contains
+none of the finite-volume scheme (no reconstruction, flux, source or time
+stepping), so both the GPU library and the CPU oracle can consume its output.
+
+Sign convention (Section 2.1): ``h`` is the still-water depth (positive below
+the datum, negative on land), ``z = -h`` is the bed elevation, ``H = h + eta``
+is the total depth and ``w = (H, Hu, Hv)`` is the conserved state.
+
+Cases:
+
+* ``thacker_case``   -- radially symmetric oscillating paraboloid (Section 3):
+  [0,4]^2 m, bowl z = -h0 (1 - r^2/a^2), h0 = 0.1 m, a = 1 m, r0 = 0.8 m.
+* ``basin_case``     -- 500 x 500 km synthetic ocean basin standing in for the
+  real-case workload of Section 5 (the Rockall Bank bathymetry is not
+  available): 4000 m abyss, linear shelf, dry land strip, Gaussian seamounts,
+  2 m Gaussian hump, mesh graded 250 m (coast) to 2 km.
+* ``channel_case``   -- long flat channel with a dam over a dry bed, for the
+  Ritter closed-form solution.
+
+Every generator is deterministic in its seed: ``numpy.random.SeedSequence``
+of ``200204889 + k`` spawned into mesh / bathymetry / initial-condition
+streams.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+SEED_BASE = 200204889
+GRAVITY = 9.81
+
+# Thacker paraboloid parameters (Section 3).
+THACKER_H0 = 0.1
+THACKER_ALPHA = 1.0
+THACKER_R0 = 0.8
+THACKER_L = 4.0
+
+
+@dataclasses.dataclass
+class Case:
+    """A complete solver input: mesh, bathymetry, state and run parameters."""
+
+    name: str
+    vx: np.ndarray          # float64 [nv]
+    vy: np.ndarray          # float64 [nv]
+    tri: np.ndarray         # int32 [nc, 3]
+    h: np.ndarray           # float64 [nc], still-water depth at centroids
+    H: np.ndarray           # float64 [nc]
+    HU: np.ndarray          # float64 [nc]
+    HV: np.ndarray          # float64 [nc]
+    g: float = GRAVITY
+    cfl: float = 0.45
+    h_threshold: float = 1e-3
+    t0: float = 0.0
+    t_end: float = math.inf
+    info: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def nc(self) -> int:
+        return int(self.tri.shape[0])
+
+    @property
+    def nv(self) -> int:
+        return int(self.vx.shape[0])
+
+    def centroids(self):
+        t = self.tri
+        cx = (self.vx[t[:, 0]] + self.vx[t[:, 1]] + self.vx[t[:, 2]]) / 3.0
+        cy = (self.vy[t[:, 0]] + self.vy[t[:, 1]] + self.vy[t[:, 2]]) / 3.0
+        return cx, cy
+
+    def copy(self) -> "Case":
+        return dataclasses.replace(
+            self, vx=self.vx.copy(), vy=self.vy.copy(), tri=self.tri.copy(),
+            h=self.h.copy(), H=self.H.copy(), HU=self.HU.copy(),
+            HV=self.HV.copy(), info=dict(self.info))
+
+
+def streams(k: int):
+    """Independent (mesh, bathymetry, initial-condition) generators for case k."""
+    ss = np.random.SeedSequence(SEED_BASE + k)
+    return [np.random.default_rng(s) for s in ss.spawn(3)]
+
+
+def _delaunay(px: np.ndarray, py: np.ndarray):
+    from scipy.spatial import Delaunay
+
+    pts = np.stack([px, py], axis=1)
+    d = Delaunay(pts)
+    tri = np.ascontiguousarray(d.simplices.astype(np.int32))
+    # Drop vertices that the triangulation did not use (none expected).
+    used = np.zeros(len(px), dtype=bool)
+    used[tri.ravel()] = True
+    if not used.all():
+        remap = -np.ones(len(px), dtype=np.int64)
+        remap[used] = np.arange(int(used.sum()))
+        tri = remap[tri].astype(np.int32)
+        px, py = px[used], py[used]
+    return np.ascontiguousarray(px), np.ascontiguousarray(py), tri
+
+
+def jittered_grid(nx: int, ny: int, lx: float, ly: float, rng, jitter=0.3):
+    """nx x ny grid on [0,lx]x[0,ly]; interior points jittered in both
+    directions, edge points only along their edge, corners fixed."""
+    sx, sy = lx / (nx - 1), ly / (ny - 1)
+    gx = np.linspace(0.0, lx, nx)
+    gy = np.linspace(0.0, ly, ny)
+    X, Y = np.meshgrid(gx, gy, indexing="ij")
+    jx = rng.uniform(-jitter, jitter, X.shape) * sx
+    jy = rng.uniform(-jitter, jitter, Y.shape) * sy
+    on_x_edge = np.zeros(X.shape, dtype=bool)
+    on_x_edge[0, :] = on_x_edge[-1, :] = True
+    on_y_edge = np.zeros(X.shape, dtype=bool)
+    on_y_edge[:, 0] = on_y_edge[:, -1] = True
+    jx[on_x_edge] = 0.0
+    jy[on_y_edge] = 0.0
+    return (X + jx).ravel(), (Y + jy).ravel()
+
+
+# ---------------------------------------------------------------- Thacker
+
+def thacker_constants(g: float = GRAVITY):
+    a, r0, h0 = THACKER_ALPHA, THACKER_R0, THACKER_H0
+    A = (a * a - r0 * r0) / (a * a + r0 * r0)
+    omega = math.sqrt(8.0 * g * h0) / a
+    return {"A": A, "omega": omega, "T1": 2.0 * math.pi / omega,
+            "h0": h0, "alpha": a, "r0": r0, "L": THACKER_L}
+
+
+def thacker_exact(x, y, t, g: float = GRAVITY):
+    """Closed-form Thacker solution (Section 3) at points (x, y) in [0,L]^2.
+
+    Returns (eta, H, u, v).  The printed expression for "h(r,t)" subtracts
+    the bed elevation, so it is the total depth; it is clipped at zero where
+    the bowl is dry.  eta = H + z where wet and eta = z on dry ground."""
+    c = thacker_constants(g)
+    A, om, h0, a, L = c["A"], c["omega"], c["h0"], c["alpha"], c["L"]
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    xc, yc = x - L / 2.0, y - L / 2.0
+    r2 = xc * xc + yc * yc
+    den = 1.0 - A * math.cos(om * t)
+    z = -h0 * (1.0 - r2 / (a * a))
+    eta_w = h0 * (math.sqrt(1.0 - A * A) / den - 1.0
+                  - r2 / (a * a) * ((1.0 - A * A) / (den * den) - 1.0))
+    H = np.maximum(0.0, eta_w - z)
+    wet = H > 0.0
+    eta = np.where(wet, eta_w, z)
+    fac = om * A * math.sin(om * t) / (2.0 * den)
+    u = np.where(wet, fac * xc, 0.0)
+    v = np.where(wet, fac * yc, 0.0)
+    return eta, H, u, v
+
+
+def thacker_case(n: int = 45, k: int = 0, t_end=None, still: bool = False,
+                 cfl: float = 0.45, h_threshold: float = 1e-5) -> Case:
+    """Thacker paraboloid on a seeded jittered n x n Delaunay mesh.
+
+    ``still=True`` gives the lake-at-rest variant (eta = 0 in the bowl, dry
+    rim) used for the well-balancing invariant."""
+    rm, _, _ = streams(k)
+    px, py = jittered_grid(n, n, THACKER_L, THACKER_L, rm)
+    vx, vy, tri = _delaunay(px, py)
+    cx = (vx[tri[:, 0]] + vx[tri[:, 1]] + vx[tri[:, 2]]) / 3.0
+    cy = (vy[tri[:, 0]] + vy[tri[:, 1]] + vy[tri[:, 2]]) / 3.0
+    r2 = (cx - 2.0) ** 2 + (cy - 2.0) ** 2
+    h = THACKER_H0 * (1.0 - r2 / THACKER_ALPHA ** 2)
+    c = thacker_constants()
+    if still:
+        H = np.maximum(0.0, h)
+        HU = np.zeros_like(H)
+        HV = np.zeros_like(H)
+    else:
+        _, H, u, v = thacker_exact(cx, cy, 0.0)
+        HU, HV = H * u, H * v
+    return Case(name=f"thacker{n}" + ("-still" if still else ""),
+                vx=vx, vy=vy, tri=tri, h=h, H=H, HU=HU, HV=HV,
+                cfl=cfl, h_threshold=h_threshold,
+                t_end=c["T1"] if t_end is None else t_end,
+                info={"n": n, "seed": SEED_BASE + k, **c})
+
+
+# ---------------------------------------------------------------- basin
+
+BASIN_L = 500e3
+BASIN_SHORE_X = 480e3
+BASIN_SHELF_X = 380e3
+
+
+def _graded_columns(lx, ly, size_fn, rng, jitter=0.3):
+    """Points in columns whose spacing follows size_fn(x) in both directions.
+
+    Columns sit at x_0 = 0, x_{i+1} = x_i + size_fn(x_i), plus a last column
+    at x = lx.  Each column holds evenly spaced points in y at the local size.
+    Interior points are jittered in x and y; points on the boundary move only
+    along it, corners not at all."""
+    xs = [0.0]
+    while xs[-1] + size_fn(xs[-1]) < lx - 0.5 * size_fn(lx):
+        xs.append(xs[-1] + size_fn(xs[-1]))
+    xs.append(lx)
+    xs = np.array(xs)
+    pxs, pys = [], []
+    ncol = len(xs)
+    for i, x in enumerate(xs):
+        ny = max(2, int(round(ly / size_fn(x))) + 1)
+        y = np.linspace(0.0, ly, ny)
+        dy = ly / (ny - 1)
+        jy = rng.uniform(-jitter, jitter, ny) * dy
+        jy[0] = jy[-1] = 0.0
+        if 0 < i < ncol - 1:
+            sx = min(xs[i] - xs[i - 1], xs[i + 1] - xs[i])
+            jx = rng.uniform(-jitter, jitter, ny) * sx
+        else:
+            jx = np.zeros(ny)
+        pxs.append(x + jx)
+        pys.append(y + jy)
+    return np.concatenate(pxs), np.concatenate(pys)
+
+
+def basin_size_field(k_grade: float, smin=250.0, smax=2000.0):
+    def size(x):
+        d = abs(x - BASIN_SHORE_X)
+        return min(smax, smin + k_grade * d)
+    return size
+
+
+def basin_bed(x, y, mounts):
+    """Bed elevation z (m) of the synthetic basin: abyss, shelf, land strip
+    and Gaussian seamounts."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.where(x < BASIN_SHELF_X, -4000.0,
+                 np.where(x < BASIN_SHORE_X,
+                          -4000.0 * (BASIN_SHORE_X - x) / (BASIN_SHORE_X - BASIN_SHELF_X),
+                          100.0 * (x - BASIN_SHORE_X) / (BASIN_L - BASIN_SHORE_X)))
+    for (mx, my, amp, sig) in mounts:
+        z = z + amp * np.exp(-((x - mx) ** 2 + (y - my) ** 2) / (2.0 * sig * sig))
+    return z
+
+
+# Grading slope tuned so the default basin lands within 5% of 1M triangles.
+BASIN_K_1M = 0.0047
+
+
+def basin_case(k_grade: float = BASIN_K_1M, k: int = 1, smin: float = 250.0,
+               smax: float = 2000.0, scale: float = 1.0, eta_amp: float = 2.0,
+               cfl: float = 0.45, h_threshold: float = 1e-3,
+               n_mounts: int = 12) -> Case:
+    """Synthetic 500 x 500 km ocean basin (stand-in for the real case).
+
+    ``scale`` multiplies both mesh sizes, which gives small meshes of the same
+    shape for tests (scale=8 gives about 16k triangles).  ``eta_amp=0`` is the
+    lake-at-rest variant."""
+    rm, rb, ri = streams(k)
+    size = basin_size_field(k_grade, smin * scale, smax * scale)
+    px, py = _graded_columns(BASIN_L, BASIN_L, size, rm)
+    vx, vy, tri = _delaunay(px, py)
+    mounts = []
+    for _ in range(n_mounts):
+        mx = rb.uniform(20e3, 360e3)
+        my = rb.uniform(20e3, 480e3)
+        amp = rb.uniform(1000.0, 3500.0)
+        sig = rb.uniform(5e3, 25e3)
+        mounts.append((mx, my, amp, sig))
+    cx = (vx[tri[:, 0]] + vx[tri[:, 1]] + vx[tri[:, 2]]) / 3.0
+    cy = (vy[tri[:, 0]] + vy[tri[:, 1]] + vy[tri[:, 2]]) / 3.0
+    z = basin_bed(cx, cy, mounts)
+    h = -z
+    sig0 = 20e3
+    eta0 = eta_amp * np.exp(-((cx - 200e3) ** 2 + (cy - 250e3) ** 2) / (2.0 * sig0 * sig0))
+    H = np.maximum(0.0, eta0 + h)
+    HU = np.zeros_like(H)
+    HV = np.zeros_like(H)
+    return Case(name=f"basin{len(tri)}", vx=vx, vy=vy, tri=tri, h=h, H=H,
+                HU=HU, HV=HV, cfl=cfl, h_threshold=h_threshold,
+                info={"k_grade": k_grade, "scale": scale, "seed": SEED_BASE + k,
+                      "mounts": mounts, "eta_amp": eta_amp})
+
+
+# ---------------------------------------------------------------- channel
+
+def channel_case(length: float = 100.0, width: float = 2.0, n_len: int = 401,
+                 n_wid: int = 9, x_dam: float = 50.0, H0: float = 1.0, k: int = 5,
+                 cfl: float = 0.45, h_threshold: float = 1e-6) -> Case:
+    """Flat-bed channel (h = 0) with water H0 for x < x_dam and a dry bed
+    beyond: the dry dam break whose exact solution is Ritter's."""
+    rm, _, _ = streams(k)
+    px, py = jittered_grid(n_len, n_wid, length, width, rm, jitter=0.2)
+    vx, vy, tri = _delaunay(px, py)
+    cx = (vx[tri[:, 0]] + vx[tri[:, 1]] + vx[tri[:, 2]]) / 3.0
+    h = np.zeros(len(tri))
+    H = np.where(cx < x_dam, H0, 0.0)
+    return Case(name=f"channel{len(tri)}", vx=vx, vy=vy, tri=tri, h=h, H=H,
+                HU=np.zeros_like(H), HV=np.zeros_like(H), cfl=cfl,
+                h_threshold=h_threshold,
+                info={"x_dam": x_dam, "H0": H0, "length": length, "width": width})
+
+
+# ---------------------------------------------------------------- wave
+
+def standing_wave_case(n: int = 45, amp: float = 1e-6, depth: float = 1.0,
+                       length: float = 4.0, k: int = 7, cfl: float = 0.45,
+                       h_threshold: float = 1e-6) -> Case:
+    """Flat basin of depth ``depth`` on [0,L]^2 with the lowest wall-bounded
+    standing mode eta = amp cos(pi x / L) at rest: a smooth, everywhere wet
+    state (no wet/dry front) for convergence checks."""
+    rm, _, _ = streams(k)
+    px, py = jittered_grid(n, n, length, length, rm)
+    vx, vy, tri = _delaunay(px, py)
+    cx = (vx[tri[:, 0]] + vx[tri[:, 1]] + vx[tri[:, 2]]) / 3.0
+    h = np.full(len(tri), depth)
+    H = depth + amp * np.cos(math.pi * cx / length)
+    return Case(name=f"wave{n}", vx=vx, vy=vy, tri=tri, h=h, H=H,
+                HU=np.zeros_like(H), HV=np.zeros_like(H), cfl=cfl,
+                h_threshold=h_threshold,
+                info={"amp": amp, "depth": depth, "length": length})
+
+
+# ---------------------------------------------------------------- tiny meshes
+
+def tiny_mesh(kind: str = "square2"):
+    """Hand-made meshes: 'square2' (2 triangles), 'square8' (8 triangles
+    around a centre vertex of a 2x2 patch)."""
+    if kind == "square2":
+        vx = np.array([0.0, 1.0, 1.0, 0.0])
+        vy = np.array([0.0, 0.0, 1.0, 1.0])
+        tri = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    elif kind == "square8":
+        vx = np.array([0.0, 1.0, 2.0, 0.0, 1.0, 2.0, 0.0, 1.0, 2.0])
+        vy = np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0, 2.0, 2.0, 2.0])
+        tri = np.array([[0, 1, 4], [0, 4, 3], [1, 2, 4], [2, 5, 4],
+                        [3, 4, 6], [4, 7, 6], [4, 5, 8], [4, 8, 7]], dtype=np.int32)
+    else:
+        raise ValueError(kind)
+    return vx, vy, tri
