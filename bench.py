@@ -1,0 +1,157 @@
+"""Benchmark: SSP-RK(2,2) steps of the shallow-water finite-volume scheme on
+the 1M-triangle synthetic ocean basin, FP64, one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.  value = cell-updates/s (one cell advanced by one full
+two-stage step) over the timed region, with the mesh and the state already
+resident in HBM.  The roofline entry uses the dominant kernel's average
+launch duration from HIP events recorded on the solver's stream around each
+launch, in a second pass over the same number of steps.  cpu_baseline times
+the FP64 oracle (single thread) on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X datasheet HBM3E bandwidth
+
+# Algorithmic bytes per cell for one stage (FP64): the state a stage must
+# read and write, the still-water depth, the mesh connectivity (3 neighbour
+# indices + 3 vertex indices, 24 B) and the vertex coordinates amortised
+# over the cells (about one value per cell).
+#   stage 1: read w^n (24) + h (8) + coords (8) + topology (24) + write w1 (24)
+#   stage 2: read w1 (24) + w^n (24) + h (8) + coords (8) + topology (24)
+#            + write w^{n+1} (24)
+ALG_BYTES_STAGE1 = 88
+ALG_BYTES_STAGE2 = 112
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(case, steps):
+    import oracle
+
+    m = oracle.Mesh.from_case(case)
+    p = oracle.params(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold)
+    t0 = time.perf_counter()
+    r = m.run(p, case.H, case.HU, case.HV, 0.0, steps)
+    el = time.perf_counter() - t0
+    return {"value": case.nc * r["steps"] / el, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{r['steps']} steps of the same {case.nc}-cell basin from its initial "
+                      f"state, single-threaded C oracle (gcc -O2), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--scale", type=float, default=1.0, help="mesh size multiplier (1 = 1M cells)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "sharding of this solver is a design note, not a built path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2002_04889_amd import vsw
+    from paper_2002_04889_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    case = W.basin_case(scale=args.scale)
+    log(f"[bench] workload {case.name}: {case.nc} cells, generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.Stream(device=dev)
+    s = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold, device=0)
+    vsw.vsw_set_stream(s.h, stream.cuda_stream)
+    s.upload_mesh(case.vx, case.vy, case.tri, case.h)
+    nc, ne, nw = vsw.vsw_mesh_info(s.h)
+    dH = torch.tensor(case.H, device=dev)
+    dHU = torch.tensor(case.HU, device=dev)
+    dHV = torch.tensor(case.HV, device=dev)
+    torch.cuda.synchronize()
+    vsw.vsw_set_state_device(s.h, dH.data_ptr(), dHU.data_ptr(), dHV.data_ptr(), 0.0)
+
+    # warmup
+    rc, done, t = s.step(args.warmup)
+    log(f"[bench] warmup {done} steps, t={t:.3f} s")
+
+    # timed region: K steps, state resident in HBM
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        ev0.record(stream)
+    w0 = time.perf_counter()
+    rc, done, t = s.step(args.steps)
+    with torch.cuda.stream(stream):
+        ev1.record(stream)
+    ev1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    assert done == args.steps, (rc, done)
+    value = nc * args.steps / (ms / 1e3)
+    log(f"[bench] timed {args.steps} steps: {ms:.1f} ms (host wall {wall * 1e3:.1f} ms), "
+        f"{value:.3e} cell-updates/s")
+
+    # per-kernel durations: HIP events around each launch on the solver's stream
+    vsw.vsw_set_profiling(s.h, True)
+    rc, done2, _ = s.step(args.steps)
+    kt = vsw.vsw_kernel_times(s.h)
+    vsw.vsw_set_profiling(s.h, False)
+    log("[bench] kernel times: " + ", ".join(
+        f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us x{v[1]}" for k, v in kt.items() if v[1]))
+    # dominant stage: stage 2 = recon + update2, stage 1 = recon + update1
+    avg = {k: v[0] / v[1] for k, v in kt.items() if v[1]}
+    recon = avg.get("recon_kernel", 0.0)
+    st1 = recon + avg.get("update1_kernel", 0.0)
+    st2 = recon + avg.get("update2_kernel", 0.0)
+    if st2 >= st1:
+        dom, dur_ms, per_cell = "stage2 (recon_kernel + update2_kernel)", st2, ALG_BYTES_STAGE2
+    else:
+        dom, dur_ms, per_cell = "stage1 (recon_kernel + update1_kernel)", st1, ALG_BYTES_STAGE1
+    traffic = per_cell * nc
+    achieved = traffic / (dur_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom, "alg_bytes_per_cell": per_cell,
+                "avg_launch_us": round(dur_ms * 1e3, 2)}
+
+    out = {"metric": "cell-updates/s", "value": value, "unit": "cell-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"synthetic ocean basin 500x500 km, {nc} triangles "
+                                  f"(graded 250 m-2 km), Gaussian hump, walls, CFL 0.45",
+                      "cells": nc, "edges": ne, "walls": nw, "precision": "fp64",
+                      "ordering": "hilbert", "global_batch": nc, "parallelism": "single-gpu"},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * vsw.h -- C ABI of the MI355X (gfx950) shallow-water finite-volume library.
+ *
+ * The library advances the 2D nonlinear shallow water equations (Section
+ * 2.1 of Giles et al., "Performance analysis of Volna-OP2", 2020) on an
+ * unstructured triangular mesh with the explicit scheme of Sections 2.2-2.5:
+ * cell-centred finite volumes, MUSCL reconstruction by a least-squares
+ * gradient and a Barth-Jespersen limiter (eq. (3)), HLL fluxes with the wave
+ * speeds of Section 2.2, wall boundaries by ghost cells (Section 2.5), and
+ * the SSP-RK(2,2) time stepper with a CFL time step (Section 2.3).  Every
+ * step runs in HIP kernels on one GPU.
+ *
+ * Conventions
+ *  - Return value 0 (VSW_OK) on success, a negative VSW_E* code on failure;
+ *    vsw_last_error() then describes the failure.  No C++ exception crosses
+ *    this interface.
+ *  - Units are SI.  h is the still-water depth (positive below the datum,
+ *    negative on land; the bed elevation is z = -h), H = h + eta the total
+ *    depth, (HU, HV) = H (u, v) the momentum.  State arrays are FP64.
+ *  - Pointers named host_* or without a suffix are host memory owned by the
+ *    caller; the library copies from or into them during the call and keeps
+ *    no reference.  Pointers named dev_* are device memory on the solver's
+ *    device, owned by the caller, used only during the call (in stream order
+ *    on the solver's stream).
+ *  - Cell order at the interface is always the caller's order; the internal
+ *    renumbering is invisible.
+ *  - A solver is used by one host thread at a time.
+ */
+#ifndef VSW_H
+#define VSW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VSW_OK = 0,
+    VSW_EINVAL = -1,    /* bad argument (NULL, size, non-finite, H < 0) */
+    VSW_EMESH = -2,     /* invalid mesh (see vsw_upload_mesh) */
+    VSW_ESTATE = -3,    /* call out of order (no mesh or no state yet) */
+    VSW_ENOMEM = -4,    /* device or host allocation failed */
+    VSW_EDEVICE = -5,   /* HIP runtime error */
+    VSW_EUNSTABLE = -6  /* non-finite state or no valid time step */
+};
+
+enum { VSW_FP64 = 0 };                     /* arithmetic of the solver */
+enum { VSW_ORDER_HILBERT = 0, VSW_ORDER_NONE = 1, VSW_ORDER_RANDOM = 2 };
+
+typedef struct vsw_params {
+    double g;            /* gravity (m/s^2), > 0 */
+    double cfl;          /* Courant number of the dt rule, > 0 (Section 2.3) */
+    double h_threshold;  /* threshold depth H_thr (m), >= 0 (Section 2.4):
+                            below it a cell is not reconstructed and its
+                            velocity is taken as zero */
+    double dt_fixed;     /* > 0: constant time step; 0: CFL rule
+                            dt = cfl * min_K |K| / (P_K (|u_K| + sqrt(g H_K)))
+                            over cells with H_K >= H_thr */
+    int32_t precision;   /* VSW_FP64 */
+    int32_t ordering;    /* internal cell order: VSW_ORDER_* */
+    uint64_t seed;       /* seed of VSW_ORDER_RANDOM */
+} vsw_params;
+
+typedef struct vsw_solver vsw_solver;
+
+/* Create a solver on HIP device `device` (Section 2 parameters in p).
+ * EINVAL if p is NULL, g <= 0, cfl <= 0, h_threshold < 0, dt_fixed < 0 or
+ * an unknown precision/ordering; EDEVICE if the device cannot be used. */
+int vsw_create(const vsw_params *p, int device, vsw_solver **out);
+
+/* Free every device and host resource of the solver.  NULL is a no-op. */
+void vsw_destroy(vsw_solver *s);
+
+/* Upload the triangular mesh (Section 2.2): nv vertices (vx, vy), nc
+ * triangles tri[3*nc] (vertex indices, either orientation) and the
+ * still-water depth h[nc] sampled at each triangle's centroid.  Builds
+ * edges, neighbours and wall faces (every face with one triangle is a wall,
+ * Section 2.5), the geometry and the internal renumbering, and copies the
+ * result to the device.  EMESH on an index out of range, a zero-area
+ * triangle, a face shared by more than two triangles, two triangles on the
+ * same side of a face, or duplicate vertex coordinates on a face.  Replaces
+ * any previous mesh and discards the state. */
+int vsw_upload_mesh(vsw_solver *s, int64_t nv, const double *vx,
+                    const double *vy, int64_t nc, const int32_t *tri,
+                    const double *h);
+
+/* Set the state w = (H, HU, HV) (Section 2.1) from host arrays of nc values
+ * in the caller's cell order, at time t.  EINVAL on a non-finite value or
+ * H < 0; ESTATE before vsw_upload_mesh. */
+int vsw_set_state(vsw_solver *s, const double *H, const double *HU,
+                  const double *HV, double t);
+
+/* Same as vsw_set_state from device arrays (caller's cell order).  The
+ * values are not validated. */
+int vsw_set_state_device(vsw_solver *s, const double *dev_H,
+                         const double *dev_HU, const double *dev_HV, double t);
+
+/* Advance up to n SSP-RK(2,2) steps (Section 2.3), stopping early when the
+ * time reaches t_stop (the last step is shortened so that t lands exactly
+ * on t_stop; pass INFINITY for no limit).  Kernels are queued on the
+ * solver's stream without host synchronisation between steps; the call
+ * synchronises once at the end.  *steps_done (may be NULL) receives the
+ * number of completed steps and *t_out (may be NULL) the new time.
+ * EUNSTABLE if the state became non-finite (steps_done then counts the good
+ * steps before it; the state is that of the failing step) or no valid time
+ * step exists; ESTATE without mesh and state. */
+int vsw_step(vsw_solver *s, int64_t n, double t_stop, int64_t *steps_done,
+             double *t_out);
+
+/* Copy the state to host arrays (caller's order); *t (may be NULL) gets the
+ * time. */
+int vsw_get_state(vsw_solver *s, double *H, double *HU, double *HV, double *t);
+
+/* Copy the state to device arrays (caller's order). */
+int vsw_get_state_device(vsw_solver *s, double *dev_H, double *dev_HU,
+                         double *dev_HV, double *t);
+
+/* dt of the last completed step (0 before the first). */
+int vsw_last_dt(vsw_solver *s, double *dt);
+
+/* dt of each completed step of the last vsw_step call: up to max values
+ * into dts (may be NULL); *count receives the number of steps. */
+int vsw_dt_history(vsw_solver *s, int64_t max, double *dts, int64_t *count);
+
+/* Number of negative depths set to zero after a stage since the last
+ * vsw_set_state (a post-stage positivity fix; 0 in a well-resolved run). */
+int vsw_clamp_count(vsw_solver *s, int64_t *count);
+
+/* Run on the caller's HIP stream (a hipStream_t passed as void*, on the
+ * solver's device); NULL returns to the solver's own stream. */
+int vsw_set_stream(vsw_solver *s, void *hip_stream);
+
+/* Per-kernel timing with HIP events recorded around every launch of the
+ * stage kernels on the solver's stream (off by default).  vsw_kernel_times
+ * returns, for kernel kinds 0..nkinds-1 (see vsw_kernel_name), the summed
+ * milliseconds and launch counts since profiling was switched on. */
+int vsw_set_profiling(vsw_solver *s, int on);
+int vsw_kernel_times(vsw_solver *s, int nkinds, double *ms, int64_t *launches);
+const char *vsw_kernel_name(int kind);
+
+/* Host-only mesh preparation (no device needed): runs the same validation,
+ * face matching, canonical orientation and geometry as vsw_upload_mesh and
+ * returns them in the caller's cell order.  Outputs (any may be NULL):
+ * geom[7*3*nc] as [field][face j][cell] with fields nx, ny (outward unit
+ * normal of face j, which joins local vertices j and j+1 of the
+ * counter-clockwise triangle), len, dx, dy (face midpoint minus centroid),
+ * wx, wy (least-squares weights of stencil member j); area[nc], perim[nc];
+ * nbr[3*nc] as [face j][cell]: neighbour cell or -1 for a wall; is_left
+ * [3*nc]: 1 if the cell is the canonical left side of the face (walls: 1).
+ * Returns VSW_EMESH / VSW_EINVAL like vsw_upload_mesh. */
+int vsw_prepare_mesh_host(int64_t nv, const double *vx, const double *vy,
+                          int64_t nc, const int32_t *tri, const double *h,
+                          double *geom, double *area, double *perim,
+                          int32_t *nbr, int32_t *is_left, int64_t *ne,
+                          int64_t *nw);
+
+/* Internal cell order: perm[i] = caller's index of internal cell i. */
+int vsw_get_permutation(vsw_solver *s, int64_t *perm);
+
+/* Mesh sizes after upload: cells, edges, wall faces. */
+int vsw_mesh_info(vsw_solver *s, int64_t *nc, int64_t *ne, int64_t *nw);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *vsw_last_error(void);
+
+/* Library version string. */
+const char *vsw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VSW_H */

@@ -1,0 +1,499 @@
+// C ABI of the solver (include/vsw.h): context, device buffers, stream,
+// mesh upload, state transfer and the step loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vsw.h"
+#include "vsw_kernels.hpp"
+#include "vsw_mesh.hpp"
+
+using namespace vsw;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? VSW_ENOMEM : VSW_EDEVICE,           \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));             \
+    } while (0)
+
+enum KernelKind { KK_RECON = 0, KK_UPDATE1, KK_UPDATE2, KK_DTINIT, KK_COUNT };
+const char* kKernelNames[KK_COUNT] = {"recon_kernel", "update1_kernel", "update2_kernel",
+                                      "dt_init_kernel"};
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t alloc(size_t count) {
+        release();
+        if (count == 0) return hipSuccess;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+};
+
+}  // namespace
+
+struct vsw_solver {
+    vsw_params prm{};
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    bool has_mesh = false, has_state = false;
+    int64_t nc = 0, ne = 0, nw = 0;
+    std::vector<int64_t> perm;     // internal -> caller
+    DevBuf<int64_t> d_perm;
+    DevBuf<uint32_t> d_nbr;
+    DevBuf<double> d_geom, d_area, d_perim, d_h;
+    DevBuf<double> d_w;            // H, HU, HV of w^n: 3 * nc
+    DevBuf<double> d_w1;           // stage-1 state: 3 * nc
+    DevBuf<double> d_face;         // 15 * nc face buffer
+    DevBuf<double> d_sc;           // 2 * nc
+    DevBuf<int32_t> d_order;       // nc
+    DevBuf<double> d_tmp;          // 3 * nc staging for permutation
+    DevBuf<double> d_log;          // 2 * cap: t and dt per step
+    DevBuf<Ctrl> d_ctrl;
+    double t = 0.0;
+    double dt_last = 0.0;
+    int64_t clamps = 0;
+    // profiling
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_kind;      // kind of each event pair
+    double prof_ms[KK_COUNT] = {0, 0, 0, 0};
+    int64_t prof_n[KK_COUNT] = {0, 0, 0, 0};
+    std::vector<double> last_dts;
+
+    void release_mesh() {
+        d_perm.release(); d_nbr.release(); d_geom.release(); d_area.release();
+        d_perim.release(); d_h.release(); d_w.release(); d_w1.release();
+        d_face.release(); d_sc.release(); d_order.release(); d_tmp.release();
+        has_mesh = has_state = false;
+    }
+    DevMesh dev_mesh() const {
+        DevMesh m;
+        m.nc = nc;
+        m.nbr = d_nbr.p;
+        m.geom = d_geom.p;
+        m.area = d_area.p;
+        m.perim = d_perim.p;
+        m.h = d_h.p;
+        return m;
+    }
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+unsigned grid_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+extern "C" {
+
+const char* vsw_last_error(void) { return g_last_error.c_str(); }
+
+const char* vsw_version(void) { return "vsw 0.1 gfx950 fp64"; }
+
+const char* vsw_kernel_name(int kind) {
+    return (kind >= 0 && kind < KK_COUNT) ? kKernelNames[kind] : "";
+}
+
+int vsw_create(const vsw_params* p, int device, vsw_solver** out) {
+    if (!p || !out) return fail(VSW_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (!(p->g > 0.0) || !std::isfinite(p->g)) return fail(VSW_EINVAL, "g must be > 0");
+    if (!(p->cfl > 0.0) || !std::isfinite(p->cfl)) return fail(VSW_EINVAL, "cfl must be > 0");
+    if (!(p->h_threshold >= 0.0) || !std::isfinite(p->h_threshold))
+        return fail(VSW_EINVAL, "h_threshold must be >= 0");
+    if (!(p->dt_fixed >= 0.0) || !std::isfinite(p->dt_fixed))
+        return fail(VSW_EINVAL, "dt_fixed must be >= 0");
+    if (p->precision != VSW_FP64) return fail(VSW_EINVAL, "unsupported precision");
+    if (p->ordering < VSW_ORDER_HILBERT || p->ordering > VSW_ORDER_RANDOM)
+        return fail(VSW_EINVAL, "unknown ordering");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(VSW_EDEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(VSW_EINVAL, "device index out of range");
+    DeviceGuard dg(device);
+    vsw_solver* s = new vsw_solver();
+    s->prm = *p;
+    s->device = device;
+    hipError_t e = hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = s->d_ctrl.alloc(1);
+    if (e != hipSuccess) {
+        vsw_destroy(s);
+        return fail(VSW_EDEVICE, std::string("device setup: ") + hipGetErrorString(e));
+    }
+    s->stream = s->own_stream;
+    *out = s;
+    return VSW_OK;
+}
+
+void vsw_destroy(vsw_solver* s) {
+    if (!s) return;
+    DeviceGuard dg(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    s->release_mesh();
+    s->d_log.release();
+    s->d_ctrl.release();
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+    delete s;
+}
+
+int vsw_set_stream(vsw_solver* s, void* hip_stream) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    s->stream = hip_stream ? (hipStream_t)hip_stream : s->own_stream;
+    return VSW_OK;
+}
+
+int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* vy, int64_t nc,
+                    const int32_t* tri, const double* h) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    HostMesh hm;
+    std::string err;
+    int rc = build_host_mesh(nv, vx, vy, nc, tri, h, s->prm.ordering, s->prm.seed, hm, err);
+    if (rc != VSW_OK) return fail(rc, err);
+    DeviceGuard dg(s->device);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->release_mesh();
+    s->nc = hm.nc;
+    s->ne = hm.ne;
+    s->nw = hm.nw;
+    s->perm = hm.perm;
+    const size_t n = size_t(hm.nc);
+    HIP_TRY(s->d_perm.alloc(n));
+    HIP_TRY(s->d_nbr.alloc(3 * n));
+    HIP_TRY(s->d_geom.alloc(size_t(G_NFACE) * 3 * n));
+    HIP_TRY(s->d_area.alloc(n));
+    HIP_TRY(s->d_perim.alloc(n));
+    HIP_TRY(s->d_h.alloc(n));
+    HIP_TRY(s->d_w.alloc(3 * n));
+    HIP_TRY(s->d_w1.alloc(3 * n));
+    HIP_TRY(s->d_face.alloc(15 * n));
+    HIP_TRY(s->d_sc.alloc(2 * n));
+    HIP_TRY(s->d_order.alloc(n));
+    HIP_TRY(s->d_tmp.alloc(3 * n));
+    HIP_TRY(hipMemcpy(s->d_perm.p, hm.perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_nbr.p, hm.nbr.data(), 3 * n * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_geom.p, hm.face_geom.data(), hm.face_geom.size() * sizeof(double),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_area.p, hm.area.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_perim.p, hm.perim.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_h.p, hm.h.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    s->has_mesh = true;
+    s->has_state = false;
+    return VSW_OK;
+}
+
+int vsw_set_state(vsw_solver* s, const double* H, const double* HU, const double* HV, double t) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
+    if (!H || !HU || !HV) return fail(VSW_EINVAL, "NULL state array");
+    if (!std::isfinite(t)) return fail(VSW_EINVAL, "non-finite time");
+    const int64_t nc = s->nc;
+    std::vector<double> w(3 * size_t(nc));
+    for (int64_t i = 0; i < nc; ++i) {
+        const int64_t k = s->perm[i];
+        const double a = H[k], b = HU[k], c = HV[k];
+        if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c))
+            return fail(VSW_EINVAL, "non-finite state value");
+        if (a < 0.0) return fail(VSW_EINVAL, "negative depth H");
+        w[i] = a;
+        w[nc + i] = b;
+        w[2 * nc + i] = c;
+    }
+    DeviceGuard dg(s->device);
+    HIP_TRY(hipMemcpyAsync(s->d_w.p, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->t = t;
+    s->dt_last = 0.0;
+    s->clamps = 0;
+    s->has_state = true;
+    return VSW_OK;
+}
+
+int vsw_set_state_device(vsw_solver* s, const double* dH, const double* dHU, const double* dHV,
+                         double t) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
+    if (!dH || !dHU || !dHV) return fail(VSW_EINVAL, "NULL state array");
+    if (!std::isfinite(t)) return fail(VSW_EINVAL, "non-finite time");
+    DeviceGuard dg(s->device);
+    const int64_t nc = s->nc;
+    const double* src[3] = {dH, dHU, dHV};
+    for (int c = 0; c < 3; ++c) {
+        hipLaunchKernelGGL(gather_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
+                           s->d_perm.p, src[c], s->d_w.p + c * nc);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->t = t;
+    s->dt_last = 0.0;
+    s->clamps = 0;
+    s->has_state = true;
+    return VSW_OK;
+}
+
+int vsw_get_state(vsw_solver* s, double* H, double* HU, double* HV, double* t) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_state) return fail(VSW_ESTATE, "no state");
+    DeviceGuard dg(s->device);
+    const int64_t nc = s->nc;
+    std::vector<double> w(3 * size_t(nc));
+    HIP_TRY(hipMemcpyAsync(w.data(), s->d_w.p, w.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int64_t i = 0; i < nc; ++i) {
+        const int64_t k = s->perm[i];
+        if (H) H[k] = w[i];
+        if (HU) HU[k] = w[nc + i];
+        if (HV) HV[k] = w[2 * nc + i];
+    }
+    if (t) *t = s->t;
+    return VSW_OK;
+}
+
+int vsw_get_state_device(vsw_solver* s, double* dH, double* dHU, double* dHV, double* t) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_state) return fail(VSW_ESTATE, "no state");
+    DeviceGuard dg(s->device);
+    const int64_t nc = s->nc;
+    double* dst[3] = {dH, dHU, dHV};
+    for (int c = 0; c < 3; ++c) {
+        if (!dst[c]) continue;
+        hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
+                           s->d_perm.p, s->d_w.p + c * nc, dst[c]);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (t) *t = s->t;
+    return VSW_OK;
+}
+
+int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, double* t_out) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_mesh || !s->has_state) return fail(VSW_ESTATE, "mesh and state required");
+    if (n < 0) return fail(VSW_EINVAL, "negative step count");
+    if (std::isnan(t_stop)) return fail(VSW_EINVAL, "t_stop is NaN");
+    if (n > INT32_MAX) return fail(VSW_EINVAL, "too many steps in one call");
+    if (steps_done) *steps_done = 0;
+    if (t_out) *t_out = s->t;
+    if (n == 0) return VSW_OK;
+    DeviceGuard dg(s->device);
+    if (s->d_log.n < size_t(2 * n)) HIP_TRY(s->d_log.alloc(size_t(2 * n)));
+    const int64_t nc = s->nc;
+    const DevMesh m = s->dev_mesh();
+    StepParams p;
+    p.g = s->prm.g;
+    p.hg = 0.5 * s->prm.g;
+    p.thr = s->prm.h_threshold;
+    p.cfl = s->prm.cfl;
+    p.dt_fixed = s->prm.dt_fixed;
+    p.t_stop = t_stop;
+    double* H = s->d_w.p;
+    double* HU = H + nc;
+    double* HV = H + 2 * nc;
+    double* H1 = s->d_w1.p;
+    double* HU1 = H1 + nc;
+    double* HV1 = H1 + 2 * nc;
+    FaceBuf fb{s->d_face.p, s->d_sc.p, s->d_order.p};
+    Ctrl* c = s->d_ctrl.p;
+    double* tlog = s->d_log.p;
+    double* dtlog = s->d_log.p + n;
+    const dim3 grid(grid_for(nc)), block(kBlock);
+    hipStream_t st = s->stream;
+
+    // profiling events: one pair per timed launch
+    size_t ev_used = 0;
+    auto ev_begin = [&](int kind) {
+        if (!s->profiling) return;
+        if (ev_used + 2 > s->ev_pool.size()) {
+            for (int i = 0; i < 64; ++i) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) break;
+                s->ev_pool.push_back(e);
+            }
+        }
+        if (ev_used + 2 > s->ev_pool.size()) return;
+        (void)hipEventRecord(s->ev_pool[ev_used], st);
+        if (s->ev_kind.size() < s->ev_pool.size() / 2 + 1) s->ev_kind.resize(s->ev_pool.size() / 2 + 1);
+        s->ev_kind[ev_used / 2] = kind;
+    };
+    auto ev_end = [&]() {
+        if (!s->profiling || ev_used + 2 > s->ev_pool.size()) return;
+        (void)hipEventRecord(s->ev_pool[ev_used + 1], st);
+        ev_used += 2;
+    };
+
+    hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(64), 0, st, c, s->t);
+    ev_begin(KK_DTINIT);
+    hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, H, HU, HV, p.g, p.thr, c);
+    ev_end();
+    for (int64_t k = 0; k < n; ++k) {
+        const int slot = int(k & 1);
+        ev_begin(KK_RECON);
+        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, H, HU, HV, fb, p, c, slot);
+        ev_end();
+        ev_begin(KK_UPDATE1);
+        hipLaunchKernelGGL(update1_kernel, grid, block, 0, st, m, H, HU, HV, H1, HU1, HV1, fb, p,
+                           c, slot);
+        ev_end();
+        ev_begin(KK_RECON);
+        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, H1, HU1, HV1, fb, p, c, slot);
+        ev_end();
+        ev_begin(KK_UPDATE2);
+        hipLaunchKernelGGL(update2_kernel, grid, block, 0, st, m, H, HU, HV, H1, HU1, HV1, fb, p,
+                           c, slot, int(k), tlog, dtlog);
+        ev_end();
+    }
+    HIP_TRY(hipGetLastError());
+    Ctrl hc;
+    HIP_TRY(hipMemcpyAsync(&hc, c, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    std::vector<double> logs(2 * size_t(n));
+    HIP_TRY(hipMemcpyAsync(logs.data(), s->d_log.p, 2 * size_t(n) * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (s->profiling) {
+        for (size_t i = 0; i + 1 < ev_used; i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, s->ev_pool[i], s->ev_pool[i + 1]) == hipSuccess) {
+                const int kind = s->ev_kind[i / 2];
+                s->prof_ms[kind] += ms;
+                s->prof_n[kind] += 1;
+            }
+        }
+    }
+    int64_t done = hc.steps_done;
+    int rc = VSW_OK;
+    if (hc.err) {
+        done = hc.err_step;
+        rc = fail(VSW_EUNSTABLE, hc.err == 1 ? "non-finite state" : "no valid time step");
+    }
+    s->clamps = int64_t(hc.clamps);
+    s->last_dts.assign(logs.begin() + n, logs.begin() + n + done);
+    if (done > 0) {
+        s->t = logs[done - 1];
+        s->dt_last = logs[n + done - 1];
+    }
+    if (steps_done) *steps_done = done;
+    if (t_out) *t_out = s->t;
+    return rc;
+}
+
+int vsw_last_dt(vsw_solver* s, double* dt) {
+    if (!s || !dt) return fail(VSW_EINVAL, "NULL argument");
+    *dt = s->dt_last;
+    return VSW_OK;
+}
+
+int vsw_clamp_count(vsw_solver* s, int64_t* count) {
+    if (!s || !count) return fail(VSW_EINVAL, "NULL argument");
+    *count = s->clamps;
+    return VSW_OK;
+}
+
+int vsw_dt_history(vsw_solver* s, int64_t max, double* dts, int64_t* count) {
+    if (!s || !count) return fail(VSW_EINVAL, "NULL argument");
+    const int64_t n = int64_t(s->last_dts.size());
+    *count = n;
+    if (dts)
+        for (int64_t i = 0; i < n && i < max; ++i) dts[i] = s->last_dts[i];
+    return VSW_OK;
+}
+
+int vsw_set_profiling(vsw_solver* s, int on) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    s->profiling = on != 0;
+    for (int i = 0; i < KK_COUNT; ++i) {
+        s->prof_ms[i] = 0;
+        s->prof_n[i] = 0;
+    }
+    return VSW_OK;
+}
+
+int vsw_kernel_times(vsw_solver* s, int nkinds, double* ms, int64_t* launches) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    for (int i = 0; i < nkinds; ++i) {
+        if (ms) ms[i] = i < KK_COUNT ? s->prof_ms[i] : 0.0;
+        if (launches) launches[i] = i < KK_COUNT ? s->prof_n[i] : 0;
+    }
+    return VSW_OK;
+}
+
+int vsw_prepare_mesh_host(int64_t nv, const double* vx, const double* vy, int64_t nc,
+                          const int32_t* tri, const double* h, double* geom, double* area,
+                          double* perim, int32_t* nbr, int32_t* is_left, int64_t* ne,
+                          int64_t* nw) {
+    HostMesh hm;
+    std::string err;
+    int rc = build_host_mesh(nv, vx, vy, nc, tri, h, VSW_ORDER_NONE, 0, hm, err);
+    if (rc != VSW_OK) return fail(rc, err);
+    for (int64_t i = 0; i < nc; ++i) {
+        const int64_t k = hm.perm[i];
+        for (int j = 0; j < 3; ++j) {
+            for (int f = 0; f < G_NFACE; ++f)
+                if (geom)
+                    geom[(size_t(f) * 3 + j) * nc + k] = hm.face_geom[(size_t(f) * 3 + j) * nc + i];
+            const uint32_t sl = hm.nbr[size_t(j) * nc + i];
+            if (nbr) nbr[size_t(j) * nc + k] = sl == kWall ? -1 : int32_t(hm.perm[sl >> 3]);
+            if (is_left) is_left[size_t(j) * nc + k] = (sl == kWall || (sl & 4u)) ? 1 : 0;
+        }
+        if (area) area[k] = hm.area[i];
+        if (perim) perim[k] = hm.perim[i];
+    }
+    if (ne) *ne = hm.ne;
+    if (nw) *nw = hm.nw;
+    return VSW_OK;
+}
+
+int vsw_get_permutation(vsw_solver* s, int64_t* perm) {
+    if (!s || !perm) return fail(VSW_EINVAL, "NULL argument");
+    if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
+    std::memcpy(perm, s->perm.data(), s->perm.size() * sizeof(int64_t));
+    return VSW_OK;
+}
+
+int vsw_mesh_info(vsw_solver* s, int64_t* nc, int64_t* ne, int64_t* nw) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
+    if (nc) *nc = s->nc;
+    if (ne) *ne = s->ne;
+    if (nw) *nw = s->nw;
+    return VSW_OK;
+}
+
+}  // extern "C"

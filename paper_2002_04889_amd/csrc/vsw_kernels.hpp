@@ -1,0 +1,52 @@
+// Shared declarations of the stage kernels and their launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "vsw_device.hpp"
+
+namespace vsw {
+
+constexpr int kBlock = 256;  // threads per block (four wave64)
+
+// Device control block: per-step time and CFL minimum in two slots (the
+// step using slot s writes the next step's values into slot s ^ 1).
+struct Ctrl {
+    unsigned long long rmin[2];  // bits of min_K |K| / (P_K (|u| + c))
+    double t[2];                 // time at the start of the step
+    double dt_last;
+    unsigned long long clamps;   // negative depths set to zero
+    long long steps_done;
+    int err;                     // 0 ok, 1 non-finite state, 2 no valid dt
+    int err_step;                // first failing step of the call
+};
+
+struct StepParams {
+    double g, hg, thr, cfl, dt_fixed, t_stop;
+};
+
+// Face buffer of one stage: per face j and cell k the face state
+// (eta, h, H, u, v) at f[(5 j + c) nc + k]; the centred bed source at
+// sc[k], sc[nc + k]; the reconstruction order (1 or 2) at order[k].
+struct FaceBuf {
+    double* __restrict__ f;
+    double* __restrict__ sc;
+    int32_t* __restrict__ order;
+};
+
+__global__ void ctrl_init_kernel(Ctrl* c, double t0);
+__global__ void dt_init_kernel(DevMesh m, const double* H, const double* HU, const double* HV,
+                               double g, double thr, Ctrl* c);
+__global__ void recon_kernel(DevMesh m, const double* H, const double* HU, const double* HV,
+                             FaceBuf fb, StepParams p, const Ctrl* c, int slot);
+__global__ void update1_kernel(DevMesh m, const double* H, const double* HU, const double* HV,
+                               double* H1, double* HU1, double* HV1, FaceBuf fb, StepParams p,
+                               Ctrl* c, int slot);
+__global__ void update2_kernel(DevMesh m, double* H, double* HU, double* HV, const double* H1,
+                               const double* HU1, const double* HV1, FaceBuf fb, StepParams p,
+                               Ctrl* c, int slot, int step, double* tlog, double* dtlog);
+__global__ void gather_kernel(int64_t n, const int64_t* perm, const double* src, double* dst);
+__global__ void scatter_kernel(int64_t n, const int64_t* perm, const double* src, double* dst);
+
+}  // namespace vsw

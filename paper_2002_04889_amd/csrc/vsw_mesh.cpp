@@ -1,0 +1,272 @@
+// Host-side mesh preparation for the GPU solver.
+//
+// Geometry follows the cell-centred finite-volume discretisation of
+// Section 2.2 and the reconstruction of Section 2.4 (cell centre x_0, face
+// centre x_f, least-squares stencil of the three face neighbours, wall ghost
+// cells of Section 2.5).  The arithmetic of every geometric quantity is
+// written out operation by operation and the file is compiled without
+// floating-point contraction, so the values are the IEEE-754 results of the
+// expressions as written.
+#include "vsw_mesh.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+
+#include "../../include/vsw.h"
+
+namespace vsw {
+namespace {
+
+// Hilbert index of (x, y) on a 2^16 x 2^16 grid (classic rotate-and-flip
+// walk, most significant level first).
+uint64_t hilbert16(uint32_t x, uint32_t y) {
+    uint64_t d = 0;
+    for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
+        uint32_t rx = (x & s) ? 1u : 0u;
+        uint32_t ry = (y & s) ? 1u : 0u;
+        d += uint64_t(s) * uint64_t(s) * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = (s - 1) - (x & (s - 1)) + (x & ~(s - 1));
+                y = (s - 1) - (y & (s - 1)) + (y & ~(s - 1));
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+uint64_t splitmix64(uint64_t& st) {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
+                    const int32_t* tri_in, const double* h_in, int ordering,
+                    uint64_t seed, HostMesh& out, std::string& err) {
+    char buf[256];
+    if (nv <= 0 || nc <= 0 || !vx || !vy || !tri_in || !h_in) {
+        err = "empty mesh or NULL array";
+        return VSW_EINVAL;
+    }
+    if (nc > kMaxCells || nv > INT32_MAX) {
+        err = "mesh too large for 29-bit cell indices";
+        return VSW_EINVAL;
+    }
+    // 1. counter-clockwise vertex order (swap local vertices 1 and 2 of a
+    //    clockwise triangle)
+    std::vector<int32_t> tri(3 * nc);
+    for (int64_t k = 0; k < nc; ++k) {
+        int32_t a = tri_in[3 * k], b = tri_in[3 * k + 1], c = tri_in[3 * k + 2];
+        if (a < 0 || a >= nv || b < 0 || b >= nv || c < 0 || c >= nv) {
+            snprintf(buf, sizeof buf, "triangle %lld: vertex index out of range", (long long)k);
+            err = buf;
+            return VSW_EMESH;
+        }
+        double cr = (vx[b] - vx[a]) * (vy[c] - vy[a]) - (vx[c] - vx[a]) * (vy[b] - vy[a]);
+        if (!(cr != 0.0) || !std::isfinite(cr)) {
+            snprintf(buf, sizeof buf, "triangle %lld: zero area", (long long)k);
+            err = buf;
+            return VSW_EMESH;
+        }
+        if (cr < 0.0) std::swap(b, c);
+        tri[3 * k] = a;
+        tri[3 * k + 1] = b;
+        tri[3 * k + 2] = c;
+    }
+    for (int64_t i = 0; i < nc; ++i)
+        if (!std::isfinite(h_in[i])) {
+            err = "non-finite depth";
+            return VSW_EINVAL;
+        }
+
+    // 2. internal order
+    std::vector<int64_t> perm(nc);
+    std::iota(perm.begin(), perm.end(), int64_t(0));
+    if (ordering == VSW_ORDER_HILBERT) {
+        std::vector<double> cx(nc), cy(nc);
+        double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+        for (int64_t k = 0; k < nc; ++k) {
+            const int32_t* t = &tri[3 * k];
+            cx[k] = (vx[t[0]] + vx[t[1]] + vx[t[2]]) / 3.0;
+            cy[k] = (vy[t[0]] + vy[t[1]] + vy[t[2]]) / 3.0;
+            x0 = std::min(x0, cx[k]); x1 = std::max(x1, cx[k]);
+            y0 = std::min(y0, cy[k]); y1 = std::max(y1, cy[k]);
+        }
+        double span = std::max(x1 - x0, y1 - y0);
+        double sc = span > 0 ? 65535.0 / span : 0.0;
+        std::vector<uint64_t> key(nc);
+        for (int64_t k = 0; k < nc; ++k) {
+            uint32_t qx = uint32_t(std::min(65535.0, std::max(0.0, (cx[k] - x0) * sc)));
+            uint32_t qy = uint32_t(std::min(65535.0, std::max(0.0, (cy[k] - y0) * sc)));
+            key[k] = (hilbert16(qx, qy) << 32) | uint64_t(k);
+        }
+        std::sort(key.begin(), key.end());
+        for (int64_t i = 0; i < nc; ++i) perm[i] = int64_t(key[i] & 0xFFFFFFFFull);
+    } else if (ordering == VSW_ORDER_RANDOM) {
+        uint64_t st = seed;
+        for (int64_t i = nc - 1; i > 0; --i) {
+            int64_t j = int64_t(splitmix64(st) % uint64_t(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+    } else if (ordering != VSW_ORDER_NONE) {
+        err = "unknown ordering";
+        return VSW_EINVAL;
+    }
+    std::vector<int64_t> inv(nc);
+    for (int64_t i = 0; i < nc; ++i) inv[perm[i]] = i;
+
+    // 3. face matching: bucket directed faces by their smaller vertex, then
+    //    pair equal larger vertices inside a bucket
+    std::vector<int64_t> start(nv + 1, 0);
+    for (int64_t k = 0; k < nc; ++k)
+        for (int j = 0; j < 3; ++j) {
+            int32_t a = tri[3 * k + j], b = tri[3 * k + (j + 1) % 3];
+            start[std::min(a, b) + 1]++;
+        }
+    for (int64_t v = 0; v < nv; ++v) start[v + 1] += start[v];
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    std::vector<int64_t> slot(3 * nc);  // directed face id = 3k + j
+    for (int64_t k = 0; k < nc; ++k)
+        for (int j = 0; j < 3; ++j) {
+            int32_t a = tri[3 * k + j], b = tri[3 * k + (j + 1) % 3];
+            slot[fill[std::min(a, b)]++] = 3 * k + j;
+        }
+    std::vector<int64_t> mate(3 * nc, -1);
+    int64_t ne = 0, nw = 0;
+    for (int64_t v = 0; v < nv; ++v) {
+        for (int64_t p = start[v]; p < start[v + 1]; ++p) {
+            int64_t f = slot[p];
+            if (mate[f] != -1) continue;
+            int64_t k = f / 3;
+            int j = int(f % 3);
+            int32_t a = tri[3 * k + j], b = tri[3 * k + (j + 1) % 3];
+            int32_t hi = std::max(a, b);
+            int64_t found = -1;
+            for (int64_t q = p + 1; q < start[v + 1]; ++q) {
+                int64_t f2 = slot[q];
+                int64_t k2 = f2 / 3;
+                int j2 = int(f2 % 3);
+                int32_t a2 = tri[3 * k2 + j2], b2 = tri[3 * k2 + (j2 + 1) % 3];
+                if (std::max(a2, b2) != hi) continue;
+                if (found != -1 || mate[f2] != -1) {
+                    snprintf(buf, sizeof buf, "face of triangle %lld is shared by more than two triangles",
+                             (long long)k);
+                    err = buf;
+                    return VSW_EMESH;
+                }
+                if (a2 == a) {
+                    snprintf(buf, sizeof buf, "triangles %lld and %lld lie on the same side of a face",
+                             (long long)k, (long long)k2);
+                    err = buf;
+                    return VSW_EMESH;
+                }
+                found = f2;
+            }
+            ++ne;
+            if (found == -1) {
+                mate[f] = -2;  // wall
+                ++nw;
+            } else {
+                if (vx[a] == vx[b] && vy[a] == vy[b]) {
+                    err = "duplicate vertex coordinates on a face";
+                    return VSW_EMESH;
+                }
+                mate[f] = found;
+                mate[found] = f;
+            }
+        }
+    }
+
+    // 4. packed neighbour slots in internal order; the canonical left side
+    //    of an interior face is the cell that walks it from its
+    //    lexicographically smaller (x, y) vertex
+    out.nc = nc;
+    out.nv = nv;
+    out.ne = ne;
+    out.nw = nw;
+    out.nbr.assign(3 * nc, kWall);
+    for (int64_t i = 0; i < nc; ++i) {
+        int64_t k = perm[i];
+        for (int j = 0; j < 3; ++j) {
+            int64_t f = 3 * k + j;
+            if (mate[f] < 0) continue;
+            int64_t k2 = mate[f] / 3;
+            int j2 = int(mate[f] % 3);
+            int32_t a = tri[3 * k + j], b = tri[3 * k + (j + 1) % 3];
+            bool left = (vx[a] < vx[b]) || (vx[a] == vx[b] && vy[a] < vy[b]);
+            out.nbr[size_t(j) * nc + i] =
+                (uint32_t(inv[k2]) << 3) | (left ? 4u : 0u) | uint32_t(j2);
+        }
+    }
+
+    // 5. geometry in internal order
+    out.face_geom.assign(size_t(G_NFACE) * 3 * nc, 0.0);
+    out.area.assign(nc, 0.0);
+    out.perim.assign(nc, 0.0);
+    out.h.assign(nc, 0.0);
+    auto G = [&](int field, int j, int64_t i) -> double& {
+        return out.face_geom[(size_t(field) * 3 + j) * nc + i];
+    };
+    std::vector<double> ccx(nc), ccy(nc);
+    for (int64_t i = 0; i < nc; ++i) {
+        const int32_t* t = &tri[3 * perm[i]];
+        double xa0 = vx[t[0]], xa1 = vx[t[1]], xa2 = vx[t[2]];
+        double ya0 = vy[t[0]], ya1 = vy[t[1]], ya2 = vy[t[2]];
+        double cr = (xa1 - xa0) * (ya2 - ya0) - (xa2 - xa0) * (ya1 - ya0);
+        out.area[i] = 0.5 * cr;
+        ccx[i] = ((xa0 + xa1) + xa2) / 3.0;
+        ccy[i] = ((ya0 + ya1) + ya2) / 3.0;
+        double l[3];
+        for (int j = 0; j < 3; ++j) {
+            double xs = vx[t[j]], ys = vy[t[j]];
+            double xe = vx[t[(j + 1) % 3]], ye = vy[t[(j + 1) % 3]];
+            double ex = xe - xs, ey = ye - ys;
+            l[j] = std::sqrt(ex * ex + ey * ey);
+            G(G_LEN, j, i) = l[j];
+            G(G_NX, j, i) = ey / l[j];
+            G(G_NY, j, i) = (-ex) / l[j];
+            G(G_DX, j, i) = (xs + xe) * 0.5 - ccx[i];
+            G(G_DY, j, i) = (ys + ye) * 0.5 - ccy[i];
+        }
+        out.perim[i] = (l[0] + l[1]) + l[2];
+        out.h[i] = h_in[perm[i]];
+    }
+    // least-squares weights w_j = M^-1 delta_j, M = sum_j delta_j delta_j^T;
+    // delta_j points to the neighbour centroid or to the wall ghost (the
+    // centroid reflected in the wall face)
+    for (int64_t i = 0; i < nc; ++i) {
+        double ex[3], ey[3];
+        for (int j = 0; j < 3; ++j) {
+            uint32_t s = out.nbr[size_t(j) * nc + i];
+            if (s != kWall) {
+                int64_t n = int64_t(s >> 3);
+                ex[j] = ccx[n] - ccx[i];
+                ey[j] = ccy[n] - ccy[i];
+            } else {
+                double nx = G(G_NX, j, i), ny = G(G_NY, j, i);
+                double dn = G(G_DX, j, i) * nx + G(G_DY, j, i) * ny;
+                ex[j] = (2.0 * dn) * nx;
+                ey[j] = (2.0 * dn) * ny;
+            }
+        }
+        double sxx = (ex[0] * ex[0] + ex[1] * ex[1]) + ex[2] * ex[2];
+        double sxy = (ex[0] * ey[0] + ex[1] * ey[1]) + ex[2] * ey[2];
+        double syy = (ey[0] * ey[0] + ey[1] * ey[1]) + ey[2] * ey[2];
+        double det = sxx * syy - sxy * sxy;
+        for (int j = 0; j < 3; ++j) {
+            G(G_WX, j, i) = (syy * ex[j] - sxy * ey[j]) / det;
+            G(G_WY, j, i) = (sxx * ey[j] - sxy * ex[j]) / det;
+        }
+    }
+    out.perm = std::move(perm);
+    return VSW_OK;
+}
+
+}  // namespace vsw

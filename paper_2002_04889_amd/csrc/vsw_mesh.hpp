@@ -1,0 +1,45 @@
+// Host-side mesh preparation for the GPU solver: orientation, face
+// matching, canonical face orientation, internal cell order and geometry.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace vsw {
+
+// Neighbour slot encoding (uint32 per cell face):
+//   wall face      : kWall
+//   interior face  : (neighbour << 3) | (is_left << 2) | neighbour_face
+// where is_left says whether this cell is the canonical left side of the
+// face and neighbour_face is the face's local index inside the neighbour.
+constexpr uint32_t kWall = 0xFFFFFFFFu;
+constexpr int64_t kMaxCells = (int64_t(1) << 29) - 1;
+
+// Geometry fields, each stored as [face j][cell] (3 * nc doubles) or [cell].
+enum GeomField : int {
+    G_NX = 0,   // outward unit normal x of face j
+    G_NY,       // outward unit normal y
+    G_LEN,      // face length
+    G_DX,       // face midpoint minus centroid, x
+    G_DY,       // face midpoint minus centroid, y
+    G_WX,       // least-squares weight x of stencil member j
+    G_WY,       // least-squares weight y
+    G_NFACE     // number of per-face fields
+};
+
+struct HostMesh {
+    int64_t nc = 0, nv = 0, ne = 0, nw = 0;
+    std::vector<int64_t> perm;      // internal cell i -> caller's cell perm[i]
+    std::vector<uint32_t> nbr;      // [3][nc] packed neighbour slots
+    std::vector<double> face_geom;  // [G_NFACE][3][nc]
+    std::vector<double> area;       // [nc]
+    std::vector<double> perim;      // [nc]
+    std::vector<double> h;          // [nc] still-water depth
+};
+
+// Returns 0 or a VSW_E* code with a message in err.
+int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
+                    const int32_t* tri, const double* h, int ordering, uint64_t seed,
+                    HostMesh& out, std::string& err);
+
+}  // namespace vsw

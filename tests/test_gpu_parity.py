@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs, element by element.
+
+Bar (FP64): per field q in (H, HU, HV), max_K |q_gpu - q_oracle| <= 1e-12
+max_K |q_oracle|, and the same for the time and every step's dt.  Both
+sides evaluate the same expressions in the same order without contraction,
+so the observed difference is normally exactly zero; the tests print it.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2002_04889_amd import vsw
+from paper_2002_04889_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(case, n, t_stop=math.inf, ordering=vsw.VSW_ORDER_HILBERT, chunks=None, **kw):
+    s = vsw.Solver.for_case(case, ordering=ordering, **kw)
+    try:
+        if chunks is None:
+            rc, done, t = s.step(n, t_stop, check=False)
+            dts = vsw.vsw_dt_history(s.h)
+        else:
+            done, dts, rc = 0, [], 0
+            while done < n and rc == 0:
+                rc, d, t = s.step(min(chunks, n - done), t_stop, check=False)
+                dts.extend(vsw.vsw_dt_history(s.h))
+                done += d
+                if d == 0:
+                    break
+            dts = np.array(dts)
+        H, HU, HV, t = s.state()
+        return {"H": H, "HU": HU, "HV": HV, "t": t, "steps": done, "dts": dts, "rc": rc,
+                "clamps": vsw.vsw_clamp_count(s.h)}
+    finally:
+        s.close()
+
+
+def orc_run(orc, case, n, t_stop=math.inf, **kw):
+    m = orc.Mesh.from_case(case)
+    d = dict(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold)
+    d.update(kw)
+    return m.run(orc.params(**d), case.H, case.HU, case.HV, case.t0, n, t_stop, check=False)
+
+
+def assert_parity(g, o, label=""):
+    assert g["steps"] == o["steps"], (g["steps"], o["steps"])
+    report = []
+    for k in ("H", "HU", "HV"):
+        scale = max(np.abs(o[k]).max(), 1e-300)
+        diff = np.abs(g[k] - o[k]).max()
+        report.append(f"{k}: maxdiff {diff:.3e} rel {diff / scale:.3e} "
+                      f"bitwise {np.mean(g[k] == o[k]) * 100:.2f}%")
+        assert diff <= TOL * scale, (k, diff, scale)
+    assert abs(g["t"] - o["t"]) <= TOL * max(abs(o["t"]), 1e-300)
+    if len(o["dts"]):
+        assert np.abs(g["dts"] - o["dts"]).max() <= TOL * o["dts"].max()
+    say(label, "steps", g["steps"], "t", g["t"], "|", "; ".join(report))
+
+
+def test_thacker_period(orc):
+    c = W.thacker_case(45)
+    say("thacker45", c.nc, "cells, one period")
+    g = gpu_run(c, 5000, c.t_end)
+    o = orc_run(orc, c, 5000, c.t_end)
+    assert g["t"] == c.t_end
+    assert_parity(g, o, "thacker45")
+
+
+def test_thacker_chunked_calls_equal_one_call():
+    c = W.thacker_case(23)
+    a = gpu_run(c, 300)
+    b = gpu_run(c, 300, chunks=37)
+    for k in ("H", "HU", "HV"):
+        assert np.array_equal(a[k], b[k])
+    assert np.array_equal(a["dts"], b["dts"]) and a["t"] == b["t"]
+
+
+def test_basin_small(orc):
+    c = W.basin_case(scale=8)
+    say("basin scale 8", c.nc, "cells, 300 steps")
+    g = gpu_run(c, 300)
+    o = orc_run(orc, c, 300)
+    assert_parity(g, o, "basin-s8")
+    assert g["clamps"] == o["clamps"]
+
+
+@pytest.mark.parametrize("ordering", [vsw.VSW_ORDER_NONE, vsw.VSW_ORDER_RANDOM])
+def test_orderings_bitwise(ordering):
+    c = W.basin_case(scale=16)
+    a = gpu_run(c, 100)
+    b = gpu_run(c, 100, ordering=ordering, seed=99)
+    for k in ("H", "HU", "HV"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("which", ["thacker", "basin"])
+def test_lake_at_rest(which):
+    c = W.thacker_case(45, still=True) if which == "thacker" else W.basin_case(scale=16,
+                                                                               eta_amp=0.0)
+    g = gpu_run(c, 500)
+    Hm = c.H.max()
+    assert np.abs(g["H"] - c.H).max() <= 1e-12 * Hm
+    vmax = 1e-12 * Hm * math.sqrt(c.g * Hm)
+    assert np.abs(g["HU"]).max() <= vmax and np.abs(g["HV"]).max() <= vmax
+
+
+@pytest.mark.parametrize("kind", ["single", "square2", "square8"])
+def test_tiny_meshes(orc, kind):
+    if kind == "single":
+        vx, vy, tri = np.array([0.0, 1.0, 0.2]), np.array([0.0, 0.1, 0.9]), np.array([[0, 2, 1]])
+    else:
+        vx, vy, tri = W.tiny_mesh(kind)
+    nc = len(tri)
+    rng = np.random.default_rng(21)
+    h = rng.uniform(0.5, 2.0, nc)
+    H = h + rng.uniform(-0.1, 0.1, nc)
+    c = W.Case(name=kind, vx=vx, vy=vy, tri=np.asarray(tri, dtype=np.int32), h=h, H=H,
+               HU=rng.normal(0, 0.3, nc), HV=rng.normal(0, 0.3, nc), cfl=0.45,
+               h_threshold=1e-3)
+    g = gpu_run(c, 40)
+    o = orc_run(orc, c, 40)
+    assert_parity(g, o, kind)
+
+
+def test_dam_break_dry_bed(orc):
+    c = W.channel_case(n_len=201, h_threshold=1e-3)
+    g = gpu_run(c, 400)
+    o = orc_run(orc, c, 400)
+    assert_parity(g, o, "channel")
+    assert g["clamps"] == o["clamps"]
+
+
+def test_fixed_dt_and_t_stop(orc):
+    c = W.thacker_case(23)
+    g = gpu_run(c, 1000, 0.3, dt_fixed=2e-3)
+    o = orc_run(orc, c, 1000, 0.3, dt_fixed=2e-3)
+    assert g["t"] == 0.3
+    assert_parity(g, o, "dt_fixed")
+
+
+def test_unstable_run_reports_eunstable(orc):
+    c = W.thacker_case(23)
+    g = gpu_run(c, 400, dt_fixed=0.2)
+    o = orc_run(orc, c, 400, dt_fixed=0.2)
+    assert o["rc"] != 0
+    assert g["rc"] == vsw.VSW_EUNSTABLE
+    assert g["steps"] == o["steps"] < 400
+
+
+def test_state_validation_and_order_errors():
+    c = W.thacker_case(23)
+    s = vsw.Solver(g=c.g, cfl=c.cfl, h_threshold=c.h_threshold)
+    try:
+        with pytest.raises(vsw.VswError, match="ESTATE"):
+            s.set_state(c.H, c.HU, c.HV)
+        s.upload_mesh(c.vx, c.vy, c.tri, c.h)
+        with pytest.raises(vsw.VswError, match="ESTATE"):
+            s.step(1)
+        bad = c.H.copy()
+        bad[3] = np.nan
+        with pytest.raises(vsw.VswError, match="EINVAL"):
+            s.set_state(bad, c.HU, c.HV)
+        bad[3] = -1.0
+        with pytest.raises(vsw.VswError, match="EINVAL"):
+            s.set_state(bad, c.HU, c.HV)
+        s.set_state(c.H, c.HU, c.HV)
+        rc, done, t = s.step(0)
+        assert rc == 0 and done == 0 and t == 0.0
+        nc, ne, nw = vsw.vsw_mesh_info(s.h)
+        assert nc == c.nc and nw == 4 * 22 and ne == (3 * nc + nw) // 2
+    finally:
+        s.close()
+
+
+def test_device_state_roundtrip_and_profiling():
+    import torch
+
+    c = W.thacker_case(23)
+    s = vsw.Solver.for_case(c)
+    try:
+        dev = torch.device("cuda:0")
+        st = torch.cuda.Stream()
+        vsw.vsw_set_stream(s.h, st.cuda_stream)
+        H = torch.tensor(c.H, device=dev)
+        HU = torch.tensor(c.HU, device=dev)
+        HV = torch.tensor(c.HV, device=dev)
+        torch.cuda.synchronize()
+        vsw.vsw_set_state_device(s.h, H.data_ptr(), HU.data_ptr(), HV.data_ptr(), 0.0)
+        vsw.vsw_set_profiling(s.h, True)
+        s.step(20)
+        times = vsw.vsw_kernel_times(s.h)
+        assert times["update2_kernel"][1] == 20 and times["recon_kernel"][1] == 40
+        assert all(ms > 0 for ms, n in times.values() if n)
+        outH = torch.empty_like(H)
+        outU = torch.empty_like(H)
+        outV = torch.empty_like(H)
+        vsw.vsw_get_state_device(s.h, outH.data_ptr(), outU.data_ptr(), outV.data_ptr())
+        h2, u2, v2, t = s.state()
+        assert np.array_equal(outH.cpu().numpy(), h2) and np.array_equal(outU.cpu().numpy(), u2)
+        vsw.vsw_set_stream(s.h, None)
+    finally:
+        s.close()
+
+
+def test_basin_1m_bench_configuration(orc):
+    """The benchmark's workload (1M-triangle basin, Hilbert order, the
+    launch configuration the benchmark times): full-field parity after 30
+    steps, then 2000 steps checked by properties that hold at any size."""
+    c = W.basin_case()
+    say("basin", c.nc, "cells: 30-step parity")
+    g = gpu_run(c, 30)
+    o = orc_run(orc, c, 30)
+    assert_parity(g, o, "basin-1M-30")
+    s = vsw.Solver.for_case(c)
+    try:
+        rc, done, t = s.step(2000)
+        assert done == 2000
+        H, HU, HV, t = s.state()
+        m = orc.Mesh.from_case(c)
+        area = m.geometry()["area"]
+        m0, m1 = (area * c.H).sum(), (area * H).sum()
+        say("basin 2000 steps: t", t, "mass rel change", (m1 - m0) / m0, "clamps",
+            vsw.vsw_clamp_count(s.h))
+        assert np.isfinite(H).all() and np.isfinite(HU).all() and np.isfinite(HV).all()
+        assert abs(m1 - m0) <= 1e-12 * m0
+        assert (H >= 0).all()
+    finally:
+        s.close()

@@ -1,0 +1,92 @@
+"""CPU checks of the GPU library: it loads, exports every symbol its header
+declares, and its host-side mesh preparation (the mesh step of the path:
+validation, face matching, canonical orientation, geometry) agrees bitwise
+with the oracle's independent construction.  No kernel runs here."""
+import numpy as np
+import pytest
+
+from paper_2002_04889_amd import vsw
+from paper_2002_04889_amd import workloads as W
+
+
+def test_library_exports_header_symbols():
+    syms = vsw.header_symbols()
+    assert len(syms) >= 15
+    L = vsw.lib()
+    missing = [s for s in syms if not hasattr(L, s)]
+    assert not missing, missing
+    assert vsw.vsw_version().startswith("vsw")
+
+
+def test_binding_covers_header():
+    names = set(vsw.header_symbols())
+    assert names <= set(vsw._SIGS), names - set(vsw._SIGS)
+
+
+@pytest.mark.parametrize("case", ["thacker", "basin", "channel"])
+def test_host_mesh_matches_oracle_bitwise(orc, case):
+    c = {"thacker": lambda: W.thacker_case(45),
+         "basin": lambda: W.basin_case(scale=16),
+         "channel": lambda: W.channel_case(n_len=101)}[case]()
+    g = vsw.vsw_prepare_mesh_host(c.vx, c.vy, c.tri, c.h)
+    m = orc.Mesh.from_case(c)
+    og = m.geometry()
+    for k in ("nx", "ny", "len", "dx", "dy", "wx", "wy", "area", "perim", "nbr", "is_left"):
+        assert np.array_equal(g[k], og[k]), k
+    assert g["ne"] == m.ne and g["nw"] == m.nw
+
+
+def test_host_mesh_orientation_independent():
+    c = W.thacker_case(23)
+    tri = c.tri.copy()
+    flip = np.arange(c.nc) % 3 == 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    a = vsw.vsw_prepare_mesh_host(c.vx, c.vy, c.tri, c.h)
+    b = vsw.vsw_prepare_mesh_host(c.vx, c.vy, tri, c.h)
+    for k in ("nx", "len", "wx", "wy", "area", "nbr", "is_left"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_host_mesh_rejects_invalid():
+    vx, vy, tri = W.tiny_mesh("square2")
+    with pytest.raises(vsw.VswError, match="EMESH.*out of range"):
+        vsw.vsw_prepare_mesh_host(vx, vy, np.array([[0, 1, 7], [0, 2, 3]]), np.ones(2))
+    with pytest.raises(vsw.VswError, match="EMESH.*zero area"):
+        vsw.vsw_prepare_mesh_host(np.array([0.0, 1.0, 2.0]), np.zeros(3), np.array([[0, 1, 2]]),
+                                  np.ones(1))
+    vx3 = np.array([0.0, 1.0, 0.5, 0.5, 0.5])
+    vy3 = np.array([0.0, 0.0, 1.0, -1.0, 2.0])
+    with pytest.raises(vsw.VswError, match="EMESH.*more than two"):
+        vsw.vsw_prepare_mesh_host(vx3, vy3, np.array([[0, 1, 2], [0, 3, 1], [0, 1, 4]]),
+                                  np.ones(3))
+    with pytest.raises(vsw.VswError, match="EMESH.*same side"):
+        vsw.vsw_prepare_mesh_host(vx3, vy3, np.array([[0, 1, 2], [0, 1, 4]]), np.ones(2))
+    with pytest.raises(vsw.VswError, match="EINVAL"):
+        vsw.vsw_prepare_mesh_host(vx, vy, tri, np.array([1.0, np.nan]))
+
+
+def test_tiny_meshes_counts():
+    for kind, (ne, nw) in {"square2": (5, 4), "square8": (16, 8)}.items():
+        vx, vy, tri = W.tiny_mesh(kind)
+        g = vsw.vsw_prepare_mesh_host(vx, vy, tri, np.ones(len(tri)))
+        assert (g["ne"], g["nw"]) == (ne, nw)
+    # a single triangle: three walls
+    g = vsw.vsw_prepare_mesh_host(np.array([0.0, 1.0, 0.0]), np.array([0.0, 0.0, 1.0]),
+                                  np.array([[0, 1, 2]]), np.ones(1))
+    assert (g["ne"], g["nw"]) == (3, 3) and (g["nbr"] == -1).all()
+
+
+def test_create_fails_cleanly_without_gpu():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(vsw.VswError, match="EDEVICE"):
+        vsw.vsw_create(vsw.make_params())
+
+
+def test_create_validates_params():
+    for kw in ({"g": 0.0}, {"cfl": -1.0}, {"h_threshold": -1e-3}, {"dt_fixed": -1.0},
+               {"ordering": 7}):
+        with pytest.raises(vsw.VswError, match="EINVAL"):
+            vsw.vsw_create(vsw.make_params(**kw))
