@@ -403,7 +403,7 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         done = hc.err_step;
         rc = fail(VSW_EUNSTABLE, hc.err == 1 ? "non-finite state" : "no valid time step");
     }
-    s->clamps = int64_t(hc.clamps);
+    s->clamps += int64_t(hc.clamps);
     s->last_dts.assign(logs.begin() + n, logs.begin() + n + done);
     if (done > 0) {
         s->t = logs[done - 1];

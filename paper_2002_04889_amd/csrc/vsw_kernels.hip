@@ -111,6 +111,8 @@ __global__ void ctrl_init_kernel(Ctrl* c, double t0) {
         c->err = 0;
         c->err_step = 0x7FFFFFFF;
         c->steps_done = 0;
+        c->clamps = 0;
+        c->dt_last = 0.0;
     }
 }
 

@@ -16,7 +16,7 @@ struct Ctrl {
     unsigned long long rmin[2];  // bits of min_K |K| / (P_K (|u| + c))
     double t[2];                 // time at the start of the step
     double dt_last;
-    unsigned long long clamps;   // negative depths set to zero
+    unsigned long long clamps;   // negative depths set to zero in this call
     long long steps_done;
     int err;                     // 0 ok, 1 non-finite state, 2 no valid dt
     int err_step;                // first failing step of the call

@@ -77,6 +77,11 @@ def lib():
     """Load libvsw.so (raises if it is missing: build it first)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname
+        # (libamdhip64.so.7).  Loading torch first makes libvsw.so bind to
+        # that one runtime; two runtimes in one process do not share a device.
+        import torch  # noqa: F401
+
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} not built; run __graft_entry__.build() "
                               "or python -m paper_2002_04889_amd.build")
