@@ -121,15 +121,13 @@ def main():
     vsw.vsw_set_profiling(s.h, False)
     log("[bench] kernel times: " + ", ".join(
         f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us x{v[1]}" for k, v in kt.items() if v[1]))
-    # dominant stage: stage 2 = recon + update2, stage 1 = recon + update1
+    # dominant kernel: the stage kernel with the longer average launch
     avg = {k: v[0] / v[1] for k, v in kt.items() if v[1]}
-    recon = avg.get("recon_kernel", 0.0)
-    st1 = recon + avg.get("update1_kernel", 0.0)
-    st2 = recon + avg.get("update2_kernel", 0.0)
+    st1, st2 = avg.get("stage1_kernel", 0.0), avg.get("stage2_kernel", 0.0)
     if st2 >= st1:
-        dom, dur_ms, per_cell = "stage2 (recon_kernel + update2_kernel)", st2, ALG_BYTES_STAGE2
+        dom, dur_ms, per_cell = "stage2_kernel", st2, ALG_BYTES_STAGE2
     else:
-        dom, dur_ms, per_cell = "stage1 (recon_kernel + update1_kernel)", st1, ALG_BYTES_STAGE1
+        dom, dur_ms, per_cell = "stage1_kernel", st1, ALG_BYTES_STAGE1
     traffic = per_cell * nc
     achieved = traffic / (dur_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,

@@ -131,6 +131,15 @@ int vsw_clamp_count(vsw_solver *s, int64_t *count);
  * solver's device); NULL returns to the solver's own stream. */
 int vsw_set_stream(vsw_solver *s, void *hip_stream);
 
+/* Kernel organisation of a stage (same results, bitwise):
+ * VSW_KERNEL_FUSED (default): one kernel per stage; each workgroup
+ *   reconstructs a tile of 256 consecutive (Hilbert-ordered) cells and its
+ *   halo faces into LDS and computes fluxes and the update from there.
+ * VSW_KERNEL_TWO_PASS: a reconstruction kernel writes every face state to
+ *   device memory, a second kernel computes fluxes and the update. */
+enum { VSW_KERNEL_FUSED = 0, VSW_KERNEL_TWO_PASS = 1 };
+int vsw_set_kernel_variant(vsw_solver *s, int variant);
+
 /* Per-kernel timing with HIP events recorded around every launch of the
  * stage kernels on the solver's stream (off by default).  vsw_kernel_times
  * returns, for kernel kinds 0..nkinds-1 (see vsw_kernel_name), the summed

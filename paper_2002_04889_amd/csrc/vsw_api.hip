@@ -2,6 +2,7 @@
 // mesh upload, state transfer and the step loop.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -31,9 +32,9 @@ int fail(int code, const std::string& msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));             \
     } while (0)
 
-enum KernelKind { KK_RECON = 0, KK_UPDATE1, KK_UPDATE2, KK_DTINIT, KK_COUNT };
-const char* kKernelNames[KK_COUNT] = {"recon_kernel", "update1_kernel", "update2_kernel",
-                                      "dt_init_kernel"};
+enum KernelKind { KK_RECON = 0, KK_UPDATE1, KK_UPDATE2, KK_DTINIT, KK_STAGE1, KK_STAGE2, KK_COUNT };
+const char* kKernelNames[KK_COUNT] = {"recon_kernel",   "update1_kernel", "update2_kernel",
+                                      "dt_init_kernel", "stage1_kernel",  "stage2_kernel"};
 
 template <class T>
 struct DevBuf {
@@ -74,6 +75,11 @@ struct vsw_solver {
     DevBuf<double> d_tmp;          // 3 * nc staging for permutation
     DevBuf<double> d_log;          // 2 * cap: t and dt per step
     DevBuf<Ctrl> d_ctrl;
+    DevBuf<uint16_t> d_nloc;       // tile map of the fused kernel
+    DevBuf<int32_t> d_bstart;
+    DevBuf<uint32_t> d_bitem;
+    int bmax = 0, ntiles = 0;
+    int variant = VSW_KERNEL_FUSED;
     double t = 0.0;
     double dt_last = 0.0;
     int64_t clamps = 0;
@@ -81,14 +87,15 @@ struct vsw_solver {
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_kind;      // kind of each event pair
-    double prof_ms[KK_COUNT] = {0, 0, 0, 0};
-    int64_t prof_n[KK_COUNT] = {0, 0, 0, 0};
+    double prof_ms[KK_COUNT] = {};
+    int64_t prof_n[KK_COUNT] = {};
     std::vector<double> last_dts;
 
     void release_mesh() {
         d_perm.release(); d_nbr.release(); d_geom.release(); d_area.release();
         d_perim.release(); d_h.release(); d_w.release(); d_w1.release();
         d_face.release(); d_sc.release(); d_order.release(); d_tmp.release();
+        d_nloc.release(); d_bstart.release(); d_bitem.release();
         has_mesh = has_state = false;
     }
     DevMesh dev_mesh() const {
@@ -213,6 +220,20 @@ int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* v
     HIP_TRY(hipMemcpy(s->d_area.p, hm.area.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->d_perim.p, hm.perim.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->d_h.p, hm.h.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    TileMapHost tmh;
+    build_tiles(hm, kTile, tmh);
+    HIP_TRY(s->d_nloc.alloc(tmh.nloc.size()));
+    HIP_TRY(s->d_bstart.alloc(tmh.bstart.size()));
+    HIP_TRY(s->d_bitem.alloc(std::max<size_t>(tmh.bitem.size(), 1)));
+    HIP_TRY(hipMemcpy(s->d_nloc.p, tmh.nloc.data(), tmh.nloc.size() * sizeof(uint16_t),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_bstart.p, tmh.bstart.data(), tmh.bstart.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice));
+    if (!tmh.bitem.empty())
+        HIP_TRY(hipMemcpy(s->d_bitem.p, tmh.bitem.data(), tmh.bitem.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice));
+    s->bmax = tmh.bmax;
+    s->ntiles = tmh.ntiles;
     s->has_mesh = true;
     s->has_state = false;
     return VSW_OK;
@@ -363,7 +384,21 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     ev_begin(KK_DTINIT);
     hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, H, HU, HV, p.g, p.thr, c);
     ev_end();
-    for (int64_t k = 0; k < n; ++k) {
+    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->bmax, s->ntiles};
+    const size_t lds = stage_lds_bytes(s->bmax);
+    const dim3 tgrid(unsigned(s->ntiles));
+    for (int64_t k = 0; s->variant == VSW_KERNEL_FUSED && k < n; ++k) {
+        const int slot = int(k & 1);
+        ev_begin(KK_STAGE1);
+        hipLaunchKernelGGL(stage_kernel<1>, tgrid, block, lds, st, m, tm, H, HU, HV, H1, HU1, HV1,
+                           p, c, slot, int(k), tlog, dtlog);
+        ev_end();
+        ev_begin(KK_STAGE2);
+        hipLaunchKernelGGL(stage_kernel<2>, tgrid, block, lds, st, m, tm, H, HU, HV, H1, HU1, HV1,
+                           p, c, slot, int(k), tlog, dtlog);
+        ev_end();
+    }
+    for (int64_t k = 0; s->variant == VSW_KERNEL_TWO_PASS && k < n; ++k) {
         const int slot = int(k & 1);
         ev_begin(KK_RECON);
         hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, H, HU, HV, fb, p, c, slot);
@@ -432,6 +467,14 @@ int vsw_dt_history(vsw_solver* s, int64_t max, double* dts, int64_t* count) {
     *count = n;
     if (dts)
         for (int64_t i = 0; i < n && i < max; ++i) dts[i] = s->last_dts[i];
+    return VSW_OK;
+}
+
+int vsw_set_kernel_variant(vsw_solver* s, int variant) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (variant != VSW_KERNEL_FUSED && variant != VSW_KERNEL_TWO_PASS)
+        return fail(VSW_EINVAL, "unknown kernel variant");
+    s->variant = variant;
     return VSW_OK;
 }
 

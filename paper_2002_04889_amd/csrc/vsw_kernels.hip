@@ -299,6 +299,196 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, double* __re
     }
 }
 
+// ---------------------------------------------------------------- fused stage
+
+namespace {
+
+// Tiles are consecutive Hilbert ranges, so tiles t and t+1 are neighbours in
+// space.  Workgroups are dealt round-robin to the eight XCDs, each with its
+// own L2; give XCD x one contiguous run of tiles so that the halo cells
+// shared by neighbouring tiles are read through the same L2.
+__device__ __forceinline__ int xcd_tile(int w, int ntiles) {
+    const int per = ntiles / 8, rem = ntiles % 8;
+    const int x = w % 8, idx = w / 8;
+    return (x < rem) ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+__device__ __forceinline__ void lds_store_face(double* lds, int stride, int slot, const Face& f) {
+    lds[0 * stride + slot] = f.eta;
+    lds[1 * stride + slot] = f.h;
+    lds[2 * stride + slot] = f.H;
+    lds[3 * stride + slot] = f.u;
+    lds[4 * stride + slot] = f.v;
+}
+
+__device__ __forceinline__ Face lds_load_face(const double* lds, int stride, int slot) {
+    Face f;
+    f.eta = lds[0 * stride + slot];
+    f.h = lds[1 * stride + slot];
+    f.H = lds[2 * stride + slot];
+    f.u = lds[3 * stride + slot];
+    f.v = lds[4 * stride + slot];
+    return f;
+}
+
+}  // namespace
+
+// One workgroup per tile of kTile cells, one thread per cell:
+//  1. reconstruct the tile's cells (Section 2.4) and store their three face
+//     states in LDS;
+//  2. reconstruct the halo cells across the tile boundary and store the one
+//     face each shares with the tile;
+//  3. per cell, the three face fluxes in canonical orientation from LDS, the
+//     centred bed source, the residual and the Runge-Kutta stage.
+template <int STAGE>
+__global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, double* __restrict__ H,
+                                                       double* __restrict__ HU,
+                                                       double* __restrict__ HV,
+                                                       double* __restrict__ H1,
+                                                       double* __restrict__ HU1,
+                                                       double* __restrict__ HV1, StepParams p,
+                                                       Ctrl* c, int slot, int step, double* tlog,
+                                                       double* dtlog) {
+    extern __shared__ double lds[];
+    const int stride = 3 * kTile + tm.bmax;
+    double dt, tn;
+    const bool active = step_dt(c, slot, p, dt, tn);
+    if (!active) {
+        if (STAGE == 2 && blockIdx.x == 0 && threadIdx.x == 0) {
+            const double t = c->t[slot];
+            c->t[slot ^ 1] = t;
+            if (!c->err && t < p.t_stop) {  // no valid time step
+                c->err = 2;
+                c->err_step = step;
+            }
+        }
+        return;
+    }
+    if (STAGE == 1 && blockIdx.x == 0 && threadIdx.x == 0) c->rmin[slot ^ 1] = 0x7FF0000000000000ull;
+    // state the stage reconstructs: w^n in stage 1, w1 in stage 2
+    const double* __restrict__ Hs = (STAGE == 1) ? H : H1;
+    const double* __restrict__ HUs = (STAGE == 1) ? HU : HU1;
+    const double* __restrict__ HVs = (STAGE == 1) ? HV : HV1;
+    const int64_t nc = m.nc;
+    const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
+    const int64_t c0 = int64_t(t) * kTile;
+    const int cnt = int(min(int64_t(kTile), nc - c0));
+    const int i = threadIdx.x;
+    const int64_t k = c0 + i;
+
+    double sc[2] = {0.0, 0.0};
+    bool second = false;
+    if (i < cnt) {
+        Recon r;
+        recon_core(m, Hs, HUs, HVs, k, p.thr, r);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) lds_store_face(lds, stride, j * kTile + i, recon_face(r, j, p.thr));
+        centred_source(m, r, k, p.hg, sc);
+        second = r.second;
+    }
+    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
+    for (int b = i; b < nb; b += kBlock) {
+        const uint32_t item = tm.bitem[b0 + b];
+        const int64_t n = int64_t(item >> 2);
+        const int jn = int(item & 3u);
+        Recon r;
+        recon_core(m, Hs, HUs, HVs, n, p.thr, r);
+        const Face f = (jn == 0) ? recon_face(r, 0, p.thr)
+                     : (jn == 1) ? recon_face(r, 1, p.thr) : recon_face(r, 2, p.thr);
+        lds_store_face(lds, stride, 3 * kTile + b, f);
+    }
+    __syncthreads();
+
+    unsigned long long clamp = 0;
+    double rr = __longlong_as_double(0x7FF0000000000000ll);
+    bool bad = false;
+    if (i < cnt) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const uint16_t s = tm.nloc[j * nc + k];
+            const Face own = lds_load_face(lds, stride, j * kTile + i);
+            const double l = gf(m, 2, j, k);
+            double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k);
+            double phi[3], pc;
+            bool left = true;
+            if (s == kNlocWall16) {
+                wall_flux(p.g, p.hg, own, nx, ny, phi, pc);
+            } else {
+                const Face other = lds_load_face(lds, stride, int(s & 0x7FFFu));
+                double pl, pr;
+                if (s & 0x8000u) {
+                    face_flux(p.g, p.hg, own, other, nx, ny, phi, pl, pr);
+                    pc = pl;
+                } else {
+                    left = false;
+                    nx = -nx;
+                    ny = -ny;
+                    face_flux(p.g, p.hg, other, own, nx, ny, phi, pl, pr);
+                    pc = pr;
+                }
+            }
+            const double t0 = l * phi[0];
+            const double t1 = l * (phi[1] + pc * nx);
+            const double t2 = l * (phi[2] + pc * ny);
+            if (left) {
+                a0 = a0 - t0; a1 = a1 - t1; a2 = a2 - t2;
+            } else {
+                a0 = a0 + t0; a1 = a1 + t1; a2 = a2 + t2;
+            }
+        }
+        if (second) {
+            a1 = a1 + sc[0];
+            a2 = a2 + sc[1];
+        }
+        const double ar = m.area[k];
+        const double R0 = a0 / ar, R1 = a1 / ar, R2 = a2 / ar;
+        if (STAGE == 1) {
+            double h1 = H[k] + dt * R0;
+            double u1 = HU[k] + dt * R1;
+            double v1 = HV[k] + dt * R2;
+            if (h1 < 0.0) { h1 = 0.0; clamp = 1; }
+            if (h1 < p.thr) { u1 = 0.0; v1 = 0.0; }
+            H1[k] = h1;
+            HU1[k] = u1;
+            HV1[k] = v1;
+        } else {
+            double hn = 0.5 * H[k] + 0.5 * (H1[k] + dt * R0);
+            double un = 0.5 * HU[k] + 0.5 * (HU1[k] + dt * R1);
+            double vn = 0.5 * HV[k] + 0.5 * (HV1[k] + dt * R2);
+            if (hn < 0.0) { hn = 0.0; clamp = 1; }
+            if (hn < p.thr) { un = 0.0; vn = 0.0; }
+            H[k] = hn;
+            HU[k] = un;
+            HV[k] = vn;
+            bad = !isfinite(hn) || !isfinite(un) || !isfinite(vn);
+            rr = cfl_ratio(hn, un, vn, ar, m.perim[k], p.g, p.thr);
+        }
+    }
+    if (STAGE == 2 && bad) {
+        atomicOr(&c->err, 1);
+        atomicMin(&c->err_step, step);
+    }
+    block_count_atomic(clamp, &c->clamps);
+    if (STAGE == 2) {
+        block_min_atomic(rr, &c->rmin[slot ^ 1]);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            c->t[slot ^ 1] = tn;
+            c->dt_last = dt;
+            c->steps_done += 1;
+            tlog[step] = tn;
+            dtlog[step] = dt;
+        }
+    }
+}
+
+template __global__ void stage_kernel<1>(DevMesh, TileMap, double*, double*, double*, double*,
+                                         double*, double*, StepParams, Ctrl*, int, int, double*,
+                                         double*);
+template __global__ void stage_kernel<2>(DevMesh, TileMap, double*, double*, double*, double*,
+                                         double*, double*, StepParams, Ctrl*, int, int, double*,
+                                         double*);
+
 // ---------------------------------------------------------------- permutation
 
 __global__ void gather_kernel(int64_t n, const int64_t* __restrict__ perm,

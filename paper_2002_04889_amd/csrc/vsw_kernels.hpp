@@ -35,6 +35,27 @@ struct FaceBuf {
     int32_t* __restrict__ order;
 };
 
+constexpr int kTile = 256;   // cells per tile of the fused stage kernel (= kBlock)
+constexpr uint16_t kNlocWall16 = 0xFFFFu;
+
+struct TileMap {
+    const uint16_t* __restrict__ nloc;   // [3][nc] LDS slot per face, bit 15 = left
+    const int32_t* __restrict__ bstart;  // [ntiles + 1]
+    const uint32_t* __restrict__ bitem;  // halo faces: (cell << 2) | face
+    int bmax;                            // most boundary faces of any tile
+    int ntiles;
+};
+
+// Fused stage kernel.  STAGE 1: w1 = w + dt R(w).  STAGE 2:
+// w^{n+1} = w/2 + (w1 + dt R(w1))/2 in place, plus the next CFL minimum and
+// the time bookkeeping.  Dynamic LDS: 5 * (3 * kTile + bmax) doubles.
+template <int STAGE>
+__global__ void stage_kernel(DevMesh m, TileMap tm, double* H, double* HU, double* HV,
+                             double* H1, double* HU1, double* HV1, StepParams p, Ctrl* c,
+                             int slot, int step, double* tlog, double* dtlog);
+
+inline size_t stage_lds_bytes(int bmax) { return sizeof(double) * 5 * size_t(3 * kTile + bmax); }
+
 __global__ void ctrl_init_kernel(Ctrl* c, double t0);
 __global__ void dt_init_kernel(DevMesh m, const double* H, const double* HU, const double* HV,
                                double g, double thr, Ctrl* c);

@@ -269,4 +269,36 @@ int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
     return VSW_OK;
 }
 
+void build_tiles(const HostMesh& hm, int tile, TileMapHost& out) {
+    const int64_t nc = hm.nc;
+    out.tile = tile;
+    out.ntiles = int((nc + tile - 1) / tile);
+    out.nloc.assign(3 * size_t(nc), kNlocWall);
+    out.bstart.assign(size_t(out.ntiles) + 1, 0);
+    out.bitem.clear();
+    out.bmax = 0;
+    for (int t = 0; t < out.ntiles; ++t) {
+        const int64_t c0 = int64_t(t) * tile, c1 = std::min(nc, c0 + tile);
+        out.bstart[t] = int32_t(out.bitem.size());
+        int nb = 0;
+        for (int64_t i = c0; i < c1; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const uint32_t s = hm.nbr[size_t(j) * nc + i];
+                if (s == kWall) continue;
+                const int64_t n = int64_t(s >> 3);
+                const uint32_t jn = s & 3u;
+                uint32_t slot;
+                if (n >= c0 && n < c1) {
+                    slot = jn * uint32_t(tile) + uint32_t(n - c0);
+                } else {
+                    slot = 3u * uint32_t(tile) + uint32_t(nb++);
+                    out.bitem.push_back((uint32_t(n) << 2) | jn);
+                }
+                out.nloc[size_t(j) * nc + i] = uint16_t(slot | ((s & 4u) ? 0x8000u : 0u));
+            }
+        out.bmax = std::max(out.bmax, nb);
+    }
+    out.bstart[out.ntiles] = int32_t(out.bitem.size());
+}
+
 }  // namespace vsw

@@ -37,6 +37,24 @@ struct HostMesh {
     std::vector<double> h;          // [nc] still-water depth
 };
 
+// Tiles of the fused stage kernel: tile t owns internal cells
+// [t * tile, (t + 1) * tile).  Every face of an owned cell gets an LDS slot:
+//   owned neighbour n with face jn : jn * tile + (n - t * tile)
+//   neighbour outside the tile     : 3 * tile + b, b-th boundary face of t
+// nloc[j][k] = slot | 0x8000 if cell k is the canonical left side; a wall is
+// kNlocWall.  bitem[bstart[t] + b] = (neighbour << 2) | face of the
+// neighbour, i.e. the halo face to reconstruct into boundary slot b.
+constexpr uint16_t kNlocWall = 0xFFFFu;
+
+struct TileMapHost {
+    int tile = 0, ntiles = 0, bmax = 0;
+    std::vector<uint16_t> nloc;     // [3][nc]
+    std::vector<int32_t> bstart;    // [ntiles + 1]
+    std::vector<uint32_t> bitem;    // [bstart[ntiles]]
+};
+
+void build_tiles(const HostMesh& hm, int tile, TileMapHost& out);
+
 // Returns 0 or a VSW_E* code with a message in err.
 int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
                     const int32_t* tri, const double* h, int ordering, uint64_t seed,

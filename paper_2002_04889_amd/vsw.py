@@ -22,6 +22,7 @@ VSW_OK, VSW_EINVAL, VSW_EMESH, VSW_ESTATE, VSW_ENOMEM, VSW_EDEVICE, VSW_EUNSTABL
     0, -1, -2, -3, -4, -5, -6
 VSW_FP64 = 0
 VSW_ORDER_HILBERT, VSW_ORDER_NONE, VSW_ORDER_RANDOM = 0, 1, 2
+VSW_KERNEL_FUSED, VSW_KERNEL_TWO_PASS = 0, 1
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM",
                -5: "EDEVICE", -6: "EUNSTABLE"}
 
@@ -60,6 +61,7 @@ _SIGS = {
     "vsw_clamp_count": (ctypes.c_int, [_vp, _lp]),
     "vsw_set_stream": (ctypes.c_int, [_vp, _vp]),
     "vsw_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vsw_set_kernel_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _lp]),
     "vsw_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
     "vsw_prepare_mesh_host": (ctypes.c_int, [_i64, _dp, _dp, _i64, _ip, _dp, _dp, _dp, _dp,
@@ -187,6 +189,10 @@ def vsw_clamp_count(h):
 
 def vsw_set_stream(h, stream_handle: int | None):
     return _check(lib().vsw_set_stream(h, stream_handle))
+
+
+def vsw_set_kernel_variant(h, variant: int):
+    return _check(lib().vsw_set_kernel_variant(h, int(variant)))
 
 
 def vsw_set_profiling(h, on: bool):

@@ -25,9 +25,11 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_run(case, n, t_stop=math.inf, ordering=vsw.VSW_ORDER_HILBERT, chunks=None, **kw):
+def gpu_run(case, n, t_stop=math.inf, ordering=vsw.VSW_ORDER_HILBERT, chunks=None,
+            variant=vsw.VSW_KERNEL_FUSED, **kw):
     s = vsw.Solver.for_case(case, ordering=ordering, **kw)
     try:
+        vsw.vsw_set_kernel_variant(s.h, variant)
         if chunks is None:
             rc, done, t = s.step(n, t_stop, check=False)
             dts = vsw.vsw_dt_history(s.h)
@@ -87,13 +89,23 @@ def test_thacker_chunked_calls_equal_one_call():
     assert np.array_equal(a["dts"], b["dts"]) and a["t"] == b["t"]
 
 
-def test_basin_small(orc):
+@pytest.mark.parametrize("variant", [vsw.VSW_KERNEL_FUSED, vsw.VSW_KERNEL_TWO_PASS])
+def test_basin_small(orc, variant):
     c = W.basin_case(scale=8)
-    say("basin scale 8", c.nc, "cells, 300 steps")
-    g = gpu_run(c, 300)
+    say("basin scale 8", c.nc, "cells, 300 steps, variant", variant)
+    g = gpu_run(c, 300, variant=variant)
     o = orc_run(orc, c, 300)
     assert_parity(g, o, "basin-s8")
     assert g["clamps"] == o["clamps"]
+
+
+def test_random_order_fused_matches_two_pass():
+    """Random order: every tile's halo is large (up to 3 x 256 faces)."""
+    c = W.basin_case(scale=16)
+    a = gpu_run(c, 60, ordering=vsw.VSW_ORDER_RANDOM, seed=7)
+    b = gpu_run(c, 60, ordering=vsw.VSW_ORDER_RANDOM, seed=7, variant=vsw.VSW_KERNEL_TWO_PASS)
+    for k in ("H", "HU", "HV"):
+        assert np.array_equal(a[k], b[k]), k
 
 
 @pytest.mark.parametrize("ordering", [vsw.VSW_ORDER_NONE, vsw.VSW_ORDER_RANDOM])
@@ -201,7 +213,7 @@ def test_device_state_roundtrip_and_profiling():
         vsw.vsw_set_profiling(s.h, True)
         s.step(20)
         times = vsw.vsw_kernel_times(s.h)
-        assert times["update2_kernel"][1] == 20 and times["recon_kernel"][1] == 40
+        assert times["stage1_kernel"][1] == 20 and times["stage2_kernel"][1] == 20
         assert all(ms > 0 for ms, n in times.values() if n)
         outH = torch.empty_like(H)
         outU = torch.empty_like(H)
