@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--scale", type=float, default=1.0, help="mesh size multiplier (1 = 1M cells)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 512 MiB three times (reference "
+                         "kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -144,6 +147,15 @@ def main():
                       "cells": nc, "edges": ne, "walls": nw, "precision": "fp64",
                       "ordering": "hilbert", "global_batch": nc, "parallelism": "single-gpu"},
            "roofline": roofline}
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
+                                   "launches": 3}
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

@@ -387,15 +387,17 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->bmax, s->ntiles};
     const size_t lds = stage_lds_bytes(s->bmax);
     const dim3 tgrid(unsigned(s->ntiles));
+    auto k1 = stage_kernel<1>;
+    auto k2 = stage_kernel<2>;
     for (int64_t k = 0; s->variant == VSW_KERNEL_FUSED && k < n; ++k) {
         const int slot = int(k & 1);
         ev_begin(KK_STAGE1);
-        hipLaunchKernelGGL(stage_kernel<1>, tgrid, block, lds, st, m, tm, H, HU, HV, H1, HU1, HV1,
-                           p, c, slot, int(k), tlog, dtlog);
+        hipLaunchKernelGGL(k1, tgrid, block, lds, st, m, tm, H, HU, HV, H1, HU1, HV1, p, c, slot,
+                           int(k), tlog, dtlog);
         ev_end();
         ev_begin(KK_STAGE2);
-        hipLaunchKernelGGL(stage_kernel<2>, tgrid, block, lds, st, m, tm, H, HU, HV, H1, HU1, HV1,
-                           p, c, slot, int(k), tlog, dtlog);
+        hipLaunchKernelGGL(k2, tgrid, block, lds, st, m, tm, H, HU, HV, H1, HU1, HV1, p, c, slot,
+                           int(k), tlog, dtlog);
         ev_end();
     }
     for (int64_t k = 0; s->variant == VSW_KERNEL_TWO_PASS && k < n; ++k) {
