@@ -65,14 +65,14 @@ struct vsw_solver {
     int64_t nc = 0, ne = 0, nw = 0;
     std::vector<int64_t> perm;     // internal -> caller
     DevBuf<int64_t> d_perm;
-    DevBuf<uint32_t> d_nbr;
+    DevBuf<Nbr4> d_nbr;            // neighbour slots per cell
     DevBuf<double> d_geom, d_area, d_perim, d_h;
-    DevBuf<double> d_w;            // H, HU, HV of w^n: 3 * nc
-    DevBuf<double> d_w1;           // stage-1 state: 3 * nc
+    DevBuf<Cell4> d_w;             // w^n records (H, HU, HV, h)
+    DevBuf<Cell4> d_w1;            // stage-1 records
     DevBuf<double> d_face;         // 15 * nc face buffer
     DevBuf<double> d_sc;           // 2 * nc
     DevBuf<int32_t> d_order;       // nc
-    DevBuf<double> d_tmp;          // 3 * nc staging for permutation
+    DevBuf<double> d_tmp;          // 3 * nc staging of caller-order arrays
     DevBuf<double> d_log;          // 2 * cap: t and dt per step
     DevBuf<Ctrl> d_ctrl;
     DevBuf<uint16_t> d_nloc;       // tile map of the fused kernel
@@ -105,7 +105,6 @@ struct vsw_solver {
         m.geom = d_geom.p;
         m.area = d_area.p;
         m.perim = d_perim.p;
-        m.h = d_h.p;
         return m;
     }
 };
@@ -202,19 +201,24 @@ int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* v
     s->perm = hm.perm;
     const size_t n = size_t(hm.nc);
     HIP_TRY(s->d_perm.alloc(n));
-    HIP_TRY(s->d_nbr.alloc(3 * n));
+    HIP_TRY(s->d_nbr.alloc(n));
     HIP_TRY(s->d_geom.alloc(size_t(G_NFACE) * 3 * n));
     HIP_TRY(s->d_area.alloc(n));
     HIP_TRY(s->d_perim.alloc(n));
     HIP_TRY(s->d_h.alloc(n));
-    HIP_TRY(s->d_w.alloc(3 * n));
-    HIP_TRY(s->d_w1.alloc(3 * n));
+    HIP_TRY(s->d_w.alloc(n));
+    HIP_TRY(s->d_w1.alloc(n));
     HIP_TRY(s->d_face.alloc(15 * n));
     HIP_TRY(s->d_sc.alloc(2 * n));
     HIP_TRY(s->d_order.alloc(n));
     HIP_TRY(s->d_tmp.alloc(3 * n));
     HIP_TRY(hipMemcpy(s->d_perm.p, hm.perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(s->d_nbr.p, hm.nbr.data(), 3 * n * sizeof(uint32_t), hipMemcpyHostToDevice));
+    {
+        std::vector<Nbr4> nb(n);
+        for (size_t i = 0; i < n; ++i)
+            nb[i] = Nbr4{hm.nbr[i], hm.nbr[n + i], hm.nbr[2 * n + i], 0u};
+        HIP_TRY(hipMemcpy(s->d_nbr.p, nb.data(), n * sizeof(Nbr4), hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMemcpy(s->d_geom.p, hm.face_geom.data(), hm.face_geom.size() * sizeof(double),
                       hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->d_area.p, hm.area.data(), n * sizeof(double), hipMemcpyHostToDevice));
@@ -245,20 +249,20 @@ int vsw_set_state(vsw_solver* s, const double* H, const double* HU, const double
     if (!H || !HU || !HV) return fail(VSW_EINVAL, "NULL state array");
     if (!std::isfinite(t)) return fail(VSW_EINVAL, "non-finite time");
     const int64_t nc = s->nc;
-    std::vector<double> w(3 * size_t(nc));
-    for (int64_t i = 0; i < nc; ++i) {
-        const int64_t k = s->perm[i];
-        const double a = H[k], b = HU[k], c = HV[k];
-        if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c))
+    for (int64_t k = 0; k < nc; ++k) {
+        if (!std::isfinite(H[k]) || !std::isfinite(HU[k]) || !std::isfinite(HV[k]))
             return fail(VSW_EINVAL, "non-finite state value");
-        if (a < 0.0) return fail(VSW_EINVAL, "negative depth H");
-        w[i] = a;
-        w[nc + i] = b;
-        w[2 * nc + i] = c;
+        if (H[k] < 0.0) return fail(VSW_EINVAL, "negative depth H");
     }
     DeviceGuard dg(s->device);
-    HIP_TRY(hipMemcpyAsync(s->d_w.p, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice,
+    double* tmp = s->d_tmp.p;
+    HIP_TRY(hipMemcpyAsync(tmp, H, nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(tmp + nc, HU, nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(tmp + 2 * nc, HV, nc * sizeof(double), hipMemcpyHostToDevice,
                            s->stream));
+    hipLaunchKernelGGL(pack_state_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
+                       s->d_perm.p, tmp, tmp + nc, tmp + 2 * nc, s->d_h.p, s->d_w.p, s->d_w1.p);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->t = t;
     s->dt_last = 0.0;
@@ -275,12 +279,9 @@ int vsw_set_state_device(vsw_solver* s, const double* dH, const double* dHU, con
     if (!std::isfinite(t)) return fail(VSW_EINVAL, "non-finite time");
     DeviceGuard dg(s->device);
     const int64_t nc = s->nc;
-    const double* src[3] = {dH, dHU, dHV};
-    for (int c = 0; c < 3; ++c) {
-        hipLaunchKernelGGL(gather_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
-                           s->d_perm.p, src[c], s->d_w.p + c * nc);
-        HIP_TRY(hipGetLastError());
-    }
+    hipLaunchKernelGGL(pack_state_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
+                       s->d_perm.p, dH, dHU, dHV, s->d_h.p, s->d_w.p, s->d_w1.p);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->t = t;
     s->dt_last = 0.0;
@@ -294,16 +295,16 @@ int vsw_get_state(vsw_solver* s, double* H, double* HU, double* HV, double* t) {
     if (!s->has_state) return fail(VSW_ESTATE, "no state");
     DeviceGuard dg(s->device);
     const int64_t nc = s->nc;
-    std::vector<double> w(3 * size_t(nc));
-    HIP_TRY(hipMemcpyAsync(w.data(), s->d_w.p, w.size() * sizeof(double), hipMemcpyDeviceToHost,
-                           s->stream));
+    double* tmp = s->d_tmp.p;
+    hipLaunchKernelGGL(unpack_state_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
+                       s->d_perm.p, s->d_w.p, tmp, tmp + nc, tmp + 2 * nc);
+    HIP_TRY(hipGetLastError());
+    double* dst[3] = {H, HU, HV};
+    for (int c = 0; c < 3; ++c)
+        if (dst[c])
+            HIP_TRY(hipMemcpyAsync(dst[c], tmp + c * nc, nc * sizeof(double),
+                                   hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    for (int64_t i = 0; i < nc; ++i) {
-        const int64_t k = s->perm[i];
-        if (H) H[k] = w[i];
-        if (HU) HU[k] = w[nc + i];
-        if (HV) HV[k] = w[2 * nc + i];
-    }
     if (t) *t = s->t;
     return VSW_OK;
 }
@@ -313,13 +314,9 @@ int vsw_get_state_device(vsw_solver* s, double* dH, double* dHU, double* dHV, do
     if (!s->has_state) return fail(VSW_ESTATE, "no state");
     DeviceGuard dg(s->device);
     const int64_t nc = s->nc;
-    double* dst[3] = {dH, dHU, dHV};
-    for (int c = 0; c < 3; ++c) {
-        if (!dst[c]) continue;
-        hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
-                           s->d_perm.p, s->d_w.p + c * nc, dst[c]);
-        HIP_TRY(hipGetLastError());
-    }
+    hipLaunchKernelGGL(unpack_state_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
+                       s->d_perm.p, s->d_w.p, dH, dHU, dHV);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));
     if (t) *t = s->t;
     return VSW_OK;
@@ -345,12 +342,8 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     p.cfl = s->prm.cfl;
     p.dt_fixed = s->prm.dt_fixed;
     p.t_stop = t_stop;
-    double* H = s->d_w.p;
-    double* HU = H + nc;
-    double* HV = H + 2 * nc;
-    double* H1 = s->d_w1.p;
-    double* HU1 = H1 + nc;
-    double* HV1 = H1 + 2 * nc;
+    Cell4* W = s->d_w.p;
+    Cell4* W1 = s->d_w1.p;
     FaceBuf fb{s->d_face.p, s->d_sc.p, s->d_order.p};
     Ctrl* c = s->d_ctrl.p;
     double* tlog = s->d_log.p;
@@ -382,7 +375,7 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
 
     hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(64), 0, st, c, s->t);
     ev_begin(KK_DTINIT);
-    hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, H, HU, HV, p.g, p.thr, c);
+    hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, W, p.g, p.thr, c);
     ev_end();
     TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->bmax, s->ntiles};
     const size_t lds = stage_lds_bytes(s->bmax);
@@ -392,29 +385,28 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     for (int64_t k = 0; s->variant == VSW_KERNEL_FUSED && k < n; ++k) {
         const int slot = int(k & 1);
         ev_begin(KK_STAGE1);
-        hipLaunchKernelGGL(k1, tgrid, block, lds, st, m, tm, H, HU, HV, H1, HU1, HV1, p, c, slot,
-                           int(k), tlog, dtlog);
+        hipLaunchKernelGGL(k1, tgrid, block, lds, st, m, tm, W, W1, p, c, slot, int(k), tlog,
+                           dtlog);
         ev_end();
         ev_begin(KK_STAGE2);
-        hipLaunchKernelGGL(k2, tgrid, block, lds, st, m, tm, H, HU, HV, H1, HU1, HV1, p, c, slot,
-                           int(k), tlog, dtlog);
+        hipLaunchKernelGGL(k2, tgrid, block, lds, st, m, tm, W, W1, p, c, slot, int(k), tlog,
+                           dtlog);
         ev_end();
     }
     for (int64_t k = 0; s->variant == VSW_KERNEL_TWO_PASS && k < n; ++k) {
         const int slot = int(k & 1);
         ev_begin(KK_RECON);
-        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, H, HU, HV, fb, p, c, slot);
+        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, W, fb, p, c, slot);
         ev_end();
         ev_begin(KK_UPDATE1);
-        hipLaunchKernelGGL(update1_kernel, grid, block, 0, st, m, H, HU, HV, H1, HU1, HV1, fb, p,
-                           c, slot);
+        hipLaunchKernelGGL(update1_kernel, grid, block, 0, st, m, W, W1, fb, p, c, slot);
         ev_end();
         ev_begin(KK_RECON);
-        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, H1, HU1, HV1, fb, p, c, slot);
+        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, W1, fb, p, c, slot);
         ev_end();
         ev_begin(KK_UPDATE2);
-        hipLaunchKernelGGL(update2_kernel, grid, block, 0, st, m, H, HU, HV, H1, HU1, HV1, fb, p,
-                           c, slot, int(k), tlog, dtlog);
+        hipLaunchKernelGGL(update2_kernel, grid, block, 0, st, m, W, W1, fb, p, c, slot, int(k),
+                           tlog, dtlog);
         ev_end();
     }
     HIP_TRY(hipGetLastError());

@@ -116,21 +116,20 @@ __global__ void ctrl_init_kernel(Ctrl* c, double t0) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void dt_init_kernel(DevMesh m, const double* __restrict__ H,
-                                                         const double* __restrict__ HU,
-                                                         const double* __restrict__ HV,
+__global__ __launch_bounds__(kBlock) void dt_init_kernel(DevMesh m, const Cell4* __restrict__ W,
                                                          double g, double thr, Ctrl* c) {
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     double r = __longlong_as_double(0x7FF0000000000000ll);
-    if (k < m.nc) r = cfl_ratio(H[k], HU[k], HV[k], m.area[k], m.perim[k], g, thr);
+    if (k < m.nc) {
+        const Cell4 q = W[k];
+        r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
+    }
     block_min_atomic(r, &c->rmin[0]);
 }
 
-// ---------------------------------------------------------------- stage kernels
+// ---------------------------------------------------------------- two-pass kernels
 
-__global__ __launch_bounds__(kBlock) void recon_kernel(DevMesh m, const double* __restrict__ H,
-                                                       const double* __restrict__ HU,
-                                                       const double* __restrict__ HV,
+__global__ __launch_bounds__(kBlock) void recon_kernel(DevMesh m, const Cell4* __restrict__ W,
                                                        FaceBuf fb, StepParams p, const Ctrl* c,
                                                        int slot) {
     double dt, tn;
@@ -140,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(DevMesh m, const double* 
     const int64_t nc = m.nc;
     Face f[3];
     double sc[2];
-    const bool second = recon_cell(m, H, HU, HV, k, p.thr, p.hg, f, sc);
+    const bool second = recon_cell(m, W, k, p.thr, p.hg, f, sc);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         fb.f[(5 * j + 0) * nc + k] = f[j].eta;
@@ -168,40 +167,22 @@ __device__ __forceinline__ Face load_face(const FaceBuf& fb, int64_t nc, int j, 
 __device__ __forceinline__ void residual_from_faces(const DevMesh& m, const FaceBuf& fb, int64_t k,
                                                     double g, double hg, double R[3]) {
     const int64_t nc = m.nc;
+    const Nbr4 nb = m.nbr[k];
+    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        const uint32_t s = m.nbr[j * nc + k];
+        const uint32_t s = sl[j];
+        const bool wall = (s == kWallSlot);
         const Face own = load_face(fb, nc, j, k);
-        const double l = gf(m, 2, j, k);
-        double phi[3], p;
-        double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k);
-        bool left = true;
-        if (s == kWallSlot) {
-            wall_flux(g, hg, own, nx, ny, phi, p);
-        } else {
-            const int64_t n = int64_t(s >> 3);
-            const int jn = int(s & 3u);
-            const Face other = load_face(fb, nc, jn, n);
-            double pl, pr;
-            if (s & 4u) {
-                face_flux(g, hg, own, other, nx, ny, phi, pl, pr);
-                p = pl;
-            } else {
-                left = false;
-                nx = -nx;
-                ny = -ny;
-                face_flux(g, hg, other, own, nx, ny, phi, pl, pr);
-                p = pr;
-            }
-        }
-        const double t0 = l * phi[0];
-        const double t1 = l * (phi[1] + p * nx);
-        const double t2 = l * (phi[2] + p * ny);
+        const Face other = wall ? own : load_face(fb, nc, int(s & 3u), int64_t(s >> 3));
+        double tt[3];
+        const bool left = face_term(g, hg, own, other, wall, (s & 4u) != 0, gf(m, 0, j, k),
+                                    gf(m, 1, j, k), gf(m, 2, j, k), tt);
         if (left) {
-            a0 = a0 - t0; a1 = a1 - t1; a2 = a2 - t2;
+            a0 = a0 - tt[0]; a1 = a1 - tt[1]; a2 = a2 - tt[2];
         } else {
-            a0 = a0 + t0; a1 = a1 + t1; a2 = a2 + t2;
+            a0 = a0 + tt[0]; a1 = a1 + tt[1]; a2 = a2 + tt[2];
         }
     }
     if (fb.order[k] == 2) {
@@ -214,13 +195,35 @@ __device__ __forceinline__ void residual_from_faces(const DevMesh& m, const Face
     R[2] = a2 / ar;
 }
 
-// Stage 1: w1 = w + dt R(w), then the post-stage fix.
-__global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, const double* __restrict__ H,
-                                                         const double* __restrict__ HU,
-                                                         const double* __restrict__ HV,
-                                                         double* __restrict__ H1,
-                                                         double* __restrict__ HU1,
-                                                         double* __restrict__ HV1, FaceBuf fb,
+// Stage 1: w1 = w + dt R(w), then the post-stage fix (negative depth set to
+// zero and counted; velocity zero below H_thr).
+__device__ __forceinline__ Cell4 stage1_update(const Cell4& w, const double R[3], double dt,
+                                               double thr, unsigned long long& clamp) {
+    Cell4 o;
+    o.H = w.H + dt * R[0];
+    o.HU = w.HU + dt * R[1];
+    o.HV = w.HV + dt * R[2];
+    o.h = w.h;
+    if (o.H < 0.0) { o.H = 0.0; clamp = 1; }
+    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; }
+    return o;
+}
+
+// Stage 2: w^{n+1} = w/2 + (w1 + dt R(w1))/2, then the post-stage fix.
+__device__ __forceinline__ Cell4 stage2_update(const Cell4& w, const Cell4& w1, const double R[3],
+                                               double dt, double thr, unsigned long long& clamp) {
+    Cell4 o;
+    o.H = 0.5 * w.H + 0.5 * (w1.H + dt * R[0]);
+    o.HU = 0.5 * w.HU + 0.5 * (w1.HU + dt * R[1]);
+    o.HV = 0.5 * w.HV + 0.5 * (w1.HV + dt * R[2]);
+    o.h = w.h;
+    if (o.H < 0.0) { o.H = 0.0; clamp = 1; }
+    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; }
+    return o;
+}
+
+__global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, const Cell4* __restrict__ W,
+                                                         Cell4* __restrict__ W1, FaceBuf fb,
                                                          StepParams p, Ctrl* c, int slot) {
     double dt, tn;
     if (!step_dt(c, slot, p, dt, tn)) return;
@@ -230,40 +233,41 @@ __global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, const double
     if (k < m.nc) {
         double R[3];
         residual_from_faces(m, fb, k, p.g, p.hg, R);
-        double h1 = H[k] + dt * R[0];
-        double u1 = HU[k] + dt * R[1];
-        double v1 = HV[k] + dt * R[2];
-        if (h1 < 0.0) { h1 = 0.0; clamp = 1; }
-        if (h1 < p.thr) { u1 = 0.0; v1 = 0.0; }
-        H1[k] = h1;
-        HU1[k] = u1;
-        HV1[k] = v1;
+        W1[k] = stage1_update(W[k], R, dt, p.thr, clamp);
     }
     block_count_atomic(clamp, &c->clamps);
 }
 
-// Stage 2: w^{n+1} = w/2 + (w1 + dt R(w1))/2, post-stage fix, the CFL ratio
-// of the new state, and the time bookkeeping (block 0).
-__global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, double* __restrict__ H,
-                                                         double* __restrict__ HU,
-                                                         double* __restrict__ HV,
-                                                         const double* __restrict__ H1,
-                                                         const double* __restrict__ HU1,
-                                                         const double* __restrict__ HV1,
-                                                         FaceBuf fb, StepParams p, Ctrl* c,
-                                                         int slot, int step, double* tlog,
-                                                         double* dtlog) {
+// Time bookkeeping at the end of stage 2 (block 0 only) or, for a step that
+// is not taken, the carry-over of the time and the no-valid-dt error.
+__device__ __forceinline__ void stage2_bookkeeping(Ctrl* c, int slot, int step, bool active,
+                                                   double dt, double tn, double t_stop,
+                                                   double* tlog, double* dtlog) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    if (active) {
+        c->t[slot ^ 1] = tn;
+        c->dt_last = dt;
+        c->steps_done += 1;
+        tlog[step] = tn;
+        dtlog[step] = dt;
+    } else {
+        const double t = c->t[slot];
+        c->t[slot ^ 1] = t;
+        if (!c->err && t < t_stop) {  // no valid time step
+            c->err = 2;
+            c->err_step = step;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, Cell4* __restrict__ W,
+                                                         const Cell4* __restrict__ W1, FaceBuf fb,
+                                                         StepParams p, Ctrl* c, int slot, int step,
+                                                         double* tlog, double* dtlog) {
     double dt, tn;
     const bool active = step_dt(c, slot, p, dt, tn);
     if (!active) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            const double t = c->t[slot];
-            c->t[slot ^ 1] = t;
-            if (!c->err && t < p.t_stop) {  // no valid time step
-                c->err = 2;
-                c->err_step = step;
-            }
-        }
+        stage2_bookkeeping(c, slot, step, false, 0.0, 0.0, p.t_stop, tlog, dtlog);
         return;
     }
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -273,16 +277,10 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, double* __re
     if (k < m.nc) {
         double R[3];
         residual_from_faces(m, fb, k, p.g, p.hg, R);
-        double hn = 0.5 * H[k] + 0.5 * (H1[k] + dt * R[0]);
-        double un = 0.5 * HU[k] + 0.5 * (HU1[k] + dt * R[1]);
-        double vn = 0.5 * HV[k] + 0.5 * (HV1[k] + dt * R[2]);
-        if (hn < 0.0) { hn = 0.0; clamp = 1; }
-        if (hn < p.thr) { un = 0.0; vn = 0.0; }
-        H[k] = hn;
-        HU[k] = un;
-        HV[k] = vn;
-        bad = !isfinite(hn) || !isfinite(un) || !isfinite(vn);
-        r = cfl_ratio(hn, un, vn, m.area[k], m.perim[k], p.g, p.thr);
+        const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp);
+        W[k] = o;
+        bad = !isfinite(o.H) || !isfinite(o.HU) || !isfinite(o.HV);
+        r = cfl_ratio(o.H, o.HU, o.HV, m.area[k], m.perim[k], p.g, p.thr);
     }
     if (bad) {
         atomicOr(&c->err, 1);
@@ -290,13 +288,7 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, double* __re
     }
     block_count_atomic(clamp, &c->clamps);
     block_min_atomic(r, &c->rmin[slot ^ 1]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        c->t[slot ^ 1] = tn;
-        c->dt_last = dt;
-        c->steps_done += 1;
-        tlog[step] = tn;
-        dtlog[step] = dt;
-    }
+    stage2_bookkeeping(c, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
 }
 
 // ---------------------------------------------------------------- fused stage
@@ -344,12 +336,8 @@ __device__ __forceinline__ Face lds_load_face(const double* lds, int stride, int
 // evaluated once per face (edge-parallel, with two more barriers to hand the
 // terms over) measured slower on the 1M-cell basin.
 template <int STAGE>
-__global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, double* __restrict__ H,
-                                                       double* __restrict__ HU,
-                                                       double* __restrict__ HV,
-                                                       double* __restrict__ H1,
-                                                       double* __restrict__ HU1,
-                                                       double* __restrict__ HV1, StepParams p,
+__global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Cell4* __restrict__ W,
+                                                       Cell4* __restrict__ W1, StepParams p,
                                                        Ctrl* c, int slot, int step, double* tlog,
                                                        double* dtlog) {
     extern __shared__ double lds[];
@@ -357,21 +345,12 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, do
     double dt, tn;
     const bool active = step_dt(c, slot, p, dt, tn);
     if (!active) {
-        if (STAGE == 2 && blockIdx.x == 0 && threadIdx.x == 0) {
-            const double t = c->t[slot];
-            c->t[slot ^ 1] = t;
-            if (!c->err && t < p.t_stop) {  // no valid time step
-                c->err = 2;
-                c->err_step = step;
-            }
-        }
+        if (STAGE == 2) stage2_bookkeeping(c, slot, step, false, 0.0, 0.0, p.t_stop, tlog, dtlog);
         return;
     }
     if (STAGE == 1 && blockIdx.x == 0 && threadIdx.x == 0) c->rmin[slot ^ 1] = 0x7FF0000000000000ull;
     // state the stage reconstructs: w^n in stage 1, w1 in stage 2
-    const double* __restrict__ Hs = (STAGE == 1) ? H : H1;
-    const double* __restrict__ HUs = (STAGE == 1) ? HU : HU1;
-    const double* __restrict__ HVs = (STAGE == 1) ? HV : HV1;
+    const Cell4* __restrict__ Ws = (STAGE == 1) ? W : W1;
     const int64_t nc = m.nc;
     const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
     const int64_t c0 = int64_t(t) * kTile;
@@ -379,12 +358,11 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, do
     const int i = threadIdx.x;
     const int64_t k = c0 + i;
 
-    // 1. reconstruction of the tile's cells and of its halo faces
     double sc[2] = {0.0, 0.0};
     bool second = false;
     if (i < cnt) {
         Recon r;
-        recon_core(m, Hs, HUs, HVs, k, p.thr, r);
+        recon_core(m, Ws, k, p.thr, r);
 #pragma unroll
         for (int j = 0; j < 3; ++j) lds_store_face(lds, stride, j * kTile + i, recon_face(r, j, p.thr));
         centred_source(m, r, k, p.hg, sc);
@@ -396,14 +374,13 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, do
         const int64_t n = int64_t(item >> 2);
         const int jn = int(item & 3u);
         Recon r;
-        recon_core(m, Hs, HUs, HVs, n, p.thr, r);
+        recon_core(m, Ws, n, p.thr, r);
         const Face f = (jn == 0) ? recon_face(r, 0, p.thr)
                      : (jn == 1) ? recon_face(r, 1, p.thr) : recon_face(r, 2, p.thr);
         lds_store_face(lds, stride, 3 * kTile + b, f);
     }
     __syncthreads();
 
-    // 3. residual and Runge-Kutta stage per cell
     unsigned long long clamp = 0;
     double rr = __longlong_as_double(0x7FF0000000000000ll);
     bool bad = false;
@@ -429,27 +406,14 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, do
             a2 = a2 + sc[1];
         }
         const double ar = m.area[k];
-        const double R0 = a0 / ar, R1 = a1 / ar, R2 = a2 / ar;
+        const double R[3] = {a0 / ar, a1 / ar, a2 / ar};
         if (STAGE == 1) {
-            double h1 = H[k] + dt * R0;
-            double u1 = HU[k] + dt * R1;
-            double v1 = HV[k] + dt * R2;
-            if (h1 < 0.0) { h1 = 0.0; clamp = 1; }
-            if (h1 < p.thr) { u1 = 0.0; v1 = 0.0; }
-            H1[k] = h1;
-            HU1[k] = u1;
-            HV1[k] = v1;
+            W1[k] = stage1_update(W[k], R, dt, p.thr, clamp);
         } else {
-            double hn = 0.5 * H[k] + 0.5 * (H1[k] + dt * R0);
-            double un = 0.5 * HU[k] + 0.5 * (HU1[k] + dt * R1);
-            double vn = 0.5 * HV[k] + 0.5 * (HV1[k] + dt * R2);
-            if (hn < 0.0) { hn = 0.0; clamp = 1; }
-            if (hn < p.thr) { un = 0.0; vn = 0.0; }
-            H[k] = hn;
-            HU[k] = un;
-            HV[k] = vn;
-            bad = !isfinite(hn) || !isfinite(un) || !isfinite(vn);
-            rr = cfl_ratio(hn, un, vn, ar, m.perim[k], p.g, p.thr);
+            const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp);
+            W[k] = o;
+            bad = !isfinite(o.H) || !isfinite(o.HU) || !isfinite(o.HV);
+            rr = cfl_ratio(o.H, o.HU, o.HV, ar, m.perim[k], p.g, p.thr);
         }
     }
     if (STAGE == 2 && bad) {
@@ -459,35 +423,46 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, do
     block_count_atomic(clamp, &c->clamps);
     if (STAGE == 2) {
         block_min_atomic(rr, &c->rmin[slot ^ 1]);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            c->t[slot ^ 1] = tn;
-            c->dt_last = dt;
-            c->steps_done += 1;
-            tlog[step] = tn;
-            dtlog[step] = dt;
-        }
+        stage2_bookkeeping(c, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
     }
 }
 
-template __global__ void stage_kernel<1>(DevMesh, TileMap, double*, double*, double*, double*,
-                                         double*, double*, StepParams, Ctrl*, int, int, double*,
-                                         double*);
-template __global__ void stage_kernel<2>(DevMesh, TileMap, double*, double*, double*, double*,
-                                         double*, double*, StepParams, Ctrl*, int, int, double*,
-                                         double*);
+template __global__ void stage_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, int,
+                                         int, double*, double*);
+template __global__ void stage_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, int,
+                                         int, double*, double*);
 
-// ---------------------------------------------------------------- permutation
+// ---------------------------------------------------------------- state transfer
 
-__global__ void gather_kernel(int64_t n, const int64_t* __restrict__ perm,
-                              const double* __restrict__ src, double* __restrict__ dst) {
+// Caller-order arrays (H, HU, HV) into internal-order state records; the
+// still-water depth comes from h (internal order), copied to both buffers.
+__global__ void pack_state_kernel(int64_t n, const int64_t* __restrict__ perm,
+                                  const double* __restrict__ H, const double* __restrict__ HU,
+                                  const double* __restrict__ HV, const double* __restrict__ h,
+                                  Cell4* __restrict__ W, Cell4* __restrict__ W1) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[perm[i]];
+    if (i >= n) return;
+    const int64_t k = perm[i];
+    Cell4 q;
+    q.H = H[k];
+    q.HU = HU[k];
+    q.HV = HV[k];
+    q.h = h[i];
+    W[i] = q;
+    W1[i] = q;
 }
 
-__global__ void scatter_kernel(int64_t n, const int64_t* __restrict__ perm,
-                               const double* __restrict__ src, double* __restrict__ dst) {
+// Internal-order state records into caller-order arrays.
+__global__ void unpack_state_kernel(int64_t n, const int64_t* __restrict__ perm,
+                                    const Cell4* __restrict__ W, double* __restrict__ H,
+                                    double* __restrict__ HU, double* __restrict__ HV) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) dst[perm[i]] = src[i];
+    if (i >= n) return;
+    const int64_t k = perm[i];
+    const Cell4 q = W[i];
+    if (H) H[k] = q.H;
+    if (HU) HU[k] = q.HU;
+    if (HV) HV[k] = q.HV;
 }
 
 }  // namespace vsw

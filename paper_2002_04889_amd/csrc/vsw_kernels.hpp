@@ -50,24 +50,23 @@ struct TileMap {
 // w^{n+1} = w/2 + (w1 + dt R(w1))/2 in place, plus the next CFL minimum and
 // the time bookkeeping.  Dynamic LDS: 5 * (3 * kTile + bmax) doubles.
 template <int STAGE>
-__global__ void stage_kernel(DevMesh m, TileMap tm, double* H, double* HU, double* HV,
-                             double* H1, double* HU1, double* HV1, StepParams p, Ctrl* c,
+__global__ void stage_kernel(DevMesh m, TileMap tm, Cell4* W, Cell4* W1, StepParams p, Ctrl* c,
                              int slot, int step, double* tlog, double* dtlog);
 
 inline size_t stage_lds_bytes(int bmax) { return sizeof(double) * 5 * size_t(3 * kTile + bmax); }
 
 __global__ void ctrl_init_kernel(Ctrl* c, double t0);
-__global__ void dt_init_kernel(DevMesh m, const double* H, const double* HU, const double* HV,
-                               double g, double thr, Ctrl* c);
-__global__ void recon_kernel(DevMesh m, const double* H, const double* HU, const double* HV,
-                             FaceBuf fb, StepParams p, const Ctrl* c, int slot);
-__global__ void update1_kernel(DevMesh m, const double* H, const double* HU, const double* HV,
-                               double* H1, double* HU1, double* HV1, FaceBuf fb, StepParams p,
+__global__ void dt_init_kernel(DevMesh m, const Cell4* W, double g, double thr, Ctrl* c);
+__global__ void recon_kernel(DevMesh m, const Cell4* W, FaceBuf fb, StepParams p, const Ctrl* c,
+                             int slot);
+__global__ void update1_kernel(DevMesh m, const Cell4* W, Cell4* W1, FaceBuf fb, StepParams p,
                                Ctrl* c, int slot);
-__global__ void update2_kernel(DevMesh m, double* H, double* HU, double* HV, const double* H1,
-                               const double* HU1, const double* HV1, FaceBuf fb, StepParams p,
+__global__ void update2_kernel(DevMesh m, Cell4* W, const Cell4* W1, FaceBuf fb, StepParams p,
                                Ctrl* c, int slot, int step, double* tlog, double* dtlog);
-__global__ void gather_kernel(int64_t n, const int64_t* perm, const double* src, double* dst);
-__global__ void scatter_kernel(int64_t n, const int64_t* perm, const double* src, double* dst);
+__global__ void pack_state_kernel(int64_t n, const int64_t* perm, const double* H,
+                                  const double* HU, const double* HV, const double* h, Cell4* W,
+                                  Cell4* W1);
+__global__ void unpack_state_kernel(int64_t n, const int64_t* perm, const Cell4* W, double* H,
+                                    double* HU, double* HV);
 
 }  // namespace vsw
