@@ -67,6 +67,7 @@ struct vsw_solver {
     DevBuf<int64_t> d_perm;
     DevBuf<Nbr4> d_nbr;            // neighbour slots per cell
     DevBuf<double> d_geom, d_area, d_perim, d_h;
+    DevBuf<RGeom> d_rgeom;         // reconstruction geometry records
     DevBuf<Cell4> d_w;             // w^n records (H, HU, HV, h)
     DevBuf<Cell4> d_w1;            // stage-1 records
     DevBuf<double> d_face;         // 15 * nc face buffer
@@ -93,6 +94,7 @@ struct vsw_solver {
 
     void release_mesh() {
         d_perm.release(); d_nbr.release(); d_geom.release(); d_area.release();
+        d_rgeom.release();
         d_perim.release(); d_h.release(); d_w.release(); d_w1.release();
         d_face.release(); d_sc.release(); d_order.release(); d_tmp.release();
         d_nloc.release(); d_bstart.release(); d_bitem.release();
@@ -103,6 +105,7 @@ struct vsw_solver {
         m.nc = nc;
         m.nbr = d_nbr.p;
         m.geom = d_geom.p;
+        m.rgeom = d_rgeom.p;
         m.area = d_area.p;
         m.perim = d_perim.p;
         return m;
@@ -222,6 +225,18 @@ int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* v
     HIP_TRY(hipMemcpy(s->d_geom.p, hm.face_geom.data(), hm.face_geom.size() * sizeof(double),
                       hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->d_area.p, hm.area.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    {
+        std::vector<RGeom> rg(n);
+        for (size_t i = 0; i < n; ++i)
+            for (int j = 0; j < 3; ++j) {
+                rg[i].w[2 * j] = hm.face_geom[(size_t(G_WX) * 3 + j) * n + i];
+                rg[i].w[2 * j + 1] = hm.face_geom[(size_t(G_WY) * 3 + j) * n + i];
+                rg[i].d[2 * j] = hm.face_geom[(size_t(G_DX) * 3 + j) * n + i];
+                rg[i].d[2 * j + 1] = hm.face_geom[(size_t(G_DY) * 3 + j) * n + i];
+            }
+        HIP_TRY(s->d_rgeom.alloc(n));
+        HIP_TRY(hipMemcpy(s->d_rgeom.p, rg.data(), n * sizeof(RGeom), hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMemcpy(s->d_perim.p, hm.perim.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->d_h.p, hm.h.data(), n * sizeof(double), hipMemcpyHostToDevice));
     TileMapHost tmh;
