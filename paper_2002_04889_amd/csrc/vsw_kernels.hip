@@ -46,8 +46,13 @@ __device__ __forceinline__ bool step_dt(const Ctrl* c, int slot, const StepParam
     if (c->err) return false;
     const double t = c->t[slot];
     if (!(t < p.t_stop)) return false;
-    double d = (p.dt_fixed > 0.0) ? p.dt_fixed
-                                  : p.cfl * __longlong_as_double((long long)c->rmin[slot]);
+    unsigned long long rb = c->rmin[slot][0];
+#pragma unroll
+    for (int g = 1; g < kMinGroups; ++g) {
+        const unsigned long long v = c->rmin[slot][g * kMinStride];
+        rb = (v < rb) ? v : rb;
+    }
+    double d = (p.dt_fixed > 0.0) ? p.dt_fixed : p.cfl * __longlong_as_double((long long)rb);
     const double rem = p.t_stop - t;
     if (d >= rem) {
         d = rem;
@@ -69,8 +74,12 @@ __device__ __forceinline__ double cfl_ratio(double H, double HU, double HV, doub
     return area / (perim * s);
 }
 
-// Block-wide min of a positive double, then one atomic min on its bits.
-__device__ __forceinline__ void block_min_atomic(double v, unsigned long long* target) {
+// Block-wide min of a positive double, then one atomic min on its bits in
+// the block's group.  The bits of positive doubles order like the values; a
+// plain read first skips the atomic when the group already holds a value at
+// least as small (values only decrease, so a stale read never loses one).
+__device__ __forceinline__ void block_min_atomic(double v, unsigned long long* slot_base) {
+    unsigned long long* target = slot_base + (blockIdx.x % kMinGroups) * kMinStride;
     __shared__ double part[kBlock / 64];
     v = wave_min(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -80,7 +89,10 @@ __device__ __forceinline__ void block_min_atomic(double v, unsigned long long* t
         double m = part[0];
 #pragma unroll
         for (int i = 1; i < kBlock / 64; ++i) m = (part[i] < m) ? part[i] : m;
-        if (m < __longlong_as_double(0x7FF0000000000000ll)) atomicMin(target, dbits(m));
+        const unsigned long long b = dbits(m);
+        if (m < __longlong_as_double(0x7FF0000000000000ll) &&
+            b < __hip_atomic_load(target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMin(target, b);
     }
 }
 
@@ -104,8 +116,10 @@ __device__ __forceinline__ void block_count_atomic(unsigned long long v, unsigne
 
 __global__ void ctrl_init_kernel(Ctrl* c, double t0) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        c->rmin[0] = 0x7FF0000000000000ull;
-        c->rmin[1] = 0x7FF0000000000000ull;
+        for (int g = 0; g < kMinGroups; ++g) {
+            c->rmin[0][g * kMinStride] = 0x7FF0000000000000ull;
+            c->rmin[1][g * kMinStride] = 0x7FF0000000000000ull;
+        }
         c->t[0] = t0;
         c->t[1] = t0;
         c->err = 0;
@@ -124,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void dt_init_kernel(DevMesh m, const Cell4*
         const Cell4 q = W[k];
         r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
     }
-    block_min_atomic(r, &c->rmin[0]);
+    block_min_atomic(r, c->rmin[0]);
 }
 
 // ---------------------------------------------------------------- two-pass kernels
@@ -227,7 +241,8 @@ __global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, const Cell4*
                                                          StepParams p, Ctrl* c, int slot) {
     double dt, tn;
     if (!step_dt(c, slot, p, dt, tn)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) c->rmin[slot ^ 1] = 0x7FF0000000000000ull;
+    if (blockIdx.x == 0 && threadIdx.x < kMinGroups)
+        c->rmin[slot ^ 1][threadIdx.x * kMinStride] = 0x7FF0000000000000ull;
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     unsigned long long clamp = 0;
     if (k < m.nc) {
@@ -287,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, Cell4* __res
         atomicMin(&c->err_step, step);
     }
     block_count_atomic(clamp, &c->clamps);
-    block_min_atomic(r, &c->rmin[slot ^ 1]);
+    block_min_atomic(r, c->rmin[slot ^ 1]);
     stage2_bookkeeping(c, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
 }
 
@@ -348,7 +363,8 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
         if (STAGE == 2) stage2_bookkeeping(c, slot, step, false, 0.0, 0.0, p.t_stop, tlog, dtlog);
         return;
     }
-    if (STAGE == 1 && blockIdx.x == 0 && threadIdx.x == 0) c->rmin[slot ^ 1] = 0x7FF0000000000000ull;
+    if (STAGE == 1 && blockIdx.x == 0 && threadIdx.x < kMinGroups)
+        c->rmin[slot ^ 1][threadIdx.x * kMinStride] = 0x7FF0000000000000ull;
     // state the stage reconstructs: w^n in stage 1, w1 in stage 2
     const Cell4* __restrict__ Ws = (STAGE == 1) ? W : W1;
     const int64_t nc = m.nc;
@@ -422,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
     }
     block_count_atomic(clamp, &c->clamps);
     if (STAGE == 2) {
-        block_min_atomic(rr, &c->rmin[slot ^ 1]);
+        block_min_atomic(rr, c->rmin[slot ^ 1]);
         stage2_bookkeeping(c, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
     }
 }

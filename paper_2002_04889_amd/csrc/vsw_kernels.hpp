@@ -10,10 +10,17 @@ namespace vsw {
 
 constexpr int kBlock = 256;  // threads per block (four wave64)
 
+// The CFL minimum of a step is reduced into kMinGroups partial minima, each
+// on its own 128-byte line (block b uses group b % kMinGroups, which follows
+// the round-robin dealing of workgroups to XCDs), so the blocks' atomics do
+// not all queue on one address.  The step's minimum is the min of the groups.
+constexpr int kMinGroups = 8;
+constexpr int kMinStride = 16;  // 16 x 8 bytes = one 128-byte line per group
+
 // Device control block: per-step time and CFL minimum in two slots (the
 // step using slot s writes the next step's values into slot s ^ 1).
 struct Ctrl {
-    unsigned long long rmin[2];  // bits of min_K |K| / (P_K (|u| + c))
+    unsigned long long rmin[2][kMinGroups * kMinStride];  // bits of min_K |K| / (P_K (|u| + c))
     double t[2];                 // time at the start of the step
     double dt_last;
     unsigned long long clamps;   // negative depths set to zero in this call

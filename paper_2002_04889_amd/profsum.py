@@ -1,0 +1,75 @@
+"""Summarise rocprofv3 CSV output (kernel stats, PMC counters) as markdown.
+
+python -m paper_2002_04889_amd.profsum --stats DIR/run_kernel_stats.csv
+python -m paper_2002_04889_amd.profsum --pmc DIR/run_counter_collection.csv \
+       [--copy-bytes N]
+
+--copy-bytes: bytes one plain copy kernel moved (read and written); the
+counter value that the copy kernel (rocclr copyBuffer) reports for its
+largest dispatch gives the scale factor from counter units to bytes.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import re
+
+
+def short(name: str) -> str:
+    name = re.sub(r"\(.*", "", name)
+    return name.replace("void ", "").strip()
+
+
+def stats(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                   f"{float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
+def pmc(path: str, copy_bytes: float | None) -> str:
+    rows = list(csv.DictReader(open(path)))
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows:
+        agg[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    counters = sorted({c for v in agg.values() for c in v})
+    scale = {}
+    if copy_bytes:
+        cp = [k for k in agg if "copyBuffer" in k]
+        for c in counters:
+            if cp and c in ("FETCH_SIZE", "WRITE_SIZE") and agg[cp[0]][c]:
+                scale[c] = copy_bytes / 1024.0 / max(agg[cp[0]][c])
+    head = "| kernel | dispatches | " + " | ".join(
+        f"{c} (avg{', x' + format(scale[c], '.4f') + ' = KiB' if c in scale else ''})"
+        for c in counters) + " |"
+    out = [head, "|" + "---|" * (len(counters) + 2)]
+    for k, v in agg.items():
+        n = max(len(x) for x in v.values())
+        vals = []
+        for c in counters:
+            x = v.get(c, [])
+            a = sum(x) / len(x) if x else float("nan")
+            vals.append(f"{a * scale.get(c, 1.0):.1f}")
+        out.append(f"| {k} | {n} | " + " | ".join(vals) + " |")
+    return "\n".join(out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats")
+    ap.add_argument("--pmc", action="append", default=[])
+    ap.add_argument("--copy-bytes", type=float)
+    a = ap.parse_args()
+    if a.stats:
+        print(stats(a.stats))
+    for p in a.pmc:
+        print()
+        print(pmc(p, a.copy_bytes))
+
+
+if __name__ == "__main__":
+    main()
