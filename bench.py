@@ -34,6 +34,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X datasheet HBM3E bandwidth
 #            + write w^{n+1} (24)
 ALG_BYTES_STAGE1 = 88
 ALG_BYTES_STAGE2 = 112
+# Same count with 4-byte values (FP32 state): stage 1 8 values + 24 B,
+# stage 2 11 values + 24 B.
+ALG_BYTES_STAGE1_F32 = 56
+ALG_BYTES_STAGE2_F32 = 68
 
 
 def log(*a):
@@ -54,12 +58,48 @@ def cpu_baseline(case, steps):
                       f"state, single-threaded C oracle (gcc -O2), {el:.1f} s"}
 
 
+def kernel_roofline(vsw, s, steps, nc, bytes1, bytes2):
+    """Per-launch HIP events on the solver's stream over `steps` more steps;
+    roofline entry of the dominant stage kernel."""
+    vsw.vsw_set_profiling(s.h, True)
+    s.step(steps)
+    kt = vsw.vsw_kernel_times(s.h)
+    vsw.vsw_set_profiling(s.h, False)
+    log("[bench] kernel times: " + ", ".join(
+        f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us x{v[1]}" for k, v in kt.items() if v[1]))
+    avg = {k: v[0] / v[1] for k, v in kt.items() if v[1]}
+    st1, st2 = avg.get("stage1_kernel", 0.0), avg.get("stage2_kernel", 0.0)
+    if st2 >= st1:
+        dom, dur_ms, per_cell = "stage2_kernel", st2, bytes2
+    else:
+        dom, dur_ms, per_cell = "stage1_kernel", st1, bytes1
+    achieved = per_cell * nc / (dur_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": dom, "alg_bytes_per_cell": per_cell,
+            "avg_launch_us": round(dur_ms * 1e3, 2)}
+
+
+def time_steps(torch, stream, s, steps):
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    rc, done, t = s.step(steps)
+    ev1.record(stream)
+    ev1.synchronize()
+    torch.cuda.synchronize()
+    assert done == steps, (rc, done)
+    return ev0.elapsed_time(ev1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--scale", type=float, default=1.0, help="mesh size multiplier (1 = 1M cells)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -99,44 +139,14 @@ def main():
     log(f"[bench] warmup {done} steps, t={t:.3f} s")
 
     # timed region: K steps, state resident in HBM
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        ev0.record(stream)
     w0 = time.perf_counter()
-    rc, done, t = s.step(args.steps)
-    with torch.cuda.stream(stream):
-        ev1.record(stream)
-    ev1.synchronize()
-    torch.cuda.synchronize()
+    ms = time_steps(torch, stream, s, args.steps)
     wall = time.perf_counter() - w0
-    ms = ev0.elapsed_time(ev1)
-    assert done == args.steps, (rc, done)
     value = nc * args.steps / (ms / 1e3)
     log(f"[bench] timed {args.steps} steps: {ms:.1f} ms (host wall {wall * 1e3:.1f} ms), "
         f"{value:.3e} cell-updates/s")
 
-    # per-kernel durations: HIP events around each launch on the solver's stream
-    vsw.vsw_set_profiling(s.h, True)
-    rc, done2, _ = s.step(args.steps)
-    kt = vsw.vsw_kernel_times(s.h)
-    vsw.vsw_set_profiling(s.h, False)
-    log("[bench] kernel times: " + ", ".join(
-        f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us x{v[1]}" for k, v in kt.items() if v[1]))
-    # dominant kernel: the stage kernel with the longer average launch
-    avg = {k: v[0] / v[1] for k, v in kt.items() if v[1]}
-    st1, st2 = avg.get("stage1_kernel", 0.0), avg.get("stage2_kernel", 0.0)
-    if st2 >= st1:
-        dom, dur_ms, per_cell = "stage2_kernel", st2, ALG_BYTES_STAGE2
-    else:
-        dom, dur_ms, per_cell = "stage1_kernel", st1, ALG_BYTES_STAGE1
-    traffic = per_cell * nc
-    achieved = traffic / (dur_ms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dom, "alg_bytes_per_cell": per_cell,
-                "avg_launch_us": round(dur_ms * 1e3, 2)}
+    roofline = kernel_roofline(vsw, s, args.steps, nc, ALG_BYTES_STAGE1, ALG_BYTES_STAGE2)
 
     out = {"metric": "cell-updates/s", "value": value, "unit": "cell-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -147,6 +157,22 @@ def main():
                       "cells": nc, "edges": ne, "walls": nw, "precision": "fp64",
                       "ordering": "hilbert", "global_batch": nc, "parallelism": "single-gpu"},
            "roofline": roofline}
+    if not args.no_fp32:
+        # the same mesh and initial state with the mixed-precision solver
+        s32 = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold, device=0,
+                         precision=vsw.VSW_FP32)
+        vsw.vsw_set_stream(s32.h, stream.cuda_stream)
+        s32.upload_mesh(case.vx, case.vy, case.tri, case.h)
+        vsw.vsw_set_state_device(s32.h, dH.data_ptr(), dHU.data_ptr(), dHV.data_ptr(), 0.0)
+        s32.step(args.warmup)
+        ms32 = time_steps(torch, stream, s32, args.steps)
+        v32 = nc * args.steps / (ms32 / 1e3)
+        log(f"[bench] fp32: {args.steps} steps {ms32:.1f} ms, {v32:.3e} cell-updates/s")
+        out["fp32"] = {"value": v32, "unit": "cell-updates/s", "ms_per_step": ms32 / args.steps,
+                       "dtype": "f32 state and fluxes, f64 depths/pressure/accumulation",
+                       "roofline": kernel_roofline(vsw, s32, args.steps, nc,
+                                                   ALG_BYTES_STAGE1_F32, ALG_BYTES_STAGE2_F32)}
+        s32.close()
     if args.copy_calibration:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -45,7 +45,14 @@ enum {
     VSW_EUNSTABLE = -6  /* non-finite state or no valid time step */
 };
 
-enum { VSW_FP64 = 0 };                     /* arithmetic of the solver */
+/* Arithmetic of the solver.  VSW_FP64: every step in FP64.  VSW_FP32:
+ * mixed precision -- the free surface eta = H - h and the momentum are
+ * stored in FP32, and the reconstruction, face velocities, wave speeds and
+ * the mass and tangential fluxes are FP32; depths, the hydrostatic
+ * reconstruction, the normal-momentum flux, the bed-source terms, each
+ * cell's residual accumulation, the stage update and the CFL reduction stay
+ * FP64.  State transfer stays FP64 at the interface. */
+enum { VSW_FP64 = 0, VSW_FP32 = 1 };
 enum { VSW_ORDER_HILBERT = 0, VSW_ORDER_NONE = 1, VSW_ORDER_RANDOM = 2 };
 
 typedef struct vsw_params {
@@ -57,7 +64,7 @@ typedef struct vsw_params {
     double dt_fixed;     /* > 0: constant time step; 0: CFL rule
                             dt = cfl * min_K |K| / (P_K (|u_K| + sqrt(g H_K)))
                             over cells with H_K >= H_thr */
-    int32_t precision;   /* VSW_FP64 */
+    int32_t precision;   /* VSW_FP64 or VSW_FP32 */
     int32_t ordering;    /* internal cell order: VSW_ORDER_* */
     uint64_t seed;       /* seed of VSW_ORDER_RANDOM */
 } vsw_params;
@@ -122,6 +129,19 @@ int vsw_last_dt(vsw_solver *s, double *dt);
 /* dt of each completed step of the last vsw_step call: up to max values
  * into dts (may be NULL); *count receives the number of steps. */
 int vsw_dt_history(vsw_solver *s, int64_t max, double *dts, int64_t *count);
+
+/* Virtual gauges (the time series of Sections 3 and 5): n cells in the
+ * caller's order whose free surface eta = H - h is recorded on the device
+ * after every step of each vsw_step call.  n = 0 removes them.  EINVAL on a
+ * cell index out of range; ESTATE before vsw_upload_mesh (a new mesh clears
+ * the gauges). */
+int vsw_set_gauges(vsw_solver *s, int32_t n, const int32_t *cells);
+
+/* Records of the last vsw_step call: *count = its steps; up to max_steps
+ * rows into eta_out[step * n + gauge] and the time after each step into
+ * t_out (either may be NULL). */
+int vsw_get_gauges(vsw_solver *s, int64_t max_steps, double *eta_out,
+                   double *t_out, int64_t *count);
 
 /* Number of negative depths set to zero after a stage since the last
  * vsw_set_state (a post-stage positivity fix; 0 in a well-resolved run). */

@@ -11,6 +11,7 @@
 
 #include "../../include/vsw.h"
 #include "vsw_kernels.hpp"
+#include "vsw_kernels_f32.hpp"
 #include "vsw_mesh.hpp"
 
 using namespace vsw;
@@ -68,14 +69,21 @@ struct vsw_solver {
     DevBuf<Nbr4> d_nbr;            // neighbour slots per cell
     DevBuf<double> d_geom, d_area, d_perim, d_h;
     DevBuf<RGeom> d_rgeom;         // reconstruction geometry records
-    DevBuf<Cell4> d_w;             // w^n records (H, HU, HV, h)
-    DevBuf<Cell4> d_w1;            // stage-1 records
+    DevBuf<Cell4> d_w;             // w^n records (H, HU, HV, h), FP64 solver
+    DevBuf<Cell4> d_w1;            // stage-1 records, FP64 solver
+    DevBuf<CellF> d_wf;            // w^n records (h, eta, Hu, Hv), FP32 solver
+    DevBuf<CellF> d_w1f;           // stage-1 records, FP32 solver
     DevBuf<double> d_face;         // 15 * nc face buffer
     DevBuf<double> d_sc;           // 2 * nc
     DevBuf<int32_t> d_order;       // nc
     DevBuf<double> d_tmp;          // 3 * nc staging of caller-order arrays
     DevBuf<double> d_log;          // 2 * cap: t and dt per step
     DevBuf<Ctrl> d_ctrl;
+    DevBuf<int64_t> d_gauge_cells; // internal indices of the gauge cells
+    DevBuf<double> d_gauge_log;    // [step][gauge] free surface of the last call
+    int ngauges = 0;
+    std::vector<double> gauge_eta; // host copy of the last call's records
+    std::vector<double> gauge_t;
     DevBuf<uint16_t> d_nloc;       // tile map of the fused kernel
     DevBuf<int32_t> d_bstart;
     DevBuf<uint32_t> d_bitem;
@@ -96,9 +104,32 @@ struct vsw_solver {
         d_perm.release(); d_nbr.release(); d_geom.release(); d_area.release();
         d_rgeom.release();
         d_perim.release(); d_h.release(); d_w.release(); d_w1.release();
+        d_wf.release(); d_w1f.release();
         d_face.release(); d_sc.release(); d_order.release(); d_tmp.release();
         d_nloc.release(); d_bstart.release(); d_bitem.release();
+        d_gauge_cells.release();
+        ngauges = 0;
         has_mesh = has_state = false;
+    }
+    // caller-order arrays (device) -> state records of both stage buffers
+    void pack(const double* H, const double* HU, const double* HV) {
+        if (prm.precision == VSW_FP32)
+            hipLaunchKernelGGL(pack_state_f32_kernel, dim3(unsigned((nc + kBlock - 1) / kBlock)),
+                               dim3(kBlock), 0, stream, nc, d_perm.p, H, HU, HV, d_h.p, d_wf.p,
+                               d_w1f.p);
+        else
+            hipLaunchKernelGGL(pack_state_kernel, dim3(unsigned((nc + kBlock - 1) / kBlock)),
+                               dim3(kBlock), 0, stream, nc, d_perm.p, H, HU, HV, d_h.p, d_w.p,
+                               d_w1.p);
+    }
+    // state records -> caller-order arrays (device; NULL skips a field)
+    void unpack(double* H, double* HU, double* HV) {
+        if (prm.precision == VSW_FP32)
+            hipLaunchKernelGGL(unpack_state_f32_kernel, dim3(unsigned((nc + kBlock - 1) / kBlock)),
+                               dim3(kBlock), 0, stream, nc, d_perm.p, d_wf.p, H, HU, HV);
+        else
+            hipLaunchKernelGGL(unpack_state_kernel, dim3(unsigned((nc + kBlock - 1) / kBlock)),
+                               dim3(kBlock), 0, stream, nc, d_perm.p, d_w.p, H, HU, HV);
     }
     DevMesh dev_mesh() const {
         DevMesh m;
@@ -148,7 +179,8 @@ int vsw_create(const vsw_params* p, int device, vsw_solver** out) {
         return fail(VSW_EINVAL, "h_threshold must be >= 0");
     if (!(p->dt_fixed >= 0.0) || !std::isfinite(p->dt_fixed))
         return fail(VSW_EINVAL, "dt_fixed must be >= 0");
-    if (p->precision != VSW_FP64) return fail(VSW_EINVAL, "unsupported precision");
+    if (p->precision != VSW_FP64 && p->precision != VSW_FP32)
+        return fail(VSW_EINVAL, "unsupported precision");
     if (p->ordering < VSW_ORDER_HILBERT || p->ordering > VSW_ORDER_RANDOM)
         return fail(VSW_EINVAL, "unknown ordering");
     int ndev = 0;
@@ -177,6 +209,7 @@ void vsw_destroy(vsw_solver* s) {
     s->release_mesh();
     s->d_log.release();
     s->d_ctrl.release();
+    s->d_gauge_log.release();
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
@@ -209,11 +242,16 @@ int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* v
     HIP_TRY(s->d_area.alloc(n));
     HIP_TRY(s->d_perim.alloc(n));
     HIP_TRY(s->d_h.alloc(n));
-    HIP_TRY(s->d_w.alloc(n));
-    HIP_TRY(s->d_w1.alloc(n));
-    HIP_TRY(s->d_face.alloc(15 * n));
-    HIP_TRY(s->d_sc.alloc(2 * n));
-    HIP_TRY(s->d_order.alloc(n));
+    if (s->prm.precision == VSW_FP32) {
+        HIP_TRY(s->d_wf.alloc(n));
+        HIP_TRY(s->d_w1f.alloc(n));
+    } else {
+        HIP_TRY(s->d_w.alloc(n));
+        HIP_TRY(s->d_w1.alloc(n));
+        HIP_TRY(s->d_face.alloc(15 * n));
+        HIP_TRY(s->d_sc.alloc(2 * n));
+        HIP_TRY(s->d_order.alloc(n));
+    }
     HIP_TRY(s->d_tmp.alloc(3 * n));
     HIP_TRY(hipMemcpy(s->d_perm.p, hm.perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
     {
@@ -275,8 +313,7 @@ int vsw_set_state(vsw_solver* s, const double* H, const double* HU, const double
     HIP_TRY(hipMemcpyAsync(tmp + nc, HU, nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(tmp + 2 * nc, HV, nc * sizeof(double), hipMemcpyHostToDevice,
                            s->stream));
-    hipLaunchKernelGGL(pack_state_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
-                       s->d_perm.p, tmp, tmp + nc, tmp + 2 * nc, s->d_h.p, s->d_w.p, s->d_w1.p);
+    s->pack(tmp, tmp + nc, tmp + 2 * nc);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->t = t;
@@ -293,9 +330,7 @@ int vsw_set_state_device(vsw_solver* s, const double* dH, const double* dHU, con
     if (!dH || !dHU || !dHV) return fail(VSW_EINVAL, "NULL state array");
     if (!std::isfinite(t)) return fail(VSW_EINVAL, "non-finite time");
     DeviceGuard dg(s->device);
-    const int64_t nc = s->nc;
-    hipLaunchKernelGGL(pack_state_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
-                       s->d_perm.p, dH, dHU, dHV, s->d_h.p, s->d_w.p, s->d_w1.p);
+    s->pack(dH, dHU, dHV);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->t = t;
@@ -311,8 +346,7 @@ int vsw_get_state(vsw_solver* s, double* H, double* HU, double* HV, double* t) {
     DeviceGuard dg(s->device);
     const int64_t nc = s->nc;
     double* tmp = s->d_tmp.p;
-    hipLaunchKernelGGL(unpack_state_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
-                       s->d_perm.p, s->d_w.p, tmp, tmp + nc, tmp + 2 * nc);
+    s->unpack(tmp, tmp + nc, tmp + 2 * nc);
     HIP_TRY(hipGetLastError());
     double* dst[3] = {H, HU, HV};
     for (int c = 0; c < 3; ++c)
@@ -328,9 +362,7 @@ int vsw_get_state_device(vsw_solver* s, double* dH, double* dHU, double* dHV, do
     if (!s) return fail(VSW_EINVAL, "NULL solver");
     if (!s->has_state) return fail(VSW_ESTATE, "no state");
     DeviceGuard dg(s->device);
-    const int64_t nc = s->nc;
-    hipLaunchKernelGGL(unpack_state_kernel, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
-                       s->d_perm.p, s->d_w.p, dH, dHU, dHV);
+    s->unpack(dH, dHU, dHV);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));
     if (t) *t = s->t;
@@ -348,6 +380,9 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     if (n == 0) return VSW_OK;
     DeviceGuard dg(s->device);
     if (s->d_log.n < size_t(2 * n)) HIP_TRY(s->d_log.alloc(size_t(2 * n)));
+    const int ng = s->ngauges;
+    if (ng > 0 && s->d_gauge_log.n < size_t(n) * size_t(ng))
+        HIP_TRY(s->d_gauge_log.alloc(size_t(n) * size_t(ng)));
     const int64_t nc = s->nc;
     const DevMesh m = s->dev_mesh();
     StepParams p;
@@ -390,14 +425,33 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
 
     hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(64), 0, st, c, s->t);
     ev_begin(KK_DTINIT);
-    hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, W, p.g, p.thr, c);
+    const bool f32 = (s->prm.precision == VSW_FP32);
+    if (f32)
+        hipLaunchKernelGGL(dt_init_f32_kernel, grid, block, 0, st, m, s->d_wf.p, p.g, p.thr, c);
+    else
+        hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, W, p.g, p.thr, c);
     ev_end();
     TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->bmax, s->ntiles};
     const size_t lds = stage_lds_bytes(s->bmax);
+    const size_t lds32 = stage_f32_lds_bytes(s->bmax);
     const dim3 tgrid(unsigned(s->ntiles));
     auto k1 = stage_kernel<1>;
     auto k2 = stage_kernel<2>;
-    for (int64_t k = 0; s->variant == VSW_KERNEL_FUSED && k < n; ++k) {
+    for (int64_t k = 0; f32 && k < n; ++k) {
+        const int slot = int(k & 1);
+        ev_begin(KK_STAGE1);
+        hipLaunchKernelGGL(stage_f32_kernel<1>, tgrid, block, lds32, st, m, tm, s->d_wf.p,
+                           s->d_w1f.p, p, c, slot, int(k), tlog, dtlog);
+        ev_end();
+        ev_begin(KK_STAGE2);
+        hipLaunchKernelGGL(stage_f32_kernel<2>, tgrid, block, lds32, st, m, tm, s->d_wf.p,
+                           s->d_w1f.p, p, c, slot, int(k), tlog, dtlog);
+        ev_end();
+        if (ng > 0)
+            hipLaunchKernelGGL(gauge_f32_kernel, dim3(unsigned((ng + 63) / 64)), dim3(64), 0, st,
+                               s->d_wf.p, s->d_gauge_cells.p, ng, c, int(k), s->d_gauge_log.p);
+    }
+    for (int64_t k = 0; !f32 && s->variant == VSW_KERNEL_FUSED && k < n; ++k) {
         const int slot = int(k & 1);
         ev_begin(KK_STAGE1);
         hipLaunchKernelGGL(k1, tgrid, block, lds, st, m, tm, W, W1, p, c, slot, int(k), tlog,
@@ -407,8 +461,11 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         hipLaunchKernelGGL(k2, tgrid, block, lds, st, m, tm, W, W1, p, c, slot, int(k), tlog,
                            dtlog);
         ev_end();
+        if (ng > 0)
+            hipLaunchKernelGGL(gauge_kernel, dim3(unsigned((ng + 63) / 64)), dim3(64), 0, st, W,
+                               s->d_gauge_cells.p, ng, c, int(k), s->d_gauge_log.p);
     }
-    for (int64_t k = 0; s->variant == VSW_KERNEL_TWO_PASS && k < n; ++k) {
+    for (int64_t k = 0; !f32 && s->variant == VSW_KERNEL_TWO_PASS && k < n; ++k) {
         const int slot = int(k & 1);
         ev_begin(KK_RECON);
         hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, W, fb, p, c, slot);
@@ -423,6 +480,9 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         hipLaunchKernelGGL(update2_kernel, grid, block, 0, st, m, W, W1, fb, p, c, slot, int(k),
                            tlog, dtlog);
         ev_end();
+        if (ng > 0)
+            hipLaunchKernelGGL(gauge_kernel, dim3(unsigned((ng + 63) / 64)), dim3(64), 0, st, W,
+                               s->d_gauge_cells.p, ng, c, int(k), s->d_gauge_log.p);
     }
     HIP_TRY(hipGetLastError());
     Ctrl hc;
@@ -449,6 +509,11 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     }
     s->clamps += int64_t(hc.clamps);
     s->last_dts.assign(logs.begin() + n, logs.begin() + n + done);
+    s->gauge_t.assign(logs.begin(), logs.begin() + done);
+    s->gauge_eta.assign(size_t(done) * size_t(ng), 0.0);
+    if (ng > 0 && done > 0)
+        HIP_TRY(hipMemcpy(s->gauge_eta.data(), s->d_gauge_log.p,
+                          size_t(done) * size_t(ng) * sizeof(double), hipMemcpyDeviceToHost));
     if (done > 0) {
         s->t = logs[done - 1];
         s->dt_last = logs[n + done - 1];
@@ -479,10 +544,46 @@ int vsw_dt_history(vsw_solver* s, int64_t max, double* dts, int64_t* count) {
     return VSW_OK;
 }
 
+int vsw_set_gauges(vsw_solver* s, int32_t n, const int32_t* cells) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
+    if (n < 0 || (n > 0 && !cells)) return fail(VSW_EINVAL, "bad gauge list");
+    std::vector<int64_t> inv(s->nc);
+    for (int64_t i = 0; i < s->nc; ++i) inv[s->perm[i]] = i;
+    std::vector<int64_t> idx(n);
+    for (int32_t g = 0; g < n; ++g) {
+        if (cells[g] < 0 || cells[g] >= s->nc) return fail(VSW_EINVAL, "gauge cell out of range");
+        idx[g] = inv[cells[g]];
+    }
+    DeviceGuard dg(s->device);
+    HIP_TRY(s->d_gauge_cells.alloc(size_t(n)));
+    if (n > 0)
+        HIP_TRY(hipMemcpy(s->d_gauge_cells.p, idx.data(), size_t(n) * sizeof(int64_t),
+                          hipMemcpyHostToDevice));
+    s->ngauges = n;
+    s->gauge_eta.clear();
+    s->gauge_t.clear();
+    return VSW_OK;
+}
+
+int vsw_get_gauges(vsw_solver* s, int64_t max_steps, double* eta_out, double* t_out,
+                   int64_t* count) {
+    if (!s || !count) return fail(VSW_EINVAL, "NULL argument");
+    const int64_t steps = int64_t(s->gauge_t.size());
+    *count = steps;
+    const int64_t m = std::min(steps, max_steps);
+    if (eta_out && s->ngauges > 0)
+        std::memcpy(eta_out, s->gauge_eta.data(), size_t(m) * s->ngauges * sizeof(double));
+    if (t_out) std::memcpy(t_out, s->gauge_t.data(), size_t(m) * sizeof(double));
+    return VSW_OK;
+}
+
 int vsw_set_kernel_variant(vsw_solver* s, int variant) {
     if (!s) return fail(VSW_EINVAL, "NULL solver");
     if (variant != VSW_KERNEL_FUSED && variant != VSW_KERNEL_TWO_PASS)
         return fail(VSW_EINVAL, "unknown kernel variant");
+    if (variant == VSW_KERNEL_TWO_PASS && s->prm.precision == VSW_FP32)
+        return fail(VSW_EINVAL, "the two-pass variant is FP64 only");
     s->variant = variant;
     return VSW_OK;
 }

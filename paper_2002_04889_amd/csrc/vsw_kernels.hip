@@ -14,103 +14,9 @@
 //                  double).
 // The time step and the current time live in a small device control block,
 // so the host never synchronises between steps.
-#include "vsw_kernels.hpp"
+#include "vsw_common.hpp"
 
 namespace vsw {
-
-namespace {
-
-__device__ __forceinline__ unsigned long long dbits(double x) {
-    return (unsigned long long)__double_as_longlong(x);
-}
-
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        double w = __shfl_xor(v, o, 64);
-        v = (w < v) ? w : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// dt of the step using control slot `slot`: CFL rule (or fixed dt), clipped
-// so the time lands exactly on t_stop.  False if the step is not taken.
-__device__ __forceinline__ bool step_dt(const Ctrl* c, int slot, const StepParams& p,
-                                        double& dt, double& tn) {
-    if (c->err) return false;
-    const double t = c->t[slot];
-    if (!(t < p.t_stop)) return false;
-    unsigned long long rb = c->rmin[slot][0];
-#pragma unroll
-    for (int g = 1; g < kMinGroups; ++g) {
-        const unsigned long long v = c->rmin[slot][g * kMinStride];
-        rb = (v < rb) ? v : rb;
-    }
-    double d = (p.dt_fixed > 0.0) ? p.dt_fixed : p.cfl * __longlong_as_double((long long)rb);
-    const double rem = p.t_stop - t;
-    if (d >= rem) {
-        d = rem;
-        tn = p.t_stop;
-    } else {
-        tn = t + d;
-    }
-    if (!(d > 0.0) || !isfinite(d)) return false;
-    dt = d;
-    return true;
-}
-
-// CFL ratio |K| / (P_K (|u| + sqrt(g H))) of a wet cell, +inf otherwise.
-__device__ __forceinline__ double cfl_ratio(double H, double HU, double HV, double area,
-                                            double perim, double g, double thr) {
-    if (!(H >= thr)) return __longlong_as_double(0x7FF0000000000000ll);
-    const double u = HU / H, v = HV / H;
-    const double s = sqrt(u * u + v * v) + sqrt(g * H);
-    return area / (perim * s);
-}
-
-// Block-wide min of a positive double, then one atomic min on its bits in
-// the block's group.  The bits of positive doubles order like the values; a
-// plain read first skips the atomic when the group already holds a value at
-// least as small (values only decrease, so a stale read never loses one).
-__device__ __forceinline__ void block_min_atomic(double v, unsigned long long* slot_base) {
-    unsigned long long* target = slot_base + (blockIdx.x % kMinGroups) * kMinStride;
-    __shared__ double part[kBlock / 64];
-    v = wave_min(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) part[wid] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = part[0];
-#pragma unroll
-        for (int i = 1; i < kBlock / 64; ++i) m = (part[i] < m) ? part[i] : m;
-        const unsigned long long b = dbits(m);
-        if (m < __longlong_as_double(0x7FF0000000000000ll) &&
-            b < __hip_atomic_load(target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            atomicMin(target, b);
-    }
-}
-
-__device__ __forceinline__ void block_count_atomic(unsigned long long v, unsigned long long* target) {
-    __shared__ unsigned long long part[kBlock / 64];
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) part[wid] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long s = 0;
-#pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) s += part[i];
-        if (s) atomicAdd(target, s);
-    }
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------- control
 
@@ -253,28 +159,6 @@ __global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, const Cell4*
     block_count_atomic(clamp, &c->clamps);
 }
 
-// Time bookkeeping at the end of stage 2 (block 0 only) or, for a step that
-// is not taken, the carry-over of the time and the no-valid-dt error.
-__device__ __forceinline__ void stage2_bookkeeping(Ctrl* c, int slot, int step, bool active,
-                                                   double dt, double tn, double t_stop,
-                                                   double* tlog, double* dtlog) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    if (active) {
-        c->t[slot ^ 1] = tn;
-        c->dt_last = dt;
-        c->steps_done += 1;
-        tlog[step] = tn;
-        dtlog[step] = dt;
-    } else {
-        const double t = c->t[slot];
-        c->t[slot ^ 1] = t;
-        if (!c->err && t < t_stop) {  // no valid time step
-            c->err = 2;
-            c->err_step = step;
-        }
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, Cell4* __restrict__ W,
                                                          const Cell4* __restrict__ W1, FaceBuf fb,
                                                          StepParams p, Ctrl* c, int slot, int step,
@@ -309,16 +193,6 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, Cell4* __res
 // ---------------------------------------------------------------- fused stage
 
 namespace {
-
-// Tiles are consecutive Hilbert ranges, so tiles t and t+1 are neighbours in
-// space.  Workgroups are dealt round-robin to the eight XCDs, each with its
-// own L2; give XCD x one contiguous run of tiles so that the halo cells
-// shared by neighbouring tiles are read through the same L2.
-__device__ __forceinline__ int xcd_tile(int w, int ntiles) {
-    const int per = ntiles / 8, rem = ntiles % 8;
-    const int x = w % 8, idx = w / 8;
-    return (x < rem) ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
-}
 
 __device__ __forceinline__ void lds_store_face(double* lds, int stride, int slot, const Face& f) {
     lds[0 * stride + slot] = f.eta;
@@ -447,6 +321,18 @@ template __global__ void stage_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, StepP
                                          int, double*, double*);
 template __global__ void stage_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, int,
                                          int, double*, double*);
+
+// ---------------------------------------------------------------- gauges
+
+// Free surface eta = H - h at the gauge cells after step `step`, if the step
+// was taken (steps_done counts the steps taken in this call).
+__global__ void gauge_kernel(const Cell4* __restrict__ W, const int64_t* __restrict__ cells,
+                             int ng, const Ctrl* c, int step, double* __restrict__ log) {
+    const int gi = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gi >= ng || c->steps_done <= step) return;
+    const Cell4 q = W[cells[gi]];
+    log[int64_t(step) * ng + gi] = q.H - q.h;
+}
 
 // ---------------------------------------------------------------- state transfer
 

@@ -70,6 +70,8 @@ __global__ void update1_kernel(DevMesh m, const Cell4* W, Cell4* W1, FaceBuf fb,
                                Ctrl* c, int slot);
 __global__ void update2_kernel(DevMesh m, Cell4* W, const Cell4* W1, FaceBuf fb, StepParams p,
                                Ctrl* c, int slot, int step, double* tlog, double* dtlog);
+__global__ void gauge_kernel(const Cell4* W, const int64_t* cells, int ng, const Ctrl* c, int step,
+                             double* log);
 __global__ void pack_state_kernel(int64_t n, const int64_t* perm, const double* H,
                                   const double* HU, const double* HV, const double* h, Cell4* W,
                                   Cell4* W1);

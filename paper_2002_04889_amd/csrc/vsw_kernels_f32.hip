@@ -1,0 +1,438 @@
+// Mixed-precision (FP32) variant of the fused stage kernel.
+//
+// Same scheme as the FP64 kernel (Sections 2.2-2.5), evaluated with FP32
+// state and FP32 arithmetic wherever the quantities are small:
+//   FP32: the prognostic free surface eta and momentum (Hu, Hv) in memory,
+//         the least-squares gradients and Barth-Jespersen limiter, face
+//         values of eta, Hu, Hv, face velocities, wave speeds, the mass and
+//         tangential-momentum fluxes.
+//   FP64: depths (H = eta + h with h ~ 4000 m cannot be held to 1e-4 m in
+//         FP32), the hydrostatic reconstruction h* = min(h_L, h_R),
+//         H* = max(0, eta + h*), the normal-momentum flux that carries
+//         g H*^2 / 2, the hydrostatic and centred bed-source terms, the
+//         accumulation of each cell's residual, the stage update and the CFL
+//         reduction.
+// At rest (eta = 0, u = 0) every FP32 quantity is exactly zero, so the lake
+// at rest is kept to FP64 round-off as in the FP64 kernel.  A cell set dry
+// by the post-stage fix stores eta = -h rounded upward, so its depth
+// eta + h is never negative.
+#include "vsw_common.hpp"
+#include "vsw_kernels_f32.hpp"
+
+namespace vsw {
+
+namespace {
+
+struct ReconF {
+    float fe[3], fu[3], fv[3];   // face eta, Hu, Hv
+    double fh[3], fH[3];         // face bed depth and total depth
+    double Hk, hk;
+    bool second;
+};
+
+__device__ __forceinline__ float fminf_(float a, float b) { return (b < a) ? b : a; }
+__device__ __forceinline__ float fmaxf_(float a, float b) { return (b > a) ? b : a; }
+
+__device__ __forceinline__ void recon_core_f32(const DevMesh& m, const CellF* __restrict__ W,
+                                               int64_t k, double thr, ReconF& r) {
+    const CellF ck = W[k];
+    const double hk = ck.h;
+    const float ek = ck.eta, uk = ck.hu, vk = ck.hv;
+    const double Hk = double(ek) + hk;
+    const Nbr4 nb = m.nbr[k];
+    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
+    float qe[3], qu[3], qv[3], dh[3];
+    bool cand = (Hk >= thr);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t s = sl[j];
+        if (s != kWallSlot) {
+            const CellF cn = W[int64_t(s >> 3)];
+            const double Hn = double(cn.eta) + cn.h;
+            qe[j] = cn.eta;
+            qu[j] = cn.hu;
+            qv[j] = cn.hv;
+            dh[j] = float(cn.h - hk);
+            if (!(Hn >= thr)) cand = false;
+        } else {
+            // wall ghost: same depth and surface, mirrored momentum
+            const float nx = float(gf(m, 0, j, k)), ny = float(gf(m, 1, j, k));
+            const float mn = uk * nx + vk * ny;
+            qe[j] = ek;
+            qu[j] = uk - (2.0f * mn) * nx;
+            qv[j] = vk - (2.0f * mn) * ny;
+            dh[j] = 0.0f;
+        }
+    }
+    r.Hk = Hk;
+    r.hk = hk;
+    if (cand) {
+        const RGeom rg = m.rgeom[k];
+        const float wx0 = float(rg.w[0]), wx1 = float(rg.w[2]), wx2 = float(rg.w[4]);
+        const float wy0 = float(rg.w[1]), wy1 = float(rg.w[3]), wy2 = float(rg.w[5]);
+        const float dxs[3] = {float(rg.d[0]), float(rg.d[2]), float(rg.d[4])};
+        const float dys[3] = {float(rg.d[1]), float(rg.d[3]), float(rg.d[5])};
+        auto project = [&](const float* qs, float q0, float* pj) {
+            const float d0 = qs[0] - q0, d1 = qs[1] - q0, d2 = qs[2] - q0;
+            const float gx = wx0 * d0 + wx1 * d1 + wx2 * d2;
+            const float gy = wy0 * d0 + wy1 * d1 + wy2 * d2;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) pj[j] = gx * dxs[j] + gy * dys[j];
+        };
+        float pe[3], pu[3], pv[3], ph[3];
+        project(qe, ek, pe);
+        project(qu, uk, pu);
+        project(qv, vk, pv);
+        project(dh, 0.0f, ph);
+        // Barth-Jespersen, as in the FP64 kernel (at most two divisions)
+        auto limiter = [](float q0, const float* qs, const float* pj) -> float {
+            float qmax = q0, qmin = q0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                qmax = fmaxf_(qmax, qs[j]);
+                qmin = fminf_(qmin, qs[j]);
+            }
+            const float up = qmax - q0, dn = qmin - q0;
+            float dpos_max = 0.0f, dneg_min = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                dpos_max = fmaxf_(dpos_max, pj[j]);
+                dneg_min = fminf_(dneg_min, pj[j]);
+            }
+            float a = 1.0f;
+            if (dpos_max > 0.0f && up < dpos_max) a = up / dpos_max;
+            if (dneg_min < 0.0f && dn > dneg_min) a = fminf_(a, dn / dneg_min);
+            return a;
+        };
+        const float ae = limiter(ek, qe, pe);
+        const float au = limiter(uk, qu, pu);
+        const float av = limiter(vk, qv, pv);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            r.fe[j] = ek + ae * pe[j];
+            r.fu[j] = uk + au * pu[j];
+            r.fv[j] = vk + av * pv[j];
+            r.fh[j] = hk + double(ph[j]);
+            r.fH[j] = double(r.fe[j]) + r.fh[j];
+            if (r.fH[j] < thr) cand = false;
+        }
+    }
+    if (!cand) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            r.fe[j] = ek; r.fu[j] = uk; r.fv[j] = vk; r.fh[j] = hk; r.fH[j] = Hk;
+        }
+    }
+    r.second = cand;
+}
+
+__device__ __forceinline__ FaceF recon_face_f32(const ReconF& r, int j, double thr) {
+    FaceF f;
+    f.eta = r.fe[j];
+    f.h = r.fh[j];
+    f.H = r.fH[j];
+    if (r.fH[j] >= thr) {
+        const float Hf = float(r.fH[j]);
+        f.u = r.fu[j] / Hf;
+        f.v = r.fv[j] / Hf;
+    } else {
+        f.u = 0.0f;
+        f.v = 0.0f;
+    }
+    return f;
+}
+
+// HLL flux in the face frame (Section 2.2) with FP64 depths HL, HR: the
+// mass and tangential fluxes in FP32, the normal-momentum flux (which holds
+// g H^2 / 2) in FP64.
+__device__ __forceinline__ void hll_face_f32(double g, double hg, double HL, float unL, float utL,
+                                             double HR, float unR, float utR, float& f0,
+                                             double& f1, float& f2) {
+    if (HL == 0.0 && HR == 0.0) {
+        f0 = 0.0f; f1 = 0.0; f2 = 0.0f;
+        return;
+    }
+    const float cL = sqrtf(float(g * HL)), cR = sqrtf(float(g * HR));
+    float sL, sR;
+    if (HL == 0.0) {
+        sL = unR - 2.0f * cR;
+        sR = unR + cR;
+    } else if (HR == 0.0) {
+        sL = unL - cL;
+        sR = unL + 2.0f * cL;
+    } else {
+        const float us = 0.5f * (unL + unR) + (cL - cR);
+        const float cs = 0.5f * (cL + cR) - 0.25f * (unR - unL);
+        sL = fminf_(unL - cL, us - cs);
+        sR = fmaxf_(us + cs, unR + cR);
+    }
+    const float HLf = float(HL), HRf = float(HR);
+    const float qL = HLf * unL, qR = HRf * unR;
+    const float fL0 = qL, fL2 = qL * utL;
+    const float fR0 = qR, fR2 = qR * utR;
+    const double fL1 = double(qL * unL) + hg * (HL * HL);
+    const double fR1 = double(qR * unR) + hg * (HR * HR);
+    if (sL >= 0.0f) {
+        f0 = fL0; f1 = fL1; f2 = fL2;
+    } else if (sR < 0.0f) {
+        f0 = fR0; f1 = fR1; f2 = fR2;
+    } else {
+        // The speeds are FP32; the denominator is their exact difference in
+        // FP64, so F* of a uniform state returns that state's flux (an FP32
+        // rounded sR - sL would bias the g H^2 / 2 part, ~1e8, by ~1e-7
+        // relative on every face).  Mass and normal-momentum star fluxes are
+        // formed in FP64 from the FP32 terms; the tangential one in FP32.
+        const double dR = double(sR), dL = double(sL), den = dR - dL, sLR = dL * dR;
+        f0 = float(((dR * double(fL0) - dL * double(fR0)) + sLR * (HR - HL)) / den);
+        f1 = ((dR * fL1 - dL * fR1) + sLR * (double(qR) - double(qL))) / den;
+        f2 = ((sR * fL2 - sL * fR2) + float(sLR) * (HRf * utR - HLf * utL)) / float(den);
+    }
+}
+
+// One face seen from a cell, canonical orientation, no divergent branches
+// (see face_term of the FP64 kernel).  Returns l (phi + (0, p n)) in FP64.
+__device__ __forceinline__ bool face_term_f32(double g, double hg, const FaceF& own,
+                                              const FaceF& other, bool wall, bool own_left,
+                                              double nx_out, double ny_out, double l, double t[3]) {
+    const bool left = wall || own_left;
+    const float eL = left ? own.eta : other.eta, eR = left ? other.eta : own.eta;
+    const double hL = left ? own.h : other.h, hR = left ? other.h : own.h;
+    const double HL = left ? own.H : other.H, HR = left ? other.H : own.H;
+    const float uL = left ? own.u : other.u, uR = left ? other.u : own.u;
+    const float vL = left ? own.v : other.v, vR = left ? other.v : own.v;
+    const double nx = left ? nx_out : -nx_out, ny = left ? ny_out : -ny_out;
+    const float nxf = float(nx), nyf = float(ny);
+    const float unL = uL * nxf + vL * nyf, utL = vL * nxf - uL * nyf;
+    float unR = uR * nxf + vR * nyf;
+    const float utR = vR * nxf - uR * nyf;
+    const double hs = dmin(hL, hR);
+    const double HsL = dpos(double(eL) + hs), HsR = dpos(double(eR) + hs);
+    if (wall) unR = -unL;
+    float f0, f2;
+    double f1;
+    hll_face_f32(g, hg, HsL, unL, utL, HsR, unR, utR, f0, f1, f2);
+    const double pc = left ? hg * (HL * HL - HsL * HsL) : hg * (HR * HR - HsR * HsR);
+    const double phi1 = f1 * nx - double(f2) * ny;
+    const double phi2 = f1 * ny + double(f2) * nx;
+    t[0] = l * double(f0);
+    t[1] = l * (phi1 + pc * nx);
+    t[2] = l * (phi2 + pc * ny);
+    return left;
+}
+
+// Store a stage result: eta rounded to nearest, or, for a cell set dry,
+// eta = -h rounded upward so that eta + h >= 0.
+__device__ __forceinline__ CellF store_state(double h, double eta, double hu, double hv, bool dry) {
+    CellF o;
+    o.h = h;
+    o.eta = dry ? __double2float_ru(-h) : float(eta);
+    if (double(o.eta) + h < 0.0) o.eta = __double2float_ru(dry ? -h : eta);
+    o.hu = float(hu);
+    o.hv = float(hv);
+    o.pad = 0.0f;
+    return o;
+}
+
+__device__ __forceinline__ double cfl_ratio_f32(const CellF& q, double area, double perim, double g,
+                                                double thr) {
+    const double H = double(q.eta) + q.h;
+    return cfl_ratio(H, double(q.hu), double(q.hv), area, perim, g, thr);
+}
+
+__device__ __forceinline__ void lds_store_face_f32(double* ld, float* lf, int stride, int slot,
+                                                   const FaceF& f) {
+    ld[0 * stride + slot] = f.h;
+    ld[1 * stride + slot] = f.H;
+    lf[0 * stride + slot] = f.eta;
+    lf[1 * stride + slot] = f.u;
+    lf[2 * stride + slot] = f.v;
+}
+
+__device__ __forceinline__ FaceF lds_load_face_f32(const double* ld, const float* lf, int stride,
+                                                   int slot) {
+    FaceF f;
+    f.h = ld[0 * stride + slot];
+    f.H = ld[1 * stride + slot];
+    f.eta = lf[0 * stride + slot];
+    f.u = lf[1 * stride + slot];
+    f.v = lf[2 * stride + slot];
+    return f;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void dt_init_f32_kernel(DevMesh m, const CellF* __restrict__ W,
+                                                             double g, double thr, Ctrl* c) {
+    const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    double r = __longlong_as_double(0x7FF0000000000000ll);
+    if (k < m.nc) r = cfl_ratio_f32(W[k], m.area[k], m.perim[k], g, thr);
+    block_min_atomic(r, c->rmin[0]);
+}
+
+// Same three phases as the FP64 stage kernel; LDS holds per face slot the
+// FP64 (h, H) and FP32 (eta, u, v) of the face state.
+template <int STAGE>
+__global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm,
+                                                           CellF* __restrict__ W,
+                                                           CellF* __restrict__ W1, StepParams p,
+                                                           Ctrl* c, int slot, int step,
+                                                           double* tlog, double* dtlog) {
+    extern __shared__ double lds[];
+    const int stride = 3 * kTile + tm.bmax;
+    double* ld = lds;
+    float* lf = reinterpret_cast<float*>(lds + 2 * stride);
+    double dt, tn;
+    const bool active = step_dt(c, slot, p, dt, tn);
+    if (!active) {
+        if (STAGE == 2) stage2_bookkeeping(c, slot, step, false, 0.0, 0.0, p.t_stop, tlog, dtlog);
+        return;
+    }
+    if (STAGE == 1 && blockIdx.x == 0 && threadIdx.x < kMinGroups)
+        c->rmin[slot ^ 1][threadIdx.x * kMinStride] = 0x7FF0000000000000ull;
+    const CellF* __restrict__ Ws = (STAGE == 1) ? W : W1;
+    const int64_t nc = m.nc;
+    const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
+    const int64_t c0 = int64_t(t) * kTile;
+    const int cnt = int(min(int64_t(kTile), nc - c0));
+    const int i = threadIdx.x;
+    const int64_t k = c0 + i;
+
+    bool second = false;
+    if (i < cnt) {
+        ReconF r;
+        recon_core_f32(m, Ws, k, p.thr, r);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            lds_store_face_f32(ld, lf, stride, j * kTile + i, recon_face_f32(r, j, p.thr));
+        second = r.second;
+    }
+    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
+    for (int b = i; b < nb; b += kBlock) {
+        const uint32_t item = tm.bitem[b0 + b];
+        const int64_t n = int64_t(item >> 2);
+        const int jn = int(item & 3u);
+        ReconF r;
+        recon_core_f32(m, Ws, n, p.thr, r);
+        const FaceF f = (jn == 0) ? recon_face_f32(r, 0, p.thr)
+                      : (jn == 1) ? recon_face_f32(r, 1, p.thr) : recon_face_f32(r, 2, p.thr);
+        lds_store_face_f32(ld, lf, stride, 3 * kTile + b, f);
+    }
+    __syncthreads();
+
+    unsigned long long clamp = 0;
+    double rr = __longlong_as_double(0x7FF0000000000000ll);
+    bool bad = false;
+    if (i < cnt) {
+        double fH[3], fh[3], fnx[3], fny[3], fl[3];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const uint16_t s = tm.nloc[j * nc + k];
+            const bool wall = (s == kNlocWall16);
+            const FaceF own = lds_load_face_f32(ld, lf, stride, j * kTile + i);
+            const FaceF other =
+                lds_load_face_f32(ld, lf, stride, wall ? j * kTile + i : int(s & 0x7FFFu));
+            fnx[j] = gf(m, 0, j, k);
+            fny[j] = gf(m, 1, j, k);
+            fl[j] = gf(m, 2, j, k);
+            fH[j] = own.H;
+            fh[j] = own.h;
+            double tt[3];
+            const bool left = face_term_f32(p.g, p.hg, own, other, wall, (s & 0x8000u) != 0,
+                                            fnx[j], fny[j], fl[j], tt);
+            if (left) {
+                a0 = a0 - tt[0]; a1 = a1 - tt[1]; a2 = a2 - tt[2];
+            } else {
+                a0 = a0 + tt[0]; a1 = a1 + tt[1]; a2 = a2 + tt[2];
+            }
+        }
+        if (second) {
+            const CellF q = Ws[k];
+            double c3[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) c3[j] = (fl[j] * ((double(q.eta) + q.h) + fH[j])) * (fh[j] - q.h);
+            const double sx = c3[0] * fnx[0] + c3[1] * fnx[1] + c3[2] * fnx[2];
+            const double sy = c3[0] * fny[0] + c3[1] * fny[1] + c3[2] * fny[2];
+            a1 = a1 + p.hg * sx;
+            a2 = a2 + p.hg * sy;
+        }
+        const double ar = m.area[k];
+        const double R0 = a0 / ar, R1 = a1 / ar, R2 = a2 / ar;
+        const CellF w = W[k];
+        double e, u, v;
+        if (STAGE == 1) {
+            e = double(w.eta) + dt * R0;
+            u = double(w.hu) + dt * R1;
+            v = double(w.hv) + dt * R2;
+        } else {
+            const CellF w1 = W1[k];
+            e = 0.5 * double(w.eta) + 0.5 * (double(w1.eta) + dt * R0);
+            u = 0.5 * double(w.hu) + 0.5 * (double(w1.hu) + dt * R1);
+            v = 0.5 * double(w.hv) + 0.5 * (double(w1.hv) + dt * R2);
+        }
+        const double Hn = e + w.h;
+        bool dry = false;
+        if (Hn < 0.0) { dry = true; clamp = 1; }
+        if (Hn < p.thr) { u = 0.0; v = 0.0; }
+        const CellF o = store_state(w.h, e, u, v, dry);
+        if (STAGE == 1) {
+            W1[k] = o;
+        } else {
+            W[k] = o;
+            bad = !isfinite(e) || !isfinite(u) || !isfinite(v);
+            rr = cfl_ratio_f32(o, ar, m.perim[k], p.g, p.thr);
+        }
+    }
+    if (STAGE == 2 && bad) {
+        atomicOr(&c->err, 1);
+        atomicMin(&c->err_step, step);
+    }
+    block_count_atomic(clamp, &c->clamps);
+    if (STAGE == 2) {
+        block_min_atomic(rr, c->rmin[slot ^ 1]);
+        stage2_bookkeeping(c, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
+    }
+}
+
+template __global__ void stage_f32_kernel<1>(DevMesh, TileMap, CellF*, CellF*, StepParams, Ctrl*,
+                                             int, int, double*, double*);
+template __global__ void stage_f32_kernel<2>(DevMesh, TileMap, CellF*, CellF*, StepParams, Ctrl*,
+                                             int, int, double*, double*);
+
+// Free surface at the gauge cells after step `step` (see gauge_kernel).
+__global__ void gauge_f32_kernel(const CellF* __restrict__ W, const int64_t* __restrict__ cells,
+                                 int ng, const Ctrl* c, int step, double* __restrict__ log) {
+    const int gi = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gi >= ng || c->steps_done <= step) return;
+    const CellF q = W[cells[gi]];
+    log[int64_t(step) * ng + gi] = (double(q.eta) + q.h) - q.h;
+}
+
+// Caller-order FP64 (H, HU, HV) into FP32 state records: eta = H - h rounded
+// to nearest (upward for a dry cell so that eta + h >= 0).
+__global__ void pack_state_f32_kernel(int64_t n, const int64_t* __restrict__ perm,
+                                      const double* __restrict__ H, const double* __restrict__ HU,
+                                      const double* __restrict__ HV, const double* __restrict__ h,
+                                      CellF* __restrict__ W, CellF* __restrict__ W1) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t k = perm[i];
+    const CellF q = store_state(h[i], H[k] - h[i], HU[k], HV[k], !(H[k] > 0.0));
+    W[i] = q;
+    W1[i] = q;
+}
+
+// FP32 state records into caller-order FP64 arrays, H = eta + h.
+__global__ void unpack_state_f32_kernel(int64_t n, const int64_t* __restrict__ perm,
+                                        const CellF* __restrict__ W, double* __restrict__ H,
+                                        double* __restrict__ HU, double* __restrict__ HV) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t k = perm[i];
+    const CellF q = W[i];
+    if (H) H[k] = double(q.eta) + q.h;
+    if (HU) HU[k] = double(q.hu);
+    if (HV) HV[k] = double(q.hv);
+}
+
+}  // namespace vsw

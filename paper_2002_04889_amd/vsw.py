@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "vsw.h")
 
 VSW_OK, VSW_EINVAL, VSW_EMESH, VSW_ESTATE, VSW_ENOMEM, VSW_EDEVICE, VSW_EUNSTABLE = \
     0, -1, -2, -3, -4, -5, -6
-VSW_FP64 = 0
+VSW_FP64, VSW_FP32 = 0, 1
 VSW_ORDER_HILBERT, VSW_ORDER_NONE, VSW_ORDER_RANDOM = 0, 1, 2
 VSW_KERNEL_FUSED, VSW_KERNEL_TWO_PASS = 0, 1
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM",
@@ -59,6 +59,8 @@ _SIGS = {
     "vsw_last_dt": (ctypes.c_int, [_vp, _dp]),
     "vsw_dt_history": (ctypes.c_int, [_vp, _i64, _dp, _lp]),
     "vsw_clamp_count": (ctypes.c_int, [_vp, _lp]),
+    "vsw_set_gauges": (ctypes.c_int, [_vp, ctypes.c_int32, _ip]),
+    "vsw_get_gauges": (ctypes.c_int, [_vp, _i64, _dp, _dp, _lp]),
     "vsw_set_stream": (ctypes.c_int, [_vp, _vp]),
     "vsw_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_set_kernel_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -187,6 +189,20 @@ def vsw_clamp_count(h):
     return n.value
 
 
+def vsw_set_gauges(h, cells):
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    return _check(lib().vsw_set_gauges(h, len(cells), cells.ctypes.data_as(_ip)))
+
+
+def vsw_get_gauges(h, ngauges):
+    n = ctypes.c_int64(0)
+    _check(lib().vsw_get_gauges(h, 0, None, None, ctypes.byref(n)))
+    eta = np.empty((n.value, ngauges))
+    t = np.empty(n.value)
+    _check(lib().vsw_get_gauges(h, n.value, _dptr(eta), _dptr(t), ctypes.byref(n)))
+    return t, eta
+
+
 def vsw_set_stream(h, stream_handle: int | None):
     return _check(lib().vsw_set_stream(h, stream_handle))
 
@@ -250,16 +266,16 @@ def vsw_version():
 # ---------------------------------------------------------------- wrapper
 
 def make_params(g=9.81, cfl=0.45, h_threshold=1e-3, dt_fixed=0.0,
-                ordering=VSW_ORDER_HILBERT, seed=0) -> VswParams:
-    return VswParams(g, cfl, h_threshold, dt_fixed, VSW_FP64, ordering, seed)
+                ordering=VSW_ORDER_HILBERT, seed=0, precision=VSW_FP64) -> VswParams:
+    return VswParams(g, cfl, h_threshold, dt_fixed, precision, ordering, seed)
 
 
 class Solver:
     """Owns one vsw_solver handle."""
 
     def __init__(self, g=9.81, cfl=0.45, h_threshold=1e-3, dt_fixed=0.0,
-                 ordering=VSW_ORDER_HILBERT, seed=0, device=0):
-        self.params = make_params(g, cfl, h_threshold, dt_fixed, ordering, seed)
+                 ordering=VSW_ORDER_HILBERT, seed=0, device=0, precision=VSW_FP64):
+        self.params = make_params(g, cfl, h_threshold, dt_fixed, ordering, seed, precision)
         self.h = vsw_create(self.params, device)
         self.nc = 0
 

@@ -250,3 +250,27 @@ def test_basin_1m_bench_configuration(orc):
         assert (H >= 0).all()
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("precision", [vsw.VSW_FP64, vsw.VSW_FP32])
+def test_gauges_record_each_step(orc, precision):
+    c = W.thacker_case(23)
+    cells = np.array([5, 100, 400, 967], dtype=np.int32)
+    s = vsw.Solver.for_case(c, precision=precision)
+    try:
+        vsw.vsw_set_gauges(s.h, cells)
+        s.step(37)
+        t1, e1 = vsw.vsw_get_gauges(s.h, len(cells))
+        rc, done, t = s.step(23)
+        t2, e2 = vsw.vsw_get_gauges(s.h, len(cells))
+        H, HU, HV, tt = s.state()
+        assert e1.shape == (37, 4) and e2.shape == (23, 4)
+        assert t2[-1] == tt and np.all(np.diff(np.concatenate([t1, t2])) > 0)
+        assert np.array_equal(e2[-1], H[cells] - c.h[cells])
+        with pytest.raises(vsw.VswError, match="EINVAL"):
+            vsw.vsw_set_gauges(s.h, np.array([c.nc], dtype=np.int32))
+    finally:
+        s.close()
+    if precision == vsw.VSW_FP64:
+        o = orc_run(orc, c, 60)
+        assert np.array_equal(e2[-1], o["H"][cells] - c.h[cells])
