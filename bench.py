@@ -1,11 +1,14 @@
 """Benchmark: SSP-RK(2,2) steps of the shallow-water finite-volume scheme on
-the 1M-triangle synthetic ocean basin, FP64, one MI355X.
+the 1M-triangle synthetic ocean basin, FP64, one MI355X (default), or on the
+12M-triangle coastal mesh in FP32 (--workload coastal).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                [--workload basin|coastal]
 
 Prints one JSON line.  value = cell-updates/s (one cell advanced by one full
 two-stage step) over the timed region, with the mesh and the state already
-resident in HBM.  The roofline entry uses the dominant kernel's average
+resident in HBM; the other legs (FP32 on the basin; FP64 and random cell
+order on the coastal mesh) are reported beside it.  The roofline entry uses the dominant kernel's average
 launch duration from HIP events recorded on the solver's stream around each
 launch, in a second pass over the same number of steps.  cpu_baseline times
 the FP64 oracle (single thread) on a bounded sample of the same workload.
@@ -54,7 +57,7 @@ def cpu_baseline(case, steps):
     el = time.perf_counter() - t0
     return {"value": case.nc * r["steps"] / el, "unit": "cell-updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{r['steps']} steps of the same {case.nc}-cell basin from its initial "
+            "sample": f"{r['steps']} steps of the same {case.nc}-cell mesh from its initial "
                       f"state, single-threaded C oracle (gcc -O2), {el:.1f} s"}
 
 
@@ -93,15 +96,51 @@ def time_steps(torch, stream, s, steps):
     return ev0.elapsed_time(ev1)
 
 
+def run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, precision, ordering, steps, warmup,
+            bytes1, bytes2, label):
+    """Warm up and time `steps` steps of one solver configuration; returns
+    (leg summary dict, solver handle still open)."""
+    s = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold, device=0,
+                   precision=precision, ordering=ordering)
+    vsw.vsw_set_stream(s.h, stream.cuda_stream)
+    t0 = time.perf_counter()
+    s.upload_mesh(case.vx, case.vy, case.tri, case.h)
+    log(f"[bench] {label}: mesh uploaded in {time.perf_counter() - t0:.1f} s")
+    nc, ne, nw = vsw.vsw_mesh_info(s.h)
+    vsw.vsw_set_state_device(s.h, dH.data_ptr(), dHU.data_ptr(), dHV.data_ptr(), 0.0)
+    rc, done, t = s.step(warmup)
+    log(f"[bench] {label}: warmup {done} steps, t={t:.3f} s")
+    w0 = time.perf_counter()
+    ms = time_steps(torch, stream, s, steps)
+    wall = time.perf_counter() - w0
+    value = nc * steps / (ms / 1e3)
+    log(f"[bench] {label}: timed {steps} steps: {ms:.1f} ms (host wall {wall * 1e3:.1f} ms), "
+        f"{value:.3e} cell-updates/s")
+    leg = {"value": value, "unit": "cell-updates/s", "ms_per_step": ms / steps,
+           "roofline": kernel_roofline(vsw, s, steps, nc, bytes1, bytes2),
+           "mesh": {"cells": nc, "edges": ne, "walls": nw}}
+    return leg, s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 2000 basin, 1000 coastal)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before timing (default 100 basin, 20 coastal)")
+    ap.add_argument("--workload", choices=["basin", "coastal"], default="basin",
+                    help="basin: 1M-triangle ocean basin, FP64 (and the FP32 leg); coastal: "
+                         "12M-triangle coastal mesh, FP32 and FP64 in Hilbert and random "
+                         "cell order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the mixed-precision leg")
-    ap.add_argument("--cpu-steps", type=int, default=40)
-    ap.add_argument("--scale", type=float, default=1.0, help="mesh size multiplier (1 = 1M cells)")
+    ap.add_argument("--no-random", action="store_true",
+                    help="coastal: skip the random-order legs")
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps for cpu_baseline (default 40 basin, 3 coastal)")
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="mesh size multiplier (1 = the named workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 512 MiB three times (reference "
                          "kernel for scaling HBM byte counters)")
@@ -110,8 +149,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "sharding of this solver is a design note, not a built path.", file=sys.stderr)
         sys.exit(2)
+    coastal = args.workload == "coastal"
+    steps = args.steps if args.steps is not None else (1000 if coastal else 2000)
+    warmup = args.warmup if args.warmup is not None else (20 if coastal else 100)
+    cpu_steps = args.cpu_steps if args.cpu_steps is not None else (3 if coastal else 40)
 
-    import numpy as np
     import torch
 
     from paper_2002_04889_amd import vsw
@@ -120,59 +162,62 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    case = W.basin_case(scale=args.scale)
+    if coastal:
+        case = W.coastal_case(scale=args.scale, log=lambda m: log("[bench] " + m))
+        desc = (f"large graded coastal mesh 1000x1000 km, {case.nc} triangles (50 m-5 km), "
+                f"fractal coastline, {case.info['dry_fraction'] * 100:.1f}% dry, elliptical "
+                "uplift 150x60 km 3 m, walls, CFL 0.45")
+    else:
+        case = W.basin_case(scale=args.scale)
+        desc = (f"synthetic ocean basin 500x500 km, {case.nc} triangles "
+                "(graded 250 m-2 km), Gaussian hump, walls, CFL 0.45")
     log(f"[bench] workload {case.name}: {case.nc} cells, generated in "
         f"{time.perf_counter() - t0:.1f} s")
     stream = torch.cuda.Stream(device=dev)
-    s = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold, device=0)
-    vsw.vsw_set_stream(s.h, stream.cuda_stream)
-    s.upload_mesh(case.vx, case.vy, case.tri, case.h)
-    nc, ne, nw = vsw.vsw_mesh_info(s.h)
     dH = torch.tensor(case.H, device=dev)
     dHU = torch.tensor(case.HU, device=dev)
     dHV = torch.tensor(case.HV, device=dev)
     torch.cuda.synchronize()
-    vsw.vsw_set_state_device(s.h, dH.data_ptr(), dHU.data_ptr(), dHV.data_ptr(), 0.0)
 
-    # warmup
-    rc, done, t = s.step(args.warmup)
-    log(f"[bench] warmup {done} steps, t={t:.3f} s")
-
-    # timed region: K steps, state resident in HBM
-    w0 = time.perf_counter()
-    ms = time_steps(torch, stream, s, args.steps)
-    wall = time.perf_counter() - w0
-    value = nc * args.steps / (ms / 1e3)
-    log(f"[bench] timed {args.steps} steps: {ms:.1f} ms (host wall {wall * 1e3:.1f} ms), "
-        f"{value:.3e} cell-updates/s")
-
-    roofline = kernel_roofline(vsw, s, args.steps, nc, ALG_BYTES_STAGE1, ALG_BYTES_STAGE2)
-
-    out = {"metric": "cell-updates/s", "value": value, "unit": "cell-updates/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"synthetic ocean basin 500x500 km, {nc} triangles "
-                                  f"(graded 250 m-2 km), Gaussian hump, walls, CFL 0.45",
-                      "cells": nc, "edges": ne, "walls": nw, "precision": "fp64",
-                      "ordering": "hilbert", "global_batch": nc, "parallelism": "single-gpu"},
-           "roofline": roofline}
+    legs = [("fp64", vsw.VSW_FP64, vsw.VSW_ORDER_HILBERT)]
     if not args.no_fp32:
-        # the same mesh and initial state with the mixed-precision solver
-        s32 = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold, device=0,
-                         precision=vsw.VSW_FP32)
-        vsw.vsw_set_stream(s32.h, stream.cuda_stream)
-        s32.upload_mesh(case.vx, case.vy, case.tri, case.h)
-        vsw.vsw_set_state_device(s32.h, dH.data_ptr(), dHU.data_ptr(), dHV.data_ptr(), 0.0)
-        s32.step(args.warmup)
-        ms32 = time_steps(torch, stream, s32, args.steps)
-        v32 = nc * args.steps / (ms32 / 1e3)
-        log(f"[bench] fp32: {args.steps} steps {ms32:.1f} ms, {v32:.3e} cell-updates/s")
-        out["fp32"] = {"value": v32, "unit": "cell-updates/s", "ms_per_step": ms32 / args.steps,
-                       "dtype": "f32 state and fluxes, f64 depths/pressure/accumulation",
-                       "roofline": kernel_roofline(vsw, s32, args.steps, nc,
-                                                   ALG_BYTES_STAGE1_F32, ALG_BYTES_STAGE2_F32)}
-        s32.close()
+        legs.append(("fp32", vsw.VSW_FP32, vsw.VSW_ORDER_HILBERT))
+    if coastal and not args.no_random:
+        legs.append(("fp64_random_order", vsw.VSW_FP64, vsw.VSW_ORDER_RANDOM))
+        if not args.no_fp32:
+            legs.append(("fp32_random_order", vsw.VSW_FP32, vsw.VSW_ORDER_RANDOM))
+    res = {}
+    for name, prec, order in legs:
+        b1, b2 = ((ALG_BYTES_STAGE1, ALG_BYTES_STAGE2) if prec == vsw.VSW_FP64
+                  else (ALG_BYTES_STAGE1_F32, ALG_BYTES_STAGE2_F32))
+        leg, s = run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, prec, order, steps,
+                         warmup, b1, b2, name)
+        s.close()
+        leg["dtype"] = ("f64" if prec == vsw.VSW_FP64 else
+                        "f32 state and fluxes, f64 depths/pressure/accumulation")
+        leg["ordering"] = "hilbert" if order == vsw.VSW_ORDER_HILBERT else "random"
+        res[name] = leg
+        torch.cuda.synchronize()
+
+    # The basin is quoted in FP64 (the plain method), the coastal mesh in FP32.
+    main_leg = "fp32" if coastal and "fp32" in res else "fp64"
+    top = res.pop(main_leg)
+    mesh = top.pop("mesh")
+    out = {"metric": "cell-updates/s", "value": top["value"], "unit": "cell-updates/s",
+           "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": top["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if main_leg == "fp32" else "f64",
+           "data": "synthetic",
+           "config": {"workload": desc, "cells": mesh["cells"], "edges": mesh["edges"],
+                      "walls": mesh["walls"],
+                      "precision": "fp32 state, fp64 accumulation" if main_leg == "fp32"
+                      else "fp64",
+                      "ordering": "hilbert", "global_batch": mesh["cells"],
+                      "parallelism": "single-gpu"},
+           "roofline": top["roofline"]}
+    for name, leg in res.items():
+        leg.pop("mesh")
+        out[name] = leg
     if args.copy_calibration:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -183,9 +228,8 @@ def main():
         out["copy_calibration"] = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
                                    "launches": 3}
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
-    s.close()
+        log(f"[bench] cpu baseline: oracle, {cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(case, cpu_steps)
     print(json.dumps(out), flush=True)
 
 

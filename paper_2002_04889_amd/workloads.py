@@ -17,6 +17,9 @@ Cases:
   real-case workload of Section 5 (the Rockall Bank bathymetry is not
   available): 4000 m abyss, linear shelf, dry land strip, Gaussian seamounts,
   2 m Gaussian hump, mesh graded 250 m (coast) to 2 km.
+* ``coastal_case``   -- 1000 x 1000 km graded coastal mesh (12M triangles,
+  50 m to 5 km, fractal coastline, 15% dry cells, elliptical uplift): the
+  workload large enough that its state does not fit in the on-chip caches.
 * ``channel_case``   -- long flat channel with a dam over a dry bed, for the
   Ritter closed-form solution.
 
@@ -338,3 +341,188 @@ def tiny_mesh(kind: str = "square2"):
     else:
         raise ValueError(kind)
     return vx, vy, tri
+
+
+# ---------------------------------------------------------------- coastal
+
+COAST_L = 1000e3
+COAST_X0 = 800e3
+COAST_AMP = 40e3
+COAST_SHELF = 250e3
+
+
+def fbm_1d(t, rng, hurst=0.6, octaves=10):
+    """Seeded fractional-Brownian-like noise on t in [0, 1]: value noise with
+    cosine interpolation, octave o on 2^o + 1 knots with amplitude 2^(-hurst o),
+    scaled so that max |f| = 1 over the knots of the finest octave."""
+    t = np.asarray(t, dtype=np.float64)
+    f = np.zeros_like(t)
+    for o in range(octaves):
+        n = 2 ** o
+        knots = rng.uniform(-1.0, 1.0, n + 1)
+        u = t * n
+        i = np.clip(np.floor(u).astype(np.int64), 0, n - 1)
+        a = u - i
+        w = 0.5 - 0.5 * np.cos(math.pi * a)
+        f += 2.0 ** (-hurst * o) * ((1.0 - w) * knots[i] + w * knots[i + 1])
+    return f
+
+
+def value_noise_2d(x, y, rng, lx, octaves=8, base=8, hurst=0.6):
+    """Seeded 2D value noise (bilinear, cosine-smoothed) summed over octaves,
+    normalised by the sum of the octave amplitudes to lie in [-1, 1]."""
+    x = np.asarray(x, dtype=np.float64) / lx
+    y = np.asarray(y, dtype=np.float64) / lx
+    f = np.zeros_like(x)
+    tot = 0.0
+    for o in range(octaves):
+        n = base * 2 ** o
+        g = rng.uniform(-1.0, 1.0, (n + 1, n + 1))
+        u, v = np.clip(x * n, 0, n - 1e-9), np.clip(y * n, 0, n - 1e-9)
+        i, j = u.astype(np.int64), v.astype(np.int64)
+        a = 0.5 - 0.5 * np.cos(math.pi * (u - i))
+        b = 0.5 - 0.5 * np.cos(math.pi * (v - j))
+        amp = 2.0 ** (-hurst * o)
+        f += amp * ((1 - a) * (1 - b) * g[i, j] + a * (1 - b) * g[i + 1, j]
+                    + (1 - a) * b * g[i, j + 1] + a * b * g[i + 1, j + 1])
+        tot += amp
+    return f / tot
+
+
+def _quadtree_points(L, size_fn, s0, max_level, rng, jitter=0.3):
+    """Points graded by a size field on [0, L]^2 from a quadtree of square
+    blocks: a block of side s is split while the target size at its centre is
+    below s / sqrt(2) (down to max_level), and each leaf holds one point at its
+    centre jittered by at most jitter * s.  Leaves on the domain boundary add
+    their corners on that boundary, so the hull is the exact square."""
+    n0 = int(round(L / s0))
+    s = L / n0
+    ix, iy = np.meshgrid(np.arange(n0), np.arange(n0), indexing="ij")
+    bx = (ix.ravel() + 0.5) * s
+    by = (iy.ravel() + 0.5) * s
+    px, py, ex, ey = [], [], [], []
+    for lev in range(max_level + 1):
+        want = size_fn(bx, by)
+        split = want < s / math.sqrt(2.0) if lev < max_level else np.zeros(len(bx), bool)
+        lx, ly = bx[~split], by[~split]
+        px.append(lx + rng.uniform(-jitter, jitter, len(lx)) * s)
+        py.append(ly + rng.uniform(-jitter, jitter, len(ly)) * s)
+        h = 0.5 * s
+        for side in (0, 1):
+            c = (lx, ly)[side]
+            o = (ly, lx)[side]
+            for edge in (0.0, L):
+                on = np.abs(c - edge) < h * 1.0001
+                for sgn in (-1.0, 1.0):
+                    e_c = np.full(int(on.sum()), edge)
+                    e_o = o[on] + sgn * h
+                    if side == 0:
+                        ex.append(e_c); ey.append(e_o)
+                    else:
+                        ex.append(e_o); ey.append(e_c)
+        sx, sy = bx[split], by[split]
+        q = 0.25 * s
+        bx = np.concatenate([sx - q, sx + q, sx - q, sx + q])
+        by = np.concatenate([sy - q, sy - q, sy + q, sy + q])
+        s *= 0.5
+        if len(bx) == 0:
+            break
+    bxy = np.unique(np.round(np.stack([np.concatenate(ex), np.concatenate(ey)], 1), 3), axis=0)
+    return (np.concatenate(px + [bxy[:, 0]]), np.concatenate(py + [bxy[:, 1]]))
+
+
+# Grading slopes (seaward, landward) tuned so the default coastal mesh has
+# 12M triangles within 5% and 15% of them dry at t = 0.
+COAST_K_SEA = 0.00455
+COAST_K_LAND = 0.0261
+
+
+def coastal_case(k_sea: float = COAST_K_SEA, k_land: float = COAST_K_LAND, k: int = 2,
+                 smin: float = 50.0, smax: float = 5000.0, scale: float = 1.0,
+                 uplift: float = 3.0, cfl: float = 0.45, h_threshold: float = 1e-3,
+                 ordering_seed=None, log=None) -> Case:
+    """Large graded coastal mesh on 1000 x 1000 km (see _coastal_base).
+
+    ``ordering_seed`` shuffles the triangles with a seeded permutation (the
+    random-ordering variant of the same mesh).  If the environment variable
+    VSW_CASE_CACHE names a directory, the generated mesh and state are kept
+    there as .npz and reused (generation of the 12M-cell mesh takes minutes).
+    ``log`` (a print-like callable) receives progress lines."""
+    import os
+
+    key = f"coastal_k{k}_{k_sea:g}_{k_land:g}_{smin:g}_{smax:g}_{scale:g}_{uplift:g}"
+    cache = os.environ.get("VSW_CASE_CACHE")
+    path = os.path.join(cache, key + ".npz") if cache else None
+    if path and os.path.exists(path):
+        z = np.load(path)
+        vx, vy, tri, h, H = z["vx"], z["vy"], z["tri"], z["h"], z["H"]
+    else:
+        vx, vy, tri, h, H = _coastal_base(k_sea, k_land, k, smin, smax, scale, uplift,
+                                          log or (lambda *a: None))
+        if path:
+            os.makedirs(cache, exist_ok=True)
+            np.savez(path + ".tmp.npz", vx=vx, vy=vy, tri=tri, h=h, H=H)
+            os.replace(path + ".tmp.npz", path)
+    if ordering_seed is not None:
+        p = np.random.default_rng(ordering_seed).permutation(len(tri))
+        tri, h, H = np.ascontiguousarray(tri[p]), h[p], H[p]
+    return Case(name=f"coastal{len(tri)}", vx=vx, vy=vy, tri=tri, h=h, H=H,
+                HU=np.zeros_like(H), HV=np.zeros_like(H), cfl=cfl, h_threshold=h_threshold,
+                info={"k_sea": k_sea, "k_land": k_land, "scale": scale, "seed": SEED_BASE + k,
+                      "dry_fraction": float(np.mean(H < h_threshold)),
+                      "ordering_seed": ordering_seed})
+
+
+def _coastal_base(k_sea, k_land, k, smin, smax, scale, uplift, log):
+    """Large graded coastal mesh on 1000 x 1000 km (the HBM-roofline workload).
+
+    Coastline x_c(y) = 800 km + 40 km f(y) with f seeded fractal noise (Hurst
+    0.6, 10 octaves).  Bed: 4000 m abyss, linear shelf over the 250 km before
+    the coast, land rising 2 m/km beyond it, plus +-20 m of 2D fractal bed
+    noise within 15 km of the coast.  Mesh size min(5 km, 50 m + k d) with d
+    the distance to the coastline (k_sea seaward, k_land landward; ``scale``
+    multiplies both sizes).  Initial free surface: a cos^2-tapered elliptical
+    uplift with semi-axes 30 km (x) and 75 km (y), 3 m peak, centre (650, 500)
+    km; at rest.  Returns (vx, vy, tri, h, H)."""
+    from scipy.spatial import cKDTree
+
+    rm, rb, ri = streams(k)
+    ycs = np.linspace(0.0, 1.0, 40001)
+    xcs = COAST_X0 + COAST_AMP * fbm_1d(ycs, rm)
+    ycs = ycs * COAST_L
+    tree = cKDTree(np.stack([xcs, ycs], 1))
+    coarse = cKDTree(np.stack([xcs[::40], ycs[::40]], 1))   # 1 km samples
+
+    def coast_x(y):
+        return np.interp(y, ycs, xcs)
+
+    def coast_dist(x, y):
+        """Distance to the coastline: 25 m samples within 25 km of it, 1 km
+        samples (error below 1 km) farther out."""
+        q = np.stack([x, y], 1)
+        d, _ = coarse.query(q, workers=-1)
+        near = d < 25e3
+        dn, _ = tree.query(q[near], workers=-1, distance_upper_bound=26e3)
+        d[near] = np.minimum(d[near], dn)
+        return d
+
+    def size(x, y):
+        d = coast_dist(x, y)
+        kk = np.where(x < coast_x(y), k_sea, k_land)
+        return np.minimum(smax * scale, (smin + kk * d) * scale)
+
+    px, py = _quadtree_points(COAST_L, size, smax * scale, 16, rm)
+    log(f"coastal mesh: {len(px)} points, triangulating")
+    vx, vy, tri = _delaunay(px, py)
+    log(f"coastal mesh: {len(tri)} triangles, bathymetry")
+    cx = (vx[tri[:, 0]] + vx[tri[:, 1]] + vx[tri[:, 2]]) / 3.0
+    cy = (vy[tri[:, 0]] + vy[tri[:, 1]] + vy[tri[:, 2]]) / 3.0
+    xi = coast_x(cy) - cx                       # > 0 at sea
+    h = np.where(xi > 0, 4000.0 * np.minimum(1.0, xi / COAST_SHELF), 2e-3 * xi)
+    d = coast_dist(cx, cy)
+    band = np.clip(1.0 - d / 15e3, 0.0, 1.0)
+    h = h - 20.0 * band * value_noise_2d(cx, cy, rb, COAST_L)
+    rho = np.sqrt(((cx - 650e3) / 30e3) ** 2 + ((cy - 500e3) / 75e3) ** 2)
+    eta0 = np.where(rho < 1.0, uplift * np.cos(0.5 * math.pi * np.minimum(rho, 1.0)) ** 2, 0.0)
+    H = np.maximum(0.0, eta0 + h)
+    return vx, vy, tri, h, H

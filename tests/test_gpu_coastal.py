@@ -1,0 +1,120 @@
+"""The large graded coastal workload (fractal coastline, 15% dry cells at
+t = 0, elliptical uplift): Hilbert against random cell order, the FP64 kernel
+against the oracle, the FP32 state against FP64.
+
+By default the recipe runs with every mesh size multiplied by 4 (about 750k
+triangles, generated in about 15 s).  With VSW_FULL_SIZE=1 the tests use the
+full 12M-triangle mesh; generating it takes about three minutes of CPU, and
+VSW_CASE_CACHE=<dir> keeps it on disk for the next process.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2002_04889_amd import vsw
+from paper_2002_04889_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+ETA_TOL = 1e-4  # m
+FULL = os.environ.get("VSW_FULL_SIZE") == "1"
+SCALE = 1.0 if FULL else 4.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def coast():
+    c = W.coastal_case(scale=SCALE, log=say)
+    say(f"coastal scale {SCALE}: {c.nc} cells, {c.info['dry_fraction'] * 100:.1f}% dry")
+    return c
+
+
+def gpu_state(case, n, precision=vsw.VSW_FP64, ordering=vsw.VSW_ORDER_HILBERT, t_stop=math.inf):
+    s = vsw.Solver.for_case(case, precision=precision, ordering=ordering)
+    try:
+        H0 = s.state()[0]
+        rc, done, t = s.step(n, t_stop, check=False)
+        H, HU, HV, t = s.state()
+        return {"H": H, "HU": HU, "HV": HV, "t": t, "steps": done, "rc": rc, "H0": H0,
+                "dts": vsw.vsw_dt_history(s.h), "clamps": vsw.vsw_clamp_count(s.h)}
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("precision", [vsw.VSW_FP64, vsw.VSW_FP32], ids=["fp64", "fp32"])
+def test_coastal_hilbert_and_random_order_bitwise(coast, precision):
+    """Canonical face orientation makes every result independent of the cell
+    numbering: the Hilbert-ordered and randomly ordered runs agree bit for
+    bit (and with the caller's own order)."""
+    n = 100
+    a = gpu_state(coast, n, precision, vsw.VSW_ORDER_HILBERT)
+    b = gpu_state(coast, n, precision, vsw.VSW_ORDER_RANDOM)
+    c = gpu_state(coast, n, precision, vsw.VSW_ORDER_NONE)
+    say(f"precision {precision}: {n} steps, t = {a['t']:.3f} s, clamps {a['clamps']}")
+    assert a["rc"] == 0 and a["steps"] == n
+    for other in (b, c):
+        assert other["steps"] == n and other["t"] == a["t"]
+        assert np.array_equal(other["dts"], a["dts"])
+        for k in ("H", "HU", "HV"):
+            assert np.array_equal(other[k], a[k]), k
+
+
+def test_coastal_against_oracle(coast, orc):
+    """Full-field parity with the FP64 oracle after a few steps (3 at full
+    size, where the oracle needs about 5 s per step; 10 otherwise)."""
+    n = 3 if FULL else 10
+    g = gpu_state(coast, n)
+    m = orc.Mesh.from_case(coast)
+    o = m.run(orc.params(g=coast.g, cfl=coast.cfl, h_threshold=coast.h_threshold),
+              coast.H, coast.HU, coast.HV, 0.0, n, check=False)
+    assert g["steps"] == o["steps"] == n
+    for k in ("H", "HU", "HV"):
+        scale = max(np.abs(o[k]).max(), 1e-300)
+        diff = np.abs(g[k] - o[k]).max()
+        say(f"{k}: maxdiff {diff:.3e} rel {diff / scale:.3e} bitwise "
+            f"{np.mean(g[k] == o[k]) * 100:.2f}%")
+        assert diff <= TOL * scale
+    assert np.abs(g["dts"] - o["dts"]).max() <= TOL * o["dts"].max()
+    assert g["clamps"] == o["clamps"]
+
+
+def test_coastal_fp32_1000_steps(coast):
+    """The workload's run (1000 steps): FP32 state against the FP64 kernel at
+    the same end time, with the FP64 scheme's response to FP32-sized input
+    noise as the cellwise allowance; mass conserved in both.  The FP32
+    solver's mass is taken from its own initial state: a dry cell holds
+    eta = -h rounded up to FP32, so its depth reads back as a few ulp of h
+    (a fixed offset of about 6e-10 of the total here, not a drift)."""
+    d = gpu_state(coast, 1000)
+    g = gpu_state(coast, 4000, vsw.VSW_FP32, t_stop=d["t"])
+    rng = np.random.default_rng(0)
+    noisy = coast.copy()
+    eta = coast.H - coast.h
+    eta2 = eta * (1 + 1e-7 * rng.normal(size=coast.nc)) + 1e-9 * rng.normal(size=coast.nc)
+    noisy.H = np.where(coast.H > 0, np.maximum(0.0, eta2 + coast.h), coast.H)
+    dn = gpu_state(noisy, 4000, t_stop=d["t"])
+    assert d["rc"] == 0 and g["rc"] == 0 and g["t"] == d["t"]
+    d32 = np.abs(g["H"] - d["H"])
+    dnn = np.abs(dn["H"] - d["H"])
+    frac = np.mean(d32 <= ETA_TOL)
+    say(f"t = {d['t']:.2f} s: fp64 {d['steps']} steps, fp32 {g['steps']} steps; max "
+        f"|eta32 - eta64| {d32.max():.3e} m, FP64 response to FP32-sized noise "
+        f"{dnn.max():.3e} m; within 1e-4 m: {frac * 100:.4f}%")
+    assert np.all(d32 <= ETA_TOL + 2.0 * dnn)
+    assert frac >= 0.999
+    x0, y0 = coast.vx[coast.tri], coast.vy[coast.tri]
+    area = 0.5 * np.abs((x0[:, 1] - x0[:, 0]) * (y0[:, 2] - y0[:, 0])
+                        - (x0[:, 2] - x0[:, 0]) * (y0[:, 1] - y0[:, 0]))
+    for r in (d, g):
+        m0, m1 = (area * r["H0"]).sum(), (area * r["H"]).sum()
+        say(f"mass rel change {(m1 - m0) / m0:.3e} (initial offset of the stored state "
+            f"{((area * r['H0']).sum() - (area * coast.H).sum()) / m0:.3e})")
+        assert abs(m1 - m0) <= 1e-12 * m0

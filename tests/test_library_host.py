@@ -23,10 +23,11 @@ def test_binding_covers_header():
     assert names <= set(vsw._SIGS), names - set(vsw._SIGS)
 
 
-@pytest.mark.parametrize("case", ["thacker", "basin", "channel"])
+@pytest.mark.parametrize("case", ["thacker", "basin", "channel", "coastal"])
 def test_host_mesh_matches_oracle_bitwise(orc, case):
     c = {"thacker": lambda: W.thacker_case(45),
          "basin": lambda: W.basin_case(scale=16),
+         "coastal": lambda: W.coastal_case(scale=16),
          "channel": lambda: W.channel_case(n_len=101)}[case]()
     g = vsw.vsw_prepare_mesh_host(c.vx, c.vy, c.tri, c.h)
     m = orc.Mesh.from_case(c)
