@@ -83,6 +83,28 @@ def kernel_roofline(vsw, s, steps, nc, bytes1, bytes2):
             "avg_launch_us": round(dur_ms * 1e3, 2)}
 
 
+def measured_traffic(workload, ordering, precision_name, kernel, cells):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (profiles/traffic_<workload>_<ordering>.json: FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy kernel), or None when there is none or the kernel
+    sources have changed since the counters were taken."""
+    from paper_2002_04889_amd import profsum
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{ordering}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("digest") != profsum.source_digest():
+        return None
+    stage = kernel[5]  # "stage1_kernel" -> "1"
+    name = (f"vsw::stage_kernel<{stage}>" if precision_name == "fp64"
+            else f"vsw::stage_f32_kernel<{stage}>")
+    k = d["kernels"].get(name)
+    if not k or d.get("cells") not in (None, cells):
+        return None
+    return round(k["fetch_bytes"] + k["write_bytes"])
+
+
 def time_steps(torch, stream, s, steps):
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -137,6 +159,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-random", action="store_true",
                     help="coastal: skip the random-order legs")
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated subset of fp64, fp32, fp64_random_order, "
+                         "fp32_random_order (for profiling one configuration at a time)")
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps for cpu_baseline (default 40 basin, 3 coastal)")
     ap.add_argument("--scale", type=float, default=1.0,
@@ -186,6 +211,9 @@ def main():
         legs.append(("fp64_random_order", vsw.VSW_FP64, vsw.VSW_ORDER_RANDOM))
         if not args.no_fp32:
             legs.append(("fp32_random_order", vsw.VSW_FP32, vsw.VSW_ORDER_RANDOM))
+    if args.legs:
+        keep = args.legs.split(",")
+        legs = [x for x in legs if x[0] in keep]
     res = {}
     for name, prec, order in legs:
         b1, b2 = ((ALG_BYTES_STAGE1, ALG_BYTES_STAGE2) if prec == vsw.VSW_FP64
@@ -196,23 +224,32 @@ def main():
         leg["dtype"] = ("f64" if prec == vsw.VSW_FP64 else
                         "f32 state and fluxes, f64 depths/pressure/accumulation")
         leg["ordering"] = "hilbert" if order == vsw.VSW_ORDER_HILBERT else "random"
+        rf = leg["roofline"]
+        tr = measured_traffic(args.workload + ("" if args.scale == 1.0 else f"x{args.scale:g}"),
+                              leg["ordering"], name[:4], rf["kernel"], leg["mesh"]["cells"])
+        rf["traffic"] = tr
+        if tr is not None:
+            rf["traffic_bytes_per_cell"] = round(tr / leg["mesh"]["cells"], 1)
+            rf["traffic_GBps"] = round(tr / (rf["avg_launch_us"] * 1e-6) / 1e9, 1)
         res[name] = leg
         torch.cuda.synchronize()
 
     # The basin is quoted in FP64 (the plain method), the coastal mesh in FP32.
     main_leg = "fp32" if coastal and "fp32" in res else "fp64"
+    if main_leg not in res:
+        main_leg = next(iter(res))
     top = res.pop(main_leg)
     mesh = top.pop("mesh")
     out = {"metric": "cell-updates/s", "value": top["value"], "unit": "cell-updates/s",
            "n_gpus": 1, "steps": steps, "warmup": warmup,
            "ms_per_step": top["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32" if main_leg == "fp32" else "f64",
+           "vs_baseline": None, "dtype": "f64" if main_leg.startswith("fp64") else "f32",
            "data": "synthetic",
            "config": {"workload": desc, "cells": mesh["cells"], "edges": mesh["edges"],
                       "walls": mesh["walls"],
-                      "precision": "fp32 state, fp64 accumulation" if main_leg == "fp32"
-                      else "fp64",
-                      "ordering": "hilbert", "global_batch": mesh["cells"],
+                      "precision": "fp64" if main_leg.startswith("fp64")
+                      else "fp32 state, fp64 accumulation",
+                      "ordering": top["ordering"], "global_batch": mesh["cells"],
                       "parallelism": "single-gpu"},
            "roofline": top["roofline"]}
     for name, leg in res.items():

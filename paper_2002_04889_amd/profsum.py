@@ -7,13 +7,34 @@ python -m paper_2002_04889_amd.profsum --pmc DIR/run_counter_collection.csv \
 --copy-bytes: bytes one plain copy kernel moved (read and written); the
 counter value that the copy kernel (rocclr copyBuffer) reports for its
 largest dispatch gives the scale factor from counter units to bytes.
+
+--traffic-json OUT --workload NAME: also write the scaled FETCH_SIZE and
+WRITE_SIZE per launch of every kernel, in bytes, with a digest of the
+kernel sources; the benchmark reports these as the measured HBM traffic
+only while the digest matches the sources it runs.
 """
 from __future__ import annotations
 
 import argparse
 import collections
 import csv
+import glob
+import hashlib
+import json
+import os
 import re
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def source_digest() -> str:
+    """sha256 over the kernel and host sources of the library."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def short(name: str) -> str:
@@ -31,18 +52,45 @@ def stats(path: str) -> str:
     return "\n".join(out)
 
 
-def pmc(path: str, copy_bytes: float | None) -> str:
+def _agg(path):
     rows = list(csv.DictReader(open(path)))
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     for r in rows:
         agg[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    counters = sorted({c for v in agg.values() for c in v})
+    return agg
+
+
+def _scales(agg, counters, copy_bytes):
     scale = {}
     if copy_bytes:
         cp = [k for k in agg if "copyBuffer" in k]
         for c in counters:
             if cp and c in ("FETCH_SIZE", "WRITE_SIZE") and agg[cp[0]][c]:
                 scale[c] = copy_bytes / 1024.0 / max(agg[cp[0]][c])
+    return scale
+
+
+def traffic(paths, copy_bytes: float, workload: str) -> dict:
+    """Average scaled FETCH_SIZE / WRITE_SIZE per launch, in bytes."""
+    out = {"digest": source_digest(), "workload": workload, "kernels": {}}
+    for p in paths:
+        agg = _agg(p)
+        counters = sorted({c for v in agg.values() for c in v})
+        scale = _scales(agg, counters, copy_bytes)
+        for k, v in agg.items():
+            if not k.startswith("vsw::"):
+                continue
+            for c in ("FETCH_SIZE", "WRITE_SIZE"):
+                if c in v and c in scale:
+                    out["kernels"].setdefault(k, {})[c.lower().replace("_size", "_bytes")] = \
+                        sum(v[c]) / len(v[c]) * scale[c] * 1024.0
+    return out
+
+
+def pmc(path: str, copy_bytes: float | None) -> str:
+    agg = _agg(path)
+    counters = sorted({c for v in agg.values() for c in v})
+    scale = _scales(agg, counters, copy_bytes)
     head = "| kernel | dispatches | " + " | ".join(
         f"{c} (avg{', x' + format(scale[c], '.4f') + ' = KiB' if c in scale else ''})"
         for c in counters) + " |"
@@ -63,12 +111,17 @@ def main():
     ap.add_argument("--stats")
     ap.add_argument("--pmc", action="append", default=[])
     ap.add_argument("--copy-bytes", type=float)
+    ap.add_argument("--traffic-json")
+    ap.add_argument("--workload", default="")
     a = ap.parse_args()
     if a.stats:
         print(stats(a.stats))
     for p in a.pmc:
         print()
         print(pmc(p, a.copy_bytes))
+    if a.traffic_json:
+        with open(a.traffic_json, "w") as f:
+            json.dump(traffic(a.pmc, a.copy_bytes, a.workload), f, indent=1)
 
 
 if __name__ == "__main__":
