@@ -92,6 +92,38 @@ int vsw_upload_mesh(vsw_solver *s, int64_t nv, const double *vx,
                     const double *vy, int64_t nc, const int32_t *tri,
                     const double *h);
 
+/* Ensembles: nscen independent scenarios (the many-run uncertainty and
+ * sensitivity studies that Section 1 motivates) advanced together, each on
+ * its own mesh, with its own CFL time step and time, in the same kernel
+ * launches.  Scenario s has nv[s] vertices and nc[s] triangles; vx, vy hold
+ * all scenarios' vertices one scenario after the other, tri and h all
+ * triangles (tri indexes the scenario's own vertices, from 0).  Every other
+ * call then uses the concatenated cell numbering: cell k of scenario s is
+ * cell nc[0] + ... + nc[s-1] + k (state arrays, gauges, vsw_mesh_info's
+ * cell count).  vsw_step advances every scenario by up to n steps of its
+ * own dt, each stopping on its own at t_stop; *steps_done is the most steps
+ * any scenario took and *t_out the earliest scenario time; vsw_dt_history,
+ * vsw_last_dt and the gauge times refer to scenario 0.  Errors as
+ * vsw_upload_mesh, for the failing scenario; EINVAL if nscen <= 0 or
+ * nscen > 2^22.  vsw_upload_mesh is the case nscen = 1. */
+int vsw_upload_ensemble(vsw_solver *s, int32_t nscen, const int64_t *nv,
+                        const double *vx, const double *vy, const int64_t *nc,
+                        const int32_t *tri, const double *h);
+
+/* Number of scenarios of the uploaded mesh (1 after vsw_upload_mesh). */
+int vsw_scenario_count(vsw_solver *s, int32_t *nscen);
+
+/* Per scenario (up to max): its time, its last dt and the steps it took in
+ * the last vsw_step call (any output may be NULL). */
+int vsw_scenario_status(vsw_solver *s, int32_t max, double *t, double *dt_last,
+                        int64_t *steps);
+
+/* dt of each step scenario scen took in the last vsw_step call: up to max
+ * values into dts (may be NULL); *count receives the number of steps.
+ * EINVAL on a scenario index out of range. */
+int vsw_scenario_dt_history(vsw_solver *s, int32_t scen, int64_t max,
+                            double *dts, int64_t *count);
+
 /* Set the state w = (H, HU, HV) (Section 2.1) from host arrays of nc values
  * in the caller's cell order, at time t.  EINVAL on a non-finite value or
  * H < 0; ESTATE before vsw_upload_mesh. */
@@ -184,7 +216,9 @@ int vsw_prepare_mesh_host(int64_t nv, const double *vx, const double *vy,
                           int32_t *nbr, int32_t *is_left, int64_t *ne,
                           int64_t *nw);
 
-/* Internal cell order: perm[i] = caller's index of internal cell i. */
+/* Internal cell order: perm[i] = caller's index of the i-th internal cell
+ * (nc values; the padding that rounds each scenario of an ensemble up to
+ * whole tiles is skipped). */
 int vsw_get_permutation(vsw_solver *s, int64_t *perm);
 
 /* Mesh sizes after upload: cells, edges, wall faces. */

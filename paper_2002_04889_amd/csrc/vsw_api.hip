@@ -63,8 +63,16 @@ struct vsw_solver {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     bool has_mesh = false, has_state = false;
-    int64_t nc = 0, ne = 0, nw = 0;
-    std::vector<int64_t> perm;     // internal -> caller
+    int64_t nc = 0, ne = 0, nw = 0;   // caller cells (all scenarios), faces, walls
+    int64_t nint = 0;                 // internal cells, padding included
+    int nseg = 1;                     // scenarios
+    std::vector<int64_t> seg_off;     // [nseg + 1] caller offsets of the scenarios
+    std::vector<double> seg_t;        // time of each scenario
+    std::vector<double> seg_dt;       // last dt of each scenario
+    std::vector<int64_t> seg_steps;   // steps each scenario took in the last call
+    std::vector<double> seg_log;      // last call's dt log, [step][scenario]
+    int64_t log_steps = 0;
+    std::vector<int64_t> perm;        // internal -> caller, -1 on padding
     DevBuf<int64_t> d_perm;
     DevBuf<Nbr4> d_nbr;            // neighbour slots per cell
     DevBuf<double> d_geom, d_area, d_perim, d_h;
@@ -79,6 +87,9 @@ struct vsw_solver {
     DevBuf<double> d_tmp;          // 3 * nc staging of caller-order arrays
     DevBuf<double> d_log;          // 2 * cap: t and dt per step
     DevBuf<Ctrl> d_ctrl;
+    DevBuf<Seg> d_seg;             // per-scenario control records
+    DevBuf<double> d_t0;           // per-scenario start times of a call
+    DevBuf<uint32_t> d_tinfo;      // tile words
     DevBuf<int64_t> d_gauge_cells; // internal indices of the gauge cells
     DevBuf<double> d_gauge_log;    // [step][gauge] free surface of the last call
     int ngauges = 0;
@@ -106,34 +117,46 @@ struct vsw_solver {
         d_perim.release(); d_h.release(); d_w.release(); d_w1.release();
         d_wf.release(); d_w1f.release();
         d_face.release(); d_sc.release(); d_order.release(); d_tmp.release();
-        d_nloc.release(); d_bstart.release(); d_bitem.release();
+        d_nloc.release(); d_bstart.release(); d_bitem.release(); d_tinfo.release();
+        d_seg.release(); d_t0.release();
         d_gauge_cells.release();
         ngauges = 0;
         has_mesh = has_state = false;
     }
     // caller-order arrays (device) -> state records of both stage buffers
     void pack(const double* H, const double* HU, const double* HV) {
+        const dim3 g(unsigned((nint + kBlock - 1) / kBlock));
         if (prm.precision == VSW_FP32)
-            hipLaunchKernelGGL(pack_state_f32_kernel, dim3(unsigned((nc + kBlock - 1) / kBlock)),
-                               dim3(kBlock), 0, stream, nc, d_perm.p, H, HU, HV, d_h.p, d_wf.p,
-                               d_w1f.p);
+            hipLaunchKernelGGL(pack_state_f32_kernel, g, dim3(kBlock), 0, stream, nint, d_perm.p,
+                               H, HU, HV, d_h.p, d_wf.p, d_w1f.p);
         else
-            hipLaunchKernelGGL(pack_state_kernel, dim3(unsigned((nc + kBlock - 1) / kBlock)),
-                               dim3(kBlock), 0, stream, nc, d_perm.p, H, HU, HV, d_h.p, d_w.p,
-                               d_w1.p);
+            hipLaunchKernelGGL(pack_state_kernel, g, dim3(kBlock), 0, stream, nint, d_perm.p, H,
+                               HU, HV, d_h.p, d_w.p, d_w1.p);
     }
     // state records -> caller-order arrays (device; NULL skips a field)
     void unpack(double* H, double* HU, double* HV) {
+        const dim3 g(unsigned((nint + kBlock - 1) / kBlock));
         if (prm.precision == VSW_FP32)
-            hipLaunchKernelGGL(unpack_state_f32_kernel, dim3(unsigned((nc + kBlock - 1) / kBlock)),
-                               dim3(kBlock), 0, stream, nc, d_perm.p, d_wf.p, H, HU, HV);
+            hipLaunchKernelGGL(unpack_state_f32_kernel, g, dim3(kBlock), 0, stream, nint, d_perm.p,
+                               d_wf.p, H, HU, HV);
         else
-            hipLaunchKernelGGL(unpack_state_kernel, dim3(unsigned((nc + kBlock - 1) / kBlock)),
-                               dim3(kBlock), 0, stream, nc, d_perm.p, d_w.p, H, HU, HV);
+            hipLaunchKernelGGL(unpack_state_kernel, g, dim3(kBlock), 0, stream, nint, d_perm.p,
+                               d_w.p, H, HU, HV);
+    }
+    void set_time(double t0) {
+        t = t0;
+        dt_last = 0.0;
+        clamps = 0;
+        seg_t.assign(size_t(nseg), t0);
+        seg_dt.assign(size_t(nseg), 0.0);
+        seg_steps.assign(size_t(nseg), 0);
+        seg_log.clear();
+        last_dts.clear();
+        has_state = true;
     }
     DevMesh dev_mesh() const {
         DevMesh m;
-        m.nc = nc;
+        m.nc = nint;
         m.nbr = d_nbr.p;
         m.geom = d_geom.p;
         m.rgeom = d_rgeom.p;
@@ -221,19 +244,24 @@ int vsw_set_stream(vsw_solver* s, void* hip_stream) {
     return VSW_OK;
 }
 
-int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* vy, int64_t nc,
-                    const int32_t* tri, const double* h) {
-    if (!s) return fail(VSW_EINVAL, "NULL solver");
-    HostMesh hm;
-    std::string err;
-    int rc = build_host_mesh(nv, vx, vy, nc, tri, h, s->prm.ordering, s->prm.seed, hm, err);
-    if (rc != VSW_OK) return fail(rc, err);
+namespace {
+
+// Device copies of an assembled (single or ensemble) mesh.
+int upload_assembled(vsw_solver* s, EnsembleMesh& em) {
+    HostMesh& hm = em.hm;
     DeviceGuard dg(s->device);
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->release_mesh();
-    s->nc = hm.nc;
+    s->nc = em.ncell;
+    s->nint = hm.nc;
     s->ne = hm.ne;
     s->nw = hm.nw;
+    s->nseg = em.nseg;
+    s->seg_off = em.coff;
+    s->seg_t.assign(size_t(em.nseg), 0.0);
+    s->seg_dt.assign(size_t(em.nseg), 0.0);
+    s->seg_steps.assign(size_t(em.nseg), 0);
+    s->seg_log.clear();
     s->perm = hm.perm;
     const size_t n = size_t(hm.nc);
     HIP_TRY(s->d_perm.alloc(n));
@@ -252,7 +280,9 @@ int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* v
         HIP_TRY(s->d_sc.alloc(2 * n));
         HIP_TRY(s->d_order.alloc(n));
     }
-    HIP_TRY(s->d_tmp.alloc(3 * n));
+    HIP_TRY(s->d_tmp.alloc(3 * size_t(em.ncell)));
+    HIP_TRY(s->d_seg.alloc(size_t(em.nseg)));
+    HIP_TRY(s->d_t0.alloc(size_t(em.nseg)));
     HIP_TRY(hipMemcpy(s->d_perm.p, hm.perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
     {
         std::vector<Nbr4> nb(n);
@@ -277,11 +307,11 @@ int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* v
     }
     HIP_TRY(hipMemcpy(s->d_perim.p, hm.perim.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->d_h.p, hm.h.data(), n * sizeof(double), hipMemcpyHostToDevice));
-    TileMapHost tmh;
-    build_tiles(hm, kTile, tmh);
+    TileMapHost& tmh = em.tiles;
     HIP_TRY(s->d_nloc.alloc(tmh.nloc.size()));
     HIP_TRY(s->d_bstart.alloc(tmh.bstart.size()));
     HIP_TRY(s->d_bitem.alloc(std::max<size_t>(tmh.bitem.size(), 1)));
+    HIP_TRY(s->d_tinfo.alloc(em.tinfo.size()));
     HIP_TRY(hipMemcpy(s->d_nloc.p, tmh.nloc.data(), tmh.nloc.size() * sizeof(uint16_t),
                       hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->d_bstart.p, tmh.bstart.data(), tmh.bstart.size() * sizeof(int32_t),
@@ -289,11 +319,40 @@ int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* v
     if (!tmh.bitem.empty())
         HIP_TRY(hipMemcpy(s->d_bitem.p, tmh.bitem.data(), tmh.bitem.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_tinfo.p, em.tinfo.data(), em.tinfo.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice));
     s->bmax = tmh.bmax;
     s->ntiles = tmh.ntiles;
     s->has_mesh = true;
     s->has_state = false;
     return VSW_OK;
+}
+
+}  // namespace
+
+int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* vy, int64_t nc,
+                    const int32_t* tri, const double* h) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    EnsembleMesh em;
+    std::string err;
+    int rc = build_ensemble(1, &nv, vx, vy, &nc, tri, h, s->prm.ordering, s->prm.seed, kTile,
+                            em, err);
+    if (rc != VSW_OK) return fail(rc, err);
+    return upload_assembled(s, em);
+}
+
+int vsw_upload_ensemble(vsw_solver* s, int32_t nscen, const int64_t* nv, const double* vx,
+                        const double* vy, const int64_t* nc, const int32_t* tri,
+                        const double* h) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (nscen <= 0 || nscen > (1 << 22)) return fail(VSW_EINVAL, "bad scenario count");
+    if (!vx || !vy || !tri || !h) return fail(VSW_EINVAL, "NULL array");
+    EnsembleMesh em;
+    std::string err;
+    int rc = build_ensemble(nscen, nv, vx, vy, nc, tri, h, s->prm.ordering, s->prm.seed, kTile,
+                            em, err);
+    if (rc != VSW_OK) return fail(rc, err);
+    return upload_assembled(s, em);
 }
 
 int vsw_set_state(vsw_solver* s, const double* H, const double* HU, const double* HV, double t) {
@@ -316,10 +375,7 @@ int vsw_set_state(vsw_solver* s, const double* H, const double* HU, const double
     s->pack(tmp, tmp + nc, tmp + 2 * nc);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));
-    s->t = t;
-    s->dt_last = 0.0;
-    s->clamps = 0;
-    s->has_state = true;
+    s->set_time(t);
     return VSW_OK;
 }
 
@@ -333,10 +389,7 @@ int vsw_set_state_device(vsw_solver* s, const double* dH, const double* dHU, con
     s->pack(dH, dHU, dHV);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));
-    s->t = t;
-    s->dt_last = 0.0;
-    s->clamps = 0;
-    s->has_state = true;
+    s->set_time(t);
     return VSW_OK;
 }
 
@@ -379,11 +432,12 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     if (t_out) *t_out = s->t;
     if (n == 0) return VSW_OK;
     DeviceGuard dg(s->device);
-    if (s->d_log.n < size_t(2 * n)) HIP_TRY(s->d_log.alloc(size_t(2 * n)));
+    const int nseg = s->nseg;
+    const size_t nlog = size_t(n) * size_t(nseg);
+    if (s->d_log.n < 2 * nlog) HIP_TRY(s->d_log.alloc(2 * nlog));
     const int ng = s->ngauges;
     if (ng > 0 && s->d_gauge_log.n < size_t(n) * size_t(ng))
         HIP_TRY(s->d_gauge_log.alloc(size_t(n) * size_t(ng)));
-    const int64_t nc = s->nc;
     const DevMesh m = s->dev_mesh();
     StepParams p;
     p.g = s->prm.g;
@@ -396,9 +450,10 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     Cell4* W1 = s->d_w1.p;
     FaceBuf fb{s->d_face.p, s->d_sc.p, s->d_order.p};
     Ctrl* c = s->d_ctrl.p;
+    Seg* sg = s->d_seg.p;
     double* tlog = s->d_log.p;
-    double* dtlog = s->d_log.p + n;
-    const dim3 grid(grid_for(nc)), block(kBlock);
+    double* dtlog = s->d_log.p + nlog;
+    const dim3 grid(unsigned(s->ntiles)), block(kBlock);
     hipStream_t st = s->stream;
 
     // profiling events: one pair per timed launch
@@ -423,15 +478,18 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         ev_used += 2;
     };
 
-    hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(64), 0, st, c, s->t);
+    HIP_TRY(hipMemcpy(s->d_t0.p, s->seg_t.data(), size_t(nseg) * sizeof(double),
+                      hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(256), 0, st, c, sg, nseg, s->d_t0.p);
+    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, nseg};
     ev_begin(KK_DTINIT);
     const bool f32 = (s->prm.precision == VSW_FP32);
     if (f32)
-        hipLaunchKernelGGL(dt_init_f32_kernel, grid, block, 0, st, m, s->d_wf.p, p.g, p.thr, c);
+        hipLaunchKernelGGL(dt_init_f32_kernel, grid, block, 0, st, m, tm, s->d_wf.p, p.g, p.thr,
+                           sg);
     else
-        hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, W, p.g, p.thr, c);
+        hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, tm, W, p.g, p.thr, sg);
     ev_end();
-    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->bmax, s->ntiles};
     const size_t lds = stage_lds_bytes(s->bmax);
     const size_t lds32 = stage_f32_lds_bytes(s->bmax);
     const dim3 tgrid(unsigned(s->ntiles));
@@ -441,54 +499,59 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         const int slot = int(k & 1);
         ev_begin(KK_STAGE1);
         hipLaunchKernelGGL(stage_f32_kernel<1>, tgrid, block, lds32, st, m, tm, s->d_wf.p,
-                           s->d_w1f.p, p, c, slot, int(k), tlog, dtlog);
+                           s->d_w1f.p, p, c, sg, slot, int(k), tlog, dtlog);
         ev_end();
         ev_begin(KK_STAGE2);
         hipLaunchKernelGGL(stage_f32_kernel<2>, tgrid, block, lds32, st, m, tm, s->d_wf.p,
-                           s->d_w1f.p, p, c, slot, int(k), tlog, dtlog);
+                           s->d_w1f.p, p, c, sg, slot, int(k), tlog, dtlog);
         ev_end();
         if (ng > 0)
             hipLaunchKernelGGL(gauge_f32_kernel, dim3(unsigned((ng + 63) / 64)), dim3(64), 0, st,
-                               s->d_wf.p, s->d_gauge_cells.p, ng, c, int(k), s->d_gauge_log.p);
+                               s->d_wf.p, s->d_gauge_cells.p, ng, s->d_tinfo.p, sg, int(k),
+                               s->d_gauge_log.p);
     }
     for (int64_t k = 0; !f32 && s->variant == VSW_KERNEL_FUSED && k < n; ++k) {
         const int slot = int(k & 1);
         ev_begin(KK_STAGE1);
-        hipLaunchKernelGGL(k1, tgrid, block, lds, st, m, tm, W, W1, p, c, slot, int(k), tlog,
+        hipLaunchKernelGGL(k1, tgrid, block, lds, st, m, tm, W, W1, p, c, sg, slot, int(k), tlog,
                            dtlog);
         ev_end();
         ev_begin(KK_STAGE2);
-        hipLaunchKernelGGL(k2, tgrid, block, lds, st, m, tm, W, W1, p, c, slot, int(k), tlog,
+        hipLaunchKernelGGL(k2, tgrid, block, lds, st, m, tm, W, W1, p, c, sg, slot, int(k), tlog,
                            dtlog);
         ev_end();
         if (ng > 0)
             hipLaunchKernelGGL(gauge_kernel, dim3(unsigned((ng + 63) / 64)), dim3(64), 0, st, W,
-                               s->d_gauge_cells.p, ng, c, int(k), s->d_gauge_log.p);
+                               s->d_gauge_cells.p, ng, s->d_tinfo.p, sg, int(k),
+                               s->d_gauge_log.p);
     }
     for (int64_t k = 0; !f32 && s->variant == VSW_KERNEL_TWO_PASS && k < n; ++k) {
         const int slot = int(k & 1);
         ev_begin(KK_RECON);
-        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, W, fb, p, c, slot);
+        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, tm, W, fb, p, c, sg, slot);
         ev_end();
         ev_begin(KK_UPDATE1);
-        hipLaunchKernelGGL(update1_kernel, grid, block, 0, st, m, W, W1, fb, p, c, slot);
+        hipLaunchKernelGGL(update1_kernel, grid, block, 0, st, m, tm, W, W1, fb, p, c, sg, slot);
         ev_end();
         ev_begin(KK_RECON);
-        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, W1, fb, p, c, slot);
+        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, tm, W1, fb, p, c, sg, slot);
         ev_end();
         ev_begin(KK_UPDATE2);
-        hipLaunchKernelGGL(update2_kernel, grid, block, 0, st, m, W, W1, fb, p, c, slot, int(k),
-                           tlog, dtlog);
+        hipLaunchKernelGGL(update2_kernel, grid, block, 0, st, m, tm, W, W1, fb, p, c, sg, slot,
+                           int(k), tlog, dtlog);
         ev_end();
         if (ng > 0)
             hipLaunchKernelGGL(gauge_kernel, dim3(unsigned((ng + 63) / 64)), dim3(64), 0, st, W,
-                               s->d_gauge_cells.p, ng, c, int(k), s->d_gauge_log.p);
+                               s->d_gauge_cells.p, ng, s->d_tinfo.p, sg, int(k),
+                               s->d_gauge_log.p);
     }
     HIP_TRY(hipGetLastError());
     Ctrl hc;
+    std::vector<Seg> hs(static_cast<size_t>(nseg));
     HIP_TRY(hipMemcpyAsync(&hc, c, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    std::vector<double> logs(2 * size_t(n));
-    HIP_TRY(hipMemcpyAsync(logs.data(), s->d_log.p, 2 * size_t(n) * sizeof(double),
+    HIP_TRY(hipMemcpyAsync(hs.data(), sg, size_t(nseg) * sizeof(Seg), hipMemcpyDeviceToHost, st));
+    std::vector<double> logs(2 * nlog);
+    HIP_TRY(hipMemcpyAsync(logs.data(), s->d_log.p, 2 * nlog * sizeof(double),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (s->profiling) {
@@ -501,26 +564,77 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
             }
         }
     }
-    int64_t done = hc.steps_done;
+    // A scenario's steps are a prefix of the call (once it stops it takes no
+    // later step); on an error, only the steps before the failing one count.
     int rc = VSW_OK;
+    int64_t cap = n;
     if (hc.err) {
-        done = hc.err_step;
-        rc = fail(VSW_EUNSTABLE, hc.err == 1 ? "non-finite state" : "no valid time step");
+        cap = hc.err_step;
+        rc = fail(VSW_EUNSTABLE, (hc.err & 1) ? "non-finite state" : "no valid time step");
     }
+    int64_t done = 0;
+    double tmin = INFINITY;
+    s->seg_log.assign(logs.begin() + nlog, logs.begin() + 2 * nlog);
+    s->seg_log.resize(nlog);
+    for (int q = 0; q < nseg; ++q) {
+        const int64_t d = std::min<int64_t>(hs[q].steps_done, cap);
+        s->seg_steps[q] = d;
+        if (d > 0) {
+            s->seg_t[q] = logs[size_t(d - 1) * nseg + q];
+            s->seg_dt[q] = logs[nlog + size_t(d - 1) * nseg + q];
+        }
+        done = std::max(done, d);
+        tmin = std::min(tmin, s->seg_t[q]);
+    }
+    s->log_steps = n;
     s->clamps += int64_t(hc.clamps);
-    s->last_dts.assign(logs.begin() + n, logs.begin() + n + done);
-    s->gauge_t.assign(logs.begin(), logs.begin() + done);
+    s->last_dts.resize(size_t(s->seg_steps[0]));
+    for (int64_t k = 0; k < s->seg_steps[0]; ++k) s->last_dts[k] = logs[nlog + size_t(k) * nseg];
+    s->gauge_t.assign(size_t(done), s->seg_t[0]);
+    for (int64_t k = 0; k < std::min(done, s->seg_steps[0]); ++k)
+        s->gauge_t[k] = logs[size_t(k) * nseg];
     s->gauge_eta.assign(size_t(done) * size_t(ng), 0.0);
     if (ng > 0 && done > 0)
         HIP_TRY(hipMemcpy(s->gauge_eta.data(), s->d_gauge_log.p,
                           size_t(done) * size_t(ng) * sizeof(double), hipMemcpyDeviceToHost));
-    if (done > 0) {
-        s->t = logs[done - 1];
-        s->dt_last = logs[n + done - 1];
-    }
+    s->t = tmin;
+    s->dt_last = s->seg_dt[0];
     if (steps_done) *steps_done = done;
     if (t_out) *t_out = s->t;
     return rc;
+}
+
+int vsw_scenario_count(vsw_solver* s, int32_t* nscen) {
+    if (!s || !nscen) return fail(VSW_EINVAL, "NULL argument");
+    if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
+    *nscen = s->nseg;
+    return VSW_OK;
+}
+
+int vsw_scenario_status(vsw_solver* s, int32_t max, double* t, double* dt_last,
+                        int64_t* steps) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
+    const int m = std::min<int>(max, s->nseg);
+    for (int q = 0; q < m; ++q) {
+        if (t) t[q] = s->seg_t[q];
+        if (dt_last) dt_last[q] = s->seg_dt[q];
+        if (steps) steps[q] = s->seg_steps[q];
+    }
+    return VSW_OK;
+}
+
+int vsw_scenario_dt_history(vsw_solver* s, int32_t scen, int64_t max, double* dts,
+                            int64_t* count) {
+    if (!s || !count) return fail(VSW_EINVAL, "NULL argument");
+    if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
+    if (scen < 0 || scen >= s->nseg) return fail(VSW_EINVAL, "scenario index out of range");
+    const int64_t n = s->seg_log.empty() ? 0 : s->seg_steps[scen];
+    *count = n;
+    if (dts)
+        for (int64_t k = 0; k < n && k < max; ++k)
+            dts[k] = s->seg_log[size_t(k) * s->nseg + scen];
+    return VSW_OK;
 }
 
 int vsw_last_dt(vsw_solver* s, double* dt) {
@@ -549,7 +663,8 @@ int vsw_set_gauges(vsw_solver* s, int32_t n, const int32_t* cells) {
     if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
     if (n < 0 || (n > 0 && !cells)) return fail(VSW_EINVAL, "bad gauge list");
     std::vector<int64_t> inv(s->nc);
-    for (int64_t i = 0; i < s->nc; ++i) inv[s->perm[i]] = i;
+    for (int64_t i = 0; i < s->nint; ++i)
+        if (s->perm[i] >= 0) inv[s->perm[i]] = i;
     std::vector<int64_t> idx(n);
     for (int32_t g = 0; g < n; ++g) {
         if (cells[g] < 0 || cells[g] >= s->nc) return fail(VSW_EINVAL, "gauge cell out of range");
@@ -636,7 +751,9 @@ int vsw_prepare_mesh_host(int64_t nv, const double* vx, const double* vy, int64_
 int vsw_get_permutation(vsw_solver* s, int64_t* perm) {
     if (!s || !perm) return fail(VSW_EINVAL, "NULL argument");
     if (!s->has_mesh) return fail(VSW_ESTATE, "no mesh uploaded");
-    std::memcpy(perm, s->perm.data(), s->perm.size() * sizeof(int64_t));
+    int64_t o = 0;
+    for (int64_t v : s->perm)
+        if (v >= 0) perm[o++] = v;
     return VSW_OK;
 }
 

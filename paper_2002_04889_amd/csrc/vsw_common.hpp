@@ -25,19 +25,29 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
-// dt of the step using control slot `slot`: CFL rule (or fixed dt), clipped
-// so the time lands exactly on t_stop.  False if the step is not taken.
-__device__ __forceinline__ bool step_dt(const Ctrl* c, int slot, const StepParams& p,
-                                        double& dt, double& tn) {
+struct TileInfo {
+    int seg;     // scenario of the tile
+    bool first;  // first tile of its scenario
+    int cnt;     // cells in the tile (1..kTile)
+};
+
+__device__ __forceinline__ TileInfo tile_info(uint32_t v) {
+    TileInfo t;
+    t.seg = int(v >> 9);
+    t.first = ((v >> 8) & 1u) != 0;
+    t.cnt = int(v & 255u) + 1;
+    return t;
+}
+
+// dt of the scenario's step using control slot `slot`: CFL rule (or fixed
+// dt), clipped so the time lands exactly on t_stop.  False if the step is
+// not taken.
+__device__ __forceinline__ bool step_dt(const Ctrl* c, const Seg* sg, int slot,
+                                        const StepParams& p, double& dt, double& tn) {
     if (c->err) return false;
-    const double t = c->t[slot];
+    const double t = sg->t[slot];
     if (!(t < p.t_stop)) return false;
-    unsigned long long rb = c->rmin[slot][0];
-#pragma unroll
-    for (int g = 1; g < kMinGroups; ++g) {
-        const unsigned long long v = c->rmin[slot][g * kMinStride];
-        rb = (v < rb) ? v : rb;
-    }
+    const unsigned long long rb = sg->rmin[slot];
     double d = (p.dt_fixed > 0.0) ? p.dt_fixed : p.cfl * __longlong_as_double((long long)rb);
     const double rem = p.t_stop - t;
     if (d >= rem) {
@@ -60,12 +70,11 @@ __device__ __forceinline__ double cfl_ratio(double H, double HU, double HV, doub
     return area / (perim * s);
 }
 
-// Block-wide min of a positive double, then one atomic min on its bits in
-// the block's group.  The bits of positive doubles order like the values; a
-// plain read first skips the atomic when the group already holds a value at
-// least as small (values only decrease, so a stale read never loses one).
-__device__ __forceinline__ void block_min_atomic(double v, unsigned long long* slot_base) {
-    unsigned long long* target = slot_base + (blockIdx.x % kMinGroups) * kMinStride;
+// Block-wide min of a positive double, then one atomic min on its bits.
+// The bits of positive doubles order like the values; a plain read first
+// skips the atomic when the target already holds a value at least as small
+// (values only decrease, so a stale read never loses one).
+__device__ __forceinline__ void block_min_atomic(double v, unsigned long long* target) {
     __shared__ double part[kBlock / 64];
     v = wave_min(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -96,24 +105,26 @@ __device__ __forceinline__ void block_count_atomic(unsigned long long v, unsigne
     }
 }
 
-// Time bookkeeping at the end of stage 2 (block 0 only) or, for a step that
-// is not taken, the carry-over of the time and the no-valid-dt error.
-__device__ __forceinline__ void stage2_bookkeeping(Ctrl* c, int slot, int step, bool active,
-                                                   double dt, double tn, double t_stop,
-                                                   double* tlog, double* dtlog) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// Time bookkeeping of a scenario at the end of stage 2 (thread 0 of the
+// scenario's first tile) or, for a step that is not taken, the carry-over of
+// the time and the no-valid-dt error.
+__device__ __forceinline__ void stage2_bookkeeping(Ctrl* c, Seg* sg, const TileInfo& ti, int nseg,
+                                                   int slot, int step, bool active, double dt,
+                                                   double tn, double t_stop, double* tlog,
+                                                   double* dtlog) {
+    if (!ti.first || threadIdx.x != 0) return;
     if (active) {
-        c->t[slot ^ 1] = tn;
-        c->dt_last = dt;
-        c->steps_done += 1;
-        tlog[step] = tn;
-        dtlog[step] = dt;
+        sg->t[slot ^ 1] = tn;
+        sg->dt_last = dt;
+        sg->steps_done += 1;
+        tlog[int64_t(step) * nseg + ti.seg] = tn;
+        dtlog[int64_t(step) * nseg + ti.seg] = dt;
     } else {
-        const double t = c->t[slot];
-        c->t[slot ^ 1] = t;
+        const double t = sg->t[slot];
+        sg->t[slot ^ 1] = t;
         if (!c->err && t < t_stop) {  // no valid time step
-            c->err = 2;
-            c->err_step = step;
+            atomicOr(&c->err, 2);
+            atomicMin(&c->err_step, step);
         }
     }
 }

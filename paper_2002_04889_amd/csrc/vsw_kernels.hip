@@ -20,42 +20,49 @@ namespace vsw {
 
 // ---------------------------------------------------------------- control
 
-__global__ void ctrl_init_kernel(Ctrl* c, double t0) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        for (int g = 0; g < kMinGroups; ++g) {
-            c->rmin[0][g * kMinStride] = 0x7FF0000000000000ull;
-            c->rmin[1][g * kMinStride] = 0x7FF0000000000000ull;
-        }
-        c->t[0] = t0;
-        c->t[1] = t0;
+__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->err = 0;
         c->err_step = 0x7FFFFFFF;
-        c->steps_done = 0;
         c->clamps = 0;
-        c->dt_last = 0.0;
+    }
+    for (int s = int(blockIdx.x * blockDim.x + threadIdx.x); s < nseg;
+         s += int(gridDim.x * blockDim.x)) {
+        Seg q;
+        q.rmin[0] = q.rmin[1] = 0x7FF0000000000000ull;
+        q.t[0] = q.t[1] = t0[s];
+        q.dt_last = 0.0;
+        q.steps_done = 0;
+        q.pad[0] = q.pad[1] = 0;
+        sg[s] = q;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void dt_init_kernel(DevMesh m, const Cell4* __restrict__ W,
-                                                         double g, double thr, Ctrl* c) {
-    const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void dt_init_kernel(DevMesh m, TileMap tm,
+                                                         const Cell4* __restrict__ W, double g,
+                                                         double thr, Seg* sg) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
     double r = __longlong_as_double(0x7FF0000000000000ll);
-    if (k < m.nc) {
+    if (int(threadIdx.x) < ti.cnt) {
         const Cell4 q = W[k];
         r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
     }
-    block_min_atomic(r, c->rmin[0]);
+    block_min_atomic(r, &sg[ti.seg].rmin[0]);
 }
 
 // ---------------------------------------------------------------- two-pass kernels
 
-__global__ __launch_bounds__(kBlock) void recon_kernel(DevMesh m, const Cell4* __restrict__ W,
-                                                       FaceBuf fb, StepParams p, const Ctrl* c,
+// The two-pass kernels run one block per tile (kBlock == kTile).
+__global__ __launch_bounds__(kBlock) void recon_kernel(DevMesh m, TileMap tm,
+                                                       const Cell4* __restrict__ W, FaceBuf fb,
+                                                       StepParams p, const Ctrl* c, const Seg* sg,
                                                        int slot) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     double dt, tn;
-    if (!step_dt(c, slot, p, dt, tn)) return;
+    if (!step_dt(c, sg + ti.seg, slot, p, dt, tn)) return;
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (k >= m.nc) return;
+    if (int(threadIdx.x) >= ti.cnt) return;
     const int64_t nc = m.nc;
     Face f[3];
     double sc[2];
@@ -142,16 +149,17 @@ __device__ __forceinline__ Cell4 stage2_update(const Cell4& w, const Cell4& w1, 
     return o;
 }
 
-__global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, const Cell4* __restrict__ W,
+__global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, TileMap tm,
+                                                         const Cell4* __restrict__ W,
                                                          Cell4* __restrict__ W1, FaceBuf fb,
-                                                         StepParams p, Ctrl* c, int slot) {
+                                                         StepParams p, Ctrl* c, Seg* sg, int slot) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     double dt, tn;
-    if (!step_dt(c, slot, p, dt, tn)) return;
-    if (blockIdx.x == 0 && threadIdx.x < kMinGroups)
-        c->rmin[slot ^ 1][threadIdx.x * kMinStride] = 0x7FF0000000000000ull;
+    if (!step_dt(c, sg + ti.seg, slot, p, dt, tn)) return;
+    if (ti.first && threadIdx.x == 0) sg[ti.seg].rmin[slot ^ 1] = 0x7FF0000000000000ull;
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     unsigned long long clamp = 0;
-    if (k < m.nc) {
+    if (int(threadIdx.x) < ti.cnt) {
         double R[3];
         residual_from_faces(m, fb, k, p.g, p.hg, R);
         W1[k] = stage1_update(W[k], R, dt, p.thr, clamp);
@@ -159,21 +167,25 @@ __global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, const Cell4*
     block_count_atomic(clamp, &c->clamps);
 }
 
-__global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, Cell4* __restrict__ W,
+__global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, TileMap tm,
+                                                         Cell4* __restrict__ W,
                                                          const Cell4* __restrict__ W1, FaceBuf fb,
-                                                         StepParams p, Ctrl* c, int slot, int step,
-                                                         double* tlog, double* dtlog) {
+                                                         StepParams p, Ctrl* c, Seg* sg, int slot,
+                                                         int step, double* tlog, double* dtlog) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    Seg* sgs = sg + ti.seg;
     double dt, tn;
-    const bool active = step_dt(c, slot, p, dt, tn);
+    const bool active = step_dt(c, sgs, slot, p, dt, tn);
     if (!active) {
-        stage2_bookkeeping(c, slot, step, false, 0.0, 0.0, p.t_stop, tlog, dtlog);
+        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, tlog,
+                           dtlog);
         return;
     }
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     unsigned long long clamp = 0;
     double r = __longlong_as_double(0x7FF0000000000000ll);
     bool bad = false;
-    if (k < m.nc) {
+    if (int(threadIdx.x) < ti.cnt) {
         double R[3];
         residual_from_faces(m, fb, k, p.g, p.hg, R);
         const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp);
@@ -186,8 +198,8 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, Cell4* __res
         atomicMin(&c->err_step, step);
     }
     block_count_atomic(clamp, &c->clamps);
-    block_min_atomic(r, c->rmin[slot ^ 1]);
-    stage2_bookkeeping(c, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
+    block_min_atomic(r, &sgs->rmin[slot ^ 1]);
+    stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
 }
 
 // ---------------------------------------------------------------- fused stage
@@ -227,24 +239,27 @@ __device__ __forceinline__ Face lds_load_face(const double* lds, int stride, int
 template <int STAGE>
 __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Cell4* __restrict__ W,
                                                        Cell4* __restrict__ W1, StepParams p,
-                                                       Ctrl* c, int slot, int step, double* tlog,
-                                                       double* dtlog) {
+                                                       Ctrl* c, Seg* sg, int slot, int step,
+                                                       double* tlog, double* dtlog) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
+    const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
+    const TileInfo ti = tile_info(tm.tinfo[t]);
+    Seg* sgs = sg + ti.seg;
     double dt, tn;
-    const bool active = step_dt(c, slot, p, dt, tn);
+    const bool active = step_dt(c, sgs, slot, p, dt, tn);
     if (!active) {
-        if (STAGE == 2) stage2_bookkeeping(c, slot, step, false, 0.0, 0.0, p.t_stop, tlog, dtlog);
+        if (STAGE == 2)
+            stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, tlog,
+                               dtlog);
         return;
     }
-    if (STAGE == 1 && blockIdx.x == 0 && threadIdx.x < kMinGroups)
-        c->rmin[slot ^ 1][threadIdx.x * kMinStride] = 0x7FF0000000000000ull;
+    if (STAGE == 1 && ti.first && threadIdx.x == 0) sgs->rmin[slot ^ 1] = 0x7FF0000000000000ull;
     // state the stage reconstructs: w^n in stage 1, w1 in stage 2
     const Cell4* __restrict__ Ws = (STAGE == 1) ? W : W1;
     const int64_t nc = m.nc;
-    const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
     const int64_t c0 = int64_t(t) * kTile;
-    const int cnt = int(min(int64_t(kTile), nc - c0));
+    const int cnt = ti.cnt;
     const int i = threadIdx.x;
     const int64_t k = c0 + i;
 
@@ -312,25 +327,29 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
     }
     block_count_atomic(clamp, &c->clamps);
     if (STAGE == 2) {
-        block_min_atomic(rr, c->rmin[slot ^ 1]);
-        stage2_bookkeeping(c, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
+        block_min_atomic(rr, &sgs->rmin[slot ^ 1]);
+        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
     }
 }
 
-template __global__ void stage_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, int,
-                                         int, double*, double*);
-template __global__ void stage_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, int,
-                                         int, double*, double*);
+template __global__ void stage_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, Seg*,
+                                         int, int, double*, double*);
+template __global__ void stage_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, Seg*,
+                                         int, int, double*, double*);
 
 // ---------------------------------------------------------------- gauges
 
-// Free surface eta = H - h at the gauge cells after step `step`, if the step
-// was taken (steps_done counts the steps taken in this call).
+// Free surface eta = H - h at the gauge cells after step `step`, if the
+// gauge's scenario took the step (steps_done counts the steps it took in
+// this call; once a scenario stops, it takes no later step of the call).
 __global__ void gauge_kernel(const Cell4* __restrict__ W, const int64_t* __restrict__ cells,
-                             int ng, const Ctrl* c, int step, double* __restrict__ log) {
+                             int ng, const uint32_t* __restrict__ tinfo, const Seg* sg, int step,
+                             double* __restrict__ log) {
     const int gi = int(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gi >= ng || c->steps_done <= step) return;
-    const Cell4 q = W[cells[gi]];
+    if (gi >= ng) return;
+    const int64_t k = cells[gi];
+    if (sg[tinfo[k / kTile] >> 9].steps_done <= step) return;
+    const Cell4 q = W[k];
     log[int64_t(step) * ng + gi] = q.H - q.h;
 }
 
@@ -345,6 +364,7 @@ __global__ void pack_state_kernel(int64_t n, const int64_t* __restrict__ perm,
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t k = perm[i];
+    if (k < 0) return;
     Cell4 q;
     q.H = H[k];
     q.HU = HU[k];
@@ -361,6 +381,7 @@ __global__ void unpack_state_kernel(int64_t n, const int64_t* __restrict__ perm,
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t k = perm[i];
+    if (k < 0) return;
     const Cell4 q = W[i];
     if (H) H[k] = q.H;
     if (HU) HU[k] = q.HU;

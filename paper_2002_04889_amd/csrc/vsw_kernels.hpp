@@ -10,22 +10,23 @@ namespace vsw {
 
 constexpr int kBlock = 256;  // threads per block (four wave64)
 
-// The CFL minimum of a step is reduced into kMinGroups partial minima, each
-// on its own 128-byte line (block b uses group b % kMinGroups, which follows
-// the round-robin dealing of workgroups to XCDs), so the blocks' atomics do
-// not all queue on one address.  The step's minimum is the min of the groups.
-constexpr int kMinGroups = 8;
-constexpr int kMinStride = 16;  // 16 x 8 bytes = one 128-byte line per group
-
-// Device control block: per-step time and CFL minimum in two slots (the
-// step using slot s writes the next step's values into slot s ^ 1).
-struct Ctrl {
-    unsigned long long rmin[2][kMinGroups * kMinStride];  // bits of min_K |K| / (P_K (|u| + c))
+// The solver holds one or more independent scenarios (an ensemble), each a
+// mesh of its own whose cells occupy a contiguous run of whole tiles.  Each
+// scenario has its own control record (one 64-byte line): the step using
+// slot s reads rmin[s] and t[s] and writes the next step's values into
+// slot s ^ 1, so a scenario's dt never waits for the host.
+struct Seg {
+    unsigned long long rmin[2];  // bits of min_K |K| / (P_K (|u| + c)) of the scenario
     double t[2];                 // time at the start of the step
     double dt_last;
+    long long steps_done;        // steps the scenario took in this call
+    long long pad[2];
+};
+
+// Control word of one call, shared by all scenarios.
+struct Ctrl {
     unsigned long long clamps;   // negative depths set to zero in this call
-    long long steps_done;
-    int err;                     // 0 ok, 1 non-finite state, 2 no valid dt
+    int err;                     // bit 0: non-finite state, bit 1: no valid dt
     int err_step;                // first failing step of the call
 };
 
@@ -45,33 +46,44 @@ struct FaceBuf {
 constexpr int kTile = 256;   // cells per tile of the fused stage kernel (= kBlock)
 constexpr uint16_t kNlocWall16 = 0xFFFFu;
 
+// Tile word: bits 0-7 the tile's cell count minus one, bit 8 set on the
+// first tile of a scenario, bits 9-31 the scenario index.
 struct TileMap {
     const uint16_t* __restrict__ nloc;   // [3][nc] LDS slot per face, bit 15 = left
     const int32_t* __restrict__ bstart;  // [ntiles + 1]
     const uint32_t* __restrict__ bitem;  // halo faces: (cell << 2) | face
+    const uint32_t* __restrict__ tinfo;  // [ntiles] tile words
     int bmax;                            // most boundary faces of any tile
     int ntiles;
+    int nseg;                            // scenarios
 };
 
 // Fused stage kernel.  STAGE 1: w1 = w + dt R(w).  STAGE 2:
 // w^{n+1} = w/2 + (w1 + dt R(w1))/2 in place, plus the next CFL minimum and
 // the time bookkeeping.  Dynamic LDS: 5 * (3 * kTile + bmax) doubles.
+// Logs: tlog / dtlog[step * nseg + scenario].
 template <int STAGE>
 __global__ void stage_kernel(DevMesh m, TileMap tm, Cell4* W, Cell4* W1, StepParams p, Ctrl* c,
-                             int slot, int step, double* tlog, double* dtlog);
+                             Seg* sg, int slot, int step, double* tlog, double* dtlog);
 
 inline size_t stage_lds_bytes(int bmax) { return sizeof(double) * 5 * size_t(3 * kTile + bmax); }
 
-__global__ void ctrl_init_kernel(Ctrl* c, double t0);
-__global__ void dt_init_kernel(DevMesh m, const Cell4* W, double g, double thr, Ctrl* c);
-__global__ void recon_kernel(DevMesh m, const Cell4* W, FaceBuf fb, StepParams p, const Ctrl* c,
-                             int slot);
-__global__ void update1_kernel(DevMesh m, const Cell4* W, Cell4* W1, FaceBuf fb, StepParams p,
-                               Ctrl* c, int slot);
-__global__ void update2_kernel(DevMesh m, Cell4* W, const Cell4* W1, FaceBuf fb, StepParams p,
-                               Ctrl* c, int slot, int step, double* tlog, double* dtlog);
-__global__ void gauge_kernel(const Cell4* W, const int64_t* cells, int ng, const Ctrl* c, int step,
-                             double* log);
+// Start of a call: every scenario's time from t0[s], minima cleared.
+__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0);
+// CFL minimum of the incoming state, one block per tile.
+__global__ void dt_init_kernel(DevMesh m, TileMap tm, const Cell4* W, double g, double thr,
+                               Seg* sg);
+__global__ void recon_kernel(DevMesh m, TileMap tm, const Cell4* W, FaceBuf fb, StepParams p,
+                             const Ctrl* c, const Seg* sg, int slot);
+__global__ void update1_kernel(DevMesh m, TileMap tm, const Cell4* W, Cell4* W1, FaceBuf fb,
+                               StepParams p, Ctrl* c, Seg* sg, int slot);
+__global__ void update2_kernel(DevMesh m, TileMap tm, Cell4* W, const Cell4* W1, FaceBuf fb,
+                               StepParams p, Ctrl* c, Seg* sg, int slot, int step, double* tlog,
+                               double* dtlog);
+__global__ void gauge_kernel(const Cell4* W, const int64_t* cells, int ng, const uint32_t* tinfo,
+                             const Seg* sg, int step, double* log);
+// perm[i] = caller index of internal cell i, or -1 for the padding cells
+// that round each scenario up to whole tiles (left untouched).
 __global__ void pack_state_kernel(int64_t n, const int64_t* perm, const double* H,
                                   const double* HU, const double* HV, const double* h, Cell4* W,
                                   Cell4* W1);

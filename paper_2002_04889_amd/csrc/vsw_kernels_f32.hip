@@ -261,12 +261,14 @@ __device__ __forceinline__ FaceF lds_load_face_f32(const double* ld, const float
 
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void dt_init_f32_kernel(DevMesh m, const CellF* __restrict__ W,
-                                                             double g, double thr, Ctrl* c) {
-    const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void dt_init_f32_kernel(DevMesh m, TileMap tm,
+                                                             const CellF* __restrict__ W,
+                                                             double g, double thr, Seg* sg) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
     double r = __longlong_as_double(0x7FF0000000000000ll);
-    if (k < m.nc) r = cfl_ratio_f32(W[k], m.area[k], m.perim[k], g, thr);
-    block_min_atomic(r, c->rmin[0]);
+    if (int(threadIdx.x) < ti.cnt) r = cfl_ratio_f32(W[k], m.area[k], m.perim[k], g, thr);
+    block_min_atomic(r, &sg[ti.seg].rmin[0]);
 }
 
 // Same three phases as the FP64 stage kernel; LDS holds per face slot the
@@ -275,25 +277,28 @@ template <int STAGE>
 __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm,
                                                            CellF* __restrict__ W,
                                                            CellF* __restrict__ W1, StepParams p,
-                                                           Ctrl* c, int slot, int step,
+                                                           Ctrl* c, Seg* sg, int slot, int step,
                                                            double* tlog, double* dtlog) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
     double* ld = lds;
     float* lf = reinterpret_cast<float*>(lds + 2 * stride);
+    const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
+    const TileInfo ti = tile_info(tm.tinfo[t]);
+    Seg* sgs = sg + ti.seg;
     double dt, tn;
-    const bool active = step_dt(c, slot, p, dt, tn);
+    const bool active = step_dt(c, sgs, slot, p, dt, tn);
     if (!active) {
-        if (STAGE == 2) stage2_bookkeeping(c, slot, step, false, 0.0, 0.0, p.t_stop, tlog, dtlog);
+        if (STAGE == 2)
+            stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, tlog,
+                               dtlog);
         return;
     }
-    if (STAGE == 1 && blockIdx.x == 0 && threadIdx.x < kMinGroups)
-        c->rmin[slot ^ 1][threadIdx.x * kMinStride] = 0x7FF0000000000000ull;
+    if (STAGE == 1 && ti.first && threadIdx.x == 0) sgs->rmin[slot ^ 1] = 0x7FF0000000000000ull;
     const CellF* __restrict__ Ws = (STAGE == 1) ? W : W1;
     const int64_t nc = m.nc;
-    const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
     const int64_t c0 = int64_t(t) * kTile;
-    const int cnt = int(min(int64_t(kTile), nc - c0));
+    const int cnt = ti.cnt;
     const int i = threadIdx.x;
     const int64_t k = c0 + i;
 
@@ -389,22 +394,25 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
     }
     block_count_atomic(clamp, &c->clamps);
     if (STAGE == 2) {
-        block_min_atomic(rr, c->rmin[slot ^ 1]);
-        stage2_bookkeeping(c, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
+        block_min_atomic(rr, &sgs->rmin[slot ^ 1]);
+        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
     }
 }
 
 template __global__ void stage_f32_kernel<1>(DevMesh, TileMap, CellF*, CellF*, StepParams, Ctrl*,
-                                             int, int, double*, double*);
+                                             Seg*, int, int, double*, double*);
 template __global__ void stage_f32_kernel<2>(DevMesh, TileMap, CellF*, CellF*, StepParams, Ctrl*,
-                                             int, int, double*, double*);
+                                             Seg*, int, int, double*, double*);
 
 // Free surface at the gauge cells after step `step` (see gauge_kernel).
 __global__ void gauge_f32_kernel(const CellF* __restrict__ W, const int64_t* __restrict__ cells,
-                                 int ng, const Ctrl* c, int step, double* __restrict__ log) {
+                                 int ng, const uint32_t* __restrict__ tinfo, const Seg* sg,
+                                 int step, double* __restrict__ log) {
     const int gi = int(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gi >= ng || c->steps_done <= step) return;
-    const CellF q = W[cells[gi]];
+    if (gi >= ng) return;
+    const int64_t k = cells[gi];
+    if (sg[tinfo[k / kTile] >> 9].steps_done <= step) return;
+    const CellF q = W[k];
     log[int64_t(step) * ng + gi] = (double(q.eta) + q.h) - q.h;
 }
 
@@ -417,6 +425,7 @@ __global__ void pack_state_f32_kernel(int64_t n, const int64_t* __restrict__ per
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t k = perm[i];
+    if (k < 0) return;
     const CellF q = store_state(h[i], H[k] - h[i], HU[k], HV[k], !(H[k] > 0.0));
     W[i] = q;
     W1[i] = q;
@@ -429,6 +438,7 @@ __global__ void unpack_state_f32_kernel(int64_t n, const int64_t* __restrict__ p
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t k = perm[i];
+    if (k < 0) return;
     const CellF q = W[i];
     if (H) H[k] = double(q.eta) + q.h;
     if (HU) HU[k] = double(q.hu);

@@ -301,4 +301,103 @@ void build_tiles(const HostMesh& hm, int tile, TileMapHost& out) {
     out.bstart[out.ntiles] = int32_t(out.bitem.size());
 }
 
+int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* vy,
+                   const int64_t* nc, const int32_t* tri, const double* h, int ordering,
+                   uint64_t seed, int tile, EnsembleMesh& out, std::string& err) {
+    if (nseg <= 0 || !nv || !nc) {
+        err = "empty ensemble or NULL count array";
+        return VSW_EINVAL;
+    }
+    out = EnsembleMesh();
+    out.nseg = nseg;
+    out.off.assign(size_t(nseg) + 1, 0);
+    out.coff.assign(size_t(nseg) + 1, 0);
+    for (int s = 0; s < nseg; ++s) {
+        if (nc[s] <= 0 || nv[s] <= 0 || nc[s] > kMaxCells) {
+            err = "scenario " + std::to_string(s) + ": empty or oversized mesh";
+            return VSW_EINVAL;
+        }
+        out.coff[s + 1] = out.coff[s] + nc[s];
+        out.off[s + 1] = out.off[s] + (nc[s] + tile - 1) / tile * tile;
+        if (out.off[s + 1] > kMaxCells) {
+            err = "ensemble too large for 29-bit cell indices";
+            return VSW_EINVAL;
+        }
+    }
+    out.ncell = out.coff[nseg];
+    const int64_t N = out.off[nseg];
+    const int ntiles = int(N / tile);
+    HostMesh& hm = out.hm;
+    TileMapHost& tm = out.tiles;
+    if (nseg == 1) {  // one mesh: no copy
+        int rc = build_host_mesh(nv[0], vx, vy, nc[0], tri, h, ordering, seed, hm, err);
+        if (rc) return rc;
+        build_tiles(hm, tile, tm);
+    } else {
+        hm.nc = N;
+        hm.perm.assign(size_t(N), -1);
+        hm.nbr.assign(3 * size_t(N), kWall);
+        hm.face_geom.assign(size_t(G_NFACE) * 3 * size_t(N), 0.0);
+        hm.area.assign(size_t(N), 0.0);
+        hm.perim.assign(size_t(N), 0.0);
+        hm.h.assign(size_t(N), 0.0);
+        tm.tile = tile;
+        tm.ntiles = ntiles;
+        tm.nloc.assign(3 * size_t(N), kNlocWall);
+        tm.bstart.assign(size_t(ntiles) + 1, 0);
+        tm.bmax = 0;
+        int64_t vo = 0;
+        for (int s = 0; s < nseg; ++s) {
+            HostMesh p;
+            int rc = build_host_mesh(nv[s], vx + vo, vy + vo, nc[s], tri + 3 * out.coff[s],
+                                     h + out.coff[s], ordering, seed + uint64_t(s), p, err);
+            if (rc) {
+                err = "scenario " + std::to_string(s) + ": " + err;
+                return rc;
+            }
+            TileMapHost pt;
+            build_tiles(p, tile, pt);
+            vo += nv[s];
+            const int64_t o = out.off[s], n = p.nc;
+            hm.ne += p.ne;
+            hm.nw += p.nw;
+            hm.nv += p.nv;
+            for (int64_t i = 0; i < n; ++i) {
+                hm.perm[o + i] = out.coff[s] + p.perm[i];
+                hm.area[o + i] = p.area[i];
+                hm.perim[o + i] = p.perim[i];
+                hm.h[o + i] = p.h[i];
+                for (int j = 0; j < 3; ++j) {
+                    const uint32_t sl = p.nbr[size_t(j) * n + i];
+                    hm.nbr[size_t(j) * N + o + i] =
+                        sl == kWall ? kWall : (uint32_t((sl >> 3) + o) << 3) | (sl & 7u);
+                    tm.nloc[size_t(j) * N + o + i] = pt.nloc[size_t(j) * n + i];
+                    for (int f = 0; f < G_NFACE; ++f)
+                        hm.face_geom[(size_t(f) * 3 + j) * N + o + i] =
+                            p.face_geom[(size_t(f) * 3 + j) * n + i];
+                }
+            }
+            const int t0 = int(o / tile);
+            const int32_t b0 = int32_t(tm.bitem.size());
+            for (int t = 0; t < pt.ntiles; ++t) tm.bstart[t0 + t] = b0 + pt.bstart[t];
+            for (uint32_t it : pt.bitem)
+                tm.bitem.push_back((uint32_t((it >> 2) + o) << 2) | (it & 3u));
+            tm.bmax = std::max(tm.bmax, pt.bmax);
+            // padding tiles cannot occur: each scenario's tiles end at off[s + 1]
+        }
+        tm.bstart[ntiles] = int32_t(tm.bitem.size());
+    }
+    out.tinfo.assign(size_t(ntiles), 0u);
+    for (int s = 0; s < nseg; ++s) {
+        const int t0 = int(out.off[s] / tile), t1 = int(out.off[s + 1] / tile);
+        const int64_t cend = out.off[s] + nc[s];
+        for (int t = t0; t < t1; ++t) {
+            const int64_t c0 = int64_t(t) * tile;
+            const int cnt = int(std::min<int64_t>(tile, cend - c0));
+            out.tinfo[t] = (uint32_t(s) << 9) | (t == t0 ? 0x100u : 0u) | uint32_t(cnt - 1);
+        }
+    }
+    return VSW_OK;
+}
+
 }  // namespace vsw

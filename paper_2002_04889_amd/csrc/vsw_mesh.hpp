@@ -55,6 +55,29 @@ struct TileMapHost {
 
 void build_tiles(const HostMesh& hm, int tile, TileMapHost& out);
 
+// Several independent meshes (an ensemble of scenarios) in one internal
+// numbering: scenario s owns the internal cells [off[s], off[s] + nc_s),
+// with off[s] a multiple of the tile size, so no tile spans two scenarios;
+// the cells between one scenario's end and the next tile are padding
+// (perm = -1, never read).  The caller numbers cells by concatenating the
+// scenarios: caller index coff[s] + k for cell k of scenario s.
+struct EnsembleMesh {
+    int nseg = 0;
+    int64_t ncell = 0;              // caller cells, sum of nc_s
+    std::vector<int64_t> off;       // [nseg + 1] internal offsets; off[nseg] = internal count
+    std::vector<int64_t> coff;      // [nseg + 1] caller offsets
+    HostMesh hm;                    // over all internal cells; perm = caller index or -1
+    TileMapHost tiles;
+    std::vector<uint32_t> tinfo;    // [ntiles] (scenario << 9) | (first << 8) | (cells - 1)
+};
+
+// nv[s], nc[s]: vertex and cell counts of scenario s; vx, vy, tri, h hold
+// the scenarios' arrays one after the other, tri indexing the scenario's own
+// vertices.  Scenario s is renumbered with seed + s.
+int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* vy,
+                   const int64_t* nc, const int32_t* tri, const double* h, int ordering,
+                   uint64_t seed, int tile, EnsembleMesh& out, std::string& err);
+
 // Returns 0 or a VSW_E* code with a message in err.
 int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
                     const int32_t* tri, const double* h, int ordering, uint64_t seed,

@@ -51,6 +51,10 @@ _SIGS = {
     "vsw_create": (ctypes.c_int, [ctypes.POINTER(VswParams), ctypes.c_int, ctypes.POINTER(_vp)]),
     "vsw_destroy": (None, [_vp]),
     "vsw_upload_mesh": (ctypes.c_int, [_vp, _i64, _dp, _dp, _i64, _ip, _dp]),
+    "vsw_upload_ensemble": (ctypes.c_int, [_vp, ctypes.c_int32, _lp, _dp, _dp, _lp, _ip, _dp]),
+    "vsw_scenario_count": (ctypes.c_int, [_vp, _ip]),
+    "vsw_scenario_status": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, _lp]),
+    "vsw_scenario_dt_history": (ctypes.c_int, [_vp, ctypes.c_int32, _i64, _dp, _lp]),
     "vsw_set_state": (ctypes.c_int, [_vp, _dp, _dp, _dp, _d]),
     "vsw_set_state_device": (ctypes.c_int, [_vp, _vp, _vp, _vp, _d]),
     "vsw_step": (ctypes.c_int, [_vp, _i64, _d, _lp, _dp]),
@@ -136,6 +140,42 @@ def vsw_upload_mesh(h, vx, vy, tri, depth):
     tri = np.ascontiguousarray(tri, dtype=np.int32)
     return _check(lib().vsw_upload_mesh(h, len(vx), _dptr(vx), _dptr(vy), tri.size // 3,
                                         tri.ctypes.data_as(_ip), _dptr(depth)))
+
+
+def vsw_upload_ensemble(h, meshes):
+    """meshes: sequence of (vx, vy, tri, depth), one per scenario."""
+    nv = np.array([len(m[0]) for m in meshes], dtype=np.int64)
+    nc = np.array([np.asarray(m[2]).size // 3 for m in meshes], dtype=np.int64)
+    vx = _f64(np.concatenate([np.asarray(m[0], dtype=np.float64) for m in meshes]))
+    vy = _f64(np.concatenate([np.asarray(m[1], dtype=np.float64) for m in meshes]))
+    tri = np.ascontiguousarray(np.concatenate([np.asarray(m[2], dtype=np.int32).reshape(-1)
+                                               for m in meshes]))
+    depth = _f64(np.concatenate([np.asarray(m[3], dtype=np.float64) for m in meshes]))
+    return _check(lib().vsw_upload_ensemble(h, len(meshes), nv.ctypes.data_as(_lp), _dptr(vx),
+                                            _dptr(vy), nc.ctypes.data_as(_lp),
+                                            tri.ctypes.data_as(_ip), _dptr(depth)))
+
+
+def vsw_scenario_count(h):
+    n = ctypes.c_int32(0)
+    _check(lib().vsw_scenario_count(h, ctypes.byref(n)))
+    return n.value
+
+
+def vsw_scenario_status(h):
+    n = vsw_scenario_count(h)
+    t, dt = np.empty(n), np.empty(n)
+    steps = np.empty(n, dtype=np.int64)
+    _check(lib().vsw_scenario_status(h, n, _dptr(t), _dptr(dt), steps.ctypes.data_as(_lp)))
+    return t, dt, steps
+
+
+def vsw_scenario_dt_history(h, scen):
+    n = ctypes.c_int64(0)
+    _check(lib().vsw_scenario_dt_history(h, int(scen), 0, None, ctypes.byref(n)))
+    out = np.empty(n.value)
+    _check(lib().vsw_scenario_dt_history(h, int(scen), n.value, _dptr(out), ctypes.byref(n)))
+    return out
 
 
 def vsw_set_state(h, H, HU, HV, t=0.0):
@@ -302,6 +342,22 @@ class Solver:
     def upload_mesh(self, vx, vy, tri, depth):
         vsw_upload_mesh(self.h, vx, vy, tri, depth)
         self.nc = int(np.asarray(tri).size // 3)
+
+    def upload_ensemble(self, meshes):
+        vsw_upload_ensemble(self.h, meshes)
+        self.nc = int(sum(np.asarray(m[2]).size // 3 for m in meshes))
+
+    @classmethod
+    def for_ensemble(cls, cases, **kw):
+        """One solver over several cases (same g, CFL, H_thr), state set."""
+        c0 = cases[0]
+        d = dict(g=c0.g, cfl=c0.cfl, h_threshold=c0.h_threshold)
+        d.update(kw)
+        s = cls(**d)
+        s.upload_ensemble([(c.vx, c.vy, c.tri, c.h) for c in cases])
+        s.set_state(np.concatenate([c.H for c in cases]), np.concatenate([c.HU for c in cases]),
+                    np.concatenate([c.HV for c in cases]), c0.t0)
+        return s
 
     def set_state(self, H, HU, HV, t=0.0):
         vsw_set_state(self.h, H, HU, HV, t)

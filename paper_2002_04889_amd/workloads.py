@@ -20,6 +20,8 @@ Cases:
 * ``coastal_case``   -- 1000 x 1000 km graded coastal mesh (12M triangles,
   50 m to 5 km, fractal coastline, 15% dry cells, elliptical uplift): the
   workload large enough that its state does not fit in the on-chip caches.
+* ``ensemble_cases`` -- 64 basin-style scenarios of 50k to 500k triangles
+  (log-uniform), each with its own mesh, seamounts and uplift.
 * ``channel_case``   -- long flat channel with a dam over a dry bed, for the
   Ritter closed-form solution.
 
@@ -253,12 +255,14 @@ BASIN_K_1M = 0.0047
 def basin_case(k_grade: float = BASIN_K_1M, k: int = 1, smin: float = 250.0,
                smax: float = 2000.0, scale: float = 1.0, eta_amp: float = 2.0,
                cfl: float = 0.45, h_threshold: float = 1e-3,
-               n_mounts: int = 12) -> Case:
+               n_mounts: int = 12, hump=None) -> Case:
     """Synthetic 500 x 500 km ocean basin (stand-in for the real case).
 
-    ``scale`` multiplies both mesh sizes, which gives small meshes of the same
-    shape for tests (scale=8 gives about 16k triangles).  ``eta_amp=0`` is the
-    lake-at-rest variant."""
+    ``scale`` multiplies both mesh sizes (not the grading slope), which gives
+    small meshes of the same shape for tests (scale=8 gives about 61k
+    triangles; scaling k_grade too scales the whole size field).  ``eta_amp=0`` is the
+    lake-at-rest variant.  ``hump`` = (x0, y0, amplitude, sigma) replaces the
+    default Gaussian initial hump (200 km, 250 km, eta_amp, 20 km)."""
     rm, rb, ri = streams(k)
     size = basin_size_field(k_grade, smin * scale, smax * scale)
     px, py = _graded_columns(BASIN_L, BASIN_L, size, rm)
@@ -274,8 +278,8 @@ def basin_case(k_grade: float = BASIN_K_1M, k: int = 1, smin: float = 250.0,
     cy = (vy[tri[:, 0]] + vy[tri[:, 1]] + vy[tri[:, 2]]) / 3.0
     z = basin_bed(cx, cy, mounts)
     h = -z
-    sig0 = 20e3
-    eta0 = eta_amp * np.exp(-((cx - 200e3) ** 2 + (cy - 250e3) ** 2) / (2.0 * sig0 * sig0))
+    hx, hy, ha, sig0 = hump if hump is not None else (200e3, 250e3, eta_amp, 20e3)
+    eta0 = ha * np.exp(-((cx - hx) ** 2 + (cy - hy) ** 2) / (2.0 * sig0 * sig0))
     H = np.maximum(0.0, eta0 + h)
     HU = np.zeros_like(H)
     HV = np.zeros_like(H)
@@ -283,6 +287,33 @@ def basin_case(k_grade: float = BASIN_K_1M, k: int = 1, smin: float = 250.0,
                 HU=HU, HV=HV, cfl=cfl, h_threshold=h_threshold,
                 info={"k_grade": k_grade, "scale": scale, "seed": SEED_BASE + k,
                       "mounts": mounts, "eta_amp": eta_amp})
+
+
+# ---------------------------------------------------------------- ensemble
+
+def ensemble_cases(n_scen: int = 64, nmin: float = 5e4, nmax: float = 5e5, k: int = 3,
+                   size_scale: float = 1.0, log=None):
+    """Uneven-size scenario ensemble of basin-style meshes.
+
+    Scenario i: target size N_i = round(exp U(ln nmin, ln nmax)) triangles
+    (log-uniform), a basin whose whole size field is scaled by sqrt(1M / N_i)
+    (times ``size_scale``), with its own mesh, seamount and point seeds
+    (stream 1000 + i) and its own Gaussian uplift: centre U(50, 350) x
+    U(50, 450) km, amplitude U(0.5, 5) m, width sigma U(10, 40) km.
+    Returns the list of cases and the drawn parameters."""
+    rng = np.random.default_rng(SEED_BASE + k)
+    targets = np.round(np.exp(rng.uniform(math.log(nmin), math.log(nmax), n_scen))).astype(int)
+    humps = [(rng.uniform(50e3, 350e3), rng.uniform(50e3, 450e3), rng.uniform(0.5, 5.0),
+              rng.uniform(10e3, 40e3)) for _ in range(n_scen)]
+    cases = []
+    for i in range(n_scen):
+        sc = math.sqrt(1.0e6 / targets[i]) * size_scale
+        c = basin_case(k_grade=BASIN_K_1M * sc, k=1000 + i, scale=sc, hump=humps[i])
+        c.name = f"ens{i}-{c.nc}"
+        cases.append(c)
+        if log:
+            log(f"ensemble scenario {i}: {c.nc} cells (target {targets[i]})")
+    return cases, {"targets": targets.tolist(), "humps": humps}
 
 
 # ---------------------------------------------------------------- channel
