@@ -144,6 +144,96 @@ def run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, precision, ordering, st
     return leg, s
 
 
+def bench_ensemble(args, torch, vsw, W):
+    """Uneven-size scenario ensemble: every scenario advances `steps` steps
+    (one run) with its own dt, all scenarios in the same launches, FP32.
+    value = ensemble runs/s = scenarios / seconds for the timed steps."""
+    steps = args.steps if args.steps is not None else 500
+    warmup = args.warmup if args.warmup is not None else 10
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    cases, info = W.ensemble_cases(size_scale=args.scale, log=None)
+    nsc = len(cases)
+    ncell = sum(c.nc for c in cases)
+    log(f"[bench] ensemble: {nsc} scenarios, {ncell} cells ({min(c.nc for c in cases)}-"
+        f"{max(c.nc for c in cases)}), generated in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.Stream(device=dev)
+
+    def ensemble_leg(precision, graph, label):
+        s = vsw.Solver.for_ensemble(cases, precision=precision)
+        try:
+            vsw.vsw_set_stream(s.h, stream.cuda_stream)
+            vsw.vsw_set_graph(s.h, graph)
+            s.step(warmup)
+            ms = time_steps(torch, stream, s, steps)
+            ts, dts, st = vsw.vsw_scenario_status(s.h)
+            assert (st == steps).all(), st
+            leg = {"runs_per_s": nsc / (ms / 1e3), "ms_per_step": ms / steps,
+                   "cell_updates_per_s": ncell * steps / (ms / 1e3), "graph": graph,
+                   "scenario_dt_range_s": [float(dts.min()), float(dts.max())]}
+            log(f"[bench] {label}: {steps} steps {ms:.1f} ms, {leg['runs_per_s']:.2f} runs/s, "
+                f"{leg['cell_updates_per_s']:.3e} cell-updates/s")
+            if not graph:
+                b1, b2 = ((ALG_BYTES_STAGE1, ALG_BYTES_STAGE2) if precision == vsw.VSW_FP64
+                          else (ALG_BYTES_STAGE1_F32, ALG_BYTES_STAGE2_F32))
+                leg["roofline"] = kernel_roofline(vsw, s, min(steps, 100), ncell, b1, b2)
+            return leg
+        finally:
+            s.close()
+
+    legs = {}
+    legs["fp32_graph"] = ensemble_leg(vsw.VSW_FP32, True, "ensemble fp32, graph")
+    legs["fp32_direct"] = ensemble_leg(vsw.VSW_FP32, False, "ensemble fp32, direct launches")
+    if not args.no_fp64:
+        legs["fp64_graph"] = ensemble_leg(vsw.VSW_FP64, True, "ensemble fp64, graph")
+    # the same runs one scenario after another on the same GPU
+    seq_ms = 0.0
+    for c in cases:
+        s = vsw.Solver.for_case(c, precision=vsw.VSW_FP32)
+        try:
+            vsw.vsw_set_stream(s.h, stream.cuda_stream)
+            vsw.vsw_set_graph(s.h, True)
+            s.step(warmup)
+            seq_ms += time_steps(torch, stream, s, steps)
+        finally:
+            s.close()
+    seq = {"runs_per_s": nsc / (seq_ms / 1e3), "ms_total": seq_ms, "graph": True}
+    log(f"[bench] sequential fp32: {nsc} runs in {seq_ms:.1f} ms, {seq['runs_per_s']:.2f} runs/s")
+    top = legs.pop("fp32_graph")
+    out = {"metric": "ensemble runs/s", "value": top["runs_per_s"], "unit": "runs/s",
+           "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": top["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"uneven-size scenario ensemble: {nsc} basin-style meshes, "
+                                  f"{ncell} triangles in total (log-uniform 50k-500k), own "
+                                  "uplift and dt per scenario, one run = "
+                                  f"{steps} steps", "scenarios": nsc, "cells": ncell,
+                      "precision": "fp32 state, fp64 accumulation", "ordering": "hilbert",
+                      "global_batch": ncell, "parallelism": "single-gpu"},
+           "cell_updates_per_s": top["cell_updates_per_s"],
+           "roofline": legs["fp32_direct"].get("roofline"),
+           "vs_sequential": top["runs_per_s"] / seq["runs_per_s"],
+           "sequential_fp32": seq}
+    out.update(legs)
+    if not args.no_cpu_baseline:
+        import oracle
+
+        csteps = args.cpu_steps if args.cpu_steps is not None else 2
+        el = 0.0
+        for c in cases:
+            m = oracle.Mesh.from_case(c)
+            p = oracle.params(g=c.g, cfl=c.cfl, h_threshold=c.h_threshold)
+            tt = time.perf_counter()
+            m.run(p, c.H, c.HU, c.HV, 0.0, csteps)
+            el += time.perf_counter() - tt
+        out["cpu_baseline"] = {"value": nsc / (el * steps / csteps), "unit": "runs/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{csteps} steps of each of the {nsc} scenarios, "
+                                         f"single-threaded C oracle, {el:.1f} s, scaled to "
+                                         f"{steps}-step runs"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,10 +241,11 @@ def main():
                     help="timed steps (default 2000 basin, 1000 coastal)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps before timing (default 100 basin, 20 coastal)")
-    ap.add_argument("--workload", choices=["basin", "coastal"], default="basin",
+    ap.add_argument("--workload", choices=["basin", "coastal", "ensemble"], default="basin",
                     help="basin: 1M-triangle ocean basin, FP64 (and the FP32 leg); coastal: "
                          "12M-triangle coastal mesh, FP32 and FP64 in Hilbert and random "
-                         "cell order")
+                         "cell order; ensemble: 64 uneven scenarios, ensemble runs/s")
+    ap.add_argument("--no-fp64", action="store_true", help="ensemble: skip the FP64 leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-random", action="store_true",
@@ -174,6 +265,15 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "sharding of this solver is a design note, not a built path.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "ensemble":
+        import torch
+
+        from paper_2002_04889_amd import vsw
+        from paper_2002_04889_amd import workloads as W
+
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        bench_ensemble(args, torch, vsw, W)
+        return
     coastal = args.workload == "coastal"
     steps = args.steps if args.steps is not None else (1000 if coastal else 2000)
     warmup = args.warmup if args.warmup is not None else (20 if coastal else 100)

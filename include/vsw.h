@@ -192,6 +192,15 @@ int vsw_set_stream(vsw_solver *s, void *hip_stream);
 enum { VSW_KERNEL_FUSED = 0, VSW_KERNEL_TWO_PASS = 1 };
 int vsw_set_kernel_variant(vsw_solver *s, int variant);
 
+/* Graph mode (off by default): vsw_step captures one pair of steps (their
+ * kernel launches and a one-thread kernel that advances the device-side
+ * step index) into a HIP graph once and replays it n / 2 times, an odd last
+ * step launched directly; results are bitwise the same as without it.  The
+ * graph holds kernel nodes only and is captured again when the mesh, the
+ * gauges, t_stop, the kernel variant or the log buffers change.  Profiling
+ * (vsw_set_profiling) launches directly.  on = 0 frees the graph. */
+int vsw_set_graph(vsw_solver *s, int on);
+
 /* Per-kernel timing with HIP events recorded around every launch of the
  * stage kernels on the solver's stream (off by default).  vsw_kernel_times
  * returns, for kernel kinds 0..nkinds-1 (see vsw_kernel_name), the summed

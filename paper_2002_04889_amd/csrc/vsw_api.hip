@@ -37,6 +37,22 @@ enum KernelKind { KK_RECON = 0, KK_UPDATE1, KK_UPDATE2, KK_DTINIT, KK_STAGE1, KK
 const char* kKernelNames[KK_COUNT] = {"recon_kernel",   "update1_kernel", "update2_kernel",
                                       "dt_init_kernel", "stage1_kernel",  "stage2_kernel"};
 
+// Everything a captured step pair bakes into its launch arguments besides
+// the mesh (a new mesh drops the graph).
+struct GraphKey {
+    const double* log;
+    const double* gauge_log;
+    const int64_t* gauge_cells;
+    int ngauges;
+    double t_stop;
+    int variant;
+    bool operator==(const GraphKey& o) const {
+        return log == o.log && gauge_log == o.gauge_log && gauge_cells == o.gauge_cells &&
+               ngauges == o.ngauges && (t_stop == o.t_stop || (t_stop != t_stop && o.t_stop != o.t_stop)) &&
+               variant == o.variant;
+    }
+};
+
 template <class T>
 struct DevBuf {
     T* p = nullptr;
@@ -71,7 +87,6 @@ struct vsw_solver {
     std::vector<double> seg_dt;       // last dt of each scenario
     std::vector<int64_t> seg_steps;   // steps each scenario took in the last call
     std::vector<double> seg_log;      // last call's dt log, [step][scenario]
-    int64_t log_steps = 0;
     std::vector<int64_t> perm;        // internal -> caller, -1 on padding
     DevBuf<int64_t> d_perm;
     DevBuf<Nbr4> d_nbr;            // neighbour slots per cell
@@ -100,6 +115,16 @@ struct vsw_solver {
     DevBuf<uint32_t> d_bitem;
     int bmax = 0, ntiles = 0;
     int variant = VSW_KERNEL_FUSED;
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    GraphKey graph_key{};
+    void release_graph() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+    }
     double t = 0.0;
     double dt_last = 0.0;
     int64_t clamps = 0;
@@ -112,6 +137,7 @@ struct vsw_solver {
     std::vector<double> last_dts;
 
     void release_mesh() {
+        release_graph();
         d_perm.release(); d_nbr.release(); d_geom.release(); d_area.release();
         d_rgeom.release();
         d_perim.release(); d_h.release(); d_w.release(); d_w1.release();
@@ -230,6 +256,7 @@ void vsw_destroy(vsw_solver* s) {
     DeviceGuard dg(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     s->release_mesh();
+    s->release_graph();
     s->d_log.release();
     s->d_ctrl.release();
     s->d_gauge_log.release();
@@ -434,10 +461,10 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     DeviceGuard dg(s->device);
     const int nseg = s->nseg;
     const size_t nlog = size_t(n) * size_t(nseg);
-    if (s->d_log.n < 2 * nlog) HIP_TRY(s->d_log.alloc(2 * nlog));
+    if (s->d_log.n < 2 * nlog) HIP_TRY(s->d_log.alloc(std::max(2 * nlog, 2 * s->d_log.n)));
     const int ng = s->ngauges;
     if (ng > 0 && s->d_gauge_log.n < size_t(n) * size_t(ng))
-        HIP_TRY(s->d_gauge_log.alloc(size_t(n) * size_t(ng)));
+        HIP_TRY(s->d_gauge_log.alloc(std::max(size_t(n) * size_t(ng), 2 * s->d_gauge_log.n)));
     const DevMesh m = s->dev_mesh();
     StepParams p;
     p.g = s->prm.g;
@@ -451,15 +478,19 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     FaceBuf fb{s->d_face.p, s->d_sc.p, s->d_order.p};
     Ctrl* c = s->d_ctrl.p;
     Seg* sg = s->d_seg.p;
-    double* tlog = s->d_log.p;
-    double* dtlog = s->d_log.p + nlog;
+    double* lg = s->d_log.p;
     const dim3 grid(unsigned(s->ntiles)), block(kBlock);
     hipStream_t st = s->stream;
+    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, nseg};
+    const bool f32 = (s->prm.precision == VSW_FP32);
+    const size_t lds = stage_lds_bytes(s->bmax);
+    const size_t lds32 = stage_f32_lds_bytes(s->bmax);
 
     // profiling events: one pair per timed launch
     size_t ev_used = 0;
-    auto ev_begin = [&](int kind) {
-        if (!s->profiling) return;
+    bool prof = s->profiling;
+    auto ev_begin = [&](int kind, hipStream_t q) {
+        if (!prof) return;
         if (ev_used + 2 > s->ev_pool.size()) {
             for (int i = 0; i < 64; ++i) {
                 hipEvent_t e;
@@ -468,82 +499,105 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
             }
         }
         if (ev_used + 2 > s->ev_pool.size()) return;
-        (void)hipEventRecord(s->ev_pool[ev_used], st);
+        (void)hipEventRecord(s->ev_pool[ev_used], q);
         if (s->ev_kind.size() < s->ev_pool.size() / 2 + 1) s->ev_kind.resize(s->ev_pool.size() / 2 + 1);
         s->ev_kind[ev_used / 2] = kind;
     };
-    auto ev_end = [&]() {
-        if (!s->profiling || ev_used + 2 > s->ev_pool.size()) return;
-        (void)hipEventRecord(s->ev_pool[ev_used + 1], st);
+    auto ev_end = [&](hipStream_t q) {
+        if (!prof || ev_used + 2 > s->ev_pool.size()) return;
+        (void)hipEventRecord(s->ev_pool[ev_used + 1], q);
         ev_used += 2;
     };
+    // One step on stream q with control slot `slot`; its index is the
+    // device step base plus sa.
+    auto launch_step = [&](hipStream_t q, int slot, int sa) {
+        const dim3 gg(unsigned((ng + 63) / 64));
+        if (f32) {
+            ev_begin(KK_STAGE1, q);
+            hipLaunchKernelGGL(stage_f32_kernel<1>, grid, block, lds32, q, m, tm, s->d_wf.p,
+                               s->d_w1f.p, p, c, sg, slot, sa, lg);
+            ev_end(q);
+            ev_begin(KK_STAGE2, q);
+            hipLaunchKernelGGL(stage_f32_kernel<2>, grid, block, lds32, q, m, tm, s->d_wf.p,
+                               s->d_w1f.p, p, c, sg, slot, sa, lg);
+            ev_end(q);
+            if (ng > 0)
+                hipLaunchKernelGGL(gauge_f32_kernel, gg, dim3(64), 0, q, s->d_wf.p,
+                                   s->d_gauge_cells.p, ng, s->d_tinfo.p, sg, c, sa,
+                                   s->d_gauge_log.p);
+            return;
+        }
+        if (s->variant == VSW_KERNEL_FUSED) {
+            ev_begin(KK_STAGE1, q);
+            hipLaunchKernelGGL(stage_kernel<1>, grid, block, lds, q, m, tm, W, W1, p, c, sg, slot,
+                               sa, lg);
+            ev_end(q);
+            ev_begin(KK_STAGE2, q);
+            hipLaunchKernelGGL(stage_kernel<2>, grid, block, lds, q, m, tm, W, W1, p, c, sg, slot,
+                               sa, lg);
+            ev_end(q);
+        } else {
+            ev_begin(KK_RECON, q);
+            hipLaunchKernelGGL(recon_kernel, grid, block, 0, q, m, tm, W, fb, p, c, sg, slot);
+            ev_end(q);
+            ev_begin(KK_UPDATE1, q);
+            hipLaunchKernelGGL(update1_kernel, grid, block, 0, q, m, tm, W, W1, fb, p, c, sg,
+                               slot);
+            ev_end(q);
+            ev_begin(KK_RECON, q);
+            hipLaunchKernelGGL(recon_kernel, grid, block, 0, q, m, tm, W1, fb, p, c, sg, slot);
+            ev_end(q);
+            ev_begin(KK_UPDATE2, q);
+            hipLaunchKernelGGL(update2_kernel, grid, block, 0, q, m, tm, W, W1, fb, p, c, sg, slot,
+                               sa, lg);
+            ev_end(q);
+        }
+        if (ng > 0)
+            hipLaunchKernelGGL(gauge_kernel, gg, dim3(64), 0, q, W, s->d_gauge_cells.p, ng,
+                               s->d_tinfo.p, sg, c, sa, s->d_gauge_log.p);
+    };
+
+    // Graph mode: a captured pair of steps followed by a step-base bump,
+    // replayed n / 2 times (kernel nodes only).  Rebuilt when anything baked
+    // into its launch arguments changes.
+    const bool use_graph = s->use_graph && !prof && n >= 2;
+    if (use_graph) {
+        const GraphKey key{lg, s->d_gauge_log.p, s->d_gauge_cells.p, ng, t_stop, s->variant};
+        if (!s->graph_exec || !(key == s->graph_key)) {
+            s->release_graph();
+            prof = false;
+            hipStream_t cs = s->own_stream;
+            HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            launch_step(cs, 0, 0);
+            launch_step(cs, 1, 1);
+            hipLaunchKernelGGL(step_bump_kernel, dim3(1), dim3(64), 0, cs, c, 2);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(cs, &g);
+            if (ec != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(VSW_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+            }
+            s->graph = g;
+            HIP_TRY(hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0));
+            s->graph_key = key;
+        }
+    }
 
     HIP_TRY(hipMemcpy(s->d_t0.p, s->seg_t.data(), size_t(nseg) * sizeof(double),
                       hipMemcpyHostToDevice));
     hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(256), 0, st, c, sg, nseg, s->d_t0.p);
-    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, nseg};
-    ev_begin(KK_DTINIT);
-    const bool f32 = (s->prm.precision == VSW_FP32);
+    ev_begin(KK_DTINIT, st);
     if (f32)
         hipLaunchKernelGGL(dt_init_f32_kernel, grid, block, 0, st, m, tm, s->d_wf.p, p.g, p.thr,
                            sg);
     else
         hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, tm, W, p.g, p.thr, sg);
-    ev_end();
-    const size_t lds = stage_lds_bytes(s->bmax);
-    const size_t lds32 = stage_f32_lds_bytes(s->bmax);
-    const dim3 tgrid(unsigned(s->ntiles));
-    auto k1 = stage_kernel<1>;
-    auto k2 = stage_kernel<2>;
-    for (int64_t k = 0; f32 && k < n; ++k) {
-        const int slot = int(k & 1);
-        ev_begin(KK_STAGE1);
-        hipLaunchKernelGGL(stage_f32_kernel<1>, tgrid, block, lds32, st, m, tm, s->d_wf.p,
-                           s->d_w1f.p, p, c, sg, slot, int(k), tlog, dtlog);
-        ev_end();
-        ev_begin(KK_STAGE2);
-        hipLaunchKernelGGL(stage_f32_kernel<2>, tgrid, block, lds32, st, m, tm, s->d_wf.p,
-                           s->d_w1f.p, p, c, sg, slot, int(k), tlog, dtlog);
-        ev_end();
-        if (ng > 0)
-            hipLaunchKernelGGL(gauge_f32_kernel, dim3(unsigned((ng + 63) / 64)), dim3(64), 0, st,
-                               s->d_wf.p, s->d_gauge_cells.p, ng, s->d_tinfo.p, sg, int(k),
-                               s->d_gauge_log.p);
-    }
-    for (int64_t k = 0; !f32 && s->variant == VSW_KERNEL_FUSED && k < n; ++k) {
-        const int slot = int(k & 1);
-        ev_begin(KK_STAGE1);
-        hipLaunchKernelGGL(k1, tgrid, block, lds, st, m, tm, W, W1, p, c, sg, slot, int(k), tlog,
-                           dtlog);
-        ev_end();
-        ev_begin(KK_STAGE2);
-        hipLaunchKernelGGL(k2, tgrid, block, lds, st, m, tm, W, W1, p, c, sg, slot, int(k), tlog,
-                           dtlog);
-        ev_end();
-        if (ng > 0)
-            hipLaunchKernelGGL(gauge_kernel, dim3(unsigned((ng + 63) / 64)), dim3(64), 0, st, W,
-                               s->d_gauge_cells.p, ng, s->d_tinfo.p, sg, int(k),
-                               s->d_gauge_log.p);
-    }
-    for (int64_t k = 0; !f32 && s->variant == VSW_KERNEL_TWO_PASS && k < n; ++k) {
-        const int slot = int(k & 1);
-        ev_begin(KK_RECON);
-        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, tm, W, fb, p, c, sg, slot);
-        ev_end();
-        ev_begin(KK_UPDATE1);
-        hipLaunchKernelGGL(update1_kernel, grid, block, 0, st, m, tm, W, W1, fb, p, c, sg, slot);
-        ev_end();
-        ev_begin(KK_RECON);
-        hipLaunchKernelGGL(recon_kernel, grid, block, 0, st, m, tm, W1, fb, p, c, sg, slot);
-        ev_end();
-        ev_begin(KK_UPDATE2);
-        hipLaunchKernelGGL(update2_kernel, grid, block, 0, st, m, tm, W, W1, fb, p, c, sg, slot,
-                           int(k), tlog, dtlog);
-        ev_end();
-        if (ng > 0)
-            hipLaunchKernelGGL(gauge_kernel, dim3(unsigned((ng + 63) / 64)), dim3(64), 0, st, W,
-                               s->d_gauge_cells.p, ng, s->d_tinfo.p, sg, int(k),
-                               s->d_gauge_log.p);
+    ev_end(st);
+    if (use_graph) {
+        for (int64_t k = 0; k + 1 < n; k += 2) HIP_TRY(hipGraphLaunch(s->graph_exec, st));
+        if (n & 1) launch_step(st, 0, 0);  // the base is n - 1 here
+    } else {
+        for (int64_t k = 0; k < n; ++k) launch_step(st, int(k & 1), int(k));
     }
     HIP_TRY(hipGetLastError());
     Ctrl hc;
@@ -574,25 +628,24 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     }
     int64_t done = 0;
     double tmin = INFINITY;
-    s->seg_log.assign(logs.begin() + nlog, logs.begin() + 2 * nlog);
     s->seg_log.resize(nlog);
+    for (size_t e = 0; e < nlog; ++e) s->seg_log[e] = logs[2 * e + 1];
     for (int q = 0; q < nseg; ++q) {
         const int64_t d = std::min<int64_t>(hs[q].steps_done, cap);
         s->seg_steps[q] = d;
         if (d > 0) {
-            s->seg_t[q] = logs[size_t(d - 1) * nseg + q];
-            s->seg_dt[q] = logs[nlog + size_t(d - 1) * nseg + q];
+            s->seg_t[q] = logs[2 * (size_t(d - 1) * nseg + q)];
+            s->seg_dt[q] = logs[2 * (size_t(d - 1) * nseg + q) + 1];
         }
         done = std::max(done, d);
         tmin = std::min(tmin, s->seg_t[q]);
     }
-    s->log_steps = n;
     s->clamps += int64_t(hc.clamps);
     s->last_dts.resize(size_t(s->seg_steps[0]));
-    for (int64_t k = 0; k < s->seg_steps[0]; ++k) s->last_dts[k] = logs[nlog + size_t(k) * nseg];
+    for (int64_t k = 0; k < s->seg_steps[0]; ++k) s->last_dts[k] = s->seg_log[size_t(k) * nseg];
     s->gauge_t.assign(size_t(done), s->seg_t[0]);
     for (int64_t k = 0; k < std::min(done, s->seg_steps[0]); ++k)
-        s->gauge_t[k] = logs[size_t(k) * nseg];
+        s->gauge_t[k] = logs[2 * size_t(k) * nseg];
     s->gauge_eta.assign(size_t(done) * size_t(ng), 0.0);
     if (ng > 0 && done > 0)
         HIP_TRY(hipMemcpy(s->gauge_eta.data(), s->d_gauge_log.p,
@@ -700,6 +753,17 @@ int vsw_set_kernel_variant(vsw_solver* s, int variant) {
     if (variant == VSW_KERNEL_TWO_PASS && s->prm.precision == VSW_FP32)
         return fail(VSW_EINVAL, "the two-pass variant is FP64 only");
     s->variant = variant;
+    return VSW_OK;
+}
+
+int vsw_set_graph(vsw_solver* s, int on) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    s->use_graph = on != 0;
+    if (!s->use_graph) {
+        DeviceGuard dg(s->device);
+        (void)hipStreamSynchronize(s->stream);
+        s->release_graph();
+    }
     return VSW_OK;
 }
 

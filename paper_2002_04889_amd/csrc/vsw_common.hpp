@@ -110,15 +110,15 @@ __device__ __forceinline__ void block_count_atomic(unsigned long long v, unsigne
 // the time and the no-valid-dt error.
 __device__ __forceinline__ void stage2_bookkeeping(Ctrl* c, Seg* sg, const TileInfo& ti, int nseg,
                                                    int slot, int step, bool active, double dt,
-                                                   double tn, double t_stop, double* tlog,
-                                                   double* dtlog) {
+                                                   double tn, double t_stop, double* log) {
     if (!ti.first || threadIdx.x != 0) return;
     if (active) {
         sg->t[slot ^ 1] = tn;
         sg->dt_last = dt;
         sg->steps_done += 1;
-        tlog[int64_t(step) * nseg + ti.seg] = tn;
-        dtlog[int64_t(step) * nseg + ti.seg] = dt;
+        const int64_t e = 2 * (int64_t(step) * nseg + ti.seg);
+        log[e] = tn;
+        log[e + 1] = dt;
     } else {
         const double t = sg->t[slot];
         sg->t[slot ^ 1] = t;

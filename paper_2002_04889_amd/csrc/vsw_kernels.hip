@@ -25,6 +25,8 @@ __global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0) {
         c->err = 0;
         c->err_step = 0x7FFFFFFF;
         c->clamps = 0;
+        c->kbase = 0;
+        c->pad = 0;
     }
     for (int s = int(blockIdx.x * blockDim.x + threadIdx.x); s < nseg;
          s += int(gridDim.x * blockDim.x)) {
@@ -36,6 +38,10 @@ __global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0) {
         q.pad[0] = q.pad[1] = 0;
         sg[s] = q;
     }
+}
+
+__global__ void step_bump_kernel(Ctrl* c, int by) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->kbase += by;
 }
 
 __global__ __launch_bounds__(kBlock) void dt_init_kernel(DevMesh m, TileMap tm,
@@ -171,14 +177,14 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, TileMap tm,
                                                          Cell4* __restrict__ W,
                                                          const Cell4* __restrict__ W1, FaceBuf fb,
                                                          StepParams p, Ctrl* c, Seg* sg, int slot,
-                                                         int step, double* tlog, double* dtlog) {
+                                                         int step_arg, double* log) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     Seg* sgs = sg + ti.seg;
+    const int step = c->kbase + step_arg;
     double dt, tn;
     const bool active = step_dt(c, sgs, slot, p, dt, tn);
     if (!active) {
-        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, tlog,
-                           dtlog);
+        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, log);
         return;
     }
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, TileMap tm,
     }
     block_count_atomic(clamp, &c->clamps);
     block_min_atomic(r, &sgs->rmin[slot ^ 1]);
-    stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
+    stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
 }
 
 // ---------------------------------------------------------------- fused stage
@@ -239,19 +245,19 @@ __device__ __forceinline__ Face lds_load_face(const double* lds, int stride, int
 template <int STAGE>
 __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Cell4* __restrict__ W,
                                                        Cell4* __restrict__ W1, StepParams p,
-                                                       Ctrl* c, Seg* sg, int slot, int step,
-                                                       double* tlog, double* dtlog) {
+                                                       Ctrl* c, Seg* sg, int slot, int step_arg,
+                                                       double* log) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
     const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
     const TileInfo ti = tile_info(tm.tinfo[t]);
     Seg* sgs = sg + ti.seg;
+    const int step = c->kbase + step_arg;
     double dt, tn;
     const bool active = step_dt(c, sgs, slot, p, dt, tn);
     if (!active) {
         if (STAGE == 2)
-            stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, tlog,
-                               dtlog);
+            stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, log);
         return;
     }
     if (STAGE == 1 && ti.first && threadIdx.x == 0) sgs->rmin[slot ^ 1] = 0x7FF0000000000000ull;
@@ -328,14 +334,14 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
     block_count_atomic(clamp, &c->clamps);
     if (STAGE == 2) {
         block_min_atomic(rr, &sgs->rmin[slot ^ 1]);
-        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
+        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
     }
 }
 
 template __global__ void stage_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, Seg*,
-                                         int, int, double*, double*);
+                                         int, int, double*);
 template __global__ void stage_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, Seg*,
-                                         int, int, double*, double*);
+                                         int, int, double*);
 
 // ---------------------------------------------------------------- gauges
 
@@ -343,10 +349,11 @@ template __global__ void stage_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepP
 // gauge's scenario took the step (steps_done counts the steps it took in
 // this call; once a scenario stops, it takes no later step of the call).
 __global__ void gauge_kernel(const Cell4* __restrict__ W, const int64_t* __restrict__ cells,
-                             int ng, const uint32_t* __restrict__ tinfo, const Seg* sg, int step,
-                             double* __restrict__ log) {
+                             int ng, const uint32_t* __restrict__ tinfo, const Seg* sg,
+                             const Ctrl* c, int step_arg, double* __restrict__ log) {
     const int gi = int(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gi >= ng) return;
+    const int step = c->kbase + step_arg;
     const int64_t k = cells[gi];
     if (sg[tinfo[k / kTile] >> 9].steps_done <= step) return;
     const Cell4 q = W[k];

@@ -28,6 +28,8 @@ struct Ctrl {
     unsigned long long clamps;   // negative depths set to zero in this call
     int err;                     // bit 0: non-finite state, bit 1: no valid dt
     int err_step;                // first failing step of the call
+    int kbase;                   // step index = kbase + the kernel's step argument
+    int pad;
 };
 
 struct StepParams {
@@ -61,10 +63,12 @@ struct TileMap {
 // Fused stage kernel.  STAGE 1: w1 = w + dt R(w).  STAGE 2:
 // w^{n+1} = w/2 + (w1 + dt R(w1))/2 in place, plus the next CFL minimum and
 // the time bookkeeping.  Dynamic LDS: 5 * (3 * kTile + bmax) doubles.
-// Logs: tlog / dtlog[step * nseg + scenario].
+// Step k of the call is kbase + step_arg (kbase advances on the device, so a
+// captured pair of steps can be replayed).  Log: log[2 (k nseg + scenario)]
+// = time after the step, log[2 (k nseg + scenario) + 1] = its dt.
 template <int STAGE>
 __global__ void stage_kernel(DevMesh m, TileMap tm, Cell4* W, Cell4* W1, StepParams p, Ctrl* c,
-                             Seg* sg, int slot, int step, double* tlog, double* dtlog);
+                             Seg* sg, int slot, int step_arg, double* log);
 
 inline size_t stage_lds_bytes(int bmax) { return sizeof(double) * 5 * size_t(3 * kTile + bmax); }
 
@@ -78,10 +82,12 @@ __global__ void recon_kernel(DevMesh m, TileMap tm, const Cell4* W, FaceBuf fb, 
 __global__ void update1_kernel(DevMesh m, TileMap tm, const Cell4* W, Cell4* W1, FaceBuf fb,
                                StepParams p, Ctrl* c, Seg* sg, int slot);
 __global__ void update2_kernel(DevMesh m, TileMap tm, Cell4* W, const Cell4* W1, FaceBuf fb,
-                               StepParams p, Ctrl* c, Seg* sg, int slot, int step, double* tlog,
-                               double* dtlog);
+                               StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg,
+                               double* log);
 __global__ void gauge_kernel(const Cell4* W, const int64_t* cells, int ng, const uint32_t* tinfo,
-                             const Seg* sg, int step, double* log);
+                             const Seg* sg, const Ctrl* c, int step_arg, double* log);
+// Advance the step base by `by` steps (the last node of a captured pair).
+__global__ void step_bump_kernel(Ctrl* c, int by);
 // perm[i] = caller index of internal cell i, or -1 for the padding cells
 // that round each scenario up to whole tiles (left untouched).
 __global__ void pack_state_kernel(int64_t n, const int64_t* perm, const double* H,

@@ -277,8 +277,8 @@ template <int STAGE>
 __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm,
                                                            CellF* __restrict__ W,
                                                            CellF* __restrict__ W1, StepParams p,
-                                                           Ctrl* c, Seg* sg, int slot, int step,
-                                                           double* tlog, double* dtlog) {
+                                                           Ctrl* c, Seg* sg, int slot,
+                                                           int step_arg, double* log) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
     double* ld = lds;
@@ -286,12 +286,12 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
     const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
     const TileInfo ti = tile_info(tm.tinfo[t]);
     Seg* sgs = sg + ti.seg;
+    const int step = c->kbase + step_arg;
     double dt, tn;
     const bool active = step_dt(c, sgs, slot, p, dt, tn);
     if (!active) {
         if (STAGE == 2)
-            stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, tlog,
-                               dtlog);
+            stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, log);
         return;
     }
     if (STAGE == 1 && ti.first && threadIdx.x == 0) sgs->rmin[slot ^ 1] = 0x7FF0000000000000ull;
@@ -395,21 +395,22 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
     block_count_atomic(clamp, &c->clamps);
     if (STAGE == 2) {
         block_min_atomic(rr, &sgs->rmin[slot ^ 1]);
-        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, tlog, dtlog);
+        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
     }
 }
 
 template __global__ void stage_f32_kernel<1>(DevMesh, TileMap, CellF*, CellF*, StepParams, Ctrl*,
-                                             Seg*, int, int, double*, double*);
+                                             Seg*, int, int, double*);
 template __global__ void stage_f32_kernel<2>(DevMesh, TileMap, CellF*, CellF*, StepParams, Ctrl*,
-                                             Seg*, int, int, double*, double*);
+                                             Seg*, int, int, double*);
 
 // Free surface at the gauge cells after step `step` (see gauge_kernel).
 __global__ void gauge_f32_kernel(const CellF* __restrict__ W, const int64_t* __restrict__ cells,
                                  int ng, const uint32_t* __restrict__ tinfo, const Seg* sg,
-                                 int step, double* __restrict__ log) {
+                                 const Ctrl* c, int step_arg, double* __restrict__ log) {
     const int gi = int(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gi >= ng) return;
+    const int step = c->kbase + step_arg;
     const int64_t k = cells[gi];
     if (sg[tinfo[k / kTile] >> 9].steps_done <= step) return;
     const CellF q = W[k];

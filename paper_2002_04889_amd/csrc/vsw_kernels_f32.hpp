@@ -26,11 +26,12 @@ inline size_t stage_f32_lds_bytes(int bmax) {
 
 template <int STAGE>
 __global__ void stage_f32_kernel(DevMesh m, TileMap tm, CellF* W, CellF* W1, StepParams p, Ctrl* c,
-                                 Seg* sg, int slot, int step, double* tlog, double* dtlog);
+                                 Seg* sg, int slot, int step_arg, double* log);
 __global__ void dt_init_f32_kernel(DevMesh m, TileMap tm, const CellF* W, double g, double thr,
                                    Seg* sg);
 __global__ void gauge_f32_kernel(const CellF* W, const int64_t* cells, int ng,
-                                 const uint32_t* tinfo, const Seg* sg, int step, double* log);
+                                 const uint32_t* tinfo, const Seg* sg, const Ctrl* c, int step_arg,
+                                 double* log);
 __global__ void pack_state_f32_kernel(int64_t n, const int64_t* perm, const double* H,
                                       const double* HU, const double* HV, const double* h,
                                       CellF* W, CellF* W1);

@@ -67,6 +67,7 @@ _SIGS = {
     "vsw_get_gauges": (ctypes.c_int, [_vp, _i64, _dp, _dp, _lp]),
     "vsw_set_stream": (ctypes.c_int, [_vp, _vp]),
     "vsw_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vsw_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_set_kernel_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _lp]),
     "vsw_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -249,6 +250,10 @@ def vsw_set_stream(h, stream_handle: int | None):
 
 def vsw_set_kernel_variant(h, variant: int):
     return _check(lib().vsw_set_kernel_variant(h, int(variant)))
+
+
+def vsw_set_graph(h, on: bool):
+    return _check(lib().vsw_set_graph(h, 1 if on else 0))
 
 
 def vsw_set_profiling(h, on: bool):

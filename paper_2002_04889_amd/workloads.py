@@ -301,10 +301,26 @@ def ensemble_cases(n_scen: int = 64, nmin: float = 5e4, nmax: float = 5e5, k: in
     (stream 1000 + i) and its own Gaussian uplift: centre U(50, 350) x
     U(50, 450) km, amplitude U(0.5, 5) m, width sigma U(10, 40) km.
     Returns the list of cases and the drawn parameters."""
+    import os
+
     rng = np.random.default_rng(SEED_BASE + k)
     targets = np.round(np.exp(rng.uniform(math.log(nmin), math.log(nmax), n_scen))).astype(int)
     humps = [(rng.uniform(50e3, 350e3), rng.uniform(50e3, 450e3), rng.uniform(0.5, 5.0),
               rng.uniform(10e3, 40e3)) for _ in range(n_scen)]
+    info = {"targets": targets.tolist(), "humps": humps}
+    cache = os.environ.get("VSW_CASE_CACHE")
+    path = (os.path.join(cache, f"ensemble_k{k}_{n_scen}_{nmin:g}_{nmax:g}_{size_scale:g}.npz")
+            if cache else None)
+    if path and os.path.exists(path):
+        z = np.load(path)
+        cases = []
+        for i in range(n_scen):
+            v0, v1, c0, c1 = z["voff"][i], z["voff"][i + 1], z["coff"][i], z["coff"][i + 1]
+            c = Case(name=f"ens{i}-{c1 - c0}", vx=z["vx"][v0:v1], vy=z["vy"][v0:v1],
+                     tri=z["tri"][c0:c1], h=z["h"][c0:c1], H=z["H"][c0:c1],
+                     HU=np.zeros(c1 - c0), HV=np.zeros(c1 - c0))
+            cases.append(c)
+        return cases, info
     cases = []
     for i in range(n_scen):
         sc = math.sqrt(1.0e6 / targets[i]) * size_scale
@@ -313,7 +329,16 @@ def ensemble_cases(n_scen: int = 64, nmin: float = 5e4, nmax: float = 5e5, k: in
         cases.append(c)
         if log:
             log(f"ensemble scenario {i}: {c.nc} cells (target {targets[i]})")
-    return cases, {"targets": targets.tolist(), "humps": humps}
+    if path:
+        os.makedirs(cache, exist_ok=True)
+        voff = np.cumsum([0] + [c.nv for c in cases])
+        coff = np.cumsum([0] + [c.nc for c in cases])
+        np.savez(path + ".tmp.npz", voff=voff, coff=coff,
+                 vx=np.concatenate([c.vx for c in cases]), vy=np.concatenate([c.vy for c in cases]),
+                 tri=np.concatenate([c.tri for c in cases]), h=np.concatenate([c.h for c in cases]),
+                 H=np.concatenate([c.H for c in cases]))
+        os.replace(path + ".tmp.npz", path)
+    return cases, info
 
 
 # ---------------------------------------------------------------- channel

@@ -1,0 +1,111 @@
+"""Graph mode: the step loop replayed from a captured pair of steps must give
+exactly the results of direct launches (state, times, dt history, gauges),
+for FP64 (both kernel variants) and FP32, odd and even step counts, t_stop
+inside the run, ensembles, and over repeated calls with the program's own
+eager work (state reads, synchronisation) between the replays; changing
+t_stop or the gauges recaptures the graph."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2002_04889_amd import vsw
+from paper_2002_04889_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def session(case_or_cases, calls, graph, gauges=None, **kw):
+    """Run a list of (n, t_stop) calls; after each, read the state (eager
+    kernels + synchronisation) and the logs."""
+    if isinstance(case_or_cases, list):
+        s = vsw.Solver.for_ensemble(case_or_cases, **kw)
+    else:
+        s = vsw.Solver.for_case(case_or_cases, **kw)
+    out = []
+    try:
+        vsw.vsw_set_graph(s.h, graph)
+        if gauges is not None:
+            vsw.vsw_set_gauges(s.h, gauges)
+        for n, t_stop in calls:
+            rc, done, t = s.step(n, t_stop, check=False)
+            H, HU, HV, t2 = s.state()
+            rec = {"rc": rc, "done": done, "t": t, "H": H, "HU": HU, "HV": HV,
+                   "dts": vsw.vsw_dt_history(s.h), "status": vsw.vsw_scenario_status(s.h)}
+            if gauges is not None:
+                rec["gauges"] = vsw.vsw_get_gauges(s.h, len(gauges))
+            out.append(rec)
+    finally:
+        s.close()
+    return out
+
+
+def assert_same(a, b):
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        assert x["rc"] == y["rc"] and x["done"] == y["done"] and x["t"] == y["t"]
+        for k in ("H", "HU", "HV", "dts"):
+            assert np.array_equal(x[k], y[k]), k
+        for u, v in zip(x["status"], y["status"]):
+            assert np.array_equal(u, v)
+        if "gauges" in x:
+            assert np.array_equal(x["gauges"][0], y["gauges"][0])
+            assert np.array_equal(x["gauges"][1], y["gauges"][1])
+
+
+CALLS = [(7, math.inf), (10, math.inf), (1, math.inf), (6, math.inf), (9, math.inf)]
+
+
+@pytest.mark.parametrize("config", ["fp64", "fp64-two-pass", "fp32"])
+def test_graph_equals_direct_launches(config):
+    c = W.basin_case(scale=16)
+    kw = {"precision": vsw.VSW_FP32 if config == "fp32" else vsw.VSW_FP64}
+    gauges = np.array([1, 500, 2000], dtype=np.int32)
+    if config == "fp64-two-pass":
+        def run(graph):
+            s = vsw.Solver.for_case(c, **kw)
+            try:
+                vsw.vsw_set_kernel_variant(s.h, vsw.VSW_KERNEL_TWO_PASS)
+                vsw.vsw_set_graph(s.h, graph)
+                res = []
+                for n, ts in CALLS:
+                    rc, done, t = s.step(n, ts, check=False)
+                    H, HU, HV, _ = s.state()
+                    res.append({"rc": rc, "done": done, "t": t, "H": H, "HU": HU, "HV": HV,
+                                "dts": vsw.vsw_dt_history(s.h),
+                                "status": vsw.vsw_scenario_status(s.h)})
+                return res
+            finally:
+                s.close()
+        a, b = run(False), run(True)
+    else:
+        a = session(c, CALLS, False, gauges, **kw)
+        b = session(c, CALLS, True, gauges, **kw)
+    assert_same(a, b)
+    say(config, "t", b[-1]["t"], "steps", sum(r["done"] for r in b))
+
+
+def test_graph_t_stop_changes_recapture():
+    c = W.thacker_case(23)
+    T = W.thacker_constants()["T1"]
+    calls = [(40, 0.1 * T), (40, 0.1 * T), (200, 0.5 * T), (7, T), (400, T)]
+    a = session(c, calls, False, cfl=0.45, h_threshold=1e-5)
+    b = session(c, calls, True, cfl=0.45, h_threshold=1e-5)
+    assert_same(a, b)
+    assert b[1]["done"] == 0 and b[-1]["t"] == T
+
+
+def test_graph_ensemble():
+    ens, _ = W.ensemble_cases(n_scen=4, nmin=2e3, nmax=2e4)
+    t_stop = 200.0
+    calls = [(11, t_stop), (20, t_stop), (300, t_stop)]
+    a = session(ens, calls, False)
+    b = session(ens, calls, True)
+    assert_same(a, b)
+    say("ensemble steps per scenario", b[-1]["status"][2], "t", b[-1]["status"][0])
