@@ -234,6 +234,72 @@ def bench_ensemble(args, torch, vsw, W):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args, torch, vsw, W):
+    """Twin experiment on the basin: observations at 20 seeded wet gauge
+    cells over `steps` steps from a seeded true bed displacement (200
+    Gaussian bumps over a 200 x 100 km source box, bed and initial surface
+    raised together); the gradient of the misfit at zero displacement with
+    respect to the initial state and the bed, by the discrete adjoint with
+    checkpoints every 50 steps.  value = adjoint time / forward time."""
+    import numpy as np
+
+    from paper_2002_04889_amd.adjoint import displacement_basis
+
+    steps = args.steps if args.steps is not None else 2000
+    ckpt = 50
+    case = W.basin_case(scale=args.scale)
+    nc = case.nc
+    cx, cy = case.centroids()
+    rng = np.random.default_rng(W.SEED_BASE + 4)
+    wet = np.flatnonzero(case.H > 100.0)
+    gauges = np.sort(rng.choice(wet, 20, replace=False)).astype(np.int32)
+    Phi = displacement_basis(cx, cy)
+    a_true = rng.uniform(-1.0, 1.0, Phi.shape[1])
+    h_true = case.h - Phi @ a_true
+    log(f"[bench] adjoint: {nc} cells, {steps} steps, 20 gauges, checkpoints every {ckpt}")
+
+    def forward(h, timed):
+        s = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold)
+        try:
+            s.upload_mesh(case.vx, case.vy, case.tri, h)
+            s.set_state(case.H, case.HU, case.HV, 0.0)
+            vsw.vsw_set_gauges(s.h, gauges)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, done, _ = s.step(steps)
+            el = time.perf_counter() - t0
+            assert done == steps
+            return vsw.vsw_get_gauges(s.h, len(gauges))[1], el
+        finally:
+            s.close()
+
+    obs, _ = forward(h_true, False)
+    _, t_fwd = forward(case.h, True)
+    s = vsw.Solver.for_case(case)
+    try:
+        t0 = time.perf_counter()
+        loss, gH, gU, gV, gh = vsw.vsw_adjoint_gauge_loss(s.h, nc, steps, ckpt, gauges, obs)
+        t_adj = time.perf_counter() - t0
+    finally:
+        s.close()
+    ga = -(Phi.T @ gh)
+    log(f"[bench] forward {t_fwd * 1e3:.1f} ms, adjoint (forward + reverse) {t_adj * 1e3:.1f} ms, "
+        f"ratio {t_adj / t_fwd:.2f}; loss {loss:.6e}, |dL/da| {np.abs(ga).max():.3e}")
+    out = {"metric": "adjoint/forward time", "value": t_adj / t_fwd, "unit": "ratio",
+           "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": t_adj * 1e3 / steps,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"adjoint source inversion on the {nc}-triangle basin: "
+                                  "gauge misfit at 20 seeded wet cells over "
+                                  f"{steps} steps, gradient w.r.t. initial eta and 200 bed-"
+                                  "displacement amplitudes, checkpoints every 50 steps",
+                      "cells": nc, "precision": "fp64 forward and adjoint",
+                      "global_batch": nc, "parallelism": "single-gpu"},
+           "forward_ms": t_fwd * 1e3, "adjoint_ms": t_adj * 1e3, "loss": loss,
+           "grad_amplitudes_max": float(np.abs(ga).max())}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,10 +307,12 @@ def main():
                     help="timed steps (default 2000 basin, 1000 coastal)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps before timing (default 100 basin, 20 coastal)")
-    ap.add_argument("--workload", choices=["basin", "coastal", "ensemble"], default="basin",
+    ap.add_argument("--workload", choices=["basin", "coastal", "ensemble", "adjoint"],
+                    default="basin",
                     help="basin: 1M-triangle ocean basin, FP64 (and the FP32 leg); coastal: "
                          "12M-triangle coastal mesh, FP32 and FP64 in Hilbert and random "
-                         "cell order; ensemble: 64 uneven scenarios, ensemble runs/s")
+                         "cell order; ensemble: 64 uneven scenarios, ensemble runs/s; "
+                         "adjoint: gauge-misfit gradient, adjoint/forward time")
     ap.add_argument("--no-fp64", action="store_true", help="ensemble: skip the FP64 leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the mixed-precision leg")
@@ -265,6 +333,15 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "sharding of this solver is a design note, not a built path.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "adjoint":
+        import torch
+
+        from paper_2002_04889_amd import vsw
+        from paper_2002_04889_amd import workloads as W
+
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        bench_adjoint(args, torch, vsw, W)
+        return
     if args.workload == "ensemble":
         import torch
 

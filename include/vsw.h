@@ -124,6 +124,27 @@ int vsw_scenario_status(vsw_solver *s, int32_t max, double *t, double *dt_last,
 int vsw_scenario_dt_history(vsw_solver *s, int32_t scen, int64_t max,
                             double *dts, int64_t *count);
 
+/* Discrete adjoint (FP64 solvers, one scenario).  From the current state,
+ * run nsteps steps (the solver's dt rule, no t_stop) and evaluate the gauge
+ * misfit loss = sum_{n=1..nsteps} sum_g (eta_g^n - eta_obs[(n-1) * ng + g])^2,
+ * eta = H - h at gauge_cells[g] (caller's cell indices) after step n; then
+ * run the hand-written reverse of every step (Section 2.3 stages, Section
+ * 2.2 fluxes, Section 2.4 reconstruction with its branches as taken, the
+ * post-stage fix and the CFL time step) backwards from checkpoints taken
+ * every `checkpoint_every` steps, each segment recomputed forward.  Outputs
+ * (caller's order, nc values each; any gradient pointer may be NULL): *loss,
+ * and d loss / d H, HU, HV of the initial state and d loss / d h (the bed
+ * depth, with the initial H, HU, HV held fixed).  The solver's state, time,
+ * gauges and logs are unchanged on return.  Device memory: about
+ * (nsteps / checkpoint_every + checkpoint_every) * 32 + 500 bytes per cell.
+ * EINVAL on an FP32 or ensemble solver, ng < 1 or bad counts; EUNSTABLE if
+ * the forward run fails. */
+int vsw_adjoint_gauge_loss(vsw_solver *s, int64_t nsteps,
+                           int64_t checkpoint_every, int32_t ng,
+                           const int32_t *gauge_cells, const double *eta_obs,
+                           double *loss, double *grad_H, double *grad_HU,
+                           double *grad_HV, double *grad_h);
+
 /* Set the state w = (H, HU, HV) (Section 2.1) from host arrays of nc values
  * in the caller's cell order, at time t.  EINVAL on a non-finite value or
  * H < 0; ESTATE before vsw_upload_mesh. */

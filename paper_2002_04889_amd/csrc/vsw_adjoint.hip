@@ -1,0 +1,724 @@
+// Discrete adjoint of the SSP-RK(2,2) step of the shallow-water scheme
+// (Sections 2.2-2.5), FP64, for gradients of a loss of the state with
+// respect to the initial state and the bed depth h.
+//
+// Reverse of one step w^{n+1} = fix(w/2 + (w1 + dt R(w1))/2),
+// w1 = fix(w + dt R(w)), dt = CFL min_K ratio_K(w):
+//   lt2 = mask2 lam;  lam_w = lt2/2;  lam_w1 = lt2/2 + J_R(w1)^T (dt/2 lt2)
+//   lt1 = mask1 lam_w1;  lam_w += lt1 + J_R(w)^T (dt lt1)
+//   lam_dt = sum lt2/2 . R(w1) + sum lt1 . R(w);  lam_w[K*] += lam_dt CFL d ratio_K*/d w
+// with the masks the post-stage fix applied (a clamped depth or a zeroed
+// momentum passes no derivative) and K* the cell that set the CFL minimum.
+// The bed depth h enters R through eta = H - h, its reconstruction, the
+// hydrostatic reconstruction and the bed source; its adjoint accumulates
+// over all steps.
+//
+// J_R^T mu is taken in three passes, each cell-centric and free of atomics:
+//   faces   the adjoint of every face state from the face terms of both
+//           cells that share the face (the forward evaluates each face once
+//           from each side, in canonical orientation) and from the bed source;
+//   recon   the reverse of each cell's reconstruction (least-squares
+//           gradient, Barth-Jespersen limiter with its branch recomputed,
+//           eq. (3), face velocity), giving the cell's own adjoint and one
+//           contribution per stencil member;
+//   gather  each cell adds the contributions its face neighbours made to it,
+//           in a fixed order.
+// Branches (wet/dry, upwind side, limiter case, min/max) are taken as the
+// forward takes them; the derivative is that of the taken branch.
+#include "vsw_adjoint.hpp"
+#include "vsw_common.hpp"
+
+namespace vsw {
+
+namespace {
+
+// Reverse of hll_face: adds the adjoint of (HL, unL, utL, HR, unR, utR)
+// for the flux adjoint fb.
+__device__ __forceinline__ void hll_face_rev(double g, double hg, double HL, double unL,
+                                             double utL, double HR, double unR, double utR,
+                                             const double fb[3], double& HLb, double& unLb,
+                                             double& utLb, double& HRb, double& unRb,
+                                             double& utRb) {
+    if (HL == 0.0 && HR == 0.0) return;
+    const double cL = sqrt(g * HL), cR = sqrt(g * HR);
+    double sL, sR, us = 0.0, cs = 0.0;
+    bool selL = false, selR = false;  // sL = us - cs, sR = unR + cR chosen
+    if (HL == 0.0) {
+        sL = unR - 2.0 * cR;
+        sR = unR + cR;
+    } else if (HR == 0.0) {
+        sL = unL - cL;
+        sR = unL + 2.0 * cL;
+    } else {
+        us = 0.5 * (unL + unR) + (cL - cR);
+        cs = 0.5 * (cL + cR) - 0.25 * (unR - unL);
+        const double a = unL - cL, b = us - cs;
+        selL = b < a;
+        sL = selL ? b : a;
+        const double c = us + cs, d = unR + cR;
+        selR = d > c;
+        sR = selR ? d : c;
+    }
+    const double qL = HL * unL, qR = HR * unR;
+    const double fL[3] = {qL, qL * unL + hg * (HL * HL), qL * utL};
+    const double fR[3] = {qR, qR * unR + hg * (HR * HR), qR * utR};
+    double fLb[3] = {0.0, 0.0, 0.0}, fRb[3] = {0.0, 0.0, 0.0}, dUb[3] = {0.0, 0.0, 0.0};
+    double sLb = 0.0, sRb = 0.0;
+    if (sL >= 0.0) {
+        fLb[0] = fb[0]; fLb[1] = fb[1]; fLb[2] = fb[2];
+    } else if (sR < 0.0) {
+        fRb[0] = fb[0]; fRb[1] = fb[1]; fRb[2] = fb[2];
+    } else {
+        const double den = sR - sL, sLR = sL * sR;
+        const double dU[3] = {HR - HL, qR - qL, HR * utR - HL * utL};
+        double denb = 0.0, sLRb = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double f = ((sR * fL[c] - sL * fR[c]) + sLR * dU[c]) / den;
+            const double nb = fb[c] / den;
+            denb -= fb[c] * f / den;
+            sRb += nb * fL[c];
+            fLb[c] += nb * sR;
+            sLb -= nb * fR[c];
+            fRb[c] -= nb * sL;
+            sLRb += nb * dU[c];
+            dUb[c] += nb * sLR;
+        }
+        sLb += sLRb * sR;
+        sRb += sLRb * sL;
+        sRb += denb;
+        sLb -= denb;
+    }
+    // jumps of the conserved variables
+    HRb += dUb[0];
+    HLb -= dUb[0];
+    double qLb = -dUb[1], qRb = dUb[1];
+    HRb += dUb[2] * utR;
+    utRb += dUb[2] * HR;
+    HLb -= dUb[2] * utL;
+    utLb -= dUb[2] * HL;
+    // physical fluxes
+    qLb += fLb[0] + fLb[1] * unL + fLb[2] * utL;
+    unLb += fLb[1] * qL;
+    HLb += fLb[1] * (hg * 2.0 * HL);
+    utLb += fLb[2] * qL;
+    qRb += fRb[0] + fRb[1] * unR + fRb[2] * utR;
+    unRb += fRb[1] * qR;
+    HRb += fRb[1] * (hg * 2.0 * HR);
+    utRb += fRb[2] * qR;
+    HLb += qLb * unL;
+    unLb += qLb * HL;
+    HRb += qRb * unR;
+    unRb += qRb * HR;
+    // wave speeds
+    double cLb = 0.0, cRb = 0.0;
+    if (HL == 0.0) {
+        unRb += sLb + sRb;
+        cRb += -2.0 * sLb + sRb;
+    } else if (HR == 0.0) {
+        unLb += sLb + sRb;
+        cLb += -sLb + 2.0 * sRb;
+    } else {
+        double usb = 0.0, csb = 0.0;
+        if (selL) { usb += sLb; csb -= sLb; } else { unLb += sLb; cLb -= sLb; }
+        if (selR) { unRb += sRb; cRb += sRb; } else { usb += sRb; csb += sRb; }
+        unLb += 0.5 * usb;
+        unRb += 0.5 * usb;
+        cLb += usb;
+        cRb -= usb;
+        cLb += 0.5 * csb;
+        cRb += 0.5 * csb;
+        unRb -= 0.25 * csb;
+        unLb += 0.25 * csb;
+    }
+    if (HL > 0.0) HLb += cLb * g / (2.0 * cL);
+    if (HR > 0.0) HRb += cRb * g / (2.0 * cR);
+}
+
+__device__ __forceinline__ void face_add(Face& a, const double eta, double h, double H, double u,
+                                         double v) {
+    a.eta += eta; a.h += h; a.H += H; a.u += u; a.v += v;
+}
+
+// Reverse of face_term: adds the adjoints of own and other for the term
+// adjoint tb (on a wall the caller passes own as other and adds both).
+__device__ __forceinline__ void face_term_rev(double g, double hg, const Face& own,
+                                              const Face& other, bool wall, bool own_left,
+                                              double nx_out, double ny_out, double l,
+                                              const double tb[3], Face& ownb, Face& otherb) {
+    const bool left = wall || own_left;
+    const Face& L = left ? own : other;
+    const Face& R = left ? other : own;
+    const double nx = left ? nx_out : -nx_out, ny = left ? ny_out : -ny_out;
+    const double unL = L.u * nx + L.v * ny, utL = L.v * nx - L.u * ny;
+    double unR = R.u * nx + R.v * ny;
+    const double utR = R.v * nx - R.u * ny;
+    const bool hsR = R.h < L.h;  // hs = dmin(hL, hR) takes hR
+    const double hs = hsR ? R.h : L.h;
+    const double aL = L.eta + hs, aR = R.eta + hs;
+    const double HsL = (aL > 0.0) ? aL : 0.0, HsR = (aR > 0.0) ? aR : 0.0;
+    if (wall) unR = -unL;
+    // t = l (f0, phi1 + pc nx, phi2 + pc ny), phi = rotation of f
+    const double f0b = l * tb[0], p1b = l * tb[1], p2b = l * tb[2];
+    const double pcb = p1b * nx + p2b * ny;
+    const double fb[3] = {f0b, p1b * nx + p2b * ny, -p1b * ny + p2b * nx};
+    double HLb = 0.0, HRb = 0.0, HsLb = 0.0, HsRb = 0.0;
+    if (left) {
+        HLb += pcb * hg * 2.0 * L.H;
+        HsLb -= pcb * hg * 2.0 * HsL;
+    } else {
+        HRb += pcb * hg * 2.0 * R.H;
+        HsRb -= pcb * hg * 2.0 * HsR;
+    }
+    double unLb = 0.0, utLb = 0.0, unRb = 0.0, utRb = 0.0;
+    hll_face_rev(g, hg, HsL, unL, utL, HsR, unR, utR, fb, HsLb, unLb, utLb, HsRb, unRb, utRb);
+    if (wall) {
+        unLb -= unRb;
+        unRb = 0.0;
+    }
+    double eLb = 0.0, eRb = 0.0, hsb = 0.0;
+    if (aL > 0.0) { eLb += HsLb; hsb += HsLb; }
+    if (aR > 0.0) { eRb += HsRb; hsb += HsRb; }
+    double hLb = hsR ? 0.0 : hsb, hRb = hsR ? hsb : 0.0;
+    const double uLb = unLb * nx - utLb * ny, vLb = unLb * ny + utLb * nx;
+    const double uRb = unRb * nx - utRb * ny, vRb = unRb * ny + utRb * nx;
+    Face& Lb = left ? ownb : otherb;
+    Face& Rb = left ? otherb : ownb;
+    face_add(Lb, eLb, hLb, HLb, uLb, vLb);
+    face_add(Rb, eRb, hRb, HRb, uRb, vRb);
+}
+
+struct LimInfo {
+    int br;       // 0: alpha = 1, 1: (max - q0) / max_j d_j, 2: (min - q0) / min_j d_j
+    int iq;       // stencil member giving the max (br 1) or min (br 2); -1 = the cell
+    int jd;       // face giving max_j d_j (br 1) or min_j d_j (br 2)
+    double den;   // that d_j
+};
+
+// Barth-Jespersen factor as in recon_core, with the branch taken.
+__device__ __forceinline__ double limiter_fwd(double q0, const double qs[3], const double pj[3],
+                                              LimInfo& li) {
+    double qmax = q0, qmin = q0;
+    int imax = -1, imin = -1;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (qs[j] > qmax) { qmax = qs[j]; imax = j; }
+        if (qs[j] < qmin) { qmin = qs[j]; imin = j; }
+    }
+    const double up = qmax - q0, dn = qmin - q0;
+    double dpm = 0.0, dnm = 0.0;
+    int jp = -1, jn = -1;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (pj[j] > dpm) { dpm = pj[j]; jp = j; }
+        if (pj[j] < dnm) { dnm = pj[j]; jn = j; }
+    }
+    double a = 1.0;
+    li.br = 0;
+    if (dpm > 0.0 && up < dpm) {
+        a = up / dpm;
+        li.br = 1; li.iq = imax; li.jd = jp; li.den = dpm;
+    }
+    if (dnm < 0.0 && dn > dnm) {
+        const double r = dn / dnm;
+        if (r < a) {
+            a = r;
+            li.br = 2; li.iq = imin; li.jd = jn; li.den = dnm;
+        }
+    }
+    return a;
+}
+
+__device__ __forceinline__ void limiter_rev(double a, double ab, const LimInfo& li, double& q0b,
+                                            double qsb[3], double pjb[3]) {
+    if (li.br == 0) return;
+    const double nb = ab / li.den;          // adjoint of (q_ext - q0)
+    pjb[li.jd] -= ab * a / li.den;          // adjoint of the denominator
+    q0b -= nb;
+    if (li.iq < 0) q0b += nb; else qsb[li.iq] += nb;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- forward pieces
+
+__global__ __launch_bounds__(kBlock) void adj_faces_kernel(DevMesh m, TileMap tm,
+                                                           const Cell4* __restrict__ W, FaceBuf fb,
+                                                           double thr, double hg) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x, nc = m.nc;
+    Face f[3];
+    double sc[2];
+    const bool second = recon_cell(m, W, k, thr, hg, f, sc);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        fb.f[(5 * j + 0) * nc + k] = f[j].eta;
+        fb.f[(5 * j + 1) * nc + k] = f[j].h;
+        fb.f[(5 * j + 2) * nc + k] = f[j].H;
+        fb.f[(5 * j + 3) * nc + k] = f[j].u;
+        fb.f[(5 * j + 4) * nc + k] = f[j].v;
+    }
+    fb.sc[k] = sc[0];
+    fb.sc[nc + k] = sc[1];
+    fb.order[k] = second ? 2 : 1;
+}
+
+__global__ __launch_bounds__(kBlock) void adj_residual_kernel(DevMesh m, TileMap tm, FaceBuf fb,
+                                                              double g, double hg, double* R) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    double r[3];
+    residual_from_faces(m, fb, k, g, hg, r);
+    R[3 * k] = r[0];
+    R[3 * k + 1] = r[1];
+    R[3 * k + 2] = r[2];
+}
+
+__global__ __launch_bounds__(kBlock) void adj_stage1_kernel(TileMap tm, const Cell4* __restrict__ W,
+                                                            const double* __restrict__ R0,
+                                                            double dt, double thr,
+                                                            Cell4* __restrict__ W1,
+                                                            uint8_t* __restrict__ mask1) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    const Cell4 w = W[k];
+    Cell4 o;
+    o.H = w.H + dt * R0[3 * k];
+    o.HU = w.HU + dt * R0[3 * k + 1];
+    o.HV = w.HV + dt * R0[3 * k + 2];
+    o.h = w.h;
+    uint8_t mk = 3;
+    if (o.H < 0.0) { o.H = 0.0; mk &= ~1; }
+    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; mk &= ~2; }
+    W1[k] = o;
+    mask1[k] = mk;
+}
+
+__global__ __launch_bounds__(kBlock) void adj_mask2_kernel(TileMap tm, const Cell4* __restrict__ W,
+                                                           const Cell4* __restrict__ W1,
+                                                           const double* __restrict__ R1,
+                                                           double dt, double thr,
+                                                           uint8_t* __restrict__ mask2) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    double H = 0.5 * W[k].H + 0.5 * (W1[k].H + dt * R1[3 * k]);
+    uint8_t mk = 3;
+    if (H < 0.0) { H = 0.0; mk &= ~1; }
+    if (H < thr) mk &= ~2;
+    mask2[k] = mk;
+}
+
+namespace {
+
+// Block sum in a fixed order (wavefront butterflies, then the four waves).
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double part[kBlock / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) part[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) s += part[i];
+    return s;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void adj_rk2_pre_kernel(TileMap tm, const Adj4* __restrict__ lam,
+                                                             const uint8_t* __restrict__ mask2,
+                                                             const double* __restrict__ R1,
+                                                             double dt, double* __restrict__ mu,
+                                                             Adj4* __restrict__ lamn,
+                                                             double* __restrict__ part) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    double d = 0.0;
+    if (int(threadIdx.x) < ti.cnt) {
+        const uint8_t mk = mask2[k];
+        const Adj4 l = lam[k];
+        const double l0 = (mk & 1) ? l.H : 0.0, l1 = (mk & 2) ? l.HU : 0.0,
+                     l2 = (mk & 2) ? l.HV : 0.0;
+        mu[3 * k] = 0.5 * dt * l0;
+        mu[3 * k + 1] = 0.5 * dt * l1;
+        mu[3 * k + 2] = 0.5 * dt * l2;
+        lamn[k] = Adj4{0.5 * l0, 0.5 * l1, 0.5 * l2, 0.0};
+        d = 0.5 * (l0 * R1[3 * k] + l1 * R1[3 * k + 1] + l2 * R1[3 * k + 2]);
+    }
+    const double s = block_sum(d);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void adj_rk2_post_kernel(
+    TileMap tm, const Adj4* __restrict__ lam, const uint8_t* __restrict__ mask2,
+    const Adj4* __restrict__ wb2, const uint8_t* __restrict__ mask1, const double* __restrict__ R0,
+    double dt, double* __restrict__ mu, Adj4* __restrict__ lamn, double* __restrict__ hbar,
+    double* __restrict__ part) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    double d = 0.0;
+    if (int(threadIdx.x) < ti.cnt) {
+        const uint8_t m2 = mask2[k], m1 = mask1[k];
+        const Adj4 l = lam[k], w = wb2[k];
+        const double a0 = ((m2 & 1) ? 0.5 * l.H : 0.0) + w.H;
+        const double a1 = ((m2 & 2) ? 0.5 * l.HU : 0.0) + w.HU;
+        const double a2 = ((m2 & 2) ? 0.5 * l.HV : 0.0) + w.HV;
+        const double t0 = (m1 & 1) ? a0 : 0.0, t1 = (m1 & 2) ? a1 : 0.0, t2 = (m1 & 2) ? a2 : 0.0;
+        mu[3 * k] = dt * t0;
+        mu[3 * k + 1] = dt * t1;
+        mu[3 * k + 2] = dt * t2;
+        Adj4 n = lamn[k];
+        n.H += t0; n.HU += t1; n.HV += t2;
+        lamn[k] = n;
+        hbar[k] += w.h;
+        d = t0 * R0[3 * k] + t1 * R0[3 * k + 1] + t2 * R0[3 * k + 2];
+    }
+    const double s = block_sum(d);
+    if (threadIdx.x == 0) part[blockIdx.x] += s;
+}
+
+__global__ __launch_bounds__(kBlock) void adj_rk1_post_kernel(TileMap tm, const Adj4* __restrict__ wb1,
+                                                              Adj4* __restrict__ lamn,
+                                                              double* __restrict__ hbar) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    const Adj4 w = wb1[k];
+    Adj4 n = lamn[k];
+    n.H += w.H; n.HU += w.HU; n.HV += w.HV;
+    lamn[k] = n;
+    hbar[k] += w.h;
+}
+
+// ---------------------------------------------------------------- J_R^T mu
+
+__global__ __launch_bounds__(kBlock) void adj_vjp_faces_kernel(DevMesh m, TileMap tm, FaceBuf fb,
+                                                               const Cell4* __restrict__ W,
+                                                               const double* __restrict__ mu,
+                                                               double g, double hg,
+                                                               double* __restrict__ Fb,
+                                                               double* __restrict__ D) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x, nc = m.nc;
+    const double ar = m.area[k];
+    const double ab[3] = {mu[3 * k] / ar, mu[3 * k + 1] / ar, mu[3 * k + 2] / ar};
+    const Nbr4 nb = m.nbr[k];
+    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
+    Face F[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        F[j] = Face{0.0, 0.0, 0.0, 0.0, 0.0};
+        const uint32_t s = sl[j];
+        const bool wall = (s == kWallSlot);
+        const bool own_left = wall || (s & 4u);
+        const Face own = load_face(fb, nc, j, k);
+        const double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k), l = gf(m, 2, j, k);
+        // this cell's term enters its accumulator with - (left) or + (right)
+        const double sg = own_left ? -1.0 : 1.0;
+        const double tb[3] = {sg * ab[0], sg * ab[1], sg * ab[2]};
+        Face xb{0.0, 0.0, 0.0, 0.0, 0.0};
+        if (wall) {
+            face_term_rev(g, hg, own, own, true, true, nx, ny, l, tb, F[j], xb);
+            face_add(F[j], xb.eta, xb.h, xb.H, xb.u, xb.v);
+        } else {
+            const int64_t n = int64_t(s >> 3);
+            const int jn = int(s & 3u);
+            const Face other = load_face(fb, nc, jn, n);
+            face_term_rev(g, hg, own, other, false, own_left, nx, ny, l, tb, F[j], xb);
+            // the neighbour's term of the same face, with this face as its other side
+            const double arn = m.area[n];
+            const double sn = own_left ? 1.0 : -1.0;
+            const double tbn[3] = {sn * (mu[3 * n] / arn), sn * (mu[3 * n + 1] / arn),
+                                   sn * (mu[3 * n + 2] / arn)};
+            Face ob{0.0, 0.0, 0.0, 0.0, 0.0};
+            face_term_rev(g, hg, other, own, false, !own_left, gf(m, 0, jn, n), gf(m, 1, jn, n),
+                          gf(m, 2, jn, n), tbn, ob, F[j]);
+        }
+    }
+    double DH = 0.0, Dh = 0.0;
+    if (fb.order[k] == 2) {
+        // bed source (g/2) sum_j l_j (H_K + H_Kj)(h_Kj - h_K) n_j added to the momentum rows
+        const Cell4 q = W[k];
+        const double sxb = hg * ab[1], syb = hg * ab[2];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k), l = gf(m, 2, j, k);
+            const double fH = fb.f[(5 * j + 2) * nc + k], fh = fb.f[(5 * j + 1) * nc + k];
+            const double cb = sxb * nx + syb * ny;
+            const double dHj = cb * (l * (fh - q.h)), dhj = cb * (l * (q.H + fH));
+            F[j].H += dHj;
+            F[j].h += dhj;
+            DH += dHj;
+            Dh -= dhj;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        Fb[(5 * j + 0) * nc + k] = F[j].eta;
+        Fb[(5 * j + 1) * nc + k] = F[j].h;
+        Fb[(5 * j + 2) * nc + k] = F[j].H;
+        Fb[(5 * j + 3) * nc + k] = F[j].u;
+        Fb[(5 * j + 4) * nc + k] = F[j].v;
+    }
+    D[2 * k] = DH;
+    D[2 * k + 1] = Dh;
+}
+
+__global__ __launch_bounds__(kBlock) void adj_vjp_recon_kernel(DevMesh m, TileMap tm,
+                                                               const Cell4* __restrict__ W,
+                                                               const double* __restrict__ Fb,
+                                                               const double* __restrict__ D,
+                                                               double thr, double* __restrict__ C) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x, nc = m.nc;
+    // ---- forward recomputation (the arithmetic of recon_core)
+    const Cell4 ck = W[k];
+    const double Hk = ck.H, hk = ck.h, ek = Hk - hk, uk = ck.HU, vk = ck.HV;
+    const Nbr4 nb = m.nbr[k];
+    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
+    double qe[3], qu[3], qv[3], qh[3];
+    bool cand = (Hk >= thr);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t s = sl[j];
+        if (s != kWallSlot) {
+            const Cell4 cn = W[int64_t(s >> 3)];
+            qe[j] = cn.H - cn.h;
+            qu[j] = cn.HU;
+            qv[j] = cn.HV;
+            qh[j] = cn.h;
+            if (!(cn.H >= thr)) cand = false;
+        } else {
+            const double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k);
+            const double mn = uk * nx + vk * ny;
+            qe[j] = ek;
+            qu[j] = uk - (2.0 * mn) * nx;
+            qv[j] = vk - (2.0 * mn) * ny;
+            qh[j] = hk;
+        }
+    }
+    double pe[3], pu[3], pv[3], ph[3], fe[3], fu[3], fv[3], fh[3], fH[3];
+    double ae = 1.0, au = 1.0, av = 1.0;
+    LimInfo le{0, -1, 0, 1.0}, lu{0, -1, 0, 1.0}, lv{0, -1, 0, 1.0};
+    const RGeom rg = m.rgeom[k];
+    const double wx[3] = {rg.w[0], rg.w[2], rg.w[4]}, wy[3] = {rg.w[1], rg.w[3], rg.w[5]};
+    const double dxs[3] = {rg.d[0], rg.d[2], rg.d[4]}, dys[3] = {rg.d[1], rg.d[3], rg.d[5]};
+    auto project = [&](const double* qs, double q0, double* pj) {
+        const double d0 = qs[0] - q0, d1 = qs[1] - q0, d2 = qs[2] - q0;
+        const double gx = wx[0] * d0 + wx[1] * d1 + wx[2] * d2;
+        const double gy = wy[0] * d0 + wy[1] * d1 + wy[2] * d2;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) pj[j] = gx * dxs[j] + gy * dys[j];
+    };
+    if (cand) {
+        project(qe, ek, pe);
+        project(qu, uk, pu);
+        project(qv, vk, pv);
+        project(qh, hk, ph);
+        ae = limiter_fwd(ek, qe, pe, le);
+        au = limiter_fwd(uk, qu, pu, lu);
+        av = limiter_fwd(vk, qv, pv, lv);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            fe[j] = ek + ae * pe[j];
+            fu[j] = uk + au * pu[j];
+            fv[j] = vk + av * pv[j];
+            fh[j] = hk + ph[j];
+            fH[j] = fe[j] + fh[j];
+            if (fH[j] < thr) cand = false;
+        }
+    }
+    if (!cand) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            fe[j] = ek; fu[j] = uk; fv[j] = vk; fh[j] = hk; fH[j] = Hk;
+        }
+    }
+    // ---- reverse
+    double feb[3], fub[3], fvb[3], fhb[3], fHb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        feb[j] = Fb[(5 * j + 0) * nc + k];
+        fhb[j] = Fb[(5 * j + 1) * nc + k];
+        fHb[j] = Fb[(5 * j + 2) * nc + k];
+        fub[j] = 0.0;
+        fvb[j] = 0.0;
+        if (fH[j] >= thr) {
+            const double ub = Fb[(5 * j + 3) * nc + k], vb = Fb[(5 * j + 4) * nc + k];
+            const double u = fu[j] / fH[j], v = fv[j] / fH[j];
+            fub[j] = ub / fH[j];
+            fvb[j] = vb / fH[j];
+            fHb[j] -= (ub * u + vb * v) / fH[j];
+        }
+    }
+    double Hkb = D[2 * k], hkb = D[2 * k + 1], ekb = 0.0, ukb = 0.0, vkb = 0.0;
+    double qeb[3] = {0.0, 0.0, 0.0}, qub[3] = {0.0, 0.0, 0.0}, qvb[3] = {0.0, 0.0, 0.0},
+           qhb[3] = {0.0, 0.0, 0.0};
+    if (!cand) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            ekb += feb[j]; ukb += fub[j]; vkb += fvb[j]; hkb += fhb[j]; Hkb += fHb[j];
+        }
+    } else {
+        double peb[3], pub[3], pvb[3], phb[3], aeb = 0.0, aub = 0.0, avb = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double e_b = feb[j] + fHb[j], h_b = fhb[j] + fHb[j];
+            ekb += e_b;
+            aeb += e_b * pe[j];
+            peb[j] = e_b * ae;
+            ukb += fub[j];
+            aub += fub[j] * pu[j];
+            pub[j] = fub[j] * au;
+            vkb += fvb[j];
+            avb += fvb[j] * pv[j];
+            pvb[j] = fvb[j] * av;
+            hkb += h_b;
+            phb[j] = h_b;
+        }
+        limiter_rev(ae, aeb, le, ekb, qeb, peb);
+        limiter_rev(au, aub, lu, ukb, qub, pub);
+        limiter_rev(av, avb, lv, vkb, qvb, pvb);
+        auto project_rev = [&](const double* pjb, double& q0b, double* qsb) {
+            const double gxb = pjb[0] * dxs[0] + pjb[1] * dxs[1] + pjb[2] * dxs[2];
+            const double gyb = pjb[0] * dys[0] + pjb[1] * dys[1] + pjb[2] * dys[2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double db = wx[i] * gxb + wy[i] * gyb;
+                qsb[i] += db;
+                q0b -= db;
+            }
+        };
+        project_rev(peb, ekb, qeb);
+        project_rev(pub, ukb, qub);
+        project_rev(pvb, vkb, qvb);
+        project_rev(phb, hkb, qhb);
+    }
+    double* out = C + 16 * k;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t s = sl[j];
+        if (s != kWallSlot) {
+            out[4 + 4 * j + 0] = qeb[j];
+            out[4 + 4 * j + 1] = qub[j];
+            out[4 + 4 * j + 2] = qvb[j];
+            out[4 + 4 * j + 3] = qhb[j] - qeb[j];
+        } else {
+            const double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k);
+            ekb += qeb[j];
+            ukb += qub[j];
+            vkb += qvb[j];
+            const double mnb = -2.0 * (qub[j] * nx + qvb[j] * ny);
+            ukb += mnb * nx;
+            vkb += mnb * ny;
+            hkb += qhb[j];
+            out[4 + 4 * j + 0] = 0.0;
+            out[4 + 4 * j + 1] = 0.0;
+            out[4 + 4 * j + 2] = 0.0;
+            out[4 + 4 * j + 3] = 0.0;
+        }
+    }
+    out[0] = Hkb + ekb;
+    out[1] = ukb;
+    out[2] = vkb;
+    out[3] = hkb - ekb;
+}
+
+__global__ __launch_bounds__(kBlock) void adj_vjp_gather_kernel(DevMesh m, TileMap tm,
+                                                                const double* __restrict__ C,
+                                                                Adj4* __restrict__ wb) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    const double* o = C + 16 * k;
+    double a0 = o[0], a1 = o[1], a2 = o[2], a3 = o[3];
+    const Nbr4 nb = m.nbr[k];
+    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t s = sl[j];
+        if (s == kWallSlot) continue;
+        const double* c = C + 16 * int64_t(s >> 3) + 4 + 4 * int(s & 3u);
+        a0 += c[0]; a1 += c[1]; a2 += c[2]; a3 += c[3];
+    }
+    wb[k] = Adj4{a0, a1, a2, a3};
+}
+
+// ---------------------------------------------------------------- time step
+
+__global__ __launch_bounds__(kBlock) void adj_rmin_kernel(DevMesh m, TileMap tm,
+                                                          const Cell4* __restrict__ W, double g,
+                                                          double thr, unsigned long long* rmin) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    double r = __longlong_as_double(0x7FF0000000000000ll);
+    if (int(threadIdx.x) < ti.cnt) {
+        const Cell4 q = W[k];
+        r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
+    }
+    block_min_atomic(r, rmin);
+}
+
+__global__ void adj_sum_kernel(const double* part, int n, double* out) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
+    const double t = block_sum(s);
+    if (threadIdx.x == 0) *out = t;
+}
+
+__global__ __launch_bounds__(kBlock) void adj_dt_kernel(DevMesh m, TileMap tm,
+                                                        const Cell4* __restrict__ W, double g,
+                                                        double thr, double cfl,
+                                                        const unsigned long long* rmin,
+                                                        const double* lamdt, Adj4* lamn) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    const Cell4 q = W[k];
+    const double A = m.area[k], P = m.perim[k];
+    const double r = cfl_ratio(q.H, q.HU, q.HV, A, P, g, thr);
+    if (!(r < __longlong_as_double(0x7FF0000000000000ll)) || dbits(r) != *rmin) return;
+    const double u = q.HU / q.H, v = q.HV / q.H;
+    const double m2 = u * u + v * v, mm = sqrt(m2), c = sqrt(g * q.H), s = mm + c;
+    const double sb = -(*lamdt * cfl) * r / s;
+    const double ub = (m2 > 0.0) ? sb * u / mm : 0.0, vb = (m2 > 0.0) ? sb * v / mm : 0.0;
+    Adj4 n = lamn[k];
+    n.H += sb * g / (2.0 * c) - (ub * u + vb * v) / q.H;
+    n.HU += ub / q.H;
+    n.HV += vb / q.H;
+    lamn[k] = n;
+}
+
+// ---------------------------------------------------------------- loss and output
+
+__global__ void adj_gauge_kernel(const int64_t* cells, int ng, const double* r, Adj4* lam,
+                                 double* hbar) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int i = 0; i < ng; ++i) {  // one thread: gauges may share a cell
+        const int64_t k = cells[i];
+        lam[k].H += 2.0 * r[i];
+        hbar[k] -= 2.0 * r[i];
+    }
+}
+
+__global__ void adj_unpack_kernel(int64_t n, const int64_t* perm, const Adj4* lam,
+                                  const double* hbar, double* gH, double* gHU, double* gHV,
+                                  double* gh) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t k = perm[i];
+    if (k < 0) return;
+    gH[k] = lam[i].H;
+    gHU[k] = lam[i].HU;
+    gHV[k] = lam[i].HV;
+    gh[k] = hbar[i];
+}
+
+}  // namespace vsw

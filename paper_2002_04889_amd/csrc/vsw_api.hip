@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/vsw.h"
+#include "vsw_adjoint.hpp"
 #include "vsw_kernels.hpp"
 #include "vsw_kernels_f32.hpp"
 #include "vsw_mesh.hpp"
@@ -687,6 +688,203 @@ int vsw_scenario_dt_history(vsw_solver* s, int32_t scen, int64_t max, double* dt
     if (dts)
         for (int64_t k = 0; k < n && k < max; ++k)
             dts[k] = s->seg_log[size_t(k) * s->nseg + scen];
+    return VSW_OK;
+}
+
+int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t ng,
+                           const int32_t* gauge_cells, const double* eta_obs, double* loss,
+                           double* gH, double* gHU, double* gHV, double* gh) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_mesh || !s->has_state) return fail(VSW_ESTATE, "mesh and state required");
+    if (s->prm.precision != VSW_FP64) return fail(VSW_EINVAL, "the adjoint is FP64 only");
+    if (s->nseg != 1) return fail(VSW_EINVAL, "the adjoint takes a single scenario");
+    if (nsteps < 1 || nsteps > INT32_MAX || ckpt < 1)
+        return fail(VSW_EINVAL, "bad step or checkpoint count");
+    if (ng < 1 || !gauge_cells || !eta_obs || !loss) return fail(VSW_EINVAL, "NULL argument");
+    DeviceGuard dg(s->device);
+    hipStream_t st = s->stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    const int64_t n = s->nint;
+    const int64_t nck = (nsteps + ckpt - 1) / ckpt;
+    const int64_t segl = std::min(ckpt, nsteps);
+    // the caller's solver state, restored on return
+    std::vector<int64_t> user_gauges(size_t(s->ngauges));
+    if (s->ngauges > 0)
+        HIP_TRY(hipMemcpy(user_gauges.data(), s->d_gauge_cells.p,
+                          user_gauges.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    const double t_save = s->t, dt_save = s->dt_last;
+    const int64_t clamps_save = s->clamps;
+    const std::vector<double> seg_t_save = s->seg_t, seg_dt_save = s->seg_dt;
+    const std::vector<int64_t> seg_steps_save = s->seg_steps;
+    const std::vector<double> seg_log_save = s->seg_log, last_dts_save = s->last_dts;
+    DevBuf<Cell4> W0, ck, seg, W1;
+    HIP_TRY(W0.alloc(size_t(n)));
+    HIP_TRY(hipMemcpyAsync(W0.p, s->d_w.p, size_t(n) * sizeof(Cell4), hipMemcpyDeviceToDevice,
+                           st));
+    auto restore = [&]() {
+        (void)hipMemcpyAsync(s->d_w.p, W0.p, size_t(n) * sizeof(Cell4), hipMemcpyDeviceToDevice,
+                             st);
+        (void)hipMemcpyAsync(s->d_w1.p, W0.p, size_t(n) * sizeof(Cell4),
+                             hipMemcpyDeviceToDevice, st);
+        (void)hipStreamSynchronize(st);
+        s->t = t_save;
+        s->dt_last = dt_save;
+        s->clamps = clamps_save;
+        s->seg_t = seg_t_save;
+        s->seg_dt = seg_dt_save;
+        s->seg_steps = seg_steps_save;
+        s->seg_log = seg_log_save;
+        s->last_dts = last_dts_save;
+        if (s->d_gauge_cells.alloc(user_gauges.size()) == hipSuccess && !user_gauges.empty())
+            (void)hipMemcpy(s->d_gauge_cells.p, user_gauges.data(),
+                            user_gauges.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+        s->ngauges = int(user_gauges.size());
+        s->gauge_eta.clear();
+        s->gauge_t.clear();
+        s->release_graph();
+    };
+    int rc = vsw_set_gauges(s, ng, gauge_cells);
+    if (rc != VSW_OK) {
+        restore();
+        return rc;
+    }
+    // ---- forward with checkpoints and gauge records
+    if (ck.alloc(size_t(nck) * size_t(n)) != hipSuccess) {
+        restore();
+        return fail(VSW_ENOMEM, "checkpoint memory");
+    }
+    std::vector<double> dts, eta;
+    for (int64_t c = 0; c < nck; ++c) {
+        HIP_TRY(hipMemcpyAsync(ck.p + c * n, s->d_w.p, size_t(n) * sizeof(Cell4),
+                               hipMemcpyDeviceToDevice, st));
+        const int64_t m = std::min(ckpt, nsteps - c * ckpt);
+        int64_t done = 0;
+        rc = vsw_step(s, m, INFINITY, &done, nullptr);
+        if (rc != VSW_OK || done != m) {
+            const std::string msg = g_last_error;
+            restore();
+            return fail(rc != VSW_OK ? rc : VSW_EUNSTABLE, "forward run: " + msg);
+        }
+        dts.insert(dts.end(), s->last_dts.begin(), s->last_dts.end());
+        eta.insert(eta.end(), s->gauge_eta.begin(), s->gauge_eta.end());
+    }
+    const double thr = s->prm.h_threshold, g = s->prm.g, hg = 0.5 * g, cfl = s->prm.cfl;
+    const bool cfl_dt = !(s->prm.dt_fixed > 0.0);
+    std::vector<double> r(size_t(nsteps) * size_t(ng));
+    double L = 0.0;
+    for (size_t i = 0; i < r.size(); ++i) {
+        r[i] = eta[i] - eta_obs[i];
+        L += r[i] * r[i];
+    }
+    *loss = L;
+    // ---- reverse sweep
+    DevBuf<double> d_r, f0, f1, sc0, sc1, R0, R1, mu, Fbar, D, C, hbar, part, lamdt;
+    DevBuf<int32_t> o0, o1;
+    DevBuf<uint8_t> m1, m2;
+    DevBuf<Adj4> lam, lamn, wb;
+    DevBuf<unsigned long long> rmin;
+    DevBuf<double> gout;
+    const size_t N = size_t(n);
+    hipError_t e = hipSuccess;
+    for (hipError_t x : {d_r.alloc(r.size()), seg.alloc(size_t(segl) * N), W1.alloc(N),
+                         f0.alloc(15 * N), f1.alloc(15 * N), sc0.alloc(2 * N), sc1.alloc(2 * N),
+                         o0.alloc(N), o1.alloc(N), R0.alloc(3 * N), R1.alloc(3 * N),
+                         m1.alloc(N), m2.alloc(N), lam.alloc(N), lamn.alloc(N), mu.alloc(3 * N),
+                         Fbar.alloc(15 * N), D.alloc(2 * N), C.alloc(16 * N), wb.alloc(N),
+                         hbar.alloc(N), part.alloc(size_t(s->ntiles)), lamdt.alloc(1),
+                         rmin.alloc(1), gout.alloc(4 * size_t(s->nc))})
+        if (x != hipSuccess) e = x;
+    if (e != hipSuccess) {
+        restore();
+        return fail(VSW_ENOMEM, "adjoint work memory");
+    }
+    HIP_TRY(hipMemcpy(d_r.p, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemsetAsync(lam.p, 0, N * sizeof(Adj4), st));
+    HIP_TRY(hipMemsetAsync(hbar.p, 0, N * sizeof(double), st));
+    const DevMesh m = s->dev_mesh();
+    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, 1};
+    const dim3 grid(unsigned(s->ntiles)), block(kBlock);
+    const FaceBuf fb0{f0.p, sc0.p, o0.p}, fb1{f1.p, sc1.p, o1.p};
+    int64_t* cells = s->d_gauge_cells.p;
+    const size_t lds = stage_lds_bytes(s->bmax);
+    const double zero_t = 0.0;
+    HIP_TRY(hipMemcpy(s->d_t0.p, &zero_t, sizeof(double), hipMemcpyHostToDevice));
+    if (s->d_log.n < 2) HIP_TRY(s->d_log.alloc(2));
+    auto vjp = [&](const Cell4* Wx, const FaceBuf& fbx) {
+        hipLaunchKernelGGL(adj_vjp_faces_kernel, grid, block, 0, st, m, tm, fbx, Wx, mu.p, g, hg,
+                           Fbar.p, D.p);
+        hipLaunchKernelGGL(adj_vjp_recon_kernel, grid, block, 0, st, m, tm, Wx, Fbar.p, D.p, thr,
+                           C.p);
+        hipLaunchKernelGGL(adj_vjp_gather_kernel, grid, block, 0, st, m, tm, C.p, wb.p);
+    };
+    // the misfit of the last state
+    hipLaunchKernelGGL(adj_gauge_kernel, dim3(1), dim3(64), 0, st, cells, ng,
+                       d_r.p + (nsteps - 1) * ng, lam.p, hbar.p);
+    const unsigned long long inf_bits = 0x7FF0000000000000ull;
+    for (int64_t c = nck - 1; c >= 0; --c) {
+        const int64_t n0 = c * ckpt, n1 = std::min(nsteps, n0 + ckpt);
+        // states n0 .. n1-1 of the segment, recomputed with the forward's dts
+        HIP_TRY(hipMemcpyAsync(seg.p, ck.p + c * n, N * sizeof(Cell4), hipMemcpyDeviceToDevice,
+                               st));
+        for (int64_t i = 1; i < n1 - n0; ++i) {
+            Cell4* Wi = seg.p + i * n;
+            HIP_TRY(hipMemcpyAsync(Wi, Wi - n, N * sizeof(Cell4), hipMemcpyDeviceToDevice, st));
+            StepParams p{g, hg, thr, cfl, dts[size_t(n0 + i - 1)], INFINITY};
+            hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(256), 0, st, s->d_ctrl.p,
+                               s->d_seg.p, 1, s->d_t0.p);
+            hipLaunchKernelGGL(stage_kernel<1>, grid, block, lds, st, m, tm, Wi, W1.p, p,
+                               s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p);
+            hipLaunchKernelGGL(stage_kernel<2>, grid, block, lds, st, m, tm, Wi, W1.p, p,
+                               s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p);
+        }
+        for (int64_t k = n1 - 1; k >= n0; --k) {
+            const Cell4* Wn = seg.p + (k - n0) * n;
+            const double dt = dts[size_t(k)];
+            if (cfl_dt) {
+                HIP_TRY(hipMemcpyAsync(rmin.p, &inf_bits, sizeof(inf_bits), hipMemcpyHostToDevice,
+                                       st));
+                hipLaunchKernelGGL(adj_rmin_kernel, grid, block, 0, st, m, tm, Wn, g, thr, rmin.p);
+            }
+            hipLaunchKernelGGL(adj_faces_kernel, grid, block, 0, st, m, tm, Wn, fb0, thr, hg);
+            hipLaunchKernelGGL(adj_residual_kernel, grid, block, 0, st, m, tm, fb0, g, hg, R0.p);
+            hipLaunchKernelGGL(adj_stage1_kernel, grid, block, 0, st, tm, Wn, R0.p, dt, thr, W1.p,
+                               m1.p);
+            hipLaunchKernelGGL(adj_faces_kernel, grid, block, 0, st, m, tm, W1.p, fb1, thr, hg);
+            hipLaunchKernelGGL(adj_residual_kernel, grid, block, 0, st, m, tm, fb1, g, hg, R1.p);
+            hipLaunchKernelGGL(adj_mask2_kernel, grid, block, 0, st, tm, Wn, W1.p, R1.p, dt, thr,
+                               m2.p);
+            hipLaunchKernelGGL(adj_rk2_pre_kernel, grid, block, 0, st, tm, lam.p, m2.p, R1.p, dt,
+                               mu.p, lamn.p, part.p);
+            vjp(W1.p, fb1);
+            hipLaunchKernelGGL(adj_rk2_post_kernel, grid, block, 0, st, tm, lam.p, m2.p, wb.p,
+                               m1.p, R0.p, dt, mu.p, lamn.p, hbar.p, part.p);
+            vjp(Wn, fb0);
+            hipLaunchKernelGGL(adj_rk1_post_kernel, grid, block, 0, st, tm, wb.p, lamn.p, hbar.p);
+            if (cfl_dt) {
+                hipLaunchKernelGGL(adj_sum_kernel, dim3(1), block, 0, st, part.p, s->ntiles,
+                                   lamdt.p);
+                hipLaunchKernelGGL(adj_dt_kernel, grid, block, 0, st, m, tm, Wn, g, thr, cfl,
+                                   rmin.p, lamdt.p, lamn.p);
+            }
+            std::swap(lam.p, lamn.p);
+            if (k >= 1)
+                hipLaunchKernelGGL(adj_gauge_kernel, dim3(1), dim3(64), 0, st, cells, ng,
+                                   d_r.p + (k - 1) * ng, lam.p, hbar.p);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    const int64_t nc = s->nc;
+    hipLaunchKernelGGL(adj_unpack_kernel, dim3(unsigned((n + kBlock - 1) / kBlock)), block, 0, st,
+                       n, s->d_perm.p, lam.p, hbar.p, gout.p, gout.p + nc, gout.p + 2 * nc,
+                       gout.p + 3 * nc);
+    HIP_TRY(hipGetLastError());
+    double* outs[4] = {gH, gHU, gHV, gh};
+    for (int q = 0; q < 4; ++q)
+        if (outs[q])
+            HIP_TRY(hipMemcpyAsync(outs[q], gout.p + q * nc, size_t(nc) * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    restore();
     return VSW_OK;
 }
 

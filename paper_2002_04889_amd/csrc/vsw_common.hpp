@@ -129,6 +129,49 @@ __device__ __forceinline__ void stage2_bookkeeping(Ctrl* c, Seg* sg, const TileI
     }
 }
 
+// Face state j of cell k from a face buffer (two-pass organisation).
+__device__ __forceinline__ Face load_face(const FaceBuf& fb, int64_t nc, int j, int64_t k) {
+    Face f;
+    f.eta = fb.f[(5 * j + 0) * nc + k];
+    f.h = fb.f[(5 * j + 1) * nc + k];
+    f.H = fb.f[(5 * j + 2) * nc + k];
+    f.u = fb.f[(5 * j + 3) * nc + k];
+    f.v = fb.f[(5 * j + 4) * nc + k];
+    return f;
+}
+
+// Residual of cell k from the face buffer: R = (-sum_j +-l_j G_j + S_c)/|K|.
+__device__ __forceinline__ void residual_from_faces(const DevMesh& m, const FaceBuf& fb, int64_t k,
+                                                    double g, double hg, double R[3]) {
+    const int64_t nc = m.nc;
+    const Nbr4 nb = m.nbr[k];
+    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t s = sl[j];
+        const bool wall = (s == kWallSlot);
+        const Face own = load_face(fb, nc, j, k);
+        const Face other = wall ? own : load_face(fb, nc, int(s & 3u), int64_t(s >> 3));
+        double tt[3];
+        const bool left = face_term(g, hg, own, other, wall, (s & 4u) != 0, gf(m, 0, j, k),
+                                    gf(m, 1, j, k), gf(m, 2, j, k), tt);
+        if (left) {
+            a0 = a0 - tt[0]; a1 = a1 - tt[1]; a2 = a2 - tt[2];
+        } else {
+            a0 = a0 + tt[0]; a1 = a1 + tt[1]; a2 = a2 + tt[2];
+        }
+    }
+    if (fb.order[k] == 2) {
+        a1 = a1 + fb.sc[k];
+        a2 = a2 + fb.sc[nc + k];
+    }
+    const double ar = m.area[k];
+    R[0] = a0 / ar;
+    R[1] = a1 / ar;
+    R[2] = a2 / ar;
+}
+
 // Tiles are consecutive Hilbert ranges, so tiles t and t+1 are neighbours in
 // space.  Workgroups are dealt round-robin to the eight XCDs, each with its
 // own L2; give XCD x one contiguous run of tiles so that the halo cells

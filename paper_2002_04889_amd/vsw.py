@@ -67,6 +67,8 @@ _SIGS = {
     "vsw_get_gauges": (ctypes.c_int, [_vp, _i64, _dp, _dp, _lp]),
     "vsw_set_stream": (ctypes.c_int, [_vp, _vp]),
     "vsw_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vsw_adjoint_gauge_loss": (ctypes.c_int, [_vp, _i64, _i64, ctypes.c_int32, _ip, _dp, _dp,
+                                              _dp, _dp, _dp, _dp]),
     "vsw_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_set_kernel_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _lp]),
@@ -250,6 +252,18 @@ def vsw_set_stream(h, stream_handle: int | None):
 
 def vsw_set_kernel_variant(h, variant: int):
     return _check(lib().vsw_set_kernel_variant(h, int(variant)))
+
+
+def vsw_adjoint_gauge_loss(h, nc, nsteps, checkpoint_every, gauges, eta_obs):
+    """Returns (loss, dL/dH0, dL/dHU0, dL/dHV0, dL/dh) in the caller's order."""
+    gauges = np.ascontiguousarray(gauges, dtype=np.int32)
+    obs = _f64(np.asarray(eta_obs, dtype=np.float64).reshape(int(nsteps), len(gauges)))
+    loss = ctypes.c_double(0.0)
+    out = [np.empty(nc) for _ in range(4)]
+    _check(lib().vsw_adjoint_gauge_loss(h, int(nsteps), int(checkpoint_every), len(gauges),
+                                        gauges.ctypes.data_as(_ip), _dptr(obs),
+                                        ctypes.byref(loss), *[_dptr(o) for o in out]))
+    return (loss.value, *out)
 
 
 def vsw_set_graph(h, on: bool):

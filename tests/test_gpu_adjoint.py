@@ -1,0 +1,188 @@
+"""The hand-written discrete adjoint (vsw_adjoint_gauge_loss) against
+(a) the tape gradient of the differentiable oracle (oracle/torch_scheme.py,
+    torch.autograd, FP64): every gradient field within 1e-10 of the largest
+    entry, with the CFL and the fixed time step, on the basin and on
+    Thacker's bowl (moving wet/dry front);
+(b) central finite differences of the GPU FP64 forward on 10 smooth
+    directions of the initial surface and the bed (tie-free state, best of
+    three steps, 1e-6 / 1e-5 of sum |g_i v_i| plus the loss's round-off);
+plus determinism over checkpoint intervals, the solver state left as it
+was, and the torch.autograd.Function wrapper with bed-displacement
+amplitudes."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import torch_scheme as TS
+from paper_2002_04889_amd import vsw
+from paper_2002_04889_amd import workloads as W
+from paper_2002_04889_amd.adjoint import GaugeLoss, displacement_basis
+from test_oracle_adjoint import generic_basin
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def setup_case(which):
+    if which == "basin":
+        c = generic_basin()
+        wet = np.flatnonzero(c.H > 10.0)
+    else:
+        c = W.thacker_case(23)
+        wet = np.flatnonzero(c.H > 0.02)
+    rng = np.random.default_rng(5)
+    gauges = rng.choice(wet, 5, replace=False).astype(np.int32)
+    return c, gauges, rng
+
+
+def gpu_adjoint(c, nsteps, ckpt, gauges, obs, dt_fixed=0.0):
+    s = vsw.Solver.for_case(c, dt_fixed=dt_fixed)
+    try:
+        return vsw.vsw_adjoint_gauge_loss(s.h, c.nc, nsteps, ckpt, gauges, obs)
+    finally:
+        s.close()
+
+
+def gpu_loss(c, H0, h, nsteps, gauges, obs, dt_fixed=0.0):
+    s = vsw.Solver(g=c.g, cfl=c.cfl, h_threshold=c.h_threshold, dt_fixed=dt_fixed)
+    try:
+        s.upload_mesh(c.vx, c.vy, c.tri, h)
+        s.set_state(H0, c.HU, c.HV, 0.0)
+        vsw.vsw_set_gauges(s.h, gauges)
+        rc, done, _ = s.step(nsteps)
+        assert done == nsteps
+        _, eta = vsw.vsw_get_gauges(s.h, len(gauges))
+    finally:
+        s.close()
+    r = eta - obs
+    return float((r * r).sum())
+
+
+@pytest.mark.parametrize("which,dt_mode", [("basin", "cfl"), ("basin", "fixed"),
+                                           ("thacker", "cfl")])
+def test_adjoint_matches_tape_gradient(orc, which, dt_mode):
+    c, gauges, rng = setup_case(which)
+    nsteps = 12
+    obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
+    dt_fixed = 0.0 if dt_mode == "cfl" else (2.0 if which == "basin" else 2e-3)
+    loss, gH, gU, gV, gh = gpu_adjoint(c, nsteps, 5, gauges, obs, dt_fixed)
+    G = TS.Geometry(orc.Mesh.from_case(c))
+    t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64), requires_grad=True)
+    H0, U0, V0, h = t(c.H), t(c.HU), t(c.HV), t(c.h)
+    L, _ = TS.gauge_loss(G, H0, U0, V0, h, nsteps, gauges, obs, c.g, c.h_threshold, c.cfl,
+                         dt_fixed)
+    ref = torch.autograd.grad(L, (H0, U0, V0, h))
+    Lf = float(L.detach())
+    say(f"{which}/{dt_mode}: loss gpu {loss:.15e} tape {Lf:.15e}")
+    assert abs(loss - Lf) <= 1e-12 * abs(Lf)
+    for name, a, b in zip(("H", "HU", "HV", "h"), (gH, gU, gV, gh), ref):
+        b = b.numpy()
+        scale = np.abs(b).max()
+        err = np.abs(a - b).max()
+        say(f"  d/d{name}: max |gpu - tape| {err:.3e}, max |tape| {scale:.3e}, "
+            f"rel {err / max(scale, 1e-300):.3e}")
+        assert err <= TOL * scale, name
+
+
+def test_adjoint_matches_finite_differences():
+    c, gauges, rng = setup_case("basin")
+    nsteps = 20
+    obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
+    loss, gH, gU, gV, gh = gpu_adjoint(c, nsteps, 8, gauges, obs)
+    assert abs(loss - gpu_loss(c, c.H, c.h, nsteps, gauges, obs)) <= 1e-13 * loss
+    cx, cy = c.centroids()
+    wet = c.H > 10.0
+    for k in range(10):
+        # a bump within reach of a gauge (waves travel ~50 km in 20 steps)
+        gk = gauges[k % len(gauges)]
+        x0, y0 = cx[gk] + rng.uniform(-30e3, 30e3), cy[gk] + rng.uniform(-30e3, 30e3)
+        v = np.exp(-((cx - x0) ** 2 + (cy - y0) ** 2) / (2 * 40e3 ** 2)) * wet
+        which = "eta0" if k % 2 == 0 else "bed"
+        if which == "eta0":  # initial surface, bed fixed
+            g, steps, tol = gH, (1e-2, 1e-3, 1e-4), 1e-6
+            f = lambda e: gpu_loss(c, c.H + e * v, c.h, nsteps, gauges, obs)
+        else:  # bed and total depth together (surface fixed)
+            g, steps, tol = gH + gh, (3.0, 1.0, 0.3), 1e-5
+            f = lambda e: gpu_loss(c, c.H + e * v, c.h + e * v, nsteps, gauges, obs)
+        ad = float((g * v).sum())
+        scale = float(np.abs(g * v).sum())
+        errs = [abs((f(e) - f(-e)) / (2 * e) - ad) for e in steps]
+        # round-off of the loss itself (eta = H - h at 4000 m) bounds what a
+        # difference quotient can resolve: ~1e-12 of the loss per unit step
+        noise = 1e-12 * loss / min(steps)
+        say(f"direction {k} ({which}): adjoint {ad:.10e}, best |FD - adjoint| / scale "
+            f"{min(errs) / scale:.3e} (noise floor {noise:.1e})")
+        assert min(errs) <= tol * scale + noise
+
+
+def test_adjoint_deterministic_over_checkpoints_and_leaves_state():
+    c, gauges, rng = setup_case("basin")
+    nsteps = 13
+    obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
+    outs = [gpu_adjoint(c, nsteps, k, gauges, obs) for k in (1, 4, 13, 50)]
+    for o in outs[1:]:
+        assert o[0] == outs[0][0]
+        for a, b in zip(o[1:], outs[0][1:]):
+            assert np.array_equal(a, b)
+    s = vsw.Solver.for_case(c)
+    try:
+        vsw.vsw_set_gauges(s.h, np.array([3, 7], dtype=np.int32))
+        s.step(3)
+        before = s.state()
+        dts = vsw.vsw_dt_history(s.h)
+        vsw.vsw_adjoint_gauge_loss(s.h, c.nc, 5, 2, gauges, obs[:5])
+        after = s.state()
+        for a, b in zip(before, after):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        assert np.array_equal(dts, vsw.vsw_dt_history(s.h))
+        s.step(2)
+        t, eta = vsw.vsw_get_gauges(s.h, 2)
+        assert eta.shape == (2, 2)
+    finally:
+        s.close()
+
+
+def test_autograd_function_and_displacement_amplitudes():
+    c, gauges, rng = setup_case("basin")
+    nsteps = 10
+    obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
+    cx, cy = c.centroids()
+    Phi = torch.tensor(displacement_basis(cx, cy, nx=4, ny=2, sigma=40e3))
+    h0 = torch.tensor(c.h)
+    H0 = torch.tensor(c.H)
+    params = dict(g=c.g, cfl=c.cfl, h_threshold=c.h_threshold)
+    mesh = (c.vx, c.vy, c.tri)
+
+    def loss_of(a):
+        # a displacement raises the bed and the initial surface together:
+        # the total depth H0 stays, h loses the displacement
+        h = h0 - Phi @ a
+        return GaugeLoss.apply(H0, torch.tensor(c.HU), torch.tensor(c.HV), h, mesh, params,
+                               nsteps, 4, gauges, obs)
+
+    a = torch.zeros(Phi.shape[1], dtype=torch.float64, requires_grad=True)
+    L = loss_of(a)
+    L.backward()
+    _, _, _, _, gh = gpu_adjoint(c, nsteps, 4, gauges, obs)
+    direct = -(Phi.T @ torch.tensor(gh)).numpy()
+    assert np.allclose(a.grad.numpy(), direct, rtol=1e-12, atol=0.0)
+    for i in (0, 5):
+        # an amplitude moves the initial surface by up to its value: steps
+        # of the surface directions' size
+        errs = []
+        for eps in (1e-2, 1e-3, 1e-4):
+            e = torch.zeros_like(a)
+            e[i] = eps
+            with torch.no_grad():
+                fd = float((loss_of(e) - loss_of(-e)) / (2 * eps))
+            errs.append(abs(fd - float(a.grad[i])))
+        say(f"amplitude {i}: autograd {float(a.grad[i]):.8e}, best |FD - autograd| {min(errs):.3e}")
+        assert min(errs) <= 1e-6 * float(np.abs(direct).max())
