@@ -146,8 +146,11 @@ def run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, precision, ordering, st
 
 def bench_ensemble(args, torch, vsw, W):
     """Uneven-size scenario ensemble: every scenario advances `steps` steps
-    (one run) with its own dt, all scenarios in the same launches, FP32.
-    value = ensemble runs/s = scenarios / seconds for the timed steps."""
+    (one run) with its own dt, all scenarios in the same launches, FP32, in
+    the launch configuration the autotuner picks.  value = ensemble runs/s =
+    scenarios / seconds for the timed steps."""
+    import numpy as np
+
     steps = args.steps if args.steps is not None else 500
     warmup = args.warmup if args.warmup is not None else 10
     dev = torch.device("cuda:0")
@@ -159,33 +162,37 @@ def bench_ensemble(args, torch, vsw, W):
         f"{max(c.nc for c in cases)}), generated in {time.perf_counter() - t0:.1f} s")
     stream = torch.cuda.Stream(device=dev)
 
-    def ensemble_leg(precision, graph, label):
+    def ensemble_leg(precision, label):
         s = vsw.Solver.for_ensemble(cases, precision=precision)
         try:
             vsw.vsw_set_stream(s.h, stream.cuda_stream)
-            vsw.vsw_set_graph(s.h, graph)
+            chosen, table = vsw.vsw_autotune(s.h, 40)
+            log(f"[bench] {label}: autotuner chose {vsw.tune_config_name(chosen)}; ms/step "
+                + ", ".join(f"{c}:{m:.3f}" for c, m in enumerate(table)))
             s.step(warmup)
             ms = time_steps(torch, stream, s, steps)
             ts, dts, st = vsw.vsw_scenario_status(s.h)
             assert (st == steps).all(), st
             leg = {"runs_per_s": nsc / (ms / 1e3), "ms_per_step": ms / steps,
-                   "cell_updates_per_s": ncell * steps / (ms / 1e3), "graph": graph,
+                   "cell_updates_per_s": ncell * steps / (ms / 1e3),
+                   "autotune": {"chosen": vsw.tune_config_name(chosen),
+                                "ms_per_step": {vsw.tune_config_name(c): (round(m, 4) if
+                                                np.isfinite(m) else None)
+                                                for c, m in enumerate(table)}},
                    "scenario_dt_range_s": [float(dts.min()), float(dts.max())]}
             log(f"[bench] {label}: {steps} steps {ms:.1f} ms, {leg['runs_per_s']:.2f} runs/s, "
                 f"{leg['cell_updates_per_s']:.3e} cell-updates/s")
-            if not graph:
-                b1, b2 = ((ALG_BYTES_STAGE1, ALG_BYTES_STAGE2) if precision == vsw.VSW_FP64
-                          else (ALG_BYTES_STAGE1_F32, ALG_BYTES_STAGE2_F32))
-                leg["roofline"] = kernel_roofline(vsw, s, min(steps, 100), ncell, b1, b2)
+            b1, b2 = ((ALG_BYTES_STAGE1, ALG_BYTES_STAGE2) if precision == vsw.VSW_FP64
+                      else (ALG_BYTES_STAGE1_F32, ALG_BYTES_STAGE2_F32))
+            leg["roofline"] = kernel_roofline(vsw, s, min(steps, 100), ncell, b1, b2)
             return leg
         finally:
             s.close()
 
     legs = {}
-    legs["fp32_graph"] = ensemble_leg(vsw.VSW_FP32, True, "ensemble fp32, graph")
-    legs["fp32_direct"] = ensemble_leg(vsw.VSW_FP32, False, "ensemble fp32, direct launches")
+    legs["fp32"] = ensemble_leg(vsw.VSW_FP32, "ensemble fp32")
     if not args.no_fp64:
-        legs["fp64_graph"] = ensemble_leg(vsw.VSW_FP64, True, "ensemble fp64, graph")
+        legs["fp64"] = ensemble_leg(vsw.VSW_FP64, "ensemble fp64")
     # the same runs one scenario after another on the same GPU
     seq_ms = 0.0
     for c in cases:
@@ -199,7 +206,7 @@ def bench_ensemble(args, torch, vsw, W):
             s.close()
     seq = {"runs_per_s": nsc / (seq_ms / 1e3), "ms_total": seq_ms, "graph": True}
     log(f"[bench] sequential fp32: {nsc} runs in {seq_ms:.1f} ms, {seq['runs_per_s']:.2f} runs/s")
-    top = legs.pop("fp32_graph")
+    top = legs.pop("fp32")
     out = {"metric": "ensemble runs/s", "value": top["runs_per_s"], "unit": "runs/s",
            "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": top["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -211,7 +218,7 @@ def bench_ensemble(args, torch, vsw, W):
                       "precision": "fp32 state, fp64 accumulation", "ordering": "hilbert",
                       "global_batch": ncell, "parallelism": "single-gpu"},
            "cell_updates_per_s": top["cell_updates_per_s"],
-           "roofline": legs["fp32_direct"].get("roofline"),
+           "roofline": top["roofline"], "autotune": top["autotune"],
            "vs_sequential": top["runs_per_s"] / seq["runs_per_s"],
            "sequential_fp32": seq}
     out.update(legs)

@@ -222,6 +222,26 @@ int vsw_set_kernel_variant(vsw_solver *s, int variant);
  * (vsw_set_profiling) launches directly.  on = 0 frees the graph. */
 int vsw_set_graph(vsw_solver *s, int on);
 
+/* Order in which the stage kernels' workgroups visit the tiles: 1
+ * (default) deals each of the eight XCDs (each with its own L2) one
+ * contiguous run of Hilbert-ordered tiles; 0 visits tiles in index order.
+ * Results are bitwise the same.  EINVAL for other values. */
+int vsw_set_tile_order(vsw_solver *s, int xcd_order);
+
+/* Autotuner: runs `steps` steps (after two warm-up steps) of the current
+ * state under every launch configuration c = 0 .. VSW_TUNE_CONFIGS - 1
+ * (bit 2: the two-pass kernel organisation, FP64 only; bit 1: XCD tile
+ * order; bit 0: graph mode), timing each with HIP events on the solver's
+ * stream, restores the state, time and logs after each, and keeps the
+ * fastest configuration for later vsw_step calls.  Every configuration
+ * gives bitwise the same results.  ms_per_step (may be NULL) receives
+ * VSW_TUNE_CONFIGS values (INFINITY where a configuration does not apply),
+ * *chosen (may be NULL) the winner.  EINVAL unless 2 <= steps <= 100000;
+ * ESTATE without mesh and state. */
+enum { VSW_TUNE_CONFIGS = 8 };
+int vsw_autotune(vsw_solver *s, int64_t steps, int32_t *chosen,
+                 double *ms_per_step);
+
 /* Per-kernel timing with HIP events recorded around every launch of the
  * stage kernels on the solver's stream (off by default).  vsw_kernel_times
  * returns, for kernel kinds 0..nkinds-1 (see vsw_kernel_name), the summed

@@ -117,6 +117,7 @@ struct vsw_solver {
     int bmax = 0, ntiles = 0;
     int variant = VSW_KERNEL_FUSED;
     bool use_graph = false;
+    int xcd_order = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     GraphKey graph_key{};
@@ -482,7 +483,8 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     double* lg = s->d_log.p;
     const dim3 grid(unsigned(s->ntiles)), block(kBlock);
     hipStream_t st = s->stream;
-    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, nseg};
+    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, nseg,
+               s->xcd_order};
     const bool f32 = (s->prm.precision == VSW_FP32);
     const size_t lds = stage_lds_bytes(s->bmax);
     const size_t lds32 = stage_f32_lds_bytes(s->bmax);
@@ -563,7 +565,8 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     // into its launch arguments changes.
     const bool use_graph = s->use_graph && !prof && n >= 2;
     if (use_graph) {
-        const GraphKey key{lg, s->d_gauge_log.p, s->d_gauge_cells.p, ng, t_stop, s->variant};
+        const GraphKey key{lg, s->d_gauge_log.p, s->d_gauge_cells.p, ng, t_stop,
+                           s->variant * 2 + s->xcd_order};
         if (!s->graph_exec || !(key == s->graph_key)) {
             s->release_graph();
             prof = false;
@@ -802,7 +805,8 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     HIP_TRY(hipMemsetAsync(lam.p, 0, N * sizeof(Adj4), st));
     HIP_TRY(hipMemsetAsync(hbar.p, 0, N * sizeof(double), st));
     const DevMesh m = s->dev_mesh();
-    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, 1};
+    TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, 1,
+               s->xcd_order};
     const dim3 grid(unsigned(s->ntiles)), block(kBlock);
     const FaceBuf fb0{f0.p, sc0.p, o0.p}, fb1{f1.p, sc1.p, o1.p};
     int64_t* cells = s->d_gauge_cells.p;
@@ -951,6 +955,97 @@ int vsw_set_kernel_variant(vsw_solver* s, int variant) {
     if (variant == VSW_KERNEL_TWO_PASS && s->prm.precision == VSW_FP32)
         return fail(VSW_EINVAL, "the two-pass variant is FP64 only");
     s->variant = variant;
+    return VSW_OK;
+}
+
+int vsw_set_tile_order(vsw_solver* s, int xcd_order) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (xcd_order != 0 && xcd_order != 1) return fail(VSW_EINVAL, "tile order is 0 or 1");
+    s->xcd_order = xcd_order;
+    return VSW_OK;
+}
+
+int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_step) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_mesh || !s->has_state) return fail(VSW_ESTATE, "mesh and state required");
+    if (steps < 2 || steps > 100000) return fail(VSW_EINVAL, "steps must be in [2, 100000]");
+    DeviceGuard dg(s->device);
+    hipStream_t st = s->stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    const bool f32 = s->prm.precision == VSW_FP32;
+    const size_t n = size_t(s->nint);
+    const size_t bytes = n * (f32 ? sizeof(CellF) : sizeof(Cell4));
+    DevBuf<unsigned char> save;
+    HIP_TRY(save.alloc(bytes));
+    void* wp = f32 ? (void*)s->d_wf.p : (void*)s->d_w.p;
+    HIP_TRY(hipMemcpyAsync(save.p, wp, bytes, hipMemcpyDeviceToDevice, st));
+    const double t_save = s->t, dt_save = s->dt_last;
+    const int64_t clamps_save = s->clamps;
+    const std::vector<double> seg_t_save = s->seg_t, seg_dt_save = s->seg_dt;
+    const std::vector<int64_t> seg_steps_save = s->seg_steps;
+    const int variant_save = s->variant, xcd_save = s->xcd_order;
+    const bool graph_save = s->use_graph, prof_save = s->profiling;
+    s->profiling = false;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best = INFINITY;
+    int best_c = 0;
+    int rc = VSW_OK;
+    for (int c = 0; c < VSW_TUNE_CONFIGS; ++c) {
+        const int variant = (c >> 2) & 1, xcd = (c >> 1) & 1, graph = c & 1;
+        double ms = INFINITY;
+        if (!(variant == VSW_KERNEL_TWO_PASS && f32)) {
+            s->variant = variant;
+            s->xcd_order = xcd;
+            s->use_graph = graph != 0;
+            s->release_graph();
+            s->seg_t = seg_t_save;
+            rc = vsw_step(s, 2, INFINITY, nullptr, nullptr);  // warm-up (and graph capture)
+            if (rc == VSW_OK) {
+                HIP_TRY(hipEventRecord(e0, st));
+                rc = vsw_step(s, steps, INFINITY, nullptr, nullptr);
+                HIP_TRY(hipEventRecord(e1, st));
+                HIP_TRY(hipEventSynchronize(e1));
+                float f = 0.f;
+                HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+                ms = double(f) / double(steps);
+            }
+            HIP_TRY(hipMemcpyAsync(wp, save.p, bytes, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (rc != VSW_OK) break;
+        }
+        if (ms_per_step) ms_per_step[c] = ms;
+        if (ms < best) {
+            best = ms;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // restore the state and apply the winner
+    s->t = t_save;
+    s->dt_last = dt_save;
+    s->clamps = clamps_save;
+    s->seg_t = seg_t_save;
+    s->seg_dt = seg_dt_save;
+    s->seg_steps = seg_steps_save;
+    s->seg_log.clear();
+    s->last_dts.clear();
+    s->gauge_eta.clear();
+    s->gauge_t.clear();
+    s->profiling = prof_save;
+    s->release_graph();
+    if (rc != VSW_OK) {
+        s->variant = variant_save;
+        s->xcd_order = xcd_save;
+        s->use_graph = graph_save;
+        return rc;
+    }
+    s->variant = (best_c >> 2) & 1;
+    s->xcd_order = (best_c >> 1) & 1;
+    s->use_graph = (best_c & 1) != 0;
+    if (chosen) *chosen = best_c;
     return VSW_OK;
 }
 

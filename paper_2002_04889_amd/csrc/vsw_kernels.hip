@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
                                                        double* log) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
-    const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
+    const int t = tm.xcd_order ? xcd_tile(int(blockIdx.x), tm.ntiles) : int(blockIdx.x);
     const TileInfo ti = tile_info(tm.tinfo[t]);
     Seg* sgs = sg + ti.seg;
     const int step = c->kbase + step_arg;

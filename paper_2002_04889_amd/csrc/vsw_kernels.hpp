@@ -58,6 +58,7 @@ struct TileMap {
     int bmax;                            // most boundary faces of any tile
     int ntiles;
     int nseg;                            // scenarios
+    int xcd_order;                       // 1: deal contiguous tile runs to the XCDs
 };
 
 // Fused stage kernel.  STAGE 1: w1 = w + dt R(w).  STAGE 2:

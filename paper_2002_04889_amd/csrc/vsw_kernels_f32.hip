@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
     const int stride = 3 * kTile + tm.bmax;
     double* ld = lds;
     float* lf = reinterpret_cast<float*>(lds + 2 * stride);
-    const int t = xcd_tile(int(blockIdx.x), tm.ntiles);
+    const int t = tm.xcd_order ? xcd_tile(int(blockIdx.x), tm.ntiles) : int(blockIdx.x);
     const TileInfo ti = tile_info(tm.tinfo[t]);
     Seg* sgs = sg + ti.seg;
     const int step = c->kbase + step_arg;

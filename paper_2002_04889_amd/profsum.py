@@ -18,7 +18,6 @@ from __future__ import annotations
 import argparse
 import collections
 import csv
-import glob
 import hashlib
 import json
 import os
@@ -27,13 +26,21 @@ import re
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
+# The files the stage kernels are compiled from (their code and headers)
+# and the compile flags: a change to any of them invalidates measured traffic.
+STAGE_SOURCES = ("vsw_device.hpp", "vsw_common.hpp", "vsw_kernels.hpp", "vsw_kernels.hip",
+                 "vsw_kernels_f32.hpp", "vsw_kernels_f32.hip")
+
+
 def source_digest() -> str:
-    """sha256 over the kernel and host sources of the library."""
+    """sha256 over the stage kernels' sources and the compile flags."""
+    from . import build as libbuild
+
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
-            h.update(os.path.basename(f).encode())
-            h.update(open(f, "rb").read())
+    for f in STAGE_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    h.update(" ".join(libbuild.FLAGS).encode())
     return h.hexdigest()[:16]
 
 

@@ -70,6 +70,8 @@ _SIGS = {
     "vsw_adjoint_gauge_loss": (ctypes.c_int, [_vp, _i64, _i64, ctypes.c_int32, _ip, _dp, _dp,
                                               _dp, _dp, _dp, _dp]),
     "vsw_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vsw_set_tile_order": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vsw_autotune": (ctypes.c_int, [_vp, _i64, _ip, _dp]),
     "vsw_set_kernel_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _lp]),
     "vsw_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -264,6 +266,26 @@ def vsw_adjoint_gauge_loss(h, nc, nsteps, checkpoint_every, gauges, eta_obs):
                                         gauges.ctypes.data_as(_ip), _dptr(obs),
                                         ctypes.byref(loss), *[_dptr(o) for o in out]))
     return (loss.value, *out)
+
+
+VSW_TUNE_CONFIGS = 8
+
+
+def vsw_set_tile_order(h, xcd_order: int):
+    return _check(lib().vsw_set_tile_order(h, int(xcd_order)))
+
+
+def vsw_autotune(h, steps: int):
+    """Returns (chosen configuration, ms per step of every configuration)."""
+    chosen = ctypes.c_int32(-1)
+    ms = np.empty(VSW_TUNE_CONFIGS)
+    _check(lib().vsw_autotune(h, int(steps), ctypes.byref(chosen), _dptr(ms)))
+    return chosen.value, ms
+
+
+def tune_config_name(c: int) -> str:
+    return (("two-pass" if c & 4 else "fused") + (", XCD tile order" if c & 2 else
+            ", index tile order") + (", graph" if c & 1 else ", direct launches"))
 
 
 def vsw_set_graph(h, on: bool):

@@ -109,3 +109,47 @@ def test_graph_ensemble():
     b = session(ens, calls, True)
     assert_same(a, b)
     say("ensemble steps per scenario", b[-1]["status"][2], "t", b[-1]["status"][0])
+
+
+@pytest.mark.parametrize("precision", [vsw.VSW_FP64, vsw.VSW_FP32], ids=["fp64", "fp32"])
+def test_autotune_keeps_state_and_results(precision):
+    """The autotuner times every launch configuration, restores the state
+    and keeps the fastest; every configuration gives the same bits."""
+    c = W.basin_case(scale=16)
+    ref = session(c, [(30, math.inf)], False, precision=precision)
+    s = vsw.Solver.for_case(c, precision=precision)
+    try:
+        before = s.state()
+        chosen, ms = vsw.vsw_autotune(s.h, 10)
+        say(f"precision {precision}: chosen {chosen} ({vsw.tune_config_name(chosen)}), "
+            f"ms/step {np.round(ms, 4)}")
+        assert 0 <= chosen < vsw.VSW_TUNE_CONFIGS and ms[chosen] == np.min(ms)
+        if precision == vsw.VSW_FP32:
+            assert np.all(np.isinf(ms[4:])) and np.all(np.isfinite(ms[:4]))
+        else:
+            assert np.all(np.isfinite(ms))
+        after = s.state()
+        for a, b in zip(before, after):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        rc, done, t = s.step(30)
+        H, HU, HV, _ = s.state()
+    finally:
+        s.close()
+    assert done == 30 and t == ref[0]["t"]
+    for k, v in (("H", H), ("HU", HU), ("HV", HV)):
+        assert np.array_equal(v, ref[0][k])
+
+
+def test_tile_orders_bitwise():
+    c = W.basin_case(scale=16)
+    out = []
+    for order in (0, 1):
+        s = vsw.Solver.for_case(c)
+        try:
+            vsw.vsw_set_tile_order(s.h, order)
+            s.step(25)
+            out.append(s.state())
+        finally:
+            s.close()
+    for a, b in zip(*out):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
