@@ -132,9 +132,9 @@ __device__ __forceinline__ FaceF recon_face_f32(const ReconF& r, int j, double t
     f.h = r.fh[j];
     f.H = r.fH[j];
     if (r.fH[j] >= thr) {
-        const float Hf = float(r.fH[j]);
-        f.u = r.fu[j] / Hf;
-        f.v = r.fv[j] / Hf;
+        const float rH = 1.0f / float(r.fH[j]);
+        f.u = r.fu[j] * rH;
+        f.v = r.fv[j] * rH;
     } else {
         f.u = 0.0f;
         f.v = 0.0f;
@@ -182,10 +182,13 @@ __device__ __forceinline__ void hll_face_f32(double g, double hg, double HL, flo
         // rounded sR - sL would bias the g H^2 / 2 part, ~1e8, by ~1e-7
         // relative on every face).  Mass and normal-momentum star fluxes are
         // formed in FP64 from the FP32 terms; the tangential one in FP32.
+        // One reciprocal for the three components (this path is held to a
+        // tolerance, not to the FP64 path's bits).
         const double dR = double(sR), dL = double(sL), den = dR - dL, sLR = dL * dR;
-        f0 = float(((dR * double(fL0) - dL * double(fR0)) + sLR * (HR - HL)) / den);
-        f1 = ((dR * fL1 - dL * fR1) + sLR * (double(qR) - double(qL))) / den;
-        f2 = ((sR * fL2 - sL * fR2) + float(sLR) * (HRf * utR - HLf * utL)) / float(den);
+        const double rden = 1.0 / den;
+        f0 = float(((dR * double(fL0) - dL * double(fR0)) + sLR * (HR - HL)) * rden);
+        f1 = ((dR * fL1 - dL * fR1) + sLR * (double(qR) - double(qL))) * rden;
+        f2 = ((sR * fL2 - sL * fR2) + float(sLR) * (HRf * utR - HLf * utL)) * float(rden);
     }
 }
 
@@ -362,7 +365,8 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
             a2 = a2 + p.hg * sy;
         }
         const double ar = m.area[k];
-        const double R0 = a0 / ar, R1 = a1 / ar, R2 = a2 / ar;
+        const double rar = 1.0 / ar;
+        const double R0 = a0 * rar, R1 = a1 * rar, R2 = a2 * rar;
         const CellF w = W[k];
         double e, u, v;
         if (STAGE == 1) {
