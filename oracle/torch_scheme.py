@@ -114,9 +114,10 @@ def hll(g, HL, unL, utL, HR, unR, utR):
     star = ~(upL | upR | both_dry)
     den = sR - sL
     sLR = sL * sR
+    rd = _where_div(star, torch.ones_like(den), den)
     out = []
     for c in range(3):
-        fs = _where_div(star, (sR * fL[c] - sL * fR[c]) + sLR * dU[c], den)
+        fs = ((sR * fL[c] - sL * fR[c]) + sLR * dU[c]) * rd
         f = torch.where(upL, fL[c], torch.where(upR, fR[c], fs))
         out.append(torch.where(both_dry, torch.zeros_like(f), f))
     return out
@@ -175,8 +176,9 @@ def reconstruct(G: Geometry, H, HU, HV, h, thr):
     fh = torch.where(s, fh2, h[:, None].expand(-1, 3))
     fH = torch.where(s, fH2, H[:, None].expand(-1, 3))
     wet = fH >= thr
-    u = _where_div(wet, fu, fH)
-    v = _where_div(wet, fv, fH)
+    rH = _where_div(wet, torch.ones_like(fH), fH)
+    u = fu * rH
+    v = fv * rH
     return (fe, fh, fH, u, v), second
 
 
@@ -223,14 +225,16 @@ def residual(G: Geometry, H, HU, HV, h, g, thr):
     sy = (c[:, 0] * G.ny[:, 0] + c[:, 1] * G.ny[:, 1]) + c[:, 2] * G.ny[:, 2]
     a1 = torch.where(second, a1 + hg * sx, a1)
     a2 = torch.where(second, a2 + hg * sy, a2)
-    return a0 / G.area, a1 / G.area, a2 / G.area
+    ra = 1.0 / G.area
+    return a0 * ra, a1 * ra, a2 * ra
 
 
 def cfl_dt(G: Geometry, H, HU, HV, g, thr, cfl):
     """dt = CFL min over wet cells of |K| / (P_K (|u| + sqrt(g H)))."""
     wet = H >= thr
-    u = _where_div(wet, HU, H)
-    v = _where_div(wet, HV, H)
+    rH = _where_div(wet, torch.ones_like(H), H)
+    u = HU * rH
+    v = HV * rH
     # |u| is taken with a zero derivative at rest (u = v = 0)
     s = _ssqrt(u * u + v * v, (u * u + v * v) > 0.0) + _ssqrt(g * H, wet)
     r = torch.where(wet, G.area / (G.perim * torch.where(wet, s, torch.ones_like(s))),

@@ -324,9 +324,10 @@ static void hll_face_frame(double g, double HL, double unL, double utL,
     } else if (sR < 0.0) {
         f[0] = fR[0]; f[1] = fR[1]; f[2] = fR[2];
     } else {
-        double den = sR - sL, sLR = sL * sR;
+        /* the star flux over (s_R - s_L), taken as one reciprocal */
+        double den = sR - sL, sLR = sL * sR, rd = 1.0 / den;
         for (int c = 0; c < 3; ++c)
-            f[c] = ((sR * fL[c] - sL * fR[c]) + sLR * (wR[c] - wL[c])) / den;
+            f[c] = ((sR * fL[c] - sL * fR[c]) + sLR * (wR[c] - wL[c])) * rd;
     }
 }
 
@@ -463,8 +464,9 @@ static void recon_cell(const orc_mesh *m, const orc_params *p, const double *H,
             f[1] = fq[3][j];
             f[2] = fH[j];
             if (fH[j] >= thr) {
-                f[3] = fq[1][j] / fH[j];
-                f[4] = fq[2][j] / fH[j];
+                double rH = 1.0 / fH[j];
+                f[3] = fq[1][j] * rH;
+                f[4] = fq[2][j] * rH;
             } else {
                 f[3] = 0.0;
                 f[4] = 0.0;
@@ -566,9 +568,10 @@ void orc_residual(const orc_mesh *m, const orc_params *p, const double *H,
             acc[1] = acc[1] + sc[2 * k];
             acc[2] = acc[2] + sc[2 * k + 1];
         }
-        RH[k] = acc[0] / m->area[k];
-        RHU[k] = acc[1] / m->area[k];
-        RHV[k] = acc[2] / m->area[k];
+        double ra = 1.0 / m->area[k];
+        RH[k] = acc[0] * ra;
+        RHU[k] = acc[1] * ra;
+        RHV[k] = acc[2] * ra;
     }
     free(face); free(sc); free(ord); free(term);
 }
@@ -582,7 +585,7 @@ double orc_dt(const orc_mesh *m, const orc_params *p, const double *H,
     double rmin = INFINITY;
     for (int64_t k = 0; k < m->nc; ++k) {
         if (!(H[k] >= p->h_threshold)) continue;
-        double u = HU[k] / H[k], v = HV[k] / H[k];
+        double rH = 1.0 / H[k], u = HU[k] * rH, v = HV[k] * rH;
         double s = sqrt(u * u + v * v) + sqrt(p->g * H[k]);
         double r = m->area[k] / (m->perim[k] * s);
         rmin = mind(rmin, r);

@@ -69,14 +69,15 @@ __device__ __forceinline__ void hll_face_rev(double g, double hg, double HL, dou
     } else if (sR < 0.0) {
         fRb[0] = fb[0]; fRb[1] = fb[1]; fRb[2] = fb[2];
     } else {
-        const double den = sR - sL, sLR = sL * sR;
+        const double den = sR - sL, sLR = sL * sR, rd = 1.0 / den;
         const double dU[3] = {HR - HL, qR - qL, HR * utR - HL * utL};
-        double denb = 0.0, sLRb = 0.0;
+        double rdb = 0.0, sLRb = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double f = ((sR * fL[c] - sL * fR[c]) + sLR * dU[c]) / den;
-            const double nb = fb[c] / den;
-            denb -= fb[c] * f / den;
+            // f_c = N_c * rd
+            const double N = (sR * fL[c] - sL * fR[c]) + sLR * dU[c];
+            const double nb = fb[c] * rd;
+            rdb += fb[c] * N;
             sRb += nb * fL[c];
             fLb[c] += nb * sR;
             sLb -= nb * fR[c];
@@ -86,6 +87,7 @@ __device__ __forceinline__ void hll_face_rev(double g, double hg, double HL, dou
         }
         sLb += sLRb * sR;
         sRb += sLRb * sL;
+        const double denb = -rdb * rd * rd;  // rd = 1 / den
         sRb += denb;
         sLb -= denb;
     }
@@ -551,11 +553,12 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_recon_kernel(DevMesh m, TileMa
         fub[j] = 0.0;
         fvb[j] = 0.0;
         if (fH[j] >= thr) {
+            // u = fu * rH, v = fv * rH, rH = 1 / fH
             const double ub = Fb[(5 * j + 3) * nc + k], vb = Fb[(5 * j + 4) * nc + k];
-            const double u = fu[j] / fH[j], v = fv[j] / fH[j];
-            fub[j] = ub / fH[j];
-            fvb[j] = vb / fH[j];
-            fHb[j] -= (ub * u + vb * v) / fH[j];
+            const double rH = 1.0 / fH[j];
+            fub[j] = ub * rH;
+            fvb[j] = vb * rH;
+            fHb[j] -= (ub * fu[j] + vb * fv[j]) * rH * rH;
         }
     }
     double Hkb = D[2 * k], hkb = D[2 * k + 1], ekb = 0.0, ukb = 0.0, vkb = 0.0;

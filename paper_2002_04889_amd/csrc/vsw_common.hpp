@@ -65,7 +65,7 @@ __device__ __forceinline__ bool step_dt(const Ctrl* c, const Seg* sg, int slot,
 __device__ __forceinline__ double cfl_ratio(double H, double HU, double HV, double area,
                                             double perim, double g, double thr) {
     if (!(H >= thr)) return __longlong_as_double(0x7FF0000000000000ll);
-    const double u = HU / H, v = HV / H;
+    const double rH = 1.0 / H, u = HU * rH, v = HV * rH;
     const double s = sqrt(u * u + v * v) + sqrt(g * H);
     return area / (perim * s);
 }
@@ -166,10 +166,10 @@ __device__ __forceinline__ void residual_from_faces(const DevMesh& m, const Face
         a1 = a1 + fb.sc[k];
         a2 = a2 + fb.sc[nc + k];
     }
-    const double ar = m.area[k];
-    R[0] = a0 / ar;
-    R[1] = a1 / ar;
-    R[2] = a2 / ar;
+    const double ra = 1.0 / m.area[k];
+    R[0] = a0 * ra;
+    R[1] = a1 * ra;
+    R[2] = a2 * ra;
 }
 
 // Tiles are consecutive Hilbert ranges, so tiles t and t+1 are neighbours in

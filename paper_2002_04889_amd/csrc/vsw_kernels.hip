@@ -275,7 +275,8 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
             a2 = a2 + sc[1];
         }
         const double ar = m.area[k];
-        const double R[3] = {a0 / ar, a1 / ar, a2 / ar};
+        const double ra = 1.0 / ar;
+        const double R[3] = {a0 * ra, a1 * ra, a2 * ra};
         if (STAGE == 1) {
             W1[k] = stage1_update(W[k], R, dt, p.thr, clamp);
         } else {
