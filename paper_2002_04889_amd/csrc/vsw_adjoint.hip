@@ -242,81 +242,10 @@ __device__ __forceinline__ void limiter_rev(double a, double ab, const LimInfo& 
 
 }  // namespace
 
-// ---------------------------------------------------------------- forward pieces
-
-__global__ __launch_bounds__(kBlock) void adj_faces_kernel(DevMesh m, TileMap tm,
-                                                           const Cell4* __restrict__ W, FaceBuf fb,
-                                                           double thr, double hg) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x, nc = m.nc;
-    Face f[3];
-    double sc[2];
-    const bool second = recon_cell(m, W, k, thr, hg, f, sc);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        fb.f[(5 * j + 0) * nc + k] = f[j].eta;
-        fb.f[(5 * j + 1) * nc + k] = f[j].h;
-        fb.f[(5 * j + 2) * nc + k] = f[j].H;
-        fb.f[(5 * j + 3) * nc + k] = f[j].u;
-        fb.f[(5 * j + 4) * nc + k] = f[j].v;
-    }
-    fb.sc[k] = sc[0];
-    fb.sc[nc + k] = sc[1];
-    fb.order[k] = second ? 2 : 1;
-}
-
-__global__ __launch_bounds__(kBlock) void adj_residual_kernel(DevMesh m, TileMap tm, FaceBuf fb,
-                                                              double g, double hg, double* R) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    double r[3];
-    residual_from_faces(m, fb, k, g, hg, r);
-    R[3 * k] = r[0];
-    R[3 * k + 1] = r[1];
-    R[3 * k + 2] = r[2];
-}
-
-__global__ __launch_bounds__(kBlock) void adj_stage1_kernel(TileMap tm, const Cell4* __restrict__ W,
-                                                            const double* __restrict__ R0,
-                                                            double dt, double thr,
-                                                            Cell4* __restrict__ W1,
-                                                            uint8_t* __restrict__ mask1) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    const Cell4 w = W[k];
-    Cell4 o;
-    o.H = w.H + dt * R0[3 * k];
-    o.HU = w.HU + dt * R0[3 * k + 1];
-    o.HV = w.HV + dt * R0[3 * k + 2];
-    o.h = w.h;
-    uint8_t mk = 3;
-    if (o.H < 0.0) { o.H = 0.0; mk &= ~1; }
-    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; mk &= ~2; }
-    W1[k] = o;
-    mask1[k] = mk;
-}
-
-__global__ __launch_bounds__(kBlock) void adj_mask2_kernel(TileMap tm, const Cell4* __restrict__ W,
-                                                           const Cell4* __restrict__ W1,
-                                                           const double* __restrict__ R1,
-                                                           double dt, double thr,
-                                                           uint8_t* __restrict__ mask2) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    double H = 0.5 * W[k].H + 0.5 * (W1[k].H + dt * R1[3 * k]);
-    uint8_t mk = 3;
-    if (H < 0.0) { H = 0.0; mk &= ~1; }
-    if (H < thr) mk &= ~2;
-    mask2[k] = mk;
-}
-
 namespace {
 
-// Block sum in a fixed order (wavefront butterflies, then the four waves).
+// Block sum in a fixed order (wavefront butterflies, then the four waves);
+// every thread of the block must call it.
 __device__ __forceinline__ double block_sum(double v) {
     __shared__ double part[kBlock / 64];
 #pragma unroll
@@ -330,19 +259,90 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
+// Post-stage fix of a pre-fix state: bit 0 = depth kept (not clamped),
+// bit 1 = momentum kept (depth at least H_thr).
+__device__ __forceinline__ uint8_t fix_mask(double& H, double& HU, double& HV, double thr) {
+    uint8_t mk = 3;
+    if (H < 0.0) { H = 0.0; mk &= ~1; }
+    if (H < thr) { HU = 0.0; HV = 0.0; mk &= ~2; }
+    return mk;
+}
+
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void adj_rk2_pre_kernel(TileMap tm, const Adj4* __restrict__ lam,
-                                                             const uint8_t* __restrict__ mask2,
-                                                             const double* __restrict__ R1,
-                                                             double dt, double* __restrict__ mu,
-                                                             Adj4* __restrict__ lamn,
-                                                             double* __restrict__ part) {
+// ---------------------------------------------------------------- forward pieces
+
+__global__ __launch_bounds__(kBlock) void adj_faces_kernel(DevMesh m, TileMap tm,
+                                                           const Cell4* __restrict__ W, FaceBuf fb,
+                                                           double g, double thr, double hg,
+                                                           unsigned long long* rmin) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x, nc = m.nc;
+    double r = __longlong_as_double(0x7FF0000000000000ll);
+    if (int(threadIdx.x) < ti.cnt) {
+        Face f[3];
+        double sc[2];
+        const bool second = recon_cell(m, W, k, thr, hg, f, sc);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            fb.f[(5 * j + 0) * nc + k] = f[j].eta;
+            fb.f[(5 * j + 1) * nc + k] = f[j].h;
+            fb.f[(5 * j + 2) * nc + k] = f[j].H;
+            fb.f[(5 * j + 3) * nc + k] = f[j].u;
+            fb.f[(5 * j + 4) * nc + k] = f[j].v;
+        }
+        fb.sc[k] = sc[0];
+        fb.sc[nc + k] = sc[1];
+        fb.order[k] = second ? 2 : 1;
+        if (rmin) {
+            const Cell4 q = W[k];
+            r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
+        }
+    }
+    if (rmin) block_min_atomic(r, rmin);
+}
+
+__global__ __launch_bounds__(kBlock) void adj_stage1_kernel(DevMesh m, TileMap tm, FaceBuf fb,
+                                                            const Cell4* __restrict__ W, double g,
+                                                            double hg, double dt, double thr,
+                                                            double* __restrict__ R0,
+                                                            Cell4* __restrict__ W1,
+                                                            uint8_t* __restrict__ mask1) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    double R[3];
+    residual_from_faces(m, fb, k, g, hg, R);
+    R0[3 * k] = R[0];
+    R0[3 * k + 1] = R[1];
+    R0[3 * k + 2] = R[2];
+    const Cell4 w = W[k];
+    Cell4 o;
+    o.H = w.H + dt * R[0];
+    o.HU = w.HU + dt * R[1];
+    o.HV = w.HV + dt * R[2];
+    o.h = w.h;
+    mask1[k] = fix_mask(o.H, o.HU, o.HV, thr);
+    W1[k] = o;
+}
+
+__global__ __launch_bounds__(kBlock) void adj_stage2_kernel(
+    DevMesh m, TileMap tm, FaceBuf fb, const Cell4* __restrict__ W, const Cell4* __restrict__ W1,
+    double g, double hg, double dt, double thr, const Adj4* __restrict__ lam,
+    uint8_t* __restrict__ mask2, double* __restrict__ mu, Adj4* __restrict__ lamn,
+    double* __restrict__ part) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
     double d = 0.0;
     if (int(threadIdx.x) < ti.cnt) {
-        const uint8_t mk = mask2[k];
+        double R[3];
+        residual_from_faces(m, fb, k, g, hg, R);
+        const Cell4 w = W[k], w1 = W1[k];
+        double H = 0.5 * w.H + 0.5 * (w1.H + dt * R[0]);
+        double HU = 0.5 * w.HU + 0.5 * (w1.HU + dt * R[1]);
+        double HV = 0.5 * w.HV + 0.5 * (w1.HV + dt * R[2]);
+        const uint8_t mk = fix_mask(H, HU, HV, thr);
+        mask2[k] = mk;
         const Adj4 l = lam[k];
         const double l0 = (mk & 1) ? l.H : 0.0, l1 = (mk & 2) ? l.HU : 0.0,
                      l2 = (mk & 2) ? l.HV : 0.0;
@@ -350,51 +350,10 @@ __global__ __launch_bounds__(kBlock) void adj_rk2_pre_kernel(TileMap tm, const A
         mu[3 * k + 1] = 0.5 * dt * l1;
         mu[3 * k + 2] = 0.5 * dt * l2;
         lamn[k] = Adj4{0.5 * l0, 0.5 * l1, 0.5 * l2, 0.0};
-        d = 0.5 * (l0 * R1[3 * k] + l1 * R1[3 * k + 1] + l2 * R1[3 * k + 2]);
+        d = 0.5 * (l0 * R[0] + l1 * R[1] + l2 * R[2]);
     }
     const double s = block_sum(d);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(kBlock) void adj_rk2_post_kernel(
-    TileMap tm, const Adj4* __restrict__ lam, const uint8_t* __restrict__ mask2,
-    const Adj4* __restrict__ wb2, const uint8_t* __restrict__ mask1, const double* __restrict__ R0,
-    double dt, double* __restrict__ mu, Adj4* __restrict__ lamn, double* __restrict__ hbar,
-    double* __restrict__ part) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    double d = 0.0;
-    if (int(threadIdx.x) < ti.cnt) {
-        const uint8_t m2 = mask2[k], m1 = mask1[k];
-        const Adj4 l = lam[k], w = wb2[k];
-        const double a0 = ((m2 & 1) ? 0.5 * l.H : 0.0) + w.H;
-        const double a1 = ((m2 & 2) ? 0.5 * l.HU : 0.0) + w.HU;
-        const double a2 = ((m2 & 2) ? 0.5 * l.HV : 0.0) + w.HV;
-        const double t0 = (m1 & 1) ? a0 : 0.0, t1 = (m1 & 2) ? a1 : 0.0, t2 = (m1 & 2) ? a2 : 0.0;
-        mu[3 * k] = dt * t0;
-        mu[3 * k + 1] = dt * t1;
-        mu[3 * k + 2] = dt * t2;
-        Adj4 n = lamn[k];
-        n.H += t0; n.HU += t1; n.HV += t2;
-        lamn[k] = n;
-        hbar[k] += w.h;
-        d = t0 * R0[3 * k] + t1 * R0[3 * k + 1] + t2 * R0[3 * k + 2];
-    }
-    const double s = block_sum(d);
-    if (threadIdx.x == 0) part[blockIdx.x] += s;
-}
-
-__global__ __launch_bounds__(kBlock) void adj_rk1_post_kernel(TileMap tm, const Adj4* __restrict__ wb1,
-                                                              Adj4* __restrict__ lamn,
-                                                              double* __restrict__ hbar) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    const Adj4 w = wb1[k];
-    Adj4 n = lamn[k];
-    n.H += w.H; n.HU += w.HU; n.HV += w.HV;
-    lamn[k] = n;
-    hbar[k] += w.h;
 }
 
 // ---------------------------------------------------------------- J_R^T mu
@@ -547,14 +506,17 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_recon_kernel(DevMesh m, TileMa
     double feb[3], fub[3], fvb[3], fhb[3], fHb[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        feb[j] = Fb[(5 * j + 0) * nc + k];
-        fhb[j] = Fb[(5 * j + 1) * nc + k];
-        fHb[j] = Fb[(5 * j + 2) * nc + k];
+        double a[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) a[c] = Fb[(5 * j + c) * nc + k];
+        feb[j] = a[0];
+        fhb[j] = a[1];
+        fHb[j] = a[2];
         fub[j] = 0.0;
         fvb[j] = 0.0;
         if (fH[j] >= thr) {
             // u = fu * rH, v = fv * rH, rH = 1 / fH
-            const double ub = Fb[(5 * j + 3) * nc + k], vb = Fb[(5 * j + 4) * nc + k];
+            const double ub = a[3], vb = a[4];
             const double rH = 1.0 / fH[j];
             fub[j] = ub * rH;
             fvb[j] = vb * rH;
@@ -634,12 +596,11 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_recon_kernel(DevMesh m, TileMa
     out[3] = hkb - ekb;
 }
 
-__global__ __launch_bounds__(kBlock) void adj_vjp_gather_kernel(DevMesh m, TileMap tm,
-                                                                const double* __restrict__ C,
-                                                                Adj4* __restrict__ wb) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+namespace {
+
+// own + the stencil contributions the face neighbours made to cell k
+__device__ __forceinline__ Adj4 gather_cell(const DevMesh& m, const double* __restrict__ C,
+                                            int64_t k) {
     const double* o = C + 16 * k;
     double a0 = o[0], a1 = o[1], a2 = o[2], a3 = o[3];
     const Nbr4 nb = m.nbr[k];
@@ -651,23 +612,55 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_gather_kernel(DevMesh m, TileM
         const double* c = C + 16 * int64_t(s >> 3) + 4 + 4 * int(s & 3u);
         a0 += c[0]; a1 += c[1]; a2 += c[2]; a3 += c[3];
     }
-    wb[k] = Adj4{a0, a1, a2, a3};
+    return Adj4{a0, a1, a2, a3};
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
+    DevMesh m, TileMap tm, const double* __restrict__ C, const Adj4* __restrict__ lam,
+    const uint8_t* __restrict__ mask2, const uint8_t* __restrict__ mask1,
+    const double* __restrict__ R0, double dt, double* __restrict__ mu, Adj4* __restrict__ lamn,
+    double* __restrict__ hbar, double* __restrict__ part) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    double d = 0.0;
+    if (int(threadIdx.x) < ti.cnt) {
+        const Adj4 w = gather_cell(m, C, k);
+        const uint8_t m2 = mask2[k], m1 = mask1[k];
+        const Adj4 l = lam[k];
+        const double a0 = ((m2 & 1) ? 0.5 * l.H : 0.0) + w.H;
+        const double a1 = ((m2 & 2) ? 0.5 * l.HU : 0.0) + w.HU;
+        const double a2 = ((m2 & 2) ? 0.5 * l.HV : 0.0) + w.HV;
+        const double t0 = (m1 & 1) ? a0 : 0.0, t1 = (m1 & 2) ? a1 : 0.0, t2 = (m1 & 2) ? a2 : 0.0;
+        mu[3 * k] = dt * t0;
+        mu[3 * k + 1] = dt * t1;
+        mu[3 * k + 2] = dt * t2;
+        Adj4 n = lamn[k];
+        n.H += t0; n.HU += t1; n.HV += t2;
+        lamn[k] = n;
+        hbar[k] += w.h;
+        d = t0 * R0[3 * k] + t1 * R0[3 * k + 1] + t2 * R0[3 * k + 2];
+    }
+    const double s = block_sum(d);
+    if (threadIdx.x == 0) part[blockIdx.x] += s;
+}
+
+__global__ __launch_bounds__(kBlock) void adj_gather_rk1_kernel(DevMesh m, TileMap tm,
+                                                                const double* __restrict__ C,
+                                                                Adj4* __restrict__ lamn,
+                                                                double* __restrict__ hbar) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    const Adj4 w = gather_cell(m, C, k);
+    Adj4 n = lamn[k];
+    n.H += w.H; n.HU += w.HU; n.HV += w.HV;
+    lamn[k] = n;
+    hbar[k] += w.h;
 }
 
 // ---------------------------------------------------------------- time step
-
-__global__ __launch_bounds__(kBlock) void adj_rmin_kernel(DevMesh m, TileMap tm,
-                                                          const Cell4* __restrict__ W, double g,
-                                                          double thr, unsigned long long* rmin) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    double r = __longlong_as_double(0x7FF0000000000000ll);
-    if (int(threadIdx.x) < ti.cnt) {
-        const Cell4 q = W[k];
-        r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
-    }
-    block_min_atomic(r, rmin);
-}
 
 __global__ void adj_sum_kernel(const double* part, int n, double* out) {
     double s = 0.0;

@@ -12,47 +12,49 @@ struct alignas(32) Adj4 {
     double H, HU, HV, h;
 };
 
-// Face states, centred source and order of every cell of W (no control).
-__global__ void adj_faces_kernel(DevMesh m, TileMap tm, const Cell4* W, FaceBuf fb, double thr,
-                                 double hg);
-// R(W) from a face buffer, R[3 * k + c].
-__global__ void adj_residual_kernel(DevMesh m, TileMap tm, FaceBuf fb, double g, double hg,
-                                    double* R);
-// Stage 1 forward on given dt: W1 = fix(W + dt R0); mask bit 0 = H kept,
-// bit 1 = momentum kept (bits of the post-stage fix).
-__global__ void adj_stage1_kernel(TileMap tm, const Cell4* W, const double* R0, double dt,
-                                  double thr, Cell4* W1, uint8_t* mask1);
-// Mask of stage 2 (the state itself is not needed by the reverse).
-__global__ void adj_mask2_kernel(TileMap tm, const Cell4* W, const Cell4* W1, const double* R1,
-                                 double dt, double thr, uint8_t* mask2);
-// mu2 = dt/2 lt2, lamn = lt2 / 2, part[tile] = sum lt2/2 . R1 with
-// lt2 = mask2 (.) lam (the adjoint of w^{n+1}).
-__global__ void adj_rk2_pre_kernel(TileMap tm, const Adj4* lam, const uint8_t* mask2,
-                                   const double* R1, double dt, double* mu, Adj4* lamn,
-                                   double* part);
+// Face states, centred source and order of every cell of W (no control);
+// with rmin != nullptr also the CFL minimum of W (bits of the positive
+// double, *rmin pre-set to +inf).
+__global__ void adj_faces_kernel(DevMesh m, TileMap tm, const Cell4* W, FaceBuf fb, double g,
+                                 double thr, double hg, unsigned long long* rmin);
+// Stage 1 recomputed: R0 = R(W) from W's face buffer (kept), W1 =
+// fix(W + dt R0) and its mask (bit 0: depth kept, bit 1: momentum kept).
+__global__ void adj_stage1_kernel(DevMesh m, TileMap tm, FaceBuf fb, const Cell4* W, double g,
+                                  double hg, double dt, double thr, double* R0, Cell4* W1,
+                                  uint8_t* mask1);
+// Stage 2 recomputed from W1's face buffer, R1 = R(W1), the mask of
+// w^{n+1} = fix(W/2 + (W1 + dt R1)/2), and the start of its reverse with lam
+// the adjoint of w^{n+1}: lt2 = mask2 (.) lam, mu = dt/2 lt2, lamn = lt2/2,
+// part[tile] = sum lt2/2 . R1.
+__global__ void adj_stage2_kernel(DevMesh m, TileMap tm, FaceBuf fb, const Cell4* W,
+                                  const Cell4* W1, double g, double hg, double dt, double thr,
+                                  const Adj4* lam, uint8_t* mask2, double* mu, Adj4* lamn,
+                                  double* part);
 // Vector-Jacobian product of R at W with weights mu (3 per cell):
-//  faces: face-state adjoints Fb[15 k + 5 j + c] (eta, h, H, u, v) of every
-//         cell face, plus the direct (H, h) adjoints of the bed source in D;
-//  recon: reverse of the reconstruction, per cell: own (H, HU, HV, h) in
-//         C[16 k + 0..3], stencil member j in C[16 k + 4 + 4 j + 0..3];
-//  gather: wb[k] = own + the stencil contributions of the face neighbours,
-//         in fixed order (no atomics).
+//  faces: the adjoint of every face state from the terms of both cells that
+//         share the face (each cell reverses its own term and its
+//         neighbour's term of the face and keeps the part for its own face
+//         state; measured faster than handing the neighbour's part over
+//         through memory) and from the bed source: Fb[(5 j + c) nc + k]
+//         (eta, h, H, u, v), the direct (H, h) adjoints of the source in D;
+//  recon: per cell, the reverse of the reconstruction: own (H, HU, HV, h)
+//         in C[16 k + 0..3], stencil member j in C[16 k + 4 + 4 j + 0..3];
+//  gather: own + the stencil contributions of the face neighbours, in fixed
+//         order (no atomics), then the Runge-Kutta reverse that follows:
+//   after J_R(w1)^T: lam1 = lt2/2 + wb, hbar += wb.h, lt1 = mask1 (.) lam1,
+//                    mu = dt lt1, lamn += lt1, part[tile] += lt1 . R0;
+//   after J_R(w)^T:  lamn += wb, hbar += wb.h.
 __global__ void adj_vjp_faces_kernel(DevMesh m, TileMap tm, FaceBuf fb, const Cell4* W,
                                      const double* mu, double g, double hg, double* Fb,
                                      double* D);
 __global__ void adj_vjp_recon_kernel(DevMesh m, TileMap tm, const Cell4* W, const double* Fb,
                                      const double* D, double thr, double* C);
-__global__ void adj_vjp_gather_kernel(DevMesh m, TileMap tm, const double* C, Adj4* wb);
-// After the stage-2 product wb2: lam1 = lt2/2 + wb2, hbar += wb2.h,
-// lt1 = mask1 (.) lam1, mu = dt lt1, lamn += lt1, part[tile] += lt1 . R0.
-__global__ void adj_rk2_post_kernel(TileMap tm, const Adj4* lam, const uint8_t* mask2,
-                                    const Adj4* wb2, const uint8_t* mask1, const double* R0,
-                                    double dt, double* mu, Adj4* lamn, double* hbar, double* part);
-// After the stage-1 product wb1: lamn += wb1, hbar += wb1.h.
-__global__ void adj_rk1_post_kernel(TileMap tm, const Adj4* wb1, Adj4* lamn, double* hbar);
-// CFL minimum of W (bits of the positive double) into *rmin (pre-set to +inf).
-__global__ void adj_rmin_kernel(DevMesh m, TileMap tm, const Cell4* W, double g, double thr,
-                                unsigned long long* rmin);
+__global__ void adj_gather_rk2_kernel(DevMesh m, TileMap tm, const double* C, const Adj4* lam,
+                                      const uint8_t* mask2, const uint8_t* mask1,
+                                      const double* R0, double dt, double* mu, Adj4* lamn,
+                                      double* hbar, double* part);
+__global__ void adj_gather_rk1_kernel(DevMesh m, TileMap tm, const double* C, Adj4* lamn,
+                                      double* hbar);
 // Sum of part[0 .. n) in fixed order into *out (one block).
 __global__ void adj_sum_kernel(const double* part, int n, double* out);
 // dt = cfl * ratio of the minimising cell(s): lamn += lamdt * cfl * d ratio / d w there.

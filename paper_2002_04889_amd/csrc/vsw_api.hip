@@ -781,19 +781,19 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     }
     *loss = L;
     // ---- reverse sweep
-    DevBuf<double> d_r, f0, f1, sc0, sc1, R0, R1, mu, Fbar, D, C, hbar, part, lamdt;
+    DevBuf<double> d_r, f0, f1, sc0, sc1, R0, mu, Fbar, D, C, hbar, part, lamdt;
     DevBuf<int32_t> o0, o1;
     DevBuf<uint8_t> m1, m2;
-    DevBuf<Adj4> lam, lamn, wb;
+    DevBuf<Adj4> lam, lamn;
     DevBuf<unsigned long long> rmin;
     DevBuf<double> gout;
     const size_t N = size_t(n);
     hipError_t e = hipSuccess;
     for (hipError_t x : {d_r.alloc(r.size()), seg.alloc(size_t(segl) * N), W1.alloc(N),
                          f0.alloc(15 * N), f1.alloc(15 * N), sc0.alloc(2 * N), sc1.alloc(2 * N),
-                         o0.alloc(N), o1.alloc(N), R0.alloc(3 * N), R1.alloc(3 * N),
+                         o0.alloc(N), o1.alloc(N), R0.alloc(3 * N),
                          m1.alloc(N), m2.alloc(N), lam.alloc(N), lamn.alloc(N), mu.alloc(3 * N),
-                         Fbar.alloc(15 * N), D.alloc(2 * N), C.alloc(16 * N), wb.alloc(N),
+                         Fbar.alloc(15 * N), D.alloc(2 * N), C.alloc(16 * N),
                          hbar.alloc(N), part.alloc(size_t(s->ntiles)), lamdt.alloc(1),
                          rmin.alloc(1), gout.alloc(4 * size_t(s->nc))})
         if (x != hipSuccess) e = x;
@@ -814,12 +814,12 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     const double zero_t = 0.0;
     HIP_TRY(hipMemcpy(s->d_t0.p, &zero_t, sizeof(double), hipMemcpyHostToDevice));
     if (s->d_log.n < 2) HIP_TRY(s->d_log.alloc(2));
+    // J_R(Wx)^T mu up to the per-cell contributions C (the gather follows)
     auto vjp = [&](const Cell4* Wx, const FaceBuf& fbx) {
         hipLaunchKernelGGL(adj_vjp_faces_kernel, grid, block, 0, st, m, tm, fbx, Wx, mu.p, g, hg,
                            Fbar.p, D.p);
         hipLaunchKernelGGL(adj_vjp_recon_kernel, grid, block, 0, st, m, tm, Wx, Fbar.p, D.p, thr,
                            C.p);
-        hipLaunchKernelGGL(adj_vjp_gather_kernel, grid, block, 0, st, m, tm, C.p, wb.p);
     };
     // the misfit of the last state
     hipLaunchKernelGGL(adj_gauge_kernel, dim3(1), dim3(64), 0, st, cells, ng,
@@ -844,26 +844,23 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
         for (int64_t k = n1 - 1; k >= n0; --k) {
             const Cell4* Wn = seg.p + (k - n0) * n;
             const double dt = dts[size_t(k)];
-            if (cfl_dt) {
+            if (cfl_dt)
                 HIP_TRY(hipMemcpyAsync(rmin.p, &inf_bits, sizeof(inf_bits), hipMemcpyHostToDevice,
                                        st));
-                hipLaunchKernelGGL(adj_rmin_kernel, grid, block, 0, st, m, tm, Wn, g, thr, rmin.p);
-            }
-            hipLaunchKernelGGL(adj_faces_kernel, grid, block, 0, st, m, tm, Wn, fb0, thr, hg);
-            hipLaunchKernelGGL(adj_residual_kernel, grid, block, 0, st, m, tm, fb0, g, hg, R0.p);
-            hipLaunchKernelGGL(adj_stage1_kernel, grid, block, 0, st, tm, Wn, R0.p, dt, thr, W1.p,
-                               m1.p);
-            hipLaunchKernelGGL(adj_faces_kernel, grid, block, 0, st, m, tm, W1.p, fb1, thr, hg);
-            hipLaunchKernelGGL(adj_residual_kernel, grid, block, 0, st, m, tm, fb1, g, hg, R1.p);
-            hipLaunchKernelGGL(adj_mask2_kernel, grid, block, 0, st, tm, Wn, W1.p, R1.p, dt, thr,
-                               m2.p);
-            hipLaunchKernelGGL(adj_rk2_pre_kernel, grid, block, 0, st, tm, lam.p, m2.p, R1.p, dt,
-                               mu.p, lamn.p, part.p);
+            hipLaunchKernelGGL(adj_faces_kernel, grid, block, 0, st, m, tm, Wn, fb0, g, thr, hg,
+                               cfl_dt ? rmin.p : nullptr);
+            hipLaunchKernelGGL(adj_stage1_kernel, grid, block, 0, st, m, tm, fb0, Wn, g, hg, dt,
+                               thr, R0.p, W1.p, m1.p);
+            hipLaunchKernelGGL(adj_faces_kernel, grid, block, 0, st, m, tm, W1.p, fb1, g, thr, hg,
+                               nullptr);
+            hipLaunchKernelGGL(adj_stage2_kernel, grid, block, 0, st, m, tm, fb1, Wn, W1.p, g, hg,
+                               dt, thr, lam.p, m2.p, mu.p, lamn.p, part.p);
             vjp(W1.p, fb1);
-            hipLaunchKernelGGL(adj_rk2_post_kernel, grid, block, 0, st, tm, lam.p, m2.p, wb.p,
+            hipLaunchKernelGGL(adj_gather_rk2_kernel, grid, block, 0, st, m, tm, C.p, lam.p, m2.p,
                                m1.p, R0.p, dt, mu.p, lamn.p, hbar.p, part.p);
             vjp(Wn, fb0);
-            hipLaunchKernelGGL(adj_rk1_post_kernel, grid, block, 0, st, tm, wb.p, lamn.p, hbar.p);
+            hipLaunchKernelGGL(adj_gather_rk1_kernel, grid, block, 0, st, m, tm, C.p, lamn.p,
+                               hbar.p);
             if (cfl_dt) {
                 hipLaunchKernelGGL(adj_sum_kernel, dim3(1), block, 0, st, part.p, s->ntiles,
                                    lamdt.p);
