@@ -13,14 +13,17 @@
 // hydrostatic reconstruction and the bed source; its adjoint accumulates
 // over all steps.
 //
-// J_R^T mu is taken in three passes, each cell-centric and free of atomics:
-//   faces   the adjoint of every face state from the face terms of both
-//           cells that share the face (the forward evaluates each face once
-//           from each side, in canonical orientation) and from the bed source;
-//   recon   the reverse of each cell's reconstruction (least-squares
-//           gradient, Barth-Jespersen limiter with its branch recomputed,
-//           eq. (3), face velocity), giving the cell's own adjoint and one
-//           contribution per stencil member;
+// The stages' residuals, fix masks and intermediate states are recorded by
+// the stage kernels while they replay a checkpoint segment (Tape).  J_R^T mu
+// is taken in two passes, each cell-centric and free of atomics:
+//   vjp     per tile, the face states reconstructed into LDS as in the
+//           forward; per cell, the adjoint of its face states from the face
+//           terms of both cells that share each face (the forward evaluates
+//           each face once from each side, in canonical orientation) and
+//           from the bed source, then the reverse of the cell's
+//           reconstruction (least-squares gradient, Barth-Jespersen limiter
+//           with its branch recomputed, eq. (3), face velocity), giving the
+//           cell's own adjoint and one contribution per stencil member;
 //   gather  each cell adds the contributions its face neighbours made to it,
 //           in a fixed order.
 // Branches (wet/dry, upwind side, limiter case, min/max) are taken as the
@@ -259,98 +262,44 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
-// Post-stage fix of a pre-fix state: bit 0 = depth kept (not clamped),
-// bit 1 = momentum kept (depth at least H_thr).
-__device__ __forceinline__ uint8_t fix_mask(double& H, double& HU, double& HV, double thr) {
-    uint8_t mk = 3;
-    if (H < 0.0) { H = 0.0; mk &= ~1; }
-    if (H < thr) { HU = 0.0; HV = 0.0; mk &= ~2; }
-    return mk;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------- forward pieces
 
-__global__ __launch_bounds__(kBlock) void adj_faces_kernel(DevMesh m, TileMap tm,
-                                                           const Cell4* __restrict__ W, FaceBuf fb,
-                                                           double g, double thr, double hg,
-                                                           unsigned long long* rmin) {
+__global__ __launch_bounds__(kBlock) void adj_rmin_kernel(DevMesh m, TileMap tm,
+                                                          const Cell4* __restrict__ W, double g,
+                                                          double thr, unsigned long long* rmin) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x, nc = m.nc;
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
     double r = __longlong_as_double(0x7FF0000000000000ll);
     if (int(threadIdx.x) < ti.cnt) {
-        Face f[3];
-        double sc[2];
-        const bool second = recon_cell(m, W, k, thr, hg, f, sc);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            fb.f[(5 * j + 0) * nc + k] = f[j].eta;
-            fb.f[(5 * j + 1) * nc + k] = f[j].h;
-            fb.f[(5 * j + 2) * nc + k] = f[j].H;
-            fb.f[(5 * j + 3) * nc + k] = f[j].u;
-            fb.f[(5 * j + 4) * nc + k] = f[j].v;
-        }
-        fb.sc[k] = sc[0];
-        fb.sc[nc + k] = sc[1];
-        fb.order[k] = second ? 2 : 1;
-        if (rmin) {
-            const Cell4 q = W[k];
-            r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
-        }
+        const Cell4 q = W[k];
+        r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
     }
-    if (rmin) block_min_atomic(r, rmin);
+    block_min_atomic(r, rmin);
 }
 
-__global__ __launch_bounds__(kBlock) void adj_stage1_kernel(DevMesh m, TileMap tm, FaceBuf fb,
-                                                            const Cell4* __restrict__ W, double g,
-                                                            double hg, double dt, double thr,
-                                                            double* __restrict__ R0,
-                                                            Cell4* __restrict__ W1,
-                                                            uint8_t* __restrict__ mask1) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    double R[3];
-    residual_from_faces(m, fb, k, g, hg, R);
-    R0[3 * k] = R[0];
-    R0[3 * k + 1] = R[1];
-    R0[3 * k + 2] = R[2];
-    const Cell4 w = W[k];
-    Cell4 o;
-    o.H = w.H + dt * R[0];
-    o.HU = w.HU + dt * R[1];
-    o.HV = w.HV + dt * R[2];
-    o.h = w.h;
-    mask1[k] = fix_mask(o.H, o.HU, o.HV, thr);
-    W1[k] = o;
-}
-
-__global__ __launch_bounds__(kBlock) void adj_stage2_kernel(
-    DevMesh m, TileMap tm, FaceBuf fb, const Cell4* __restrict__ W, const Cell4* __restrict__ W1,
-    double g, double hg, double dt, double thr, const Adj4* __restrict__ lam,
-    uint8_t* __restrict__ mask2, double* __restrict__ mu, Adj4* __restrict__ lamn,
-    double* __restrict__ part) {
+__global__ __launch_bounds__(kBlock) void adj_start_kernel(DevMesh m, TileMap tm,
+                                                           const Adj4* __restrict__ lam,
+                                                           const uint8_t* __restrict__ mask2,
+                                                           const double* __restrict__ R1,
+                                                           double dt, double* __restrict__ mua,
+                                                           Adj4* __restrict__ lamn,
+                                                           double* __restrict__ part) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
     double d = 0.0;
     if (int(threadIdx.x) < ti.cnt) {
-        double R[3];
-        residual_from_faces(m, fb, k, g, hg, R);
-        const Cell4 w = W[k], w1 = W1[k];
-        double H = 0.5 * w.H + 0.5 * (w1.H + dt * R[0]);
-        double HU = 0.5 * w.HU + 0.5 * (w1.HU + dt * R[1]);
-        double HV = 0.5 * w.HV + 0.5 * (w1.HV + dt * R[2]);
-        const uint8_t mk = fix_mask(H, HU, HV, thr);
-        mask2[k] = mk;
+        const uint8_t mk = mask2[k];
         const Adj4 l = lam[k];
         const double l0 = (mk & 1) ? l.H : 0.0, l1 = (mk & 2) ? l.HU : 0.0,
                      l2 = (mk & 2) ? l.HV : 0.0;
-        mu[3 * k] = 0.5 * dt * l0;
-        mu[3 * k + 1] = 0.5 * dt * l1;
-        mu[3 * k + 2] = 0.5 * dt * l2;
+        const double ra = 1.0 / m.area[k];
+        mua[3 * k] = (0.5 * dt * l0) * ra;
+        mua[3 * k + 1] = (0.5 * dt * l1) * ra;
+        mua[3 * k + 2] = (0.5 * dt * l2) * ra;
         lamn[k] = Adj4{0.5 * l0, 0.5 * l1, 0.5 * l2, 0.0};
-        d = 0.5 * (l0 * R[0] + l1 * R[1] + l2 * R[2]);
+        d = 0.5 * (l0 * R1[3 * k] + l1 * R1[3 * k + 1] + l2 * R1[3 * k + 2]);
     }
     const double s = block_sum(d);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -358,27 +307,47 @@ __global__ __launch_bounds__(kBlock) void adj_stage2_kernel(
 
 // ---------------------------------------------------------------- J_R^T mu
 
-__global__ __launch_bounds__(kBlock) void adj_vjp_faces_kernel(DevMesh m, TileMap tm, FaceBuf fb,
-                                                               const Cell4* __restrict__ W,
-                                                               const double* __restrict__ mu,
-                                                               double g, double hg,
-                                                               double* __restrict__ Fb,
-                                                               double* __restrict__ D) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x, nc = m.nc;
-    const double ar = m.area[k];
-    const double ab[3] = {mu[3 * k] / ar, mu[3 * k + 1] / ar, mu[3 * k + 2] / ar};
+// One workgroup per tile.  Phase 1 is the stage kernel's: the face states of
+// the tile's cells and of its halo faces, reconstructed into LDS.  Phase 2,
+// per cell k (no exchange between threads):
+//  a. the adjoint of each of k's three face states from the two terms of
+//     the face, k's own (weight mua_k) and its neighbour's (weight mua_n),
+//     plus the bed source of a second-order cell;
+//  b. the reverse of k's reconstruction, its branches recomputed: the
+//     adjoint of k's own variables and one contribution per stencil member,
+//     written to C.
+__global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
+                                                         const Cell4* __restrict__ W,
+                                                         const double* __restrict__ mua,
+                                                         double g, double hg, double thr,
+                                                         double* __restrict__ C) {
+    extern __shared__ double lds[];
+    const int stride = 3 * kTile + tm.bmax;
+    const int t = int(blockIdx.x);
+    const TileInfo ti = tile_info(tm.tinfo[t]);
+    const int64_t nc = m.nc, c0 = int64_t(t) * kTile;
+    const int i = threadIdx.x;
+    const int64_t k = c0 + i;
+    double sc[2], ownH[3];
+    bool second;
+    tile_faces(m, tm, W, t, c0, ti.cnt, thr, hg, lds, stride, ownH, sc, second);
+    __syncthreads();
+    if (i >= ti.cnt) return;
+
+    // ---- a. face-state adjoints
+    const double ab[3] = {mua[3 * k], mua[3 * k + 1], mua[3 * k + 2]};
     const Nbr4 nb = m.nbr[k];
     const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
     Face F[3];
+    double fhs[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         F[j] = Face{0.0, 0.0, 0.0, 0.0, 0.0};
         const uint32_t s = sl[j];
         const bool wall = (s == kWallSlot);
         const bool own_left = wall || (s & 4u);
-        const Face own = load_face(fb, nc, j, k);
+        const Face own = lds_load_face(lds, stride, j * kTile + i, ownH[j]);
+        fhs[j] = own.h;
         const double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k), l = gf(m, 2, j, k);
         // this cell's term enters its accumulator with - (left) or + (right)
         const double sg = own_left ? -1.0 : 1.0;
@@ -390,60 +359,38 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_faces_kernel(DevMesh m, TileMa
         } else {
             const int64_t n = int64_t(s >> 3);
             const int jn = int(s & 3u);
-            const Face other = load_face(fb, nc, jn, n);
+            // the neighbour's face depth enters only the neighbour's own
+            // pressure correction, whose adjoint is not needed here
+            const Face other = lds_load_face(
+                lds, stride, int(tm.nloc[j * nc + k] & 0x7FFFu), 0.0);
             face_term_rev(g, hg, own, other, false, own_left, nx, ny, l, tb, F[j], xb);
             // the neighbour's term of the same face, with this face as its other side
-            const double arn = m.area[n];
             const double sn = own_left ? 1.0 : -1.0;
-            const double tbn[3] = {sn * (mu[3 * n] / arn), sn * (mu[3 * n + 1] / arn),
-                                   sn * (mu[3 * n + 2] / arn)};
+            const double tbn[3] = {sn * mua[3 * n], sn * mua[3 * n + 1], sn * mua[3 * n + 2]};
             Face ob{0.0, 0.0, 0.0, 0.0, 0.0};
             face_term_rev(g, hg, other, own, false, !own_left, gf(m, 0, jn, n), gf(m, 1, jn, n),
                           gf(m, 2, jn, n), tbn, ob, F[j]);
         }
     }
+    const Cell4 ck = W[k];
     double DH = 0.0, Dh = 0.0;
-    if (fb.order[k] == 2) {
+    if (second) {
         // bed source (g/2) sum_j l_j (H_K + H_Kj)(h_Kj - h_K) n_j added to the momentum rows
-        const Cell4 q = W[k];
         const double sxb = hg * ab[1], syb = hg * ab[2];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k), l = gf(m, 2, j, k);
-            const double fH = fb.f[(5 * j + 2) * nc + k], fh = fb.f[(5 * j + 1) * nc + k];
             const double cb = sxb * nx + syb * ny;
-            const double dHj = cb * (l * (fh - q.h)), dhj = cb * (l * (q.H + fH));
+            const double dHj = cb * (l * (fhs[j] - ck.h)), dhj = cb * (l * (ck.H + ownH[j]));
             F[j].H += dHj;
             F[j].h += dhj;
             DH += dHj;
             Dh -= dhj;
         }
     }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        Fb[(5 * j + 0) * nc + k] = F[j].eta;
-        Fb[(5 * j + 1) * nc + k] = F[j].h;
-        Fb[(5 * j + 2) * nc + k] = F[j].H;
-        Fb[(5 * j + 3) * nc + k] = F[j].u;
-        Fb[(5 * j + 4) * nc + k] = F[j].v;
-    }
-    D[2 * k] = DH;
-    D[2 * k + 1] = Dh;
-}
 
-__global__ __launch_bounds__(kBlock) void adj_vjp_recon_kernel(DevMesh m, TileMap tm,
-                                                               const Cell4* __restrict__ W,
-                                                               const double* __restrict__ Fb,
-                                                               const double* __restrict__ D,
-                                                               double thr, double* __restrict__ C) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x, nc = m.nc;
-    // ---- forward recomputation (the arithmetic of recon_core)
-    const Cell4 ck = W[k];
+    // ---- b. reverse of the reconstruction (forward recomputed as in recon_core)
     const double Hk = ck.H, hk = ck.h, ek = Hk - hk, uk = ck.HU, vk = ck.HV;
-    const Nbr4 nb = m.nbr[k];
-    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
     double qe[3], qu[3], qv[3], qh[3];
     bool cand = (Hk >= thr);
 #pragma unroll
@@ -465,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_recon_kernel(DevMesh m, TileMa
             qh[j] = hk;
         }
     }
-    double pe[3], pu[3], pv[3], ph[3], fe[3], fu[3], fv[3], fh[3], fH[3];
+    double pe[3], pu[3], pv[3], ph[3], fe[3], fu[3], fv[3], fH[3];
     double ae = 1.0, au = 1.0, av = 1.0;
     LimInfo le{0, -1, 0, 1.0}, lu{0, -1, 0, 1.0}, lv{0, -1, 0, 1.0};
     const RGeom rg = m.rgeom[k];
@@ -491,39 +438,34 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_recon_kernel(DevMesh m, TileMa
             fe[j] = ek + ae * pe[j];
             fu[j] = uk + au * pu[j];
             fv[j] = vk + av * pv[j];
-            fh[j] = hk + ph[j];
-            fH[j] = fe[j] + fh[j];
+            fH[j] = fe[j] + (hk + ph[j]);
             if (fH[j] < thr) cand = false;
         }
     }
     if (!cand) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            fe[j] = ek; fu[j] = uk; fv[j] = vk; fh[j] = hk; fH[j] = Hk;
+            fe[j] = ek; fu[j] = uk; fv[j] = vk; fH[j] = Hk;
         }
     }
-    // ---- reverse
     double feb[3], fub[3], fvb[3], fhb[3], fHb[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        double a[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) a[c] = Fb[(5 * j + c) * nc + k];
-        feb[j] = a[0];
-        fhb[j] = a[1];
-        fHb[j] = a[2];
+        feb[j] = F[j].eta;
+        fhb[j] = F[j].h;
+        fHb[j] = F[j].H;
         fub[j] = 0.0;
         fvb[j] = 0.0;
         if (fH[j] >= thr) {
             // u = fu * rH, v = fv * rH, rH = 1 / fH
-            const double ub = a[3], vb = a[4];
+            const double ub = F[j].u, vb = F[j].v;
             const double rH = 1.0 / fH[j];
             fub[j] = ub * rH;
             fvb[j] = vb * rH;
             fHb[j] -= (ub * fu[j] + vb * fv[j]) * rH * rH;
         }
     }
-    double Hkb = D[2 * k], hkb = D[2 * k + 1], ekb = 0.0, ukb = 0.0, vkb = 0.0;
+    double Hkb = DH, hkb = Dh, ekb = 0.0, ukb = 0.0, vkb = 0.0;
     double qeb[3] = {0.0, 0.0, 0.0}, qub[3] = {0.0, 0.0, 0.0}, qvb[3] = {0.0, 0.0, 0.0},
            qhb[3] = {0.0, 0.0, 0.0};
     if (!cand) {
@@ -555,9 +497,9 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_recon_kernel(DevMesh m, TileMa
             const double gxb = pjb[0] * dxs[0] + pjb[1] * dxs[1] + pjb[2] * dxs[2];
             const double gyb = pjb[0] * dys[0] + pjb[1] * dys[1] + pjb[2] * dys[2];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const double db = wx[i] * gxb + wy[i] * gyb;
-                qsb[i] += db;
+            for (int q = 0; q < 3; ++q) {
+                const double db = wx[q] * gxb + wy[q] * gyb;
+                qsb[q] += db;
                 q0b -= db;
             }
         };
@@ -620,7 +562,7 @@ __device__ __forceinline__ Adj4 gather_cell(const DevMesh& m, const double* __re
 __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
     DevMesh m, TileMap tm, const double* __restrict__ C, const Adj4* __restrict__ lam,
     const uint8_t* __restrict__ mask2, const uint8_t* __restrict__ mask1,
-    const double* __restrict__ R0, double dt, double* __restrict__ mu, Adj4* __restrict__ lamn,
+    const double* __restrict__ R0, double dt, double* __restrict__ mua, Adj4* __restrict__ lamn,
     double* __restrict__ hbar, double* __restrict__ part) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
@@ -633,9 +575,10 @@ __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
         const double a1 = ((m2 & 2) ? 0.5 * l.HU : 0.0) + w.HU;
         const double a2 = ((m2 & 2) ? 0.5 * l.HV : 0.0) + w.HV;
         const double t0 = (m1 & 1) ? a0 : 0.0, t1 = (m1 & 2) ? a1 : 0.0, t2 = (m1 & 2) ? a2 : 0.0;
-        mu[3 * k] = dt * t0;
-        mu[3 * k + 1] = dt * t1;
-        mu[3 * k + 2] = dt * t2;
+        const double ra = 1.0 / m.area[k];
+        mua[3 * k] = (dt * t0) * ra;
+        mua[3 * k + 1] = (dt * t1) * ra;
+        mua[3 * k + 2] = (dt * t2) * ra;
         Adj4 n = lamn[k];
         n.H += t0; n.HU += t1; n.HV += t2;
         lamn[k] = n;

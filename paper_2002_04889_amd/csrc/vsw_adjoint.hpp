@@ -1,7 +1,8 @@
 // Kernels of the discrete adjoint of one SSP-RK(2,2) step (FP64): the
-// forward pieces the reverse sweep recomputes, the vector-Jacobian product
-// of the residual R(w; h) and the reverse of the Runge-Kutta stages, the
-// post-stage fix and the CFL time step.
+// vector-Jacobian product of the residual R(w; h) and the reverse of the
+// Runge-Kutta stages, the post-stage fix and the CFL time step.  The
+// stages' residuals, fix masks and states come from the tape the stage
+// kernels record while replaying a checkpoint segment (see Tape).
 #pragma once
 #include "vsw_kernels.hpp"
 
@@ -12,46 +13,33 @@ struct alignas(32) Adj4 {
     double H, HU, HV, h;
 };
 
-// Face states, centred source and order of every cell of W (no control);
-// with rmin != nullptr also the CFL minimum of W (bits of the positive
-// double, *rmin pre-set to +inf).
-__global__ void adj_faces_kernel(DevMesh m, TileMap tm, const Cell4* W, FaceBuf fb, double g,
-                                 double thr, double hg, unsigned long long* rmin);
-// Stage 1 recomputed: R0 = R(W) from W's face buffer (kept), W1 =
-// fix(W + dt R0) and its mask (bit 0: depth kept, bit 1: momentum kept).
-__global__ void adj_stage1_kernel(DevMesh m, TileMap tm, FaceBuf fb, const Cell4* W, double g,
-                                  double hg, double dt, double thr, double* R0, Cell4* W1,
-                                  uint8_t* mask1);
-// Stage 2 recomputed from W1's face buffer, R1 = R(W1), the mask of
-// w^{n+1} = fix(W/2 + (W1 + dt R1)/2), and the start of its reverse with lam
-// the adjoint of w^{n+1}: lt2 = mask2 (.) lam, mu = dt/2 lt2, lamn = lt2/2,
+// Bits of the CFL minimum of W into *rmin (pre-set to +inf).
+__global__ void adj_rmin_kernel(DevMesh m, TileMap tm, const Cell4* W, double g, double thr,
+                                unsigned long long* rmin);
+// Start of the reverse of a step from its tape (R1 = R(w1), mask2 of
+// w^{n+1} = fix(w/2 + (w1 + dt R1)/2)) with lam the adjoint of w^{n+1}:
+// lt2 = mask2 (.) lam, mua = dt/2 lt2 / |K|, lamn = lt2/2,
 // part[tile] = sum lt2/2 . R1.
-__global__ void adj_stage2_kernel(DevMesh m, TileMap tm, FaceBuf fb, const Cell4* W,
-                                  const Cell4* W1, double g, double hg, double dt, double thr,
-                                  const Adj4* lam, uint8_t* mask2, double* mu, Adj4* lamn,
-                                  double* part);
-// Vector-Jacobian product of R at W with weights mu (3 per cell):
-//  faces: the adjoint of every face state from the terms of both cells that
-//         share the face (each cell reverses its own term and its
-//         neighbour's term of the face and keeps the part for its own face
-//         state; measured faster than handing the neighbour's part over
-//         through memory) and from the bed source: Fb[(5 j + c) nc + k]
-//         (eta, h, H, u, v), the direct (H, h) adjoints of the source in D;
-//  recon: per cell, the reverse of the reconstruction: own (H, HU, HV, h)
-//         in C[16 k + 0..3], stencil member j in C[16 k + 4 + 4 j + 0..3];
-//  gather: own + the stencil contributions of the face neighbours, in fixed
-//         order (no atomics), then the Runge-Kutta reverse that follows:
+__global__ void adj_start_kernel(DevMesh m, TileMap tm, const Adj4* lam, const uint8_t* mask2,
+                                 const double* R1, double dt, double* mua, Adj4* lamn,
+                                 double* part);
+// Vector-Jacobian product of R at W with weights mua = mu / |K| (3 per
+// cell), one workgroup per tile (dynamic LDS: stage_lds_bytes(bmax)), up to
+// the per-cell contributions: own (H, HU, HV, h) in C[16 k + 0..3], stencil
+// member j in C[16 k + 4 + 4 j + 0..3].  Each cell reverses its own term and
+// its neighbour's term of each face (the forward evaluates a face from both
+// sides) and keeps the part for its own face state, so no adjoint is handed
+// between cells before the gather.
+__global__ void adj_vjp_kernel(DevMesh m, TileMap tm, const Cell4* W, const double* mua,
+                               double g, double hg, double thr, double* C);
+// Gather: own + the stencil contributions of the face neighbours, in fixed
+// order (no atomics), then the Runge-Kutta reverse that follows:
 //   after J_R(w1)^T: lam1 = lt2/2 + wb, hbar += wb.h, lt1 = mask1 (.) lam1,
-//                    mu = dt lt1, lamn += lt1, part[tile] += lt1 . R0;
+//                    mua = dt lt1 / |K|, lamn += lt1, part[tile] += lt1 . R0;
 //   after J_R(w)^T:  lamn += wb, hbar += wb.h.
-__global__ void adj_vjp_faces_kernel(DevMesh m, TileMap tm, FaceBuf fb, const Cell4* W,
-                                     const double* mu, double g, double hg, double* Fb,
-                                     double* D);
-__global__ void adj_vjp_recon_kernel(DevMesh m, TileMap tm, const Cell4* W, const double* Fb,
-                                     const double* D, double thr, double* C);
 __global__ void adj_gather_rk2_kernel(DevMesh m, TileMap tm, const double* C, const Adj4* lam,
                                       const uint8_t* mask2, const uint8_t* mask1,
-                                      const double* R0, double dt, double* mu, Adj4* lamn,
+                                      const double* R0, double dt, double* mua, Adj4* lamn,
                                       double* hbar, double* part);
 __global__ void adj_gather_rk1_kernel(DevMesh m, TileMap tm, const double* C, Adj4* lamn,
                                       double* hbar);

@@ -720,7 +720,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     const std::vector<double> seg_t_save = s->seg_t, seg_dt_save = s->seg_dt;
     const std::vector<int64_t> seg_steps_save = s->seg_steps;
     const std::vector<double> seg_log_save = s->seg_log, last_dts_save = s->last_dts;
-    DevBuf<Cell4> W0, ck, seg, W1;
+    DevBuf<Cell4> W0, ck, seg;
     HIP_TRY(W0.alloc(size_t(n)));
     HIP_TRY(hipMemcpyAsync(W0.p, s->d_w.p, size_t(n) * sizeof(Cell4), hipMemcpyDeviceToDevice,
                            st));
@@ -781,21 +781,23 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     }
     *loss = L;
     // ---- reverse sweep
-    DevBuf<double> d_r, f0, f1, sc0, sc1, R0, mu, Fbar, D, C, hbar, part, lamdt;
-    DevBuf<int32_t> o0, o1;
-    DevBuf<uint8_t> m1, m2;
+    // Per segment of L steps the stage kernels replay the steps from the
+    // checkpoint with the forward's dts (bitwise the forward's states) and
+    // record the tape: the states w and w1 of every step, both stages' residuals and
+    // fix masks, and the CFL minimum of each state.
+    const size_t N = size_t(n), SL = size_t(segl);
+    DevBuf<Cell4> segW1, wend;
+    DevBuf<double> d_r, tR0, tR1, mua, C, hbar, part, lamdt, gout;
+    DevBuf<uint8_t> tm1, tm2;
     DevBuf<Adj4> lam, lamn;
-    DevBuf<unsigned long long> rmin;
-    DevBuf<double> gout;
-    const size_t N = size_t(n);
+    DevBuf<unsigned long long> rmin_hist;
     hipError_t e = hipSuccess;
-    for (hipError_t x : {d_r.alloc(r.size()), seg.alloc(size_t(segl) * N), W1.alloc(N),
-                         f0.alloc(15 * N), f1.alloc(15 * N), sc0.alloc(2 * N), sc1.alloc(2 * N),
-                         o0.alloc(N), o1.alloc(N), R0.alloc(3 * N),
-                         m1.alloc(N), m2.alloc(N), lam.alloc(N), lamn.alloc(N), mu.alloc(3 * N),
-                         Fbar.alloc(15 * N), D.alloc(2 * N), C.alloc(16 * N),
+    for (hipError_t x : {d_r.alloc(r.size()), seg.alloc(SL * N), segW1.alloc(SL * N),
+                         wend.alloc(N), tR0.alloc(3 * SL * N), tR1.alloc(3 * SL * N),
+                         tm1.alloc(SL * N), tm2.alloc(SL * N), rmin_hist.alloc(SL + 1),
+                         lam.alloc(N), lamn.alloc(N), mua.alloc(3 * N), C.alloc(16 * N),
                          hbar.alloc(N), part.alloc(size_t(s->ntiles)), lamdt.alloc(1),
-                         rmin.alloc(1), gout.alloc(4 * size_t(s->nc))})
+                         gout.alloc(4 * size_t(s->nc))})
         if (x != hipSuccess) e = x;
     if (e != hipSuccess) {
         restore();
@@ -808,64 +810,64 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, 1,
                s->xcd_order};
     const dim3 grid(unsigned(s->ntiles)), block(kBlock);
-    const FaceBuf fb0{f0.p, sc0.p, o0.p}, fb1{f1.p, sc1.p, o1.p};
     int64_t* cells = s->d_gauge_cells.p;
     const size_t lds = stage_lds_bytes(s->bmax);
     const double zero_t = 0.0;
     HIP_TRY(hipMemcpy(s->d_t0.p, &zero_t, sizeof(double), hipMemcpyHostToDevice));
     if (s->d_log.n < 2) HIP_TRY(s->d_log.alloc(2));
-    // J_R(Wx)^T mu up to the per-cell contributions C (the gather follows)
-    auto vjp = [&](const Cell4* Wx, const FaceBuf& fbx) {
-        hipLaunchKernelGGL(adj_vjp_faces_kernel, grid, block, 0, st, m, tm, fbx, Wx, mu.p, g, hg,
-                           Fbar.p, D.p);
-        hipLaunchKernelGGL(adj_vjp_recon_kernel, grid, block, 0, st, m, tm, Wx, Fbar.p, D.p, thr,
-                           C.p);
-    };
+    const std::vector<unsigned long long> inf_bits(SL + 1, 0x7FF0000000000000ull);
     // the misfit of the last state
     hipLaunchKernelGGL(adj_gauge_kernel, dim3(1), dim3(64), 0, st, cells, ng,
                        d_r.p + (nsteps - 1) * ng, lam.p, hbar.p);
-    const unsigned long long inf_bits = 0x7FF0000000000000ull;
     for (int64_t c = nck - 1; c >= 0; --c) {
         const int64_t n0 = c * ckpt, n1 = std::min(nsteps, n0 + ckpt);
-        // states n0 .. n1-1 of the segment, recomputed with the forward's dts
+        const int64_t len = n1 - n0;
         HIP_TRY(hipMemcpyAsync(seg.p, ck.p + c * n, N * sizeof(Cell4), hipMemcpyDeviceToDevice,
                                st));
-        for (int64_t i = 1; i < n1 - n0; ++i) {
+        if (cfl_dt) {
+            HIP_TRY(hipMemcpyAsync(rmin_hist.p, inf_bits.data(), (SL + 1) * sizeof(inf_bits[0]),
+                                   hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(adj_rmin_kernel, grid, block, 0, st, m, tm, seg.p, g, thr,
+                               rmin_hist.p);
+        }
+        hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(256), 0, st, s->d_ctrl.p, s->d_seg.p,
+                           1, s->d_t0.p);
+        for (int64_t i = 0; i < len; ++i) {
             Cell4* Wi = seg.p + i * n;
-            HIP_TRY(hipMemcpyAsync(Wi, Wi - n, N * sizeof(Cell4), hipMemcpyDeviceToDevice, st));
-            StepParams p{g, hg, thr, cfl, dts[size_t(n0 + i - 1)], INFINITY};
-            hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(256), 0, st, s->d_ctrl.p,
-                               s->d_seg.p, 1, s->d_t0.p);
-            hipLaunchKernelGGL(stage_kernel<1>, grid, block, lds, st, m, tm, Wi, W1.p, p,
-                               s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p);
-            hipLaunchKernelGGL(stage_kernel<2>, grid, block, lds, st, m, tm, Wi, W1.p, p,
-                               s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p);
+            Cell4* W1i = segW1.p + i * n;
+            const StepParams p{g, hg, thr, cfl, dts[size_t(n0 + i)], INFINITY};
+            const Tape t1{tR0.p + 3 * i * n, tm1.p + i * n, nullptr, nullptr};
+            const Tape t2{tR1.p + 3 * i * n, tm2.p + i * n, (i + 1 < len) ? Wi + n : wend.p,
+                          rmin_hist.p + i + 1};
+            hipLaunchKernelGGL(stage_tape_kernel<1>, grid, block, lds, st, m, tm, Wi, W1i, p,
+                               s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t1);
+            hipLaunchKernelGGL(stage_tape_kernel<2>, grid, block, lds, st, m, tm, Wi, W1i, p,
+                               s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
         }
         for (int64_t k = n1 - 1; k >= n0; --k) {
-            const Cell4* Wn = seg.p + (k - n0) * n;
+            const int64_t i = k - n0;
+            const Cell4* Wn = seg.p + i * n;
+            const Cell4* W1 = segW1.p + i * n;
+            const double* R0 = tR0.p + 3 * i * n;
+            const double* R1 = tR1.p + 3 * i * n;
+            const uint8_t* m1 = tm1.p + i * n;
+            const uint8_t* m2 = tm2.p + i * n;
             const double dt = dts[size_t(k)];
-            if (cfl_dt)
-                HIP_TRY(hipMemcpyAsync(rmin.p, &inf_bits, sizeof(inf_bits), hipMemcpyHostToDevice,
-                                       st));
-            hipLaunchKernelGGL(adj_faces_kernel, grid, block, 0, st, m, tm, Wn, fb0, g, thr, hg,
-                               cfl_dt ? rmin.p : nullptr);
-            hipLaunchKernelGGL(adj_stage1_kernel, grid, block, 0, st, m, tm, fb0, Wn, g, hg, dt,
-                               thr, R0.p, W1.p, m1.p);
-            hipLaunchKernelGGL(adj_faces_kernel, grid, block, 0, st, m, tm, W1.p, fb1, g, thr, hg,
-                               nullptr);
-            hipLaunchKernelGGL(adj_stage2_kernel, grid, block, 0, st, m, tm, fb1, Wn, W1.p, g, hg,
-                               dt, thr, lam.p, m2.p, mu.p, lamn.p, part.p);
-            vjp(W1.p, fb1);
-            hipLaunchKernelGGL(adj_gather_rk2_kernel, grid, block, 0, st, m, tm, C.p, lam.p, m2.p,
-                               m1.p, R0.p, dt, mu.p, lamn.p, hbar.p, part.p);
-            vjp(Wn, fb0);
+            hipLaunchKernelGGL(adj_start_kernel, grid, block, 0, st, m, tm, lam.p, m2, R1, dt,
+                               mua.p, lamn.p, part.p);
+            hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, W1, mua.p, g, hg, thr,
+                               C.p);
+            hipLaunchKernelGGL(adj_gather_rk2_kernel, grid, block, 0, st, m, tm, C.p, lam.p, m2,
+                               m1, R0, dt, mua.p, lamn.p, hbar.p, part.p);
+            hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, Wn, mua.p, g, hg, thr,
+                               C.p);
             hipLaunchKernelGGL(adj_gather_rk1_kernel, grid, block, 0, st, m, tm, C.p, lamn.p,
                                hbar.p);
             if (cfl_dt) {
                 hipLaunchKernelGGL(adj_sum_kernel, dim3(1), block, 0, st, part.p, s->ntiles,
                                    lamdt.p);
                 hipLaunchKernelGGL(adj_dt_kernel, grid, block, 0, st, m, tm, Wn, g, thr, cfl,
-                                   rmin.p, lamdt.p, lamn.p);
+                                   rmin_hist.p + i, lamdt.p, lamn.p);
             }
             std::swap(lam.p, lamn.p);
             if (k >= 1)

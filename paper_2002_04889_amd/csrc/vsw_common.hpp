@@ -172,6 +172,69 @@ __device__ __forceinline__ void residual_from_faces(const DevMesh& m, const Face
     R[2] = a2 * ra;
 }
 
+// A face state in LDS: eta, h, u, v at slot + c * stride.  The face depth H
+// is read only by the cell that owns the face (its pressure correction),
+// which keeps it in registers.
+__device__ __forceinline__ void lds_store_face(double* lds, int stride, int slot, const Face& f) {
+    lds[0 * stride + slot] = f.eta;
+    lds[1 * stride + slot] = f.h;
+    lds[2 * stride + slot] = f.u;
+    lds[3 * stride + slot] = f.v;
+}
+
+__device__ __forceinline__ Face lds_load_face(const double* lds, int stride, int slot, double H) {
+    Face f;
+    f.eta = lds[0 * stride + slot];
+    f.h = lds[1 * stride + slot];
+    f.H = H;
+    f.u = lds[2 * stride + slot];
+    f.v = lds[3 * stride + slot];
+    return f;
+}
+
+// First phase of the tile kernels (one workgroup per tile t of cnt cells
+// starting at cell c0, one thread per cell): reconstruct the tile's cells
+// (Section 2.4) and store their three face states in LDS slots j kTile + i;
+// reconstruct the halo cells across the tile boundary and store the face
+// each shares with the tile in slots 3 kTile + b.  Thread i keeps its own
+// face depths, the centred bed source and the order.  The caller
+// synchronises the workgroup before reading the LDS.
+__device__ __forceinline__ void tile_faces(const DevMesh& m, const TileMap& tm,
+                                           const Cell4* __restrict__ Ws, int t, int64_t c0,
+                                           int cnt, double thr, double hg, double* lds,
+                                           int stride, double ownH[3], double sc[2],
+                                           bool& second) {
+    const int i = threadIdx.x;
+    const int64_t k = c0 + i;
+    sc[0] = 0.0;
+    sc[1] = 0.0;
+    ownH[0] = ownH[1] = ownH[2] = 0.0;
+    second = false;
+    if (i < cnt) {
+        Recon r;
+        recon_core(m, Ws, k, thr, r);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const Face f = recon_face(r, j, thr);
+            lds_store_face(lds, stride, j * kTile + i, f);
+            ownH[j] = f.H;
+        }
+        centred_source(m, r, k, hg, sc);
+        second = r.second;
+    }
+    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
+    for (int b = i; b < nb; b += kBlock) {
+        const uint32_t item = tm.bitem[b0 + b];
+        const int64_t n = int64_t(item >> 2);
+        const int jn = int(item & 3u);
+        Recon r;
+        recon_core(m, Ws, n, thr, r);
+        const Face f = (jn == 0) ? recon_face(r, 0, thr)
+                     : (jn == 1) ? recon_face(r, 1, thr) : recon_face(r, 2, thr);
+        lds_store_face(lds, stride, 3 * kTile + b, f);
+    }
+}
+
 // Tiles are consecutive Hilbert ranges, so tiles t and t+1 are neighbours in
 // space.  Workgroups are dealt round-robin to the eight XCDs, each with its
 // own L2; give XCD x one contiguous run of tiles so that the halo cells

@@ -88,28 +88,34 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(DevMesh m, TileMap tm,
 
 // Stage 1: w1 = w + dt R(w), then the post-stage fix (negative depth set to
 // zero and counted; velocity zero below H_thr).
+// mk: bit 0 cleared when the depth is clamped, bit 1 when the momentum is
+// zeroed (what the adjoint of the fix needs).
 __device__ __forceinline__ Cell4 stage1_update(const Cell4& w, const double R[3], double dt,
-                                               double thr, unsigned long long& clamp) {
+                                               double thr, unsigned long long& clamp,
+                                               uint8_t& mk) {
     Cell4 o;
     o.H = w.H + dt * R[0];
     o.HU = w.HU + dt * R[1];
     o.HV = w.HV + dt * R[2];
     o.h = w.h;
-    if (o.H < 0.0) { o.H = 0.0; clamp = 1; }
-    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; }
+    mk = 3;
+    if (o.H < 0.0) { o.H = 0.0; clamp = 1; mk &= uint8_t(~1u); }
+    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; mk &= uint8_t(~2u); }
     return o;
 }
 
 // Stage 2: w^{n+1} = w/2 + (w1 + dt R(w1))/2, then the post-stage fix.
 __device__ __forceinline__ Cell4 stage2_update(const Cell4& w, const Cell4& w1, const double R[3],
-                                               double dt, double thr, unsigned long long& clamp) {
+                                               double dt, double thr, unsigned long long& clamp,
+                                               uint8_t& mk) {
     Cell4 o;
     o.H = 0.5 * w.H + 0.5 * (w1.H + dt * R[0]);
     o.HU = 0.5 * w.HU + 0.5 * (w1.HU + dt * R[1]);
     o.HV = 0.5 * w.HV + 0.5 * (w1.HV + dt * R[2]);
     o.h = w.h;
-    if (o.H < 0.0) { o.H = 0.0; clamp = 1; }
-    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; }
+    mk = 3;
+    if (o.H < 0.0) { o.H = 0.0; clamp = 1; mk &= uint8_t(~1u); }
+    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; mk &= uint8_t(~2u); }
     return o;
 }
 
@@ -126,7 +132,8 @@ __global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, TileMap tm,
     if (int(threadIdx.x) < ti.cnt) {
         double R[3];
         residual_from_faces(m, fb, k, p.g, p.hg, R);
-        W1[k] = stage1_update(W[k], R, dt, p.thr, clamp);
+        uint8_t mk;
+        W1[k] = stage1_update(W[k], R, dt, p.thr, clamp, mk);
     }
     block_count_atomic(clamp, &c->clamps);
 }
@@ -152,7 +159,8 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, TileMap tm,
     if (int(threadIdx.x) < ti.cnt) {
         double R[3];
         residual_from_faces(m, fb, k, p.g, p.hg, R);
-        const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp);
+        uint8_t mk;
+        const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp, mk);
         W[k] = o;
         bad = !isfinite(o.H) || !isfinite(o.HU) || !isfinite(o.HV);
         r = cfl_ratio(o.H, o.HU, o.HV, m.area[k], m.perim[k], p.g, p.thr);
@@ -168,43 +176,20 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, TileMap tm,
 
 // ---------------------------------------------------------------- fused stage
 
-namespace {
-
-__device__ __forceinline__ void lds_store_face(double* lds, int stride, int slot, const Face& f) {
-    lds[0 * stride + slot] = f.eta;
-    lds[1 * stride + slot] = f.h;
-    lds[2 * stride + slot] = f.H;
-    lds[3 * stride + slot] = f.u;
-    lds[4 * stride + slot] = f.v;
-}
-
-__device__ __forceinline__ Face lds_load_face(const double* lds, int stride, int slot) {
-    Face f;
-    f.eta = lds[0 * stride + slot];
-    f.h = lds[1 * stride + slot];
-    f.H = lds[2 * stride + slot];
-    f.u = lds[3 * stride + slot];
-    f.v = lds[4 * stride + slot];
-    return f;
-}
-
-}  // namespace
-
 // One workgroup per tile of kTile cells, one thread per cell:
-//  1. reconstruct the tile's cells (Section 2.4) and store their three face
-//     states in LDS; reconstruct the halo cells across the tile boundary and
-//     store the face each shares with the tile;
+//  1. reconstruct the tile's cells and its halo faces into LDS (tile_faces);
 //  2. per cell, the three face fluxes in canonical orientation from LDS (one
 //     branch-free evaluation per face), the centred bed source, the residual
 //     and the Runge-Kutta stage.
 // Each face inside a tile is evaluated by both of its cells; a face list
 // evaluated once per face (edge-parallel, with two more barriers to hand the
-// terms over) measured slower on the 1M-cell basin.
-template <int STAGE>
-__global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Cell4* __restrict__ W,
-                                                       Cell4* __restrict__ W1, StepParams p,
-                                                       Ctrl* c, Seg* sg, int slot, int step_arg,
-                                                       double* log) {
+// terms over) measured slower on the 1M-cell basin.  TAPE adds the outputs
+// the adjoint records (see Tape) and leaves the arithmetic as it is.
+template <int STAGE, bool TAPE>
+__device__ __forceinline__ void stage_body(const DevMesh& m, const TileMap& tm,
+                                           Cell4* __restrict__ W, Cell4* __restrict__ W1,
+                                           const StepParams& p, Ctrl* c, Seg* sg, int slot,
+                                           int step_arg, double* log, const Tape& tp) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
     const int t = tm.xcd_order ? xcd_tile(int(blockIdx.x), tm.ntiles) : int(blockIdx.x);
@@ -227,27 +212,9 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
     const int i = threadIdx.x;
     const int64_t k = c0 + i;
 
-    double sc[2] = {0.0, 0.0};
-    bool second = false;
-    if (i < cnt) {
-        Recon r;
-        recon_core(m, Ws, k, p.thr, r);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) lds_store_face(lds, stride, j * kTile + i, recon_face(r, j, p.thr));
-        centred_source(m, r, k, p.hg, sc);
-        second = r.second;
-    }
-    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
-    for (int b = i; b < nb; b += kBlock) {
-        const uint32_t item = tm.bitem[b0 + b];
-        const int64_t n = int64_t(item >> 2);
-        const int jn = int(item & 3u);
-        Recon r;
-        recon_core(m, Ws, n, p.thr, r);
-        const Face f = (jn == 0) ? recon_face(r, 0, p.thr)
-                     : (jn == 1) ? recon_face(r, 1, p.thr) : recon_face(r, 2, p.thr);
-        lds_store_face(lds, stride, 3 * kTile + b, f);
-    }
+    double sc[2], ownH[3];
+    bool second;
+    tile_faces(m, tm, Ws, t, c0, cnt, p.thr, p.hg, lds, stride, ownH, sc, second);
     __syncthreads();
 
     unsigned long long clamp = 0;
@@ -259,8 +226,9 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
         for (int j = 0; j < 3; ++j) {
             const uint16_t s = tm.nloc[j * nc + k];
             const bool wall = (s == kNlocWall16);
-            const Face own = lds_load_face(lds, stride, j * kTile + i);
-            const Face other = lds_load_face(lds, stride, wall ? j * kTile + i : int(s & 0x7FFFu));
+            const Face own = lds_load_face(lds, stride, j * kTile + i, ownH[j]);
+            const Face other =
+                lds_load_face(lds, stride, wall ? j * kTile + i : int(s & 0x7FFFu), 0.0);
             double tt[3];
             const bool left = face_term(p.g, p.hg, own, other, wall, (s & 0x8000u) != 0,
                                         gf(m, 0, j, k), gf(m, 1, j, k), gf(m, 2, j, k), tt);
@@ -277,13 +245,20 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
         const double ar = m.area[k];
         const double ra = 1.0 / ar;
         const double R[3] = {a0 * ra, a1 * ra, a2 * ra};
+        uint8_t mk;
         if (STAGE == 1) {
-            W1[k] = stage1_update(W[k], R, dt, p.thr, clamp);
+            W1[k] = stage1_update(W[k], R, dt, p.thr, clamp, mk);
         } else {
-            const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp);
-            W[k] = o;
+            const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp, mk);
+            if (TAPE) tp.wout[k] = o; else W[k] = o;
             bad = !isfinite(o.H) || !isfinite(o.HU) || !isfinite(o.HV);
             rr = cfl_ratio(o.H, o.HU, o.HV, ar, m.perim[k], p.g, p.thr);
+        }
+        if (TAPE) {
+            tp.R[3 * k] = R[0];
+            tp.R[3 * k + 1] = R[1];
+            tp.R[3 * k + 2] = R[2];
+            tp.mask[k] = mk;
         }
     }
     if (STAGE == 2 && bad) {
@@ -292,15 +267,36 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Ce
     }
     block_count_atomic(clamp, &c->clamps);
     if (STAGE == 2) {
-        block_min_atomic(rr, &sgs->rmin[slot ^ 1]);
+        block_min_atomic(rr, TAPE ? tp.rmin : &sgs->rmin[slot ^ 1]);
         stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
     }
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Cell4* __restrict__ W,
+                                                       Cell4* __restrict__ W1, StepParams p,
+                                                       Ctrl* c, Seg* sg, int slot, int step_arg,
+                                                       double* log) {
+    stage_body<STAGE, false>(m, tm, W, W1, p, c, sg, slot, step_arg, log, Tape{});
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kBlock) void stage_tape_kernel(DevMesh m, TileMap tm,
+                                                            Cell4* __restrict__ W,
+                                                            Cell4* __restrict__ W1, StepParams p,
+                                                            Ctrl* c, Seg* sg, int slot,
+                                                            int step_arg, double* log, Tape tp) {
+    stage_body<STAGE, true>(m, tm, W, W1, p, c, sg, slot, step_arg, log, tp);
 }
 
 template __global__ void stage_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, Seg*,
                                          int, int, double*);
 template __global__ void stage_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, Seg*,
                                          int, int, double*);
+template __global__ void stage_tape_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*,
+                                              Seg*, int, int, double*, Tape);
+template __global__ void stage_tape_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*,
+                                              Seg*, int, int, double*, Tape);
 
 // ---------------------------------------------------------------- gauges
 

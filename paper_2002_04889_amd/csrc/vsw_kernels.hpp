@@ -63,7 +63,7 @@ struct TileMap {
 
 // Fused stage kernel.  STAGE 1: w1 = w + dt R(w).  STAGE 2:
 // w^{n+1} = w/2 + (w1 + dt R(w1))/2 in place, plus the next CFL minimum and
-// the time bookkeeping.  Dynamic LDS: 5 * (3 * kTile + bmax) doubles.
+// the time bookkeeping.  Dynamic LDS: stage_lds_bytes(bmax).
 // Step k of the call is kbase + step_arg (kbase advances on the device, so a
 // captured pair of steps can be replayed).  Log: log[2 (k nseg + scenario)]
 // = time after the step, log[2 (k nseg + scenario) + 1] = its dt.
@@ -71,7 +71,25 @@ template <int STAGE>
 __global__ void stage_kernel(DevMesh m, TileMap tm, Cell4* W, Cell4* W1, StepParams p, Ctrl* c,
                              Seg* sg, int slot, int step_arg, double* log);
 
-inline size_t stage_lds_bytes(int bmax) { return sizeof(double) * 5 * size_t(3 * kTile + bmax); }
+// LDS of the fused stage kernel: four doubles (eta, h, u, v) per face slot.
+inline size_t stage_lds_bytes(int bmax) { return sizeof(double) * 4 * size_t(3 * kTile + bmax); }
+
+// What the discrete adjoint records of a stage while it replays a checkpoint
+// segment: the stage's residual R (3 per cell) and the mask of its
+// post-stage fix (bit 0: depth not clamped, bit 1: momentum kept); stage 2
+// writes w^{n+1} to wout (w^n is kept) and the bits of the CFL minimum of
+// w^{n+1} to *rmin (pre-set to +inf) instead of the scenario's record.
+struct Tape {
+    double* __restrict__ R;
+    uint8_t* __restrict__ mask;
+    Cell4* __restrict__ wout;
+    unsigned long long* rmin;
+};
+
+// The fused stage kernel with a tape: the same arithmetic and results.
+template <int STAGE>
+__global__ void stage_tape_kernel(DevMesh m, TileMap tm, Cell4* W, Cell4* W1, StepParams p,
+                                  Ctrl* c, Seg* sg, int slot, int step_arg, double* log, Tape tp);
 
 // Start of a call: every scenario's time from t0[s], minima cleared.
 __global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0);
