@@ -145,12 +145,18 @@ __device__ __forceinline__ void face_add(Face& a, const double eta, double h, do
     a.eta += eta; a.h += h; a.H += H; a.u += u; a.v += v;
 }
 
-// Reverse of face_term: adds the adjoints of own and other for the term
-// adjoint tb (on a wall the caller passes own as other and adds both).
-__device__ __forceinline__ void face_term_rev(double g, double hg, const Face& own,
+// Reverse of the two terms of one face for the adjoint of this cell's face
+// state: this cell's term (adjoint tb) and, on an interior face, the
+// neighbour's term (adjoint tbn).  Both terms come from one flux in the
+// face's canonical orientation (they differ in sign and in the side whose
+// pressure correction they carry), so the flux is reversed once for the
+// combined adjoint.  On a wall the ghost is the mirror of own, and its
+// derivatives fold back into own.
+__device__ __forceinline__ void face_pair_rev(double g, double hg, const Face& own,
                                               const Face& other, bool wall, bool own_left,
                                               double nx_out, double ny_out, double l,
-                                              const double tb[3], Face& ownb, Face& otherb) {
+                                              const double tb[3], const double tbn[3],
+                                              Face& ownb) {
     const bool left = wall || own_left;
     const Face& L = left ? own : other;
     const Face& R = left ? other : own;
@@ -163,17 +169,21 @@ __device__ __forceinline__ void face_term_rev(double g, double hg, const Face& o
     const double aL = L.eta + hs, aR = R.eta + hs;
     const double HsL = (aL > 0.0) ? aL : 0.0, HsR = (aR > 0.0) ? aR : 0.0;
     if (wall) unR = -unL;
-    // t = l (f0, phi1 + pc nx, phi2 + pc ny), phi = rotation of f
-    const double f0b = l * tb[0], p1b = l * tb[1], p2b = l * tb[2];
-    const double pcb = p1b * nx + p2b * ny;
-    const double fb[3] = {f0b, p1b * nx + p2b * ny, -p1b * ny + p2b * nx};
+    // a term is l (f0, phi1 + pc nx, phi2 + pc ny), phi the rotated flux f
+    const double p0b = l * (tb[0] + tbn[0]), p1b = l * (tb[1] + tbn[1]),
+                 p2b = l * (tb[2] + tbn[2]);
+    const double pcob = l * (tb[1] * nx + tb[2] * ny);    // this cell's correction
+    const double pcnb = l * (tbn[1] * nx + tbn[2] * ny);  // the neighbour's
+    const double fb[3] = {p0b, p1b * nx + p2b * ny, -p1b * ny + p2b * nx};
     double HLb = 0.0, HRb = 0.0, HsLb = 0.0, HsRb = 0.0;
     if (left) {
-        HLb += pcb * hg * 2.0 * L.H;
-        HsLb -= pcb * hg * 2.0 * HsL;
+        HLb += pcob * hg * 2.0 * L.H;
+        HsLb -= pcob * hg * 2.0 * HsL;
+        HsRb -= pcnb * hg * 2.0 * HsR;
     } else {
-        HRb += pcb * hg * 2.0 * R.H;
-        HsRb -= pcb * hg * 2.0 * HsR;
+        HRb += pcob * hg * 2.0 * R.H;
+        HsRb -= pcob * hg * 2.0 * HsR;
+        HsLb -= pcnb * hg * 2.0 * HsL;
     }
     double unLb = 0.0, utLb = 0.0, unRb = 0.0, utRb = 0.0;
     hll_face_rev(g, hg, HsL, unL, utL, HsR, unR, utR, fb, HsLb, unLb, utLb, HsRb, unRb, utRb);
@@ -184,13 +194,11 @@ __device__ __forceinline__ void face_term_rev(double g, double hg, const Face& o
     double eLb = 0.0, eRb = 0.0, hsb = 0.0;
     if (aL > 0.0) { eLb += HsLb; hsb += HsLb; }
     if (aR > 0.0) { eRb += HsRb; hsb += HsRb; }
-    double hLb = hsR ? 0.0 : hsb, hRb = hsR ? hsb : 0.0;
+    const double hLb = hsR ? 0.0 : hsb, hRb = hsR ? hsb : 0.0;
     const double uLb = unLb * nx - utLb * ny, vLb = unLb * ny + utLb * nx;
     const double uRb = unRb * nx - utRb * ny, vRb = unRb * ny + utRb * nx;
-    Face& Lb = left ? ownb : otherb;
-    Face& Rb = left ? otherb : ownb;
-    face_add(Lb, eLb, hLb, HLb, uLb, vLb);
-    face_add(Rb, eRb, hRb, HRb, uRb, vRb);
+    if (left) face_add(ownb, eLb, hLb, HLb, uLb, vLb);
+    if (!left || wall) face_add(ownb, eRb, hRb, HRb, uRb, vRb);
 }
 
 struct LimInfo {
@@ -349,27 +357,21 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
         const Face own = lds_load_face(lds, stride, j * kTile + i, ownH[j]);
         fhs[j] = own.h;
         const double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k), l = gf(m, 2, j, k);
-        // this cell's term enters its accumulator with - (left) or + (right)
+        // this cell's term enters its accumulator with - (left) or + (right),
+        // the neighbour's with the opposite sign
         const double sg = own_left ? -1.0 : 1.0;
         const double tb[3] = {sg * ab[0], sg * ab[1], sg * ab[2]};
-        Face xb{0.0, 0.0, 0.0, 0.0, 0.0};
         if (wall) {
-            face_term_rev(g, hg, own, own, true, true, nx, ny, l, tb, F[j], xb);
-            face_add(F[j], xb.eta, xb.h, xb.H, xb.u, xb.v);
+            const double zero[3] = {0.0, 0.0, 0.0};
+            face_pair_rev(g, hg, own, own, true, true, nx, ny, l, tb, zero, F[j]);
         } else {
             const int64_t n = int64_t(s >> 3);
-            const int jn = int(s & 3u);
             // the neighbour's face depth enters only the neighbour's own
             // pressure correction, whose adjoint is not needed here
             const Face other = lds_load_face(
                 lds, stride, int(tm.nloc[j * nc + k] & 0x7FFFu), 0.0);
-            face_term_rev(g, hg, own, other, false, own_left, nx, ny, l, tb, F[j], xb);
-            // the neighbour's term of the same face, with this face as its other side
-            const double sn = own_left ? 1.0 : -1.0;
-            const double tbn[3] = {sn * mua[3 * n], sn * mua[3 * n + 1], sn * mua[3 * n + 2]};
-            Face ob{0.0, 0.0, 0.0, 0.0, 0.0};
-            face_term_rev(g, hg, other, own, false, !own_left, gf(m, 0, jn, n), gf(m, 1, jn, n),
-                          gf(m, 2, jn, n), tbn, ob, F[j]);
+            const double tbn[3] = {-sg * mua[3 * n], -sg * mua[3 * n + 1], -sg * mua[3 * n + 2]};
+            face_pair_rev(g, hg, own, other, false, own_left, nx, ny, l, tb, tbn, F[j]);
         }
     }
     const Cell4 ck = W[k];
