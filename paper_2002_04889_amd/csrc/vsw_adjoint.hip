@@ -591,18 +591,64 @@ __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
     if (threadIdx.x == 0) part[blockIdx.x] += s;
 }
 
-__global__ __launch_bounds__(kBlock) void adj_gather_rk1_kernel(DevMesh m, TileMap tm,
-                                                                const double* __restrict__ C,
-                                                                Adj4* __restrict__ lamn,
-                                                                double* __restrict__ hbar) {
+__global__ __launch_bounds__(kBlock) void adj_turn_kernel(
+    DevMesh m, TileMap tm, const double* __restrict__ C, const Cell4* __restrict__ W, double g,
+    double thr, double cfl, const unsigned long long* rmin, const double* lamdt,
+    const int64_t* cells, int ng, const double* r, Adj4* __restrict__ lamn,
+    double* __restrict__ hbar, const uint8_t* __restrict__ mask2p,
+    const double* __restrict__ R1p, double dtp, double* __restrict__ mua,
+    Adj4* __restrict__ lamp, double* __restrict__ part) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
     const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    const Adj4 w = gather_cell(m, C, k);
-    Adj4 n = lamn[k];
-    n.H += w.H; n.HU += w.HU; n.HV += w.HV;
-    lamn[k] = n;
-    hbar[k] += w.h;
+    double d = 0.0;
+    if (int(threadIdx.x) < ti.cnt) {
+        // after J_R(w)^T: the contributions gathered in fixed order
+        const Adj4 w = gather_cell(m, C, k);
+        Adj4 n = lamn[k];
+        n.H += w.H; n.HU += w.HU; n.HV += w.HV;
+        double hb = hbar[k] + w.h;
+        if (rmin) {
+            // dt = CFL ratio of the minimising cell(s)
+            const Cell4 q = W[k];
+            const double rr = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
+            if (rr < __longlong_as_double(0x7FF0000000000000ll) && dbits(rr) == *rmin) {
+                const double u = q.HU / q.H, v = q.HV / q.H;
+                const double m2 = u * u + v * v, mm = sqrt(m2), c = sqrt(g * q.H), sp = mm + c;
+                const double sb = -(*lamdt * cfl) * rr / sp;
+                const double ub = (m2 > 0.0) ? sb * u / mm : 0.0;
+                const double vb = (m2 > 0.0) ? sb * v / mm : 0.0;
+                n.H += sb * g / (2.0 * c) - (ub * u + vb * v) / q.H;
+                n.HU += ub / q.H;
+                n.HV += vb / q.H;
+            }
+        }
+        if (r) {
+            // gauge misfit of w^k, in gauge order (gauges may share a cell)
+            for (int gi = 0; gi < ng; ++gi)
+                if (cells[gi] == k) {
+                    n.H += 2.0 * r[gi];
+                    hb -= 2.0 * r[gi];
+                }
+        }
+        lamn[k] = n;
+        hbar[k] = hb;
+        if (mask2p) {
+            // the start of the reverse of step k-1 (as adj_start_kernel)
+            const uint8_t mk = mask2p[k];
+            const double l0 = (mk & 1) ? n.H : 0.0, l1 = (mk & 2) ? n.HU : 0.0,
+                         l2 = (mk & 2) ? n.HV : 0.0;
+            const double ra = 1.0 / m.area[k];
+            mua[3 * k] = (0.5 * dtp * l0) * ra;
+            mua[3 * k + 1] = (0.5 * dtp * l1) * ra;
+            mua[3 * k + 2] = (0.5 * dtp * l2) * ra;
+            lamp[k] = Adj4{0.5 * l0, 0.5 * l1, 0.5 * l2, 0.0};
+            d = 0.5 * (l0 * R1p[3 * k] + l1 * R1p[3 * k + 1] + l2 * R1p[3 * k + 2]);
+        }
+    }
+    if (mask2p) {
+        const double s = block_sum(d);
+        if (threadIdx.x == 0) part[blockIdx.x] = s;
+    }
 }
 
 // ---------------------------------------------------------------- time step
@@ -612,29 +658,6 @@ __global__ void adj_sum_kernel(const double* part, int n, double* out) {
     for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
     const double t = block_sum(s);
     if (threadIdx.x == 0) *out = t;
-}
-
-__global__ __launch_bounds__(kBlock) void adj_dt_kernel(DevMesh m, TileMap tm,
-                                                        const Cell4* __restrict__ W, double g,
-                                                        double thr, double cfl,
-                                                        const unsigned long long* rmin,
-                                                        const double* lamdt, Adj4* lamn) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    const Cell4 q = W[k];
-    const double A = m.area[k], P = m.perim[k];
-    const double r = cfl_ratio(q.H, q.HU, q.HV, A, P, g, thr);
-    if (!(r < __longlong_as_double(0x7FF0000000000000ll)) || dbits(r) != *rmin) return;
-    const double u = q.HU / q.H, v = q.HV / q.H;
-    const double m2 = u * u + v * v, mm = sqrt(m2), c = sqrt(g * q.H), s = mm + c;
-    const double sb = -(*lamdt * cfl) * r / s;
-    const double ub = (m2 > 0.0) ? sb * u / mm : 0.0, vb = (m2 > 0.0) ? sb * v / mm : 0.0;
-    Adj4 n = lamn[k];
-    n.H += sb * g / (2.0 * c) - (ub * u + vb * v) / q.H;
-    n.HU += ub / q.H;
-    n.HV += vb / q.H;
-    lamn[k] = n;
 }
 
 // ---------------------------------------------------------------- loss and output

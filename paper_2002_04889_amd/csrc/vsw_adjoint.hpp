@@ -33,22 +33,28 @@ __global__ void adj_start_kernel(DevMesh m, TileMap tm, const Adj4* lam, const u
 __global__ void adj_vjp_kernel(DevMesh m, TileMap tm, const Cell4* W, const double* mua,
                                double g, double hg, double thr, double* C);
 // Gather: own + the stencil contributions of the face neighbours, in fixed
-// order (no atomics), then the Runge-Kutta reverse that follows:
-//   after J_R(w1)^T: lam1 = lt2/2 + wb, hbar += wb.h, lt1 = mask1 (.) lam1,
-//                    mua = dt lt1 / |K|, lamn += lt1, part[tile] += lt1 . R0;
-//   after J_R(w)^T:  lamn += wb, hbar += wb.h.
+// order (no atomics), then the Runge-Kutta reverse that follows J_R(w1)^T:
+//   lam1 = lt2/2 + wb, hbar += wb.h, lt1 = mask1 (.) lam1,
+//   mua = dt lt1 / |K|, lamn += lt1, part[tile] += lt1 . R0.
 __global__ void adj_gather_rk2_kernel(DevMesh m, TileMap tm, const double* C, const Adj4* lam,
                                       const uint8_t* mask2, const uint8_t* mask1,
                                       const double* R0, double dt, double* mua, Adj4* lamn,
                                       double* hbar, double* part);
-__global__ void adj_gather_rk1_kernel(DevMesh m, TileMap tm, const double* C, Adj4* lamn,
-                                      double* hbar);
+// End of the reverse of step k, in one pass per cell: after J_R(w)^T the
+// gathered contributions (lamn += wb, hbar += wb.h); with rmin, the CFL
+// term dt = CFL ratio(w^k) at the cell(s) whose ratio bits equal *rmin
+// (lamn += lamdt CFL d ratio/d w); with r, the gauge misfit of w^k
+// (lamn.H += 2 r, hbar -= 2 r per gauge on the cell).  lamn then holds the
+// adjoint of w^k.  With mask2p, also the start of the reverse of step k-1
+// from its tape (R1p, mask2p, dtp), as adj_start_kernel: mua, lamp, part.
+__global__ void adj_turn_kernel(DevMesh m, TileMap tm, const double* C, const Cell4* W, double g,
+                                double thr, double cfl, const unsigned long long* rmin,
+                                const double* lamdt, const int64_t* cells, int ng,
+                                const double* r, Adj4* lamn, double* hbar, const uint8_t* mask2p,
+                                const double* R1p, double dtp, double* mua, Adj4* lamp,
+                                double* part);
 // Sum of part[0 .. n) in fixed order into *out (one block).
 __global__ void adj_sum_kernel(const double* part, int n, double* out);
-// dt = cfl * ratio of the minimising cell(s): lamn += lamdt * cfl * d ratio / d w there.
-__global__ void adj_dt_kernel(DevMesh m, TileMap tm, const Cell4* W, double g, double thr,
-                              double cfl, const unsigned long long* rmin, const double* lamdt,
-                              Adj4* lamn);
 // Gauge misfit of the state after a step: lam[cell].H += 2 r, hbar[cell] -= 2 r.
 __global__ void adj_gauge_kernel(const int64_t* cells, int ng, const double* r, Adj4* lam,
                                  double* hbar);

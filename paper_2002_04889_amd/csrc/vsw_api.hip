@@ -844,6 +844,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
             hipLaunchKernelGGL(stage_tape_kernel<2>, grid, block, lds, st, m, tm, Wi, W1i, p,
                                s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
         }
+        bool started = false;  // the start of step k was done by the previous turn
         for (int64_t k = n1 - 1; k >= n0; --k) {
             const int64_t i = k - n0;
             const Cell4* Wn = seg.p + i * n;
@@ -853,26 +854,27 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
             const uint8_t* m1 = tm1.p + i * n;
             const uint8_t* m2 = tm2.p + i * n;
             const double dt = dts[size_t(k)];
-            hipLaunchKernelGGL(adj_start_kernel, grid, block, 0, st, m, tm, lam.p, m2, R1, dt,
-                               mua.p, lamn.p, part.p);
+            if (!started)
+                hipLaunchKernelGGL(adj_start_kernel, grid, block, 0, st, m, tm, lam.p, m2, R1, dt,
+                                   mua.p, lamn.p, part.p);
             hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, W1, mua.p, g, hg, thr,
                                C.p);
             hipLaunchKernelGGL(adj_gather_rk2_kernel, grid, block, 0, st, m, tm, C.p, lam.p, m2,
                                m1, R0, dt, mua.p, lamn.p, hbar.p, part.p);
-            hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, Wn, mua.p, g, hg, thr,
-                               C.p);
-            hipLaunchKernelGGL(adj_gather_rk1_kernel, grid, block, 0, st, m, tm, C.p, lamn.p,
-                               hbar.p);
-            if (cfl_dt) {
+            if (cfl_dt)
                 hipLaunchKernelGGL(adj_sum_kernel, dim3(1), block, 0, st, part.p, s->ntiles,
                                    lamdt.p);
-                hipLaunchKernelGGL(adj_dt_kernel, grid, block, 0, st, m, tm, Wn, g, thr, cfl,
-                                   rmin_hist.p + i, lamdt.p, lamn.p);
-            }
+            hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, Wn, mua.p, g, hg, thr,
+                               C.p);
+            // step k-1's tape is in this segment: start its reverse in the same pass
+            const bool next = (k - 1 >= n0);
+            hipLaunchKernelGGL(adj_turn_kernel, grid, block, 0, st, m, tm, C.p, Wn, g, thr, cfl,
+                               cfl_dt ? rmin_hist.p + i : nullptr, lamdt.p, cells, ng,
+                               k >= 1 ? d_r.p + (k - 1) * ng : nullptr, lamn.p, hbar.p,
+                               next ? m2 - n : nullptr, next ? R1 - 3 * n : nullptr,
+                               next ? dts[size_t(k - 1)] : 0.0, mua.p, lam.p, part.p);
             std::swap(lam.p, lamn.p);
-            if (k >= 1)
-                hipLaunchKernelGGL(adj_gauge_kernel, dim3(1), dim3(64), 0, st, cells, ng,
-                                   d_r.p + (k - 1) * ng, lam.p, hbar.p);
+            started = next;
         }
         HIP_TRY(hipGetLastError());
     }
