@@ -131,14 +131,17 @@ int vsw_scenario_dt_history(vsw_solver *s, int32_t scen, int64_t max,
  * run the hand-written reverse of every step (Section 2.3 stages, Section
  * 2.2 fluxes, Section 2.4 reconstruction with its branches as taken, the
  * post-stage fix and the CFL time step) backwards from checkpoints taken
- * every `checkpoint_every` steps, each segment recomputed forward.  Outputs
+ * every `checkpoint_every` steps, each segment replayed forward with the
+ * recorded dts while the stage kernels record a tape (states, residuals,
+ * fix masks, CFL minima) for the reverse.  Outputs
  * (caller's order, nc values each; any gradient pointer may be NULL): *loss,
  * and d loss / d H, HU, HV of the initial state and d loss / d h (the bed
  * depth, with the initial H, HU, HV held fixed).  The solver's state, time,
  * gauges and logs are unchanged on return.  Device memory: about
- * (nsteps / checkpoint_every + checkpoint_every) * 32 + 500 bytes per cell.
- * EINVAL on an FP32 or ensemble solver, ng < 1 or bad counts; EUNSTABLE if
- * the forward run fails. */
+ * 32 * ceil(nsteps / checkpoint_every) + 114 * min(checkpoint_every, nsteps)
+ * + 300 bytes per cell.  EINVAL on an FP32 or ensemble solver, ng < 1 or
+ * bad counts; ENOMEM when that memory is not available; EUNSTABLE if the
+ * forward run fails. */
 int vsw_adjoint_gauge_loss(vsw_solver *s, int64_t nsteps,
                            int64_t checkpoint_every, int32_t ng,
                            const int32_t *gauge_cells, const double *eta_obs,
