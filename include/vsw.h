@@ -231,17 +231,26 @@ int vsw_set_graph(vsw_solver *s, int on);
  * Results are bitwise the same.  EINVAL for other values. */
 int vsw_set_tile_order(vsw_solver *s, int xcd_order);
 
+/* Workgroups of the fused stage kernels resident per compute unit:
+ * 0 (default) as many as registers and LDS allow (4 for FP64, 5 for FP32
+ * on gfx950); 3 or 2 cap them (each workgroup then requests more than
+ * 1/(cap + 1) of the CU's 160 KiB of LDS), which trades latency hiding for
+ * less cache pressure.  Results are bitwise the same.  EINVAL for other
+ * values. */
+int vsw_set_occupancy(vsw_solver *s, int wg_per_cu);
+
 /* Autotuner: runs `steps` steps (after two warm-up steps) of the current
  * state under every launch configuration c = 0 .. VSW_TUNE_CONFIGS - 1
- * (bit 2: the two-pass kernel organisation, FP64 only; bit 1: XCD tile
- * order; bit 0: graph mode), timing each with HIP events on the solver's
- * stream, restores the state, time and logs after each, and keeps the
- * fastest configuration for later vsw_step calls.  Every configuration
- * gives bitwise the same results.  ms_per_step (may be NULL) receives
- * VSW_TUNE_CONFIGS values (INFINITY where a configuration does not apply),
- * *chosen (may be NULL) the winner.  EINVAL unless 2 <= steps <= 100000;
- * ESTATE without mesh and state. */
-enum { VSW_TUNE_CONFIGS = 8 };
+ * (c / 8: workgroups per CU of the fused kernels, 0 = as many as fit,
+ * 1 = at most 3, 2 = at most 2; bit 2: the two-pass kernel organisation,
+ * FP64 and uncapped only; bit 1: XCD tile order; bit 0: graph mode),
+ * timing each with HIP events on the solver's stream, restores the state,
+ * time and logs after each, and keeps the fastest configuration for later
+ * vsw_step calls.  Every configuration gives bitwise the same results.
+ * ms_per_step (may be NULL) receives VSW_TUNE_CONFIGS values (INFINITY
+ * where a configuration does not apply), *chosen (may be NULL) the winner.
+ * EINVAL unless 2 <= steps <= 100000; ESTATE without mesh and state. */
+enum { VSW_TUNE_CONFIGS = 24 };
 int vsw_autotune(vsw_solver *s, int64_t steps, int32_t *chosen,
                  double *ms_per_step);
 

@@ -54,6 +54,15 @@ struct GraphKey {
     }
 };
 
+// Dynamic LDS of a fused stage launch: the kernel's own need, raised above
+// 1/(cap + 1) of the CU's 160 KiB when the resident workgroups per CU are
+// capped, so that at most `cap` fit.
+size_t capped_lds(size_t need, int cap) {
+    if (cap <= 0) return need;
+    const size_t cu = size_t(160) * 1024;
+    return std::max(need, cu / size_t(cap + 1) + 1024);
+}
+
 template <class T>
 struct DevBuf {
     T* p = nullptr;
@@ -118,6 +127,7 @@ struct vsw_solver {
     int variant = VSW_KERNEL_FUSED;
     bool use_graph = false;
     int xcd_order = 1;
+    int occupancy = 0;  // fused stage kernels: workgroups per CU cap (0 = none)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     GraphKey graph_key{};
@@ -486,8 +496,8 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, nseg,
                s->xcd_order};
     const bool f32 = (s->prm.precision == VSW_FP32);
-    const size_t lds = stage_lds_bytes(s->bmax);
-    const size_t lds32 = stage_f32_lds_bytes(s->bmax);
+    const size_t lds = capped_lds(stage_lds_bytes(s->bmax), s->occupancy);
+    const size_t lds32 = capped_lds(stage_f32_lds_bytes(s->bmax), s->occupancy);
 
     // profiling events: one pair per timed launch
     size_t ev_used = 0;
@@ -566,7 +576,7 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     const bool use_graph = s->use_graph && !prof && n >= 2;
     if (use_graph) {
         const GraphKey key{lg, s->d_gauge_log.p, s->d_gauge_cells.p, ng, t_stop,
-                           s->variant * 2 + s->xcd_order};
+                           (s->variant * 2 + s->xcd_order) * 8 + s->occupancy};
         if (!s->graph_exec || !(key == s->graph_key)) {
             s->release_graph();
             prof = false;
@@ -966,6 +976,14 @@ int vsw_set_tile_order(vsw_solver* s, int xcd_order) {
     return VSW_OK;
 }
 
+int vsw_set_occupancy(vsw_solver* s, int wg_per_cu) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (wg_per_cu != 0 && wg_per_cu != 2 && wg_per_cu != 3)
+        return fail(VSW_EINVAL, "workgroups per CU is 0, 2 or 3");
+    s->occupancy = wg_per_cu;
+    return VSW_OK;
+}
+
 int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_step) {
     if (!s) return fail(VSW_EINVAL, "NULL solver");
     if (!s->has_mesh || !s->has_state) return fail(VSW_ESTATE, "mesh and state required");
@@ -984,7 +1002,8 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
     const int64_t clamps_save = s->clamps;
     const std::vector<double> seg_t_save = s->seg_t, seg_dt_save = s->seg_dt;
     const std::vector<int64_t> seg_steps_save = s->seg_steps;
-    const int variant_save = s->variant, xcd_save = s->xcd_order;
+    const int variant_save = s->variant, xcd_save = s->xcd_order, occ_save = s->occupancy;
+    static const int kOcc[3] = {0, 3, 2};
     const bool graph_save = s->use_graph, prof_save = s->profiling;
     s->profiling = false;
     hipEvent_t e0, e1;
@@ -994,11 +1013,12 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
     int best_c = 0;
     int rc = VSW_OK;
     for (int c = 0; c < VSW_TUNE_CONFIGS; ++c) {
-        const int variant = (c >> 2) & 1, xcd = (c >> 1) & 1, graph = c & 1;
+        const int variant = (c >> 2) & 1, xcd = (c >> 1) & 1, graph = c & 1, occ = kOcc[c / 8];
         double ms = INFINITY;
-        if (!(variant == VSW_KERNEL_TWO_PASS && f32)) {
+        if (!(variant == VSW_KERNEL_TWO_PASS && (f32 || occ != 0))) {
             s->variant = variant;
             s->xcd_order = xcd;
+            s->occupancy = occ;
             s->use_graph = graph != 0;
             s->release_graph();
             s->seg_t = seg_t_save;
@@ -1041,11 +1061,13 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
         s->variant = variant_save;
         s->xcd_order = xcd_save;
         s->use_graph = graph_save;
+        s->occupancy = occ_save;
         return rc;
     }
     s->variant = (best_c >> 2) & 1;
     s->xcd_order = (best_c >> 1) & 1;
     s->use_graph = (best_c & 1) != 0;
+    s->occupancy = kOcc[best_c / 8];
     if (chosen) *chosen = best_c;
     return VSW_OK;
 }

@@ -71,6 +71,7 @@ _SIGS = {
                                               _dp, _dp, _dp, _dp]),
     "vsw_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_set_tile_order": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vsw_set_occupancy": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_autotune": (ctypes.c_int, [_vp, _i64, _ip, _dp]),
     "vsw_set_kernel_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _lp]),
@@ -268,11 +269,16 @@ def vsw_adjoint_gauge_loss(h, nc, nsteps, checkpoint_every, gauges, eta_obs):
     return (loss.value, *out)
 
 
-VSW_TUNE_CONFIGS = 8
+VSW_TUNE_CONFIGS = 24
+TUNE_OCCUPANCY = (0, 3, 2)  # workgroups per CU of configuration c // 8 (0 = as many as fit)
 
 
 def vsw_set_tile_order(h, xcd_order: int):
     return _check(lib().vsw_set_tile_order(h, int(xcd_order)))
+
+
+def vsw_set_occupancy(h, wg_per_cu: int):
+    return _check(lib().vsw_set_occupancy(h, int(wg_per_cu)))
 
 
 def vsw_autotune(h, steps: int):
@@ -284,8 +290,10 @@ def vsw_autotune(h, steps: int):
 
 
 def tune_config_name(c: int) -> str:
+    occ = TUNE_OCCUPANCY[c // 8]
     return (("two-pass" if c & 4 else "fused") + (", XCD tile order" if c & 2 else
-            ", index tile order") + (", graph" if c & 1 else ", direct launches"))
+            ", index tile order") + (", graph" if c & 1 else ", direct launches")
+            + (f", at most {occ} workgroups per CU" if occ else ""))
 
 
 def vsw_set_graph(h, on: bool):

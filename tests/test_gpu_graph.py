@@ -124,10 +124,10 @@ def test_autotune_keeps_state_and_results(precision):
         say(f"precision {precision}: chosen {chosen} ({vsw.tune_config_name(chosen)}), "
             f"ms/step {np.round(ms, 4)}")
         assert 0 <= chosen < vsw.VSW_TUNE_CONFIGS and ms[chosen] == np.min(ms)
-        if precision == vsw.VSW_FP32:
-            assert np.all(np.isinf(ms[4:])) and np.all(np.isfinite(ms[:4]))
-        else:
-            assert np.all(np.isfinite(ms))
+        # the two-pass organisation (bit 2) is FP64 only and takes no cap
+        cfg = np.arange(vsw.VSW_TUNE_CONFIGS)
+        applies = ((cfg & 4) == 0) | ((precision == vsw.VSW_FP64) & (cfg < 8))
+        assert np.all(np.isfinite(ms[applies])) and np.all(np.isinf(ms[~applies]))
         after = s.state()
         for a, b in zip(before, after):
             assert np.array_equal(np.asarray(a), np.asarray(b))
@@ -138,6 +138,25 @@ def test_autotune_keeps_state_and_results(precision):
     assert done == 30 and t == ref[0]["t"]
     for k, v in (("H", H), ("HU", HU), ("HV", HV)):
         assert np.array_equal(v, ref[0][k])
+
+
+@pytest.mark.parametrize("precision", [vsw.VSW_FP64, vsw.VSW_FP32], ids=["fp64", "fp32"])
+def test_occupancy_caps_bitwise(precision):
+    """Capping the resident workgroups per CU changes the launch, not the
+    arithmetic."""
+    c = W.basin_case(scale=16)
+    out = []
+    for occ in (0, 3, 2):
+        s = vsw.Solver.for_case(c, precision=precision)
+        try:
+            vsw.vsw_set_occupancy(s.h, occ)
+            s.step(25)
+            out.append(s.state())
+        finally:
+            s.close()
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
 
 
 def test_tile_orders_bitwise():
