@@ -54,6 +54,20 @@ struct GraphKey {
     }
 };
 
+// Runs f when the scope ends, on every return path.
+template <class F>
+struct OnExit {
+    F f;
+    bool armed = true;
+    ~OnExit() {
+        if (armed) f();
+    }
+};
+template <class F>
+OnExit<F> on_exit(F f) {
+    return OnExit<F>{f};
+}
+
 // Dynamic LDS of a fused stage launch: the kernel's own need, raised above
 // 1/(cap + 1) of the CU's 160 KiB when the resident workgroups per CU are
 // capped, so that at most `cap` fit.
@@ -756,16 +770,13 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
         s->gauge_t.clear();
         s->release_graph();
     };
+    // the caller's state, time, gauges and logs come back on every return path
+    const auto restore_on_exit = on_exit(restore);
     int rc = vsw_set_gauges(s, ng, gauge_cells);
-    if (rc != VSW_OK) {
-        restore();
-        return rc;
-    }
+    if (rc != VSW_OK) return rc;
     // ---- forward with checkpoints and gauge records
-    if (ck.alloc(size_t(nck) * size_t(n)) != hipSuccess) {
-        restore();
+    if (ck.alloc(size_t(nck) * size_t(n)) != hipSuccess)
         return fail(VSW_ENOMEM, "checkpoint memory");
-    }
     std::vector<double> dts, eta;
     for (int64_t c = 0; c < nck; ++c) {
         HIP_TRY(hipMemcpyAsync(ck.p + c * n, s->d_w.p, size_t(n) * sizeof(Cell4),
@@ -773,11 +784,8 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
         const int64_t m = std::min(ckpt, nsteps - c * ckpt);
         int64_t done = 0;
         rc = vsw_step(s, m, INFINITY, &done, nullptr);
-        if (rc != VSW_OK || done != m) {
-            const std::string msg = g_last_error;
-            restore();
-            return fail(rc != VSW_OK ? rc : VSW_EUNSTABLE, "forward run: " + msg);
-        }
+        if (rc != VSW_OK || done != m)
+            return fail(rc != VSW_OK ? rc : VSW_EUNSTABLE, "forward run: " + g_last_error);
         dts.insert(dts.end(), s->last_dts.begin(), s->last_dts.end());
         eta.insert(eta.end(), s->gauge_eta.begin(), s->gauge_eta.end());
     }
@@ -809,10 +817,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                          hbar.alloc(N), part.alloc(size_t(s->ntiles)), lamdt.alloc(1),
                          gout.alloc(4 * size_t(s->nc))})
         if (x != hipSuccess) e = x;
-    if (e != hipSuccess) {
-        restore();
-        return fail(VSW_ENOMEM, "adjoint work memory");
-    }
+    if (e != hipSuccess) return fail(VSW_ENOMEM, "adjoint work memory");
     HIP_TRY(hipMemcpy(d_r.p, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemsetAsync(lam.p, 0, N * sizeof(Adj4), st));
     HIP_TRY(hipMemsetAsync(hbar.p, 0, N * sizeof(double), st));
@@ -899,7 +904,6 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
             HIP_TRY(hipMemcpyAsync(outs[q], gout.p + q * nc, size_t(nc) * sizeof(double),
                                    hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    restore();
     return VSW_OK;
 }
 
@@ -998,20 +1002,47 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
     HIP_TRY(save.alloc(bytes));
     void* wp = f32 ? (void*)s->d_wf.p : (void*)s->d_w.p;
     HIP_TRY(hipMemcpyAsync(save.p, wp, bytes, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
     const double t_save = s->t, dt_save = s->dt_last;
     const int64_t clamps_save = s->clamps;
     const std::vector<double> seg_t_save = s->seg_t, seg_dt_save = s->seg_dt;
     const std::vector<int64_t> seg_steps_save = s->seg_steps;
     const int variant_save = s->variant, xcd_save = s->xcd_order, occ_save = s->occupancy;
-    static const int kOcc[3] = {0, 3, 2};
     const bool graph_save = s->use_graph, prof_save = s->profiling;
+    static const int kOcc[3] = {0, 3, 2};
+    // On every return path: the state, time and logs as they were; the
+    // caller's launch configuration unless a winner was applied.
+    bool applied = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const auto restore_on_exit = on_exit([&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipMemcpyAsync(wp, save.p, bytes, hipMemcpyDeviceToDevice, st);
+        (void)hipStreamSynchronize(st);
+        s->t = t_save;
+        s->dt_last = dt_save;
+        s->clamps = clamps_save;
+        s->seg_t = seg_t_save;
+        s->seg_dt = seg_dt_save;
+        s->seg_steps = seg_steps_save;
+        s->seg_log.clear();
+        s->last_dts.clear();
+        s->gauge_eta.clear();
+        s->gauge_t.clear();
+        s->profiling = prof_save;
+        s->release_graph();
+        if (!applied) {
+            s->variant = variant_save;
+            s->xcd_order = xcd_save;
+            s->use_graph = graph_save;
+            s->occupancy = occ_save;
+        }
+    });
     s->profiling = false;
-    hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     double best = INFINITY;
     int best_c = 0;
-    int rc = VSW_OK;
     for (int c = 0; c < VSW_TUNE_CONFIGS; ++c) {
         const int variant = (c >> 2) & 1, xcd = (c >> 1) & 1, graph = c & 1, occ = kOcc[c / 8];
         double ms = INFINITY;
@@ -1022,19 +1053,18 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
             s->use_graph = graph != 0;
             s->release_graph();
             s->seg_t = seg_t_save;
-            rc = vsw_step(s, 2, INFINITY, nullptr, nullptr);  // warm-up (and graph capture)
-            if (rc == VSW_OK) {
-                HIP_TRY(hipEventRecord(e0, st));
-                rc = vsw_step(s, steps, INFINITY, nullptr, nullptr);
-                HIP_TRY(hipEventRecord(e1, st));
-                HIP_TRY(hipEventSynchronize(e1));
-                float f = 0.f;
-                HIP_TRY(hipEventElapsedTime(&f, e0, e1));
-                ms = double(f) / double(steps);
-            }
+            int rc = vsw_step(s, 2, INFINITY, nullptr, nullptr);  // warm-up (and graph capture)
+            if (rc != VSW_OK) return rc;
+            HIP_TRY(hipEventRecord(e0, st));
+            rc = vsw_step(s, steps, INFINITY, nullptr, nullptr);
+            if (rc != VSW_OK) return rc;
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float f = 0.f;
+            HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+            ms = double(f) / double(steps);
             HIP_TRY(hipMemcpyAsync(wp, save.p, bytes, hipMemcpyDeviceToDevice, st));
             HIP_TRY(hipStreamSynchronize(st));
-            if (rc != VSW_OK) break;
         }
         if (ms_per_step) ms_per_step[c] = ms;
         if (ms < best) {
@@ -1042,32 +1072,11 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
             best_c = c;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    // restore the state and apply the winner
-    s->t = t_save;
-    s->dt_last = dt_save;
-    s->clamps = clamps_save;
-    s->seg_t = seg_t_save;
-    s->seg_dt = seg_dt_save;
-    s->seg_steps = seg_steps_save;
-    s->seg_log.clear();
-    s->last_dts.clear();
-    s->gauge_eta.clear();
-    s->gauge_t.clear();
-    s->profiling = prof_save;
-    s->release_graph();
-    if (rc != VSW_OK) {
-        s->variant = variant_save;
-        s->xcd_order = xcd_save;
-        s->use_graph = graph_save;
-        s->occupancy = occ_save;
-        return rc;
-    }
     s->variant = (best_c >> 2) & 1;
     s->xcd_order = (best_c >> 1) & 1;
     s->use_graph = (best_c & 1) != 0;
     s->occupancy = kOcc[best_c / 8];
+    applied = true;
     if (chosen) *chosen = best_c;
     return VSW_OK;
 }

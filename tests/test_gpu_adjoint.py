@@ -186,3 +186,27 @@ def test_autograd_function_and_displacement_amplitudes():
             errs.append(abs(fd - float(a.grad[i])))
         say(f"amplitude {i}: autograd {float(a.grad[i]):.8e}, best |FD - autograd| {min(errs):.3e}")
         assert min(errs) <= 1e-6 * float(np.abs(direct).max())
+
+
+def test_adjoint_error_leaves_state():
+    """A forward run that goes unstable inside the adjoint call (a fixed dt
+    far above the CFL limit) is reported as EUNSTABLE, and the solver's
+    state, time and gauges are as they were before the call."""
+    c = W.thacker_case(23)
+    s = vsw.Solver.for_case(c, dt_fixed=0.2)
+    try:
+        vsw.vsw_set_gauges(s.h, np.array([5, 9], dtype=np.int32))
+        before = s.state()
+        obs = np.zeros((400, 2))
+        with pytest.raises(vsw.VswError, match="EUNSTABLE"):
+            vsw.vsw_adjoint_gauge_loss(s.h, c.nc, 400, 50, np.array([3], dtype=np.int32),
+                                       obs[:, :1])
+        after = s.state()
+        for a, b in zip(before, after):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        # the caller's two gauges are back: a step records two readings
+        s.step(1)
+        _, eta = vsw.vsw_get_gauges(s.h, 2)
+        assert eta.shape == (1, 2)
+    finally:
+        s.close()
