@@ -3,15 +3,18 @@ the 1M-triangle synthetic ocean basin, FP64, one MI355X (default), or on the
 12M-triangle coastal mesh in FP32 (--workload coastal).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                [--workload basin|coastal]
+                [--workload basin|coastal|ensemble|adjoint]
 
 Prints one JSON line.  value = cell-updates/s (one cell advanced by one full
 two-stage step) over the timed region, with the mesh and the state already
 resident in HBM; the other legs (FP32 on the basin; FP64 and random cell
 order on the coastal mesh) are reported beside it.  The roofline entry uses the dominant kernel's average
 launch duration from HIP events recorded on the solver's stream around each
-launch, in a second pass over the same number of steps.  cpu_baseline times
-the FP64 oracle (single thread) on a bounded sample of the same workload.
+launch, in a second pass over the same number of steps; beside the
+datasheet peak it carries copy_GBps, the bandwidth of a plain 1 GiB device
+copy measured in the same run.  cpu_baseline times the FP64 oracle (single
+thread) on a bounded sample of the same workload.  --workload ensemble
+reports ensemble runs/s, --workload adjoint the adjoint/forward time ratio.
 """
 from __future__ import annotations
 
@@ -81,6 +84,29 @@ def kernel_roofline(vsw, s, steps, nc, bytes1, bytes2):
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": dom, "alg_bytes_per_cell": per_cell,
             "avg_launch_us": round(dur_ms * 1e3, 2)}
+
+
+def copy_bandwidth(torch, dev):
+    """A STREAM-like device copy of 1 GiB (four times the 256 MB last-level
+    cache) on the current stream: read + write bytes per second of the best
+    of five, in GB/s -- the HBM bandwidth a plain kernel attains on this GPU,
+    reported beside the datasheet peak."""
+    n = 128 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * n * 8 / (best / 1e3) / 1e9, 1)
 
 
 def measured_traffic(workload, ordering, precision_name, kernel, cells):
@@ -193,6 +219,10 @@ def bench_ensemble(args, torch, vsw, W):
     legs["fp32"] = ensemble_leg(vsw.VSW_FP32, "ensemble fp32")
     if not args.no_fp64:
         legs["fp64"] = ensemble_leg(vsw.VSW_FP64, "ensemble fp64")
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"[bench] 1 GiB device copy: {copy_gbs:.1f} GB/s (read + write)")
+    for leg in legs.values():
+        leg["roofline"]["copy_GBps"] = copy_gbs
     # the same runs one scenario after another on the same GPU
     seq_ms = 0.0
     for c in cases:
@@ -418,6 +448,10 @@ def main():
         res[name] = leg
         torch.cuda.synchronize()
 
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"[bench] 1 GiB device copy: {copy_gbs:.1f} GB/s (read + write)")
+    for leg in res.values():
+        leg["roofline"]["copy_GBps"] = copy_gbs
     # The basin is quoted in FP64 (the plain method), the coastal mesh in FP32.
     main_leg = "fp32" if coastal and "fp32" in res else "fp64"
     if main_leg not in res:
