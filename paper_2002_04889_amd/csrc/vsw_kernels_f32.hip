@@ -132,7 +132,9 @@ __device__ __forceinline__ FaceF recon_face_f32(const ReconF& r, int j, double t
     f.h = r.fh[j];
     f.H = r.fH[j];
     if (r.fH[j] >= thr) {
-        const float rH = 1.0f / float(r.fH[j]);
+        // hardware reciprocal (1 ulp; this path is held to a tolerance):
+        // the face depth is at least H_thr here
+        const float rH = __builtin_amdgcn_rcpf(float(r.fH[j]));
         f.u = r.fu[j] * rH;
         f.v = r.fv[j] * rH;
     } else {
@@ -152,7 +154,8 @@ __device__ __forceinline__ void hll_face_f32(double g, double hg, double HL, flo
         f0 = 0.0f; f1 = 0.0; f2 = 0.0f;
         return;
     }
-    const float cL = sqrtf(float(g * HL)), cR = sqrtf(float(g * HR));
+    // hardware square root (1 ulp) of non-negative arguments
+    const float cL = __builtin_amdgcn_sqrtf(float(g * HL)), cR = __builtin_amdgcn_sqrtf(float(g * HR));
     float sL, sR;
     if (HL == 0.0) {
         sL = unR - 2.0f * cR;
