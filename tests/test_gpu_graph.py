@@ -149,6 +149,9 @@ def test_occupancy_caps_bitwise(precision):
     for occ in (0, 3, 2):
         s = vsw.Solver.for_case(c, precision=precision)
         try:
+            for bad in (1, 4, -1):
+                with pytest.raises(vsw.VswError, match="EINVAL"):
+                    vsw.vsw_set_occupancy(s.h, bad)
             vsw.vsw_set_occupancy(s.h, occ)
             s.step(25)
             out.append(s.state())

@@ -274,3 +274,32 @@ def test_gauges_record_each_step(orc, precision):
     if precision == vsw.VSW_FP64:
         o = orc_run(orc, c, 60)
         assert np.array_equal(e2[-1], o["H"][cells] - c.h[cells])
+
+
+@pytest.mark.parametrize("which", ["thacker", "basin"])
+def test_resume_from_saved_state(which):
+    """Save and resume: the state and time read back mid-run and loaded
+    into a fresh solver continue bitwise as the uninterrupted run (the
+    state is the whole of the scheme's memory; dt comes from it)."""
+    c = W.thacker_case(23) if which == "thacker" else W.basin_case(scale=16)
+    a = vsw.Solver.for_case(c)
+    try:
+        a.step(37)
+        H, HU, HV, t = a.state()
+        a.step(40)
+        ref = a.state()
+        ref_dts = vsw.vsw_dt_history(a.h)
+    finally:
+        a.close()
+    b = vsw.Solver.for_case(c)
+    try:
+        b.set_state(H, HU, HV, t)
+        b.step(40)
+        out = b.state()
+        dts = vsw.vsw_dt_history(b.h)
+    finally:
+        b.close()
+    assert out[3] == ref[3]
+    for x, y in zip(out[:3], ref[:3]):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    assert np.array_equal(dts, ref_dts)
