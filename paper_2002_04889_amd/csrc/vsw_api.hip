@@ -256,7 +256,7 @@ int vsw_create(const vsw_params* p, int device, vsw_solver** out) {
         return fail(VSW_EINVAL, "dt_fixed must be >= 0");
     if (p->precision != VSW_FP64 && p->precision != VSW_FP32)
         return fail(VSW_EINVAL, "unsupported precision");
-    if (p->ordering < VSW_ORDER_HILBERT || p->ordering > VSW_ORDER_RANDOM)
+    if (p->ordering < VSW_ORDER_HILBERT || p->ordering > VSW_ORDER_BISECTION)
         return fail(VSW_EINVAL, "unknown ordering");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
@@ -1117,7 +1117,7 @@ int vsw_prepare_mesh_host(int64_t nv, const double* vx, const double* vy, int64_
                           int64_t* nw) {
     HostMesh hm;
     std::string err;
-    int rc = build_host_mesh(nv, vx, vy, nc, tri, h, VSW_ORDER_NONE, 0, hm, err);
+    int rc = build_host_mesh(nv, vx, vy, nc, tri, h, VSW_ORDER_NONE, 0, kTile, hm, err);
     if (rc != VSW_OK) return fail(rc, err);
     for (int64_t i = 0; i < nc; ++i) {
         const int64_t k = hm.perm[i];

@@ -38,6 +38,36 @@ uint64_t hilbert16(uint32_t x, uint32_t y) {
     return d;
 }
 
+// Recursive coordinate bisection of the cells idx[lo, hi) by their
+// centroids: split at the median along the longer side of their bounding
+// box into floor(nt / 2) whole tiles and the rest (nt = tiles needed),
+// recursively, down to single tiles; the leaves in tree order (left first)
+// are the tiles, compact patches with fewer faces on their boundary than
+// runs of a space-filling curve.  Inside a leaf the cells follow `key`.
+void bisect(std::vector<int64_t>& idx, int64_t lo, int64_t hi, const std::vector<double>& cx,
+            const std::vector<double>& cy, const std::vector<uint64_t>& key, int64_t tile) {
+    const int64_t n = hi - lo;
+    if (n <= tile) {
+        std::sort(idx.begin() + lo, idx.begin() + hi,
+                  [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+        return;
+    }
+    const int64_t nt = (n + tile - 1) / tile;
+    const int64_t nl = (nt / 2) * tile;
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t k = idx[i];
+        x0 = std::min(x0, cx[k]); x1 = std::max(x1, cx[k]);
+        y0 = std::min(y0, cy[k]); y1 = std::max(y1, cy[k]);
+    }
+    const std::vector<double>& c = (x1 - x0 >= y1 - y0) ? cx : cy;
+    // ties broken by the cell index: a strict order, so the split is unique
+    std::nth_element(idx.begin() + lo, idx.begin() + lo + nl, idx.begin() + hi,
+                     [&](int64_t a, int64_t b) { return c[a] < c[b] || (c[a] == c[b] && a < b); });
+    bisect(idx, lo, lo + nl, cx, cy, key, tile);
+    bisect(idx, lo + nl, hi, cx, cy, key, tile);
+}
+
 uint64_t splitmix64(uint64_t& st) {
     uint64_t z = (st += 0x9E3779B97F4A7C15ull);
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -49,7 +79,7 @@ uint64_t splitmix64(uint64_t& st) {
 
 int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
                     const int32_t* tri_in, const double* h_in, int ordering,
-                    uint64_t seed, HostMesh& out, std::string& err) {
+                    uint64_t seed, int tile, HostMesh& out, std::string& err) {
     char buf[256];
     if (nv <= 0 || nc <= 0 || !vx || !vy || !tri_in || !h_in) {
         err = "empty mesh or NULL array";
@@ -89,7 +119,7 @@ int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
     // 2. internal order
     std::vector<int64_t> perm(nc);
     std::iota(perm.begin(), perm.end(), int64_t(0));
-    if (ordering == VSW_ORDER_HILBERT) {
+    if (ordering == VSW_ORDER_HILBERT || ordering == VSW_ORDER_BISECTION) {
         std::vector<double> cx(nc), cy(nc);
         double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
         for (int64_t k = 0; k < nc; ++k) {
@@ -107,8 +137,12 @@ int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
             uint32_t qy = uint32_t(std::min(65535.0, std::max(0.0, (cy[k] - y0) * sc)));
             key[k] = (hilbert16(qx, qy) << 32) | uint64_t(k);
         }
-        std::sort(key.begin(), key.end());
-        for (int64_t i = 0; i < nc; ++i) perm[i] = int64_t(key[i] & 0xFFFFFFFFull);
+        if (ordering == VSW_ORDER_BISECTION && tile > 0) {
+            bisect(perm, 0, nc, cx, cy, key, tile);
+        } else {
+            std::sort(key.begin(), key.end());
+            for (int64_t i = 0; i < nc; ++i) perm[i] = int64_t(key[i] & 0xFFFFFFFFull);
+        }
     } else if (ordering == VSW_ORDER_RANDOM) {
         uint64_t st = seed;
         for (int64_t i = nc - 1; i > 0; --i) {
@@ -330,7 +364,7 @@ int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* 
     HostMesh& hm = out.hm;
     TileMapHost& tm = out.tiles;
     if (nseg == 1) {  // one mesh: no copy
-        int rc = build_host_mesh(nv[0], vx, vy, nc[0], tri, h, ordering, seed, hm, err);
+        int rc = build_host_mesh(nv[0], vx, vy, nc[0], tri, h, ordering, seed, tile, hm, err);
         if (rc) return rc;
         build_tiles(hm, tile, tm);
     } else {
@@ -350,7 +384,8 @@ int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* 
         for (int s = 0; s < nseg; ++s) {
             HostMesh p;
             int rc = build_host_mesh(nv[s], vx + vo, vy + vo, nc[s], tri + 3 * out.coff[s],
-                                     h + out.coff[s], ordering, seed + uint64_t(s), p, err);
+                                     h + out.coff[s], ordering, seed + uint64_t(s), tile, p,
+                                     err);
             if (rc) {
                 err = "scenario " + std::to_string(s) + ": " + err;
                 return rc;

@@ -78,9 +78,10 @@ int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* 
                    const int64_t* nc, const int32_t* tri, const double* h, int ordering,
                    uint64_t seed, int tile, EnsembleMesh& out, std::string& err);
 
-// Returns 0 or a VSW_E* code with a message in err.
+// Returns 0 or a VSW_E* code with a message in err.  tile: the tile size the
+// bisection ordering cuts the mesh into.
 int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
                     const int32_t* tri, const double* h, int ordering, uint64_t seed,
-                    HostMesh& out, std::string& err);
+                    int tile, HostMesh& out, std::string& err);
 
 }  // namespace vsw

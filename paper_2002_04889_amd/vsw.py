@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "vsw.h")
 VSW_OK, VSW_EINVAL, VSW_EMESH, VSW_ESTATE, VSW_ENOMEM, VSW_EDEVICE, VSW_EUNSTABLE = \
     0, -1, -2, -3, -4, -5, -6
 VSW_FP64, VSW_FP32 = 0, 1
-VSW_ORDER_HILBERT, VSW_ORDER_NONE, VSW_ORDER_RANDOM = 0, 1, 2
+VSW_ORDER_HILBERT, VSW_ORDER_NONE, VSW_ORDER_RANDOM, VSW_ORDER_BISECTION = 0, 1, 2, 3
 VSW_KERNEL_FUSED, VSW_KERNEL_TWO_PASS = 0, 1
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM",
                -5: "EDEVICE", -6: "EUNSTABLE"}

@@ -108,7 +108,8 @@ def test_random_order_fused_matches_two_pass():
         assert np.array_equal(a[k], b[k]), k
 
 
-@pytest.mark.parametrize("ordering", [vsw.VSW_ORDER_NONE, vsw.VSW_ORDER_RANDOM])
+@pytest.mark.parametrize("ordering", [vsw.VSW_ORDER_NONE, vsw.VSW_ORDER_RANDOM,
+                                      vsw.VSW_ORDER_BISECTION])
 def test_orderings_bitwise(ordering):
     c = W.basin_case(scale=16)
     a = gpu_run(c, 100)
