@@ -116,6 +116,7 @@ struct vsw_solver {
     DevBuf<Nbr4> d_nbr;            // neighbour slots per cell
     DevBuf<double> d_geom, d_area, d_perim, d_h;
     DevBuf<RGeom> d_rgeom;         // reconstruction geometry records
+    DevBuf<RGeomF> d_rgeomf;       // the same in FP32 (FP32 solvers)
     DevBuf<Cell4> d_w;             // w^n records (H, HU, HV, h), FP64 solver
     DevBuf<Cell4> d_w1;            // stage-1 records, FP64 solver
     DevBuf<CellF> d_wf;            // w^n records (h, eta, Hu, Hv), FP32 solver
@@ -166,6 +167,7 @@ struct vsw_solver {
         release_graph();
         d_perm.release(); d_nbr.release(); d_geom.release(); d_area.release();
         d_rgeom.release();
+        d_rgeomf.release();
         d_perim.release(); d_h.release(); d_w.release(); d_w1.release();
         d_wf.release(); d_w1f.release();
         d_face.release(); d_sc.release(); d_order.release(); d_tmp.release();
@@ -212,6 +214,7 @@ struct vsw_solver {
         m.nbr = d_nbr.p;
         m.geom = d_geom.p;
         m.rgeom = d_rgeom.p;
+        m.rgeomf = d_rgeomf.p;
         m.area = d_area.p;
         m.perim = d_perim.p;
         return m;
@@ -357,6 +360,18 @@ int upload_assembled(vsw_solver* s, EnsembleMesh& em) {
             }
         HIP_TRY(s->d_rgeom.alloc(n));
         HIP_TRY(hipMemcpy(s->d_rgeom.p, rg.data(), n * sizeof(RGeom), hipMemcpyHostToDevice));
+        if (s->prm.precision == VSW_FP32) {
+            // rounded to nearest here, as the kernel would round each value
+            std::vector<RGeomF> rf(n);
+            for (size_t i = 0; i < n; ++i)
+                for (int q = 0; q < 6; ++q) {
+                    rf[i].w[q] = float(rg[i].w[q]);
+                    rf[i].d[q] = float(rg[i].d[q]);
+                }
+            HIP_TRY(s->d_rgeomf.alloc(n));
+            HIP_TRY(hipMemcpy(s->d_rgeomf.p, rf.data(), n * sizeof(RGeomF),
+                              hipMemcpyHostToDevice));
+        }
     }
     HIP_TRY(hipMemcpy(s->d_perim.p, hm.perim.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->d_h.p, hm.h.data(), n * sizeof(double), hipMemcpyHostToDevice));

@@ -67,11 +67,11 @@ __device__ __forceinline__ void recon_core_f32(const DevMesh& m, const CellF* __
     r.Hk = Hk;
     r.hk = hk;
     if (cand) {
-        const RGeom rg = m.rgeom[k];
-        const float wx0 = float(rg.w[0]), wx1 = float(rg.w[2]), wx2 = float(rg.w[4]);
-        const float wy0 = float(rg.w[1]), wy1 = float(rg.w[3]), wy2 = float(rg.w[5]);
-        const float dxs[3] = {float(rg.d[0]), float(rg.d[2]), float(rg.d[4])};
-        const float dys[3] = {float(rg.d[1]), float(rg.d[3]), float(rg.d[5])};
+        const RGeomF rg = m.rgeomf[k];
+        const float wx0 = rg.w[0], wx1 = rg.w[2], wx2 = rg.w[4];
+        const float wy0 = rg.w[1], wy1 = rg.w[3], wy2 = rg.w[5];
+        const float dxs[3] = {rg.d[0], rg.d[2], rg.d[4]};
+        const float dys[3] = {rg.d[1], rg.d[3], rg.d[5]};
         auto project = [&](const float* qs, float q0, float* pj) {
             const float d0 = qs[0] - q0, d1 = qs[1] - q0, d2 = qs[2] - q0;
             const float gx = wx0 * d0 + wx1 * d1 + wx2 * d2;
