@@ -89,10 +89,12 @@ def test_coastal_against_oracle(coast, orc):
 def test_coastal_fp32_1000_steps(coast):
     """The workload's run (1000 steps): FP32 state against the FP64 kernel at
     the same end time, with the FP64 scheme's response to FP32-sized input
-    noise as the cellwise allowance; mass conserved in both.  The FP32
-    solver's mass is taken from its own initial state: a dry cell holds
-    eta = -h rounded up to FP32, so its depth reads back as a few ulp of h
-    (a fixed offset of about 6e-10 of the total here, not a drift)."""
+    noise as the cellwise allowance.  Mass: conserved to 1e-12 in FP64; in
+    FP32 within the rounding of the stored surface (at most one ulp of each
+    cell's eta per stage).  The FP32 solver's mass is taken from its own
+    initial state: a dry cell holds eta = -h rounded up to FP32, so its depth
+    reads back as a few ulp of h (a fixed offset of about 6e-10 of the total
+    here, not a drift)."""
     d = gpu_state(coast, 1000)
     g = gpu_state(coast, 4000, vsw.VSW_FP32, t_stop=d["t"])
     rng = np.random.default_rng(0)
@@ -113,8 +115,20 @@ def test_coastal_fp32_1000_steps(coast):
     x0, y0 = coast.vx[coast.tri], coast.vy[coast.tri]
     area = 0.5 * np.abs((x0[:, 1] - x0[:, 0]) * (y0[:, 2] - y0[:, 0])
                         - (x0[:, 2] - x0[:, 0]) * (y0[:, 1] - y0[:, 0]))
-    for r in (d, g):
+    for r, fp32 in ((d, False), (g, True)):
         m0, m1 = (area * r["H0"]).sum(), (area * r["H"]).sum()
-        say(f"mass rel change {(m1 - m0) / m0:.3e} (initial offset of the stored state "
-            f"{((area * r['H0']).sum() - (area * coast.H).sum()) / m0:.3e})")
-        assert abs(m1 - m0) <= 1e-12 * m0
+        if fp32:
+            # Each stage stores every cell's surface eta rounded to FP32
+            # (nearest; a dry cell's upward), which moves that cell's water
+            # by at most one ulp of its surface: over the run's stages the
+            # total moves by at most sum_K |K| ulp(eta_K) per stage, with
+            # |eta_K| bounded by its initial and final values and by the
+            # uplift's 3 m crest.
+            e0, e1 = np.abs(r["H0"] - coast.h), np.abs(r["H"] - coast.h)
+            emax = np.maximum(np.maximum(e0, e1), 3.0).astype(np.float32)
+            bound = 2 * r["steps"] * (area * np.spacing(emax).astype(np.float64)).sum()
+        else:
+            bound = 1e-12 * m0
+        say(f"mass rel change {(m1 - m0) / m0:.3e}, bound {bound / m0:.1e} (initial offset of "
+            f"the stored state {((area * r['H0']).sum() - (area * coast.H).sum()) / m0:.3e})")
+        assert abs(m1 - m0) <= bound
