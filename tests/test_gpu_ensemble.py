@@ -153,3 +153,57 @@ def test_single_scenario_ensemble_equals_mesh_upload(cases):
     a = run_solo(c, 50)
     rc, done, t, ens = run_ensemble([c], 50)
     assert same(ens[0], a)
+
+
+@pytest.fixture(scope="module")
+def full_cases():
+    """The benchmark's ensemble at full size (about 25 s to generate)."""
+    cases, _ = W.ensemble_cases()
+    say("full ensemble:", len(cases), "scenarios,", sum(c.nc for c in cases), "cells")
+    return cases
+
+
+@pytest.mark.parametrize("precision", [vsw.VSW_FP32, vsw.VSW_FP64], ids=["fp32", "fp64"])
+def test_full_ensemble_in_bench_configuration(full_cases, precision, orc):
+    """The ensemble workload at full size (64 scenarios, 50k-500k triangles,
+    12M in all) in the launch configuration the autotuner picks, as the
+    benchmark times it: the smallest, a middle and the largest scenario
+    equal their solo runs bit for bit after 50 steps, and (FP64) the
+    smallest matches the oracle within 1e-12."""
+    cases = full_cases
+    n = 50
+    s = vsw.Solver.for_ensemble(cases, precision=precision)
+    try:
+        chosen, _ = vsw.vsw_autotune(s.h, 10)
+        say(f"precision {precision}: autotuner chose {vsw.tune_config_name(chosen)}")
+        rc, done, t = s.step(n, check=False)
+        assert rc == 0 and done == n
+        H, HU, HV, _ = s.state()
+        ts, dts, steps = vsw.vsw_scenario_status(s.h)
+        hist = {i: vsw.vsw_scenario_dt_history(s.h, i) for i in range(len(cases))}
+    finally:
+        s.close()
+    off = np.concatenate([[0], np.cumsum([c.nc for c in cases])])
+    sizes = np.array([c.nc for c in cases])
+    picks = [int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), int(np.argmax(sizes))]
+    for i in picks:
+        c = cases[i]
+        sl = slice(off[i], off[i + 1])
+        e = {"H": H[sl], "HU": HU[sl], "HV": HV[sl], "t": ts[i], "steps": steps[i],
+             "dts": hist[i]}
+        solo = run_solo(c, n, precision)
+        assert solo["rc"] == 0 and same(e, solo), (i, c.nc)
+        say(f"scenario {i} ({c.nc} cells): ensemble == solo run, t {e['t']:.3f} s")
+    if precision == vsw.VSW_FP64:
+        i = picks[0]
+        c = cases[i]
+        m = orc.Mesh.from_case(c)
+        o = m.run(orc.params(g=c.g, cfl=c.cfl, h_threshold=c.h_threshold), c.H, c.HU, c.HV,
+                  0.0, n, check=False)
+        sl = slice(off[i], off[i + 1])
+        bitwise = True
+        for k, v in (("H", H), ("HU", HU), ("HV", HV)):
+            scale = max(np.abs(o[k]).max(), 1e-300)
+            assert np.abs(v[sl] - o[k]).max() <= 1e-12 * scale, k
+            bitwise = bitwise and np.array_equal(v[sl], o[k])
+        say(f"scenario {i}: ensemble vs oracle after {n} steps within 1e-12, bitwise {bitwise}")
