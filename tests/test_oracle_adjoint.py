@@ -47,17 +47,24 @@ def test_steps_equal_c_oracle(orc, which):
         assert np.array_equal(v.numpy(), r[k]), k
 
 
-def generic_basin(scale=32, seed=1):
+def generic_basin(scale=32, seed=1, rough_bed=0.0):
     """The basin with random depth (0-1 m), bed (0-1 m) and momentum
     (+-1 m^2/s) noise on its wet cells: no two values tie in the CFL
     minimum, a limiter's max/min or the hydrostatic reconstruction's
     min(h_L, h_R), where the scheme is only one-sided differentiable (the
-    plain basin's flat abyss at rest is full of such ties)."""
+    plain basin's flat abyss at rest is full of such ties).  rough_bed > 0
+    adds that much more bed noise (0 to rough_bed m) with the surface kept,
+    so neighbouring depths stay apart by more than a bed perturbation moves
+    them (fine meshes)."""
     c = W.basin_case(scale=scale)
     rng = np.random.default_rng(seed)
     wet = c.H > 10.0
     c.h = c.h + wet * rng.uniform(0.0, 1.0, c.nc)
     c.H = c.H + wet * rng.uniform(0.0, 1.0, c.nc)
+    if rough_bed > 0.0:
+        b = wet * rng.uniform(0.0, rough_bed, c.nc)
+        c.h = c.h + b
+        c.H = c.H + b
     c.HU = wet * rng.uniform(-1.0, 1.0, c.nc)
     c.HV = wet * rng.uniform(-1.0, 1.0, c.nc)
     return c
