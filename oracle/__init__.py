@@ -17,8 +17,11 @@ _SRC = os.path.join(_HERE, "vsw_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # -ffp-contract=off: no fused multiply-add, one rounding per operation in
-# the order the source writes it.
-CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+# the order the source writes it.  -fopenmp: the cell and face loops may run
+# on several threads, with bitwise the same results for any thread count.
+# No -march=native: the library is compiled on one host and may be loaded on
+# another (the GPU host), whose CPU may lack the build host's extensions.
+CFLAGS = ["-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-Wall", "-Wextra"]
 
 
@@ -66,11 +69,22 @@ def lib():
                               _dp, _dp]
         L.orc_dt.restype = ctypes.c_double
         L.orc_dt.argtypes = [ctypes.c_void_p, ctypes.POINTER(OrcParams), _dp, _dp, _dp]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
         L.orc_run.restype = ctypes.c_int
         L.orc_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(OrcParams), _dp, _dp, _dp, _dp,
                               ctypes.c_int64, ctypes.c_double, _lp, _dp, _lp]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _d(a):

@@ -4,21 +4,22 @@ TEST INFRASTRUCTURE ONLY: the tests use it for the tape-based gradient
 (torch.autograd) that the GPU library's hand-written discrete adjoint is
 checked against.  The GPU library never imports it.
 
-It restates, cell by cell and vectorised over the mesh, the same method as
-vsw_oracle.c (pinned against it in tests/test_oracle_adjoint.py), on the
-connectivity and geometry that the C oracle builds:
+It restates the method of vsw_oracle.c in the same order of work (pinned
+bit for bit against it in tests/test_oracle_adjoint.py), vectorised over the
+mesh, on the connectivity and geometry that the C oracle builds:
   Section 2.1  w = (H, Hu, Hv), eta = H - h
   Section 2.2  HLL flux with the two-rarefaction speeds u*, c*; dry-bed speeds
   Section 2.3  SSP-RK(2,2) with the CFL time step (reading of the CFL rule)
-  Section 2.4  least-squares gradients, Barth-Jespersen limiter, eq. (3),
-               threshold depth H_thr
+  Section 2.4  least-squares gradients, Barth-Jespersen limiter (one ratio
+               per face, the minimum over the faces), eq. (3), threshold
+               depth H_thr
   Section 2.5  wall ghosts
-with the hydrostatic reconstruction of the bed source.  Branches (wet/dry,
-upwind choice, limiter, min/max) are `torch.where` selections made on the
-values, so the tape differentiates the branch that the forward takes.  The
-Barth-Jespersen factor is written as min(1, (q_max - q_0) / max_j d_j,
-(q_min - q_0) / min_j d_j), which equals the per-face minimum of the
-limiter's definition (the ratio is monotone in d_j).
+with the hydrostatic reconstruction of the bed source: a cell pass for the
+reconstruction, one flux per face in canonical orientation whose two side
+terms are handed to the face's cells, and a cell pass that sums each cell's
+three faces in local order.  Branches (wet/dry, upwind choice, limiter,
+min/max) are `torch.where` selections made on the values, so the tape
+differentiates the branch that the forward takes.
 """
 from __future__ import annotations
 
@@ -90,6 +91,24 @@ class Geometry:
                 hit = (nbr[n, q] == rows) & (nbr[:, j] >= 0)
                 jn[hit, j] = q
         self.jn = torch.tensor(jn)
+        # faces in canonical orientation: the left side (a wall's only side)
+        # and, for interior faces, the right side
+        isl = np.asarray(g["is_left"]) != 0
+        kl, jl = np.nonzero(isl)
+        self.ekl, self.ejl = torch.tensor(kl), torch.tensor(jl)
+        ew = nbr[kl, jl] < 0
+        self.ewall = torch.tensor(ew)
+        kr = np.where(ew, kl, nbr[kl, jl])
+        jr = np.where(ew, jl, jn[kl, jl])
+        self.ekr, self.ejr = torch.tensor(kr), torch.tensor(jr)
+        # slot 3 k + j of every side term: left sides, then interior right
+        # sides; inv puts them back in (cell, face) order
+        slot = np.concatenate([3 * kl + jl, (3 * kr + jr)[~ew]])
+        assert len(slot) == 3 * self.nc and len(np.unique(slot)) == 3 * self.nc
+        inv = np.empty_like(slot)
+        inv[slot] = np.arange(len(slot))
+        self.side_inv = torch.tensor(inv)
+        self.isl = torch.tensor(isl)
 
 
 def hll(g, HL, unL, utL, HR, unR, utR):
@@ -114,10 +133,9 @@ def hll(g, HL, unL, utL, HR, unR, utR):
     star = ~(upL | upR | both_dry)
     den = sR - sL
     sLR = sL * sR
-    rd = _where_div(star, torch.ones_like(den), den)
     out = []
     for c in range(3):
-        fs = ((sR * fL[c] - sL * fR[c]) + sLR * dU[c]) * rd
+        fs = _where_div(star, (sR * fL[c] - sL * fR[c]) + sLR * dU[c], den)
         f = torch.where(upL, fL[c], torch.where(upR, fR[c], fs))
         out.append(torch.where(both_dry, torch.zeros_like(f), f))
     return out
@@ -144,22 +162,22 @@ def reconstruct(G: Geometry, H, HU, HV, h, thr):
         return gx[:, None] * G.dx + gy[:, None] * G.dy
 
     def limiter(q0, qs, pj):
+        # Barth-Jespersen: per face j the largest phi_j in [0, 1] that keeps
+        # the face value inside [q_min, q_max]; alpha = min_j phi_j
         qmax, qmin = q0, q0
         for j in range(3):
             qmax = _vmax(qmax, qs[:, j])
             qmin = _vmin(qmin, qs[:, j])
         up, dn = qmax - q0, qmin - q0
-        dpm = torch.zeros_like(q0)
-        dnm = torch.zeros_like(q0)
-        for j in range(3):
-            dpm = _vmax(dpm, pj[:, j])
-            dnm = _vmin(dnm, pj[:, j])
         one = torch.ones_like(q0)
-        c1 = (dpm > 0.0) & (up < dpm)
-        a = torch.where(c1, _where_div(c1, up, dpm), one)
-        c2 = (dnm < 0.0) & (dn > dnm)
-        r2 = _where_div(c2, dn, dnm)
-        return torch.where(c2, _vmin(a, r2), a)
+        a = one
+        for j in range(3):
+            d = pj[:, j]
+            dp, dm = d > 0.0, d < 0.0
+            phi = torch.where(dp, _vmin(one, _where_div(dp, up, d)),
+                              torch.where(dm, _vmin(one, _where_div(dm, dn, d)), one))
+            a = _vmin(a, phi)
+        return a
 
     pe, pu, pv, ph = project(qe, e), project(qu, HU), project(qv, HV), project(qh, h)
     ae, au, av = limiter(e, qe, pe), limiter(HU, qu, pu), limiter(HV, qv, pv)
@@ -176,9 +194,8 @@ def reconstruct(G: Geometry, H, HU, HV, h, thr):
     fh = torch.where(s, fh2, h[:, None].expand(-1, 3))
     fH = torch.where(s, fH2, H[:, None].expand(-1, 3))
     wet = fH >= thr
-    rH = _where_div(wet, torch.ones_like(fH), fH)
-    u = fu * rH
-    v = fv * rH
+    u = _where_div(wet, fu, fH)
+    v = _where_div(wet, fv, fH)
     return (fe, fh, fH, u, v), second
 
 
@@ -186,55 +203,50 @@ def residual(G: Geometry, H, HU, HV, h, g, thr):
     """R(w) = (-sum_j +-l_j G_j + S_c) / |K| per cell (Sections 2.2, 2.4)."""
     hg = 0.5 * g
     (fe, fh, fH, u, v), second = reconstruct(G, H, HU, HV, h, thr)
-    nb, jn, wall = G.nb, G.jn, G.wall
-    own = (fe, fh, fH, u, v)
-    oth = tuple(torch.where(wall, x, x[nb, jn]) for x in own)
-    left = G.left
-    pick = lambda a, b: (torch.where(left, a, b), torch.where(left, b, a))
-    eL, eR = pick(fe, oth[0])
-    hL, hR = pick(fh, oth[1])
-    HL, HR = pick(fH, oth[2])
-    uL, uR = pick(u, oth[3])
-    vL, vR = pick(v, oth[4])
-    nx = torch.where(left, G.nx, -G.nx)
-    ny = torch.where(left, G.ny, -G.ny)
+    # one flux per face, canonical orientation (n from left to right)
+    kl, jl, kr, jr, wall = G.ekl, G.ejl, G.ekr, G.ejr, G.ewall
+    nx, ny, ln = G.nx[kl, jl], G.ny[kl, jl], G.len[kl, jl]
+    eL, hL, HL, uL, vL = fe[kl, jl], fh[kl, jl], fH[kl, jl], u[kl, jl], v[kl, jl]
+    eR, hR, HR, uR, vR = fe[kr, jr], fh[kr, jr], fH[kr, jr], u[kr, jr], v[kr, jr]
     unL, utL = uL * nx + vL * ny, vL * nx - uL * ny
     unR, utR = uR * nx + vR * ny, vR * nx - uR * ny
-    hs = _vmin(hL, hR)
-    zero = torch.zeros_like(hs)
+    zero = torch.zeros_like(hL)
+    # a wall's ghost mirrors the left state in the face frame (Section 2.5)
+    hs = torch.where(wall, hL, _vmin(hL, hR))
     HsL = torch.where(eL + hs > 0.0, eL + hs, zero)
-    HsR = torch.where(eR + hs > 0.0, eR + hs, zero)
+    HsR = torch.where(wall, HsL, torch.where(eR + hs > 0.0, eR + hs, zero))
     unR = torch.where(wall, -unL, unR)
+    utR = torch.where(wall, utL, utR)
     f0, f1, f2 = hll(g, HsL, unL, utL, HsR, unR, utR)
-    pc = torch.where(left, hg * (HL * HL - HsL * HsL), hg * (HR * HR - HsR * HsR))
+    pcL = hg * (HL * HL - HsL * HsL)
+    pcR = hg * (HR * HR - HsR * HsR)
+    phi0 = f0
     phi1 = f1 * nx - f2 * ny
     phi2 = f1 * ny + f2 * nx
-    t0 = G.len * f0
-    t1 = G.len * (phi1 + pc * nx)
-    t2 = G.len * (phi2 + pc * ny)
-    sgn = lambda t: torch.where(left, -t, t)
-    a0 = torch.zeros_like(H)
-    a1 = torch.zeros_like(H)
-    a2 = torch.zeros_like(H)
+    tl = (ln * phi0, ln * (phi1 + pcL * nx), ln * (phi2 + pcL * ny))
+    tr = (ln * phi0, ln * (phi1 + pcR * nx), ln * (phi2 + pcR * ny))
+    inner = ~wall
+    # side terms back in (cell, face) order: [nc, 3] per component
+    term = [torch.cat([tl[c], tr[c][inner]])[G.side_inv].reshape(-1, 3) for c in range(3)]
+    # each cell sums its faces in local order: minus on its left faces
+    acc = [torch.zeros_like(H) for _ in range(3)]
     for j in range(3):
-        a0 = a0 + sgn(t0)[:, j]
-        a1 = a1 + sgn(t1)[:, j]
-        a2 = a2 + sgn(t2)[:, j]
+        lj = G.isl[:, j]
+        for c in range(3):
+            acc[c] = torch.where(lj, acc[c] - term[c][:, j], acc[c] + term[c][:, j])
     c = (G.len * (H[:, None] + fH)) * (fh - h[:, None])
     sx = (c[:, 0] * G.nx[:, 0] + c[:, 1] * G.nx[:, 1]) + c[:, 2] * G.nx[:, 2]
     sy = (c[:, 0] * G.ny[:, 0] + c[:, 1] * G.ny[:, 1]) + c[:, 2] * G.ny[:, 2]
-    a1 = torch.where(second, a1 + hg * sx, a1)
-    a2 = torch.where(second, a2 + hg * sy, a2)
-    ra = 1.0 / G.area
-    return a0 * ra, a1 * ra, a2 * ra
+    a1 = torch.where(second, acc[1] + hg * sx, acc[1])
+    a2 = torch.where(second, acc[2] + hg * sy, acc[2])
+    return acc[0] / G.area, a1 / G.area, a2 / G.area
 
 
 def cfl_dt(G: Geometry, H, HU, HV, g, thr, cfl):
     """dt = CFL min over wet cells of |K| / (P_K (|u| + sqrt(g H)))."""
     wet = H >= thr
-    rH = _where_div(wet, torch.ones_like(H), H)
-    u = HU * rH
-    v = HV * rH
+    u = _where_div(wet, HU, H)
+    v = _where_div(wet, HV, H)
     # |u| is taken with a zero derivative at rest (u = v = 0)
     s = _ssqrt(u * u + v * v, (u * u + v * v) > 0.0) + _ssqrt(g * H, wet)
     r = torch.where(wet, G.area / (G.perim * torch.where(wet, s, torch.ones_like(s))),

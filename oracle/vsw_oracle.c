@@ -17,12 +17,17 @@
  * of the repository; each one is named at its use below (hydrostatic
  * reconstruction, dry-bed speeds, CFL formula, ...).
  *
- * Build: gcc -O2 -ffp-contract=off -fno-fast-math (no FMA contraction, so
- * every operation is one IEEE-754 rounding in the order written).
+ * Build: gcc -O3 -fopenmp -ffp-contract=off -fno-fast-math (no FMA
+ * contraction, so every operation is one IEEE-754 rounding in the order
+ * written).  OpenMP splits only loops whose iterations are independent (one
+ * cell or one face per iteration, each writing its own outputs), plus the
+ * exact min and integer-count reductions, so every result is bitwise the
+ * same for any thread count.
  */
 #include "vsw_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -206,6 +211,7 @@ orc_mesh *orc_mesh_build(int64_t nv, const double *vx, const double *vy,
     free(he);
 
     /* Geometry (Section 2.4: cell centre x_0, face centre x_f). */
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < nc; ++k) {
         const int32_t *t = m->tri + 3 * k;
         double x0 = m->vx[t[0]], x1 = m->vx[t[1]], x2 = m->vx[t[2]];
@@ -231,6 +237,7 @@ orc_mesh *orc_mesh_build(int64_t nv, const double *vx, const double *vy,
      * M = sum_j delta_j delta_j^T, written as sum_j w_j (q_Sj - q_K),
      * w_j = M^-1 delta_j.  delta_j runs from the centroid to the neighbour
      * centroid, or to the wall ghost: the centroid mirrored in the face. */
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < nc; ++k) {
         double ddx[3], ddy[3];
         for (int j = 0; j < 3; ++j) {
@@ -324,10 +331,10 @@ static void hll_face_frame(double g, double HL, double unL, double utL,
     } else if (sR < 0.0) {
         f[0] = fR[0]; f[1] = fR[1]; f[2] = fR[2];
     } else {
-        /* the star flux over (s_R - s_L), taken as one reciprocal */
-        double den = sR - sL, sLR = sL * sR, rd = 1.0 / den;
+        /* the star flux of Section 2.2 over (s_R - s_L) */
+        double den = sR - sL, sLR = sL * sR;
         for (int c = 0; c < 3; ++c)
-            f[c] = ((sR * fL[c] - sL * fR[c]) + sLR * (wR[c] - wL[c])) * rd;
+            f[c] = ((sR * fL[c] - sL * fR[c]) + sLR * (wR[c] - wL[c])) / den;
     }
 }
 
@@ -464,9 +471,8 @@ static void recon_cell(const orc_mesh *m, const orc_params *p, const double *H,
             f[1] = fq[3][j];
             f[2] = fH[j];
             if (fH[j] >= thr) {
-                double rH = 1.0 / fH[j];
-                f[3] = fq[1][j] * rH;
-                f[4] = fq[2][j] * rH;
+                f[3] = fq[1][j] / fH[j];
+                f[4] = fq[2][j] / fH[j];
             } else {
                 f[3] = 0.0;
                 f[4] = 0.0;
@@ -503,6 +509,7 @@ static void recon_cell(const orc_mesh *m, const orc_params *p, const double *H,
 void orc_reconstruct(const orc_mesh *m, const orc_params *p, const double *H,
                      const double *HU, const double *HV, double *grad,
                      double *alpha, int32_t *order, double *face) {
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < m->nc; ++k) {
         int o;
         recon_cell(m, p, H, HU, HV, k, face, grad, alpha, &o, NULL);
@@ -522,11 +529,13 @@ void orc_residual(const orc_mesh *m, const orc_params *p, const double *H,
     double *term = (double *)malloc(sizeof(double) * 9 * nc); /* per face side */
 
     /* 1. cell loop: reconstruction */
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < nc; ++k)
         recon_cell(m, p, H, HU, HV, k, face, NULL, NULL, &ord[k], sc + 2 * k);
 
     /* 2. edge loop: one flux per face in canonical orientation; each side
      *    keeps l * (phi + (0, p_side n)) */
+#pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < m->ne; ++e) {
         int32_t kl = m->ecell[2 * e], jl = m->eface[2 * e];
         int32_t kr = m->ecell[2 * e + 1], jr = m->eface[2 * e + 1];
@@ -550,6 +559,7 @@ void orc_residual(const orc_mesh *m, const orc_params *p, const double *H,
 
     /* 3. cell loop: gather the three faces in local order, add the source,
      *    divide by the area */
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < nc; ++k) {
         double acc[3] = {0.0, 0.0, 0.0};
         for (int j = 0; j < 3; ++j) {
@@ -568,10 +578,9 @@ void orc_residual(const orc_mesh *m, const orc_params *p, const double *H,
             acc[1] = acc[1] + sc[2 * k];
             acc[2] = acc[2] + sc[2 * k + 1];
         }
-        double ra = 1.0 / m->area[k];
-        RH[k] = acc[0] * ra;
-        RHU[k] = acc[1] * ra;
-        RHV[k] = acc[2] * ra;
+        RH[k] = acc[0] / m->area[k];
+        RHU[k] = acc[1] / m->area[k];
+        RHV[k] = acc[2] / m->area[k];
     }
     free(face); free(sc); free(ord); free(term);
 }
@@ -583,9 +592,11 @@ void orc_residual(const orc_mesh *m, const orc_params *p, const double *H,
 double orc_dt(const orc_mesh *m, const orc_params *p, const double *H,
               const double *HU, const double *HV) {
     double rmin = INFINITY;
+    /* the minimum of a set does not depend on the order it is taken in */
+#pragma omp parallel for schedule(static) reduction(min : rmin)
     for (int64_t k = 0; k < m->nc; ++k) {
         if (!(H[k] >= p->h_threshold)) continue;
-        double rH = 1.0 / H[k], u = HU[k] * rH, v = HV[k] * rH;
+        double u = HU[k] / H[k], v = HV[k] / H[k];
         double s = sqrt(u * u + v * v) + sqrt(p->g * H[k]);
         double r = m->area[k] / (m->perim[k] * s);
         rmin = mind(rmin, r);
@@ -630,6 +641,7 @@ int orc_run(const orc_mesh *m, const orc_params *p, double *H, double *HU,
         if (!(dt > 0.0) || !isfinite(dt)) { rc = -1; break; }
         /* stage 1: w1 = w + dt L(w) */
         orc_residual(m, p, H, HU, HV, RH, RU, RV);
+#pragma omp parallel for schedule(static) reduction(+ : ncl)
         for (int64_t k = 0; k < nc; ++k) {
             H1[k] = H[k] + dt * RH[k];
             U1[k] = HU[k] + dt * RU[k];
@@ -639,6 +651,7 @@ int orc_run(const orc_mesh *m, const orc_params *p, double *H, double *HU,
         /* stage 2: w^{n+1} = w/2 + (w1 + dt L(w1))/2 */
         orc_residual(m, p, H1, U1, V1, RH, RU, RV);
         int bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : ncl) reduction(| : bad)
         for (int64_t k = 0; k < nc; ++k) {
             H[k] = 0.5 * H[k] + 0.5 * (H1[k] + dt * RH[k]);
             HU[k] = 0.5 * HU[k] + 0.5 * (U1[k] + dt * RU[k]);
@@ -656,3 +669,7 @@ int orc_run(const orc_mesh *m, const orc_params *p, double *H, double *HU,
     free(H1); free(U1); free(V1); free(RH); free(RU); free(RV);
     return rc;
 }
+
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -8,10 +8,13 @@
  * code with the GPU library: it builds its own edge table, neighbours,
  * geometry and orientation from the raw (vertices, triangles, depth) input.
  *
- * Single threaded, no blocking, no fusion: a cell loop for the
- * reconstruction, an edge loop for the fluxes (stored per edge side), a cell
- * loop that accumulates each cell's three faces in local order and applies
- * the Runge-Kutta stage.
+ * No blocking, no fusion: a cell loop for the reconstruction, an edge loop
+ * for the fluxes (stored per edge side), a cell loop that accumulates each
+ * cell's three faces in local order and applies the Runge-Kutta stage.  The
+ * loops may run on several OpenMP threads (orc_set_threads); every
+ * iteration writes only its own outputs and the reductions (CFL minimum,
+ * clamp count) are exact, so results are bitwise independent of the thread
+ * count.
  */
 #ifndef VSW_ORACLE_H
 #define VSW_ORACLE_H
@@ -87,6 +90,11 @@ double orc_dt(const orc_mesh *m, const orc_params *p, const double *H,
 int orc_run(const orc_mesh *m, const orc_params *p, double *H, double *HU,
             double *HV, double *t, int64_t nsteps, double t_stop,
             int64_t *steps_done, double *dts, int64_t *clamps);
+
+/* OpenMP threads of the loops above (default: OMP_NUM_THREADS, else all
+ * cores), and the number in use. */
+void orc_set_threads(int n);
+int orc_max_threads(void);
 
 #ifdef __cplusplus
 }

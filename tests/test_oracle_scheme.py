@@ -312,3 +312,45 @@ def test_rotation_symmetry(orc):
     assert np.abs(r["H"] - ref["H"]).max() <= 1e-12 * sH
     assert np.abs(r["HU"] + ref["HV"]).max() <= 1e-9 * sQ
     assert np.abs(r["HV"] - ref["HU"]).max() <= 1e-9 * sQ
+
+
+def test_dt_closed_form_on_right_triangles(orc):
+    """CFL rule (reading of Section 2.3): for a uniform flow on a mesh of
+    right isosceles triangles with unit legs, every cell has |K| / P_K =
+    r / 2 with the inradius r = (2 - sqrt 2) / 2, so dt = CFL r /
+    (2 (|u| + sqrt(g H)))."""
+    vx, vy, tri = W.tiny_mesh("square8")
+    m = orc.Mesh(vx, vy, tri, np.ones(8))
+    p = orc.params(g=9.81, cfl=0.45, h_threshold=1e-3)
+    r_in = (2.0 - math.sqrt(2.0)) / 2.0
+    for H, u, v in ((1.0, 0.0, 0.0), (0.25, 0.3, -0.4), (2.0, -1.5, 2.0)):
+        dt = m.dt(p, np.full(8, H), np.full(8, H * u), np.full(8, H * v))
+        exact = 0.45 * r_in / (2.0 * (math.hypot(u, v) + math.sqrt(9.81 * H)))
+        assert dt == pytest.approx(exact, rel=1e-14)
+    # a dry cell does not limit the step; below H_thr counts as dry
+    Hs = np.full(8, 1.0)
+    Hs[3] = 5e-4
+    assert m.dt(p, Hs, np.zeros(8), np.zeros(8)) == pytest.approx(
+        0.45 * r_in / (2.0 * math.sqrt(9.81)), rel=1e-14)
+    assert math.isinf(m.dt(p, np.zeros(8), np.zeros(8), np.zeros(8)))
+
+
+def test_threads_do_not_change_results(orc):
+    """The OpenMP loops of the oracle give bitwise the same run for any
+    thread count (each iteration writes only its own outputs; the CFL
+    minimum and the clamp count are exact reductions)."""
+    c = W.basin_case(scale=16)
+    m = orc.Mesh.from_case(c)
+    p = params_of(orc, c)
+    saved = orc.max_threads()
+    try:
+        out = []
+        for n in (1, 3, 8):
+            orc.set_threads(n)
+            out.append(m.run(p, c.H, c.HU, c.HV, 0.0, 40))
+    finally:
+        orc.set_threads(saved)
+    for r in out[1:]:
+        for k in ("H", "HU", "HV", "dts"):
+            assert np.array_equal(r[k], out[0][k]), k
+        assert r["t"] == out[0]["t"] and r["clamps"] == out[0]["clamps"]
