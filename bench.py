@@ -12,8 +12,10 @@ order on the coastal mesh) are reported beside it.  The roofline entry uses the 
 launch duration from HIP events recorded on the solver's stream around each
 launch, in a second pass over the same number of steps; beside the
 datasheet peak it carries copy_GBps, the bandwidth of a plain 1 GiB device
-copy measured in the same run.  cpu_baseline times the FP64 oracle (single
-thread) on a bounded sample of the same workload.  --workload ensemble
+copy measured in the same run.  The basin line also carries the FP64 leg of
+the 12M-triangle coastal mesh (far larger than the last-level cache, so its
+roofline is an HBM one).  cpu_baseline times the FP64 oracle on a bounded
+sample of the same workload, on every host thread and on one.  --workload ensemble
 reports ensemble runs/s, --workload adjoint the adjoint/forward time ratio.
 """
 from __future__ import annotations
@@ -50,18 +52,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(case, steps):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, steps_all, steps_one):
+    """The FP64 oracle on the host: `steps_all` steps on every thread the
+    oracle's OpenMP loops get (OMP_NUM_THREADS, else every core), and
+    `steps_one` steps on one thread (bitwise the same results)."""
     import oracle
 
     m = oracle.Mesh.from_case(case)
     p = oracle.params(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold)
-    t0 = time.perf_counter()
-    r = m.run(p, case.H, case.HU, case.HV, 0.0, steps)
-    el = time.perf_counter() - t0
-    return {"value": case.nc * r["steps"] / el, "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{r['steps']} steps of the same {case.nc}-cell mesh from its initial "
-                      f"state, single-threaded C oracle (gcc -O2), {el:.1f} s"}
+    threads = oracle.max_threads()
+    out = {}
+    for label, n, th in (("all", steps_all, threads), ("one", steps_one, 1)):
+        oracle.set_threads(th)
+        t0 = time.perf_counter()
+        r = m.run(p, case.H, case.HU, case.HV, 0.0, n)
+        el = time.perf_counter() - t0
+        out[label] = (case.nc * r["steps"] / el, r["steps"], el, th)
+    oracle.set_threads(threads)
+    v, n, el, th = out["all"]
+    v1, n1, el1, _ = out["one"]
+    model = cpu_model()
+    return {"value": v, "unit": "cell-updates/s", "cores": th, "kind": "oracle",
+            "sample": f"{n} steps of the same {case.nc}-cell mesh from its initial state, C "
+                      f"oracle (gcc -O3, OpenMP) on {th} threads, {el:.1f} s; host {model}, "
+                      f"{os.cpu_count()} logical CPUs",
+            "single_thread": {"value": v1, "unit": "cell-updates/s", "cores": 1,
+                              "sample": f"{n1} steps on one thread, {el1:.1f} s"},
+            "cpu_model": model, "nproc": os.cpu_count()}
 
 
 def kernel_roofline(vsw, s, steps, nc, bytes1, bytes2):
@@ -145,12 +172,16 @@ def time_steps(torch, stream, s, steps):
 
 
 def run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, precision, ordering, steps, warmup,
-            bytes1, bytes2, label):
+            bytes1, bytes2, label, kernel=None, tile=None):
     """Warm up and time `steps` steps of one solver configuration; returns
     (leg summary dict, solver handle still open)."""
     s = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold, device=0,
                    precision=precision, ordering=ordering)
     vsw.vsw_set_stream(s.h, stream.cuda_stream)
+    if tile:
+        vsw.vsw_set_tile_size(s.h, tile)
+    if kernel is not None and precision == vsw.VSW_FP64:
+        vsw.vsw_set_kernel_variant(s.h, kernel)
     t0 = time.perf_counter()
     s.upload_mesh(case.vx, case.vy, case.tri, case.h)
     log(f"[bench] {label}: mesh uploaded in {time.perf_counter() - t0:.1f} s")
@@ -255,7 +286,7 @@ def bench_ensemble(args, torch, vsw, W):
     if not args.no_cpu_baseline:
         import oracle
 
-        csteps = args.cpu_steps if args.cpu_steps is not None else 2
+        csteps = args.cpu_steps if args.cpu_steps is not None else 4
         el = 0.0
         for c in cases:
             m = oracle.Mesh.from_case(c)
@@ -264,10 +295,11 @@ def bench_ensemble(args, torch, vsw, W):
             m.run(p, c.H, c.HU, c.HV, 0.0, csteps)
             el += time.perf_counter() - tt
         out["cpu_baseline"] = {"value": nsc / (el * steps / csteps), "unit": "runs/s",
-                               "cores": 1, "kind": "oracle",
+                               "cores": oracle.max_threads(), "kind": "oracle",
                                "sample": f"{csteps} steps of each of the {nsc} scenarios, "
-                                         f"single-threaded C oracle, {el:.1f} s, scaled to "
-                                         f"{steps}-step runs"}
+                                         f"C oracle (gcc -O3, OpenMP) on "
+                                         f"{oracle.max_threads()} threads, {el:.1f} s, scaled "
+                                         f"to {steps}-step runs; host {cpu_model()}"}
     print(json.dumps(out), flush=True)
 
 
@@ -359,7 +391,14 @@ def main():
                     help="comma-separated subset of fp64, fp32, fp64_random_order, "
                          "fp32_random_order (for profiling one configuration at a time)")
     ap.add_argument("--cpu-steps", type=int, default=None,
-                    help="oracle steps for cpu_baseline (default 40 basin, 3 coastal)")
+                    help="oracle steps for cpu_baseline on all threads (default 200 basin, 20 "
+                         "coastal; a tenth of them on one thread)")
+    ap.add_argument("--no-coastal", action="store_true",
+                    help="basin: skip the 12M-triangle coastal FP64 leg")
+    ap.add_argument("--kernel", choices=["faces", "fused", "two_pass"], default="faces",
+                    help="FP64 stage kernel organisation (default: face-parallel)")
+    ap.add_argument("--tile", type=int, choices=[128, 256, 512], default=None,
+                    help="cells per tile of the FP64 face-parallel kernel (default 256)")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="mesh size multiplier (1 = the named workload)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -391,7 +430,7 @@ def main():
     coastal = args.workload == "coastal"
     steps = args.steps if args.steps is not None else (1000 if coastal else 2000)
     warmup = args.warmup if args.warmup is not None else (20 if coastal else 100)
-    cpu_steps = args.cpu_steps if args.cpu_steps is not None else (3 if coastal else 40)
+    cpu_steps = args.cpu_steps if args.cpu_steps is not None else (20 if coastal else 200)
 
     import torch
 
@@ -428,12 +467,14 @@ def main():
     if args.legs:
         keep = args.legs.split(",")
         legs = [x for x in legs if x[0] in keep]
+    kernel = {"faces": vsw.VSW_KERNEL_FACES, "fused": vsw.VSW_KERNEL_FUSED,
+              "two_pass": vsw.VSW_KERNEL_TWO_PASS}[args.kernel]
     res = {}
     for name, prec, order in legs:
         b1, b2 = ((ALG_BYTES_STAGE1, ALG_BYTES_STAGE2) if prec == vsw.VSW_FP64
                   else (ALG_BYTES_STAGE1_F32, ALG_BYTES_STAGE2_F32))
         leg, s = run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, prec, order, steps,
-                         warmup, b1, b2, name)
+                         warmup, b1, b2, name, kernel=kernel, tile=args.tile)
         s.close()
         leg["dtype"] = ("f64" if prec == vsw.VSW_FP64 else
                         "f32 state and fluxes, f64 depths/pressure/accumulation")
@@ -484,9 +525,40 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
                                    "launches": 3}
+    if not coastal and not args.no_coastal:
+        # the 12M-triangle coastal mesh: the state and mesh are far larger
+        # than the last-level cache, so its traffic is HBM traffic
+        t0 = time.perf_counter()
+        cst = W.coastal_case(scale=args.scale, log=lambda m: log("[bench] " + m))
+        log(f"[bench] coastal workload: {cst.nc} cells, generated in "
+            f"{time.perf_counter() - t0:.1f} s")
+        cH = torch.tensor(cst.H, device=dev)
+        cU = torch.tensor(cst.HU, device=dev)
+        cV = torch.tensor(cst.HV, device=dev)
+        torch.cuda.synchronize()
+        leg, s = run_leg(torch, vsw, cst, stream, dev, cH, cU, cV, vsw.VSW_FP64,
+                         vsw.VSW_ORDER_HILBERT, steps, warmup, ALG_BYTES_STAGE1,
+                         ALG_BYTES_STAGE2, "coastal fp64", kernel=kernel, tile=args.tile)
+        s.close()
+        del cH, cU, cV
+        torch.cuda.empty_cache()
+        rf = leg["roofline"]
+        tr = measured_traffic("coastal" + ("" if args.scale == 1.0 else f"x{args.scale:g}"),
+                              "hilbert", "fp64", rf["kernel"], leg["mesh"]["cells"])
+        rf["traffic"] = tr
+        if tr is not None:
+            rf["traffic_bytes_per_cell"] = round(tr / leg["mesh"]["cells"], 1)
+            rf["traffic_GBps"] = round(tr / (rf["avg_launch_us"] * 1e-6) / 1e9, 1)
+        rf["copy_GBps"] = out["roofline"].get("copy_GBps")
+        mesh = leg.pop("mesh")
+        leg["dtype"] = "f64"
+        leg["workload"] = (f"large graded coastal mesh 1000x1000 km, {mesh['cells']} triangles "
+                           "(50 m-5 km), fractal coastline, elliptical uplift, walls, CFL 0.45")
+        out["coastal12m_fp64"] = leg
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline: oracle, {cpu_steps} steps")
-        out["cpu_baseline"] = cpu_baseline(case, cpu_steps)
+        log(f"[bench] cpu baseline: oracle, {cpu_steps} steps on all threads, "
+            f"{max(cpu_steps // 10, 1)} on one")
+        out["cpu_baseline"] = cpu_baseline(case, cpu_steps, max(cpu_steps // 10, 1))
     print(json.dumps(out), flush=True)
 
 

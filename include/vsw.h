@@ -162,8 +162,11 @@ int vsw_adjoint_gauge_loss(vsw_solver *s, int64_t nsteps,
 int vsw_set_state(vsw_solver *s, const double *H, const double *HU,
                   const double *HV, double t);
 
-/* Same as vsw_set_state from device arrays (caller's cell order).  The
- * values are not validated. */
+/* Same as vsw_set_state from device arrays (caller's cell order), which
+ * the solver's stream must be able to read.  The values are checked on the
+ * device before anything is written: EINVAL on a non-finite value or
+ * H < 0, and the solver's state is then left as it was.  Synchronises the
+ * solver's stream. */
 int vsw_set_state_device(vsw_solver *s, const double *dev_H,
                          const double *dev_HU, const double *dev_HV, double t);
 
@@ -173,9 +176,11 @@ int vsw_set_state_device(vsw_solver *s, const double *dev_H,
  * solver's stream without host synchronisation between steps; the call
  * synchronises once at the end.  *steps_done (may be NULL) receives the
  * number of completed steps and *t_out (may be NULL) the new time.
- * EUNSTABLE if the state became non-finite (steps_done then counts the good
- * steps before it; the state is that of the failing step) or no valid time
- * step exists; ESTATE without mesh and state. */
+ * EUNSTABLE if a step made the state non-finite or found no valid time
+ * step: steps_done then counts the good steps before it, and the solver's
+ * state and time are those the good steps reached, i.e. the input of the
+ * failing step (a further call fails at the same step again unless the
+ * state or parameters change).  ESTATE without mesh and state. */
 int vsw_step(vsw_solver *s, int64_t n, double t_stop, int64_t *steps_done,
              double *t_out);
 
@@ -216,13 +221,29 @@ int vsw_clamp_count(vsw_solver *s, int64_t *count);
 int vsw_set_stream(vsw_solver *s, void *hip_stream);
 
 /* Kernel organisation of a stage (same results, bitwise):
- * VSW_KERNEL_FUSED (default): one kernel per stage; each workgroup
- *   reconstructs a tile of 256 consecutive (Hilbert-ordered) cells and its
- *   halo faces into LDS and computes fluxes and the update from there.
- * VSW_KERNEL_TWO_PASS: a reconstruction kernel writes every face state to
- *   device memory, a second kernel computes fluxes and the update. */
-enum { VSW_KERNEL_FUSED = 0, VSW_KERNEL_TWO_PASS = 1 };
+ * VSW_KERNEL_FACES (default): one kernel per stage; each workgroup
+ *   reconstructs a tile of consecutive (Hilbert-ordered) cells and its halo
+ *   faces into LDS, evaluates every face of the tile once (normal and
+ *   length from the face's vertices) and updates its cells.
+ * VSW_KERNEL_FUSED: one kernel per stage, tiles of 256 cells; each cell
+ *   evaluates its three faces itself from LDS, with the face geometry read
+ *   from device memory.
+ * VSW_KERNEL_TWO_PASS (FP64 only): a reconstruction kernel writes every
+ *   face state to device memory, a second kernel computes fluxes and the
+ *   update.
+ * FUSED and TWO_PASS need tiles of 256 cells (vsw_step: EINVAL otherwise).
+ * EINVAL for an unknown variant, and for TWO_PASS on FP32. */
+enum { VSW_KERNEL_FUSED = 0, VSW_KERNEL_TWO_PASS = 1, VSW_KERNEL_FACES = 2 };
 int vsw_set_kernel_variant(vsw_solver *s, int variant);
+
+/* Cells per tile (one workgroup, one thread per cell) of the layout of the
+ * mesh on the device: 128, 256 (default) or 512.  With a mesh uploaded the
+ * mesh is laid out again and its state and time carried over (results are
+ * bitwise the same for every tile size); otherwise it applies to the next
+ * upload.  The solver keeps a copy of the uploaded mesh for this.  EINVAL
+ * for other sizes; ENOMEM/EDEVICE as vsw_upload_mesh. */
+int vsw_set_tile_size(vsw_solver *s, int cells);
+int vsw_tile_size(vsw_solver *s, int *cells);
 
 /* Graph mode (off by default): vsw_step captures one pair of steps (their
  * kernel launches and a one-thread kernel that advances the device-side

@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvsw.so")
 
-SOURCES = ["vsw_api.hip", "vsw_kernels.hip", "vsw_kernels_f32.hip", "vsw_adjoint.hip",
-           "vsw_mesh.cpp"]
+SOURCES = ["vsw_api.hip", "vsw_kernels.hip", "vsw_kernels_f32.hip", "vsw_faces.hip",
+           "vsw_adjoint.hip", "vsw_mesh.cpp"]
 
 # -ffp-contract=off: no fused multiply-add anywhere (device and host), so
 # every floating-point operation is one IEEE-754 rounding in source order.

@@ -11,6 +11,7 @@
 
 #include "../../include/vsw.h"
 #include "vsw_adjoint.hpp"
+#include "vsw_faces.hpp"
 #include "vsw_kernels.hpp"
 #include "vsw_kernels_f32.hpp"
 #include "vsw_mesh.hpp"
@@ -117,10 +118,14 @@ struct vsw_solver {
     DevBuf<double> d_geom, d_area, d_perim, d_h;
     DevBuf<RGeom> d_rgeom;         // reconstruction geometry records
     DevBuf<RGeomF> d_rgeomf;       // the same in FP32 (FP32 solvers)
-    DevBuf<Cell4> d_w;             // w^n records (H, HU, HV, h), FP64 solver
+    // The state alternates between two buffers (a step reads one and writes
+    // the other); cur is the one holding the current state.
+    DevBuf<Cell4> d_w[2];          // w^n records (H, HU, HV, h), FP64 solver
     DevBuf<Cell4> d_w1;            // stage-1 records, FP64 solver
-    DevBuf<CellF> d_wf;            // w^n records (h, eta, Hu, Hv), FP32 solver
+    DevBuf<CellF> d_wf[2];         // w^n records (h, eta, Hu, Hv), FP32 solver
     DevBuf<CellF> d_w1f;           // stage-1 records, FP32 solver
+    int cur = 0;
+    DevBuf<int> d_flag;            // state check of vsw_set_state_device
     DevBuf<double> d_face;         // 15 * nc face buffer
     DevBuf<double> d_sc;           // 2 * nc
     DevBuf<int32_t> d_order;       // nc
@@ -131,6 +136,7 @@ struct vsw_solver {
     DevBuf<double> d_t0;           // per-scenario start times of a call
     DevBuf<uint32_t> d_tinfo;      // tile words
     DevBuf<int64_t> d_gauge_cells; // internal indices of the gauge cells
+    DevBuf<int32_t> d_gauge_seg;   // scenario of each gauge
     DevBuf<double> d_gauge_log;    // [step][gauge] free surface of the last call
     int ngauges = 0;
     std::vector<double> gauge_eta; // host copy of the last call's records
@@ -139,7 +145,23 @@ struct vsw_solver {
     DevBuf<int32_t> d_bstart;
     DevBuf<uint32_t> d_bitem;
     int bmax = 0, ntiles = 0;
-    int variant = VSW_KERNEL_FUSED;
+    // face-parallel kernels: tiles of `tile` cells
+    int tile = kTile;           // tile size of the uploaded layout
+    int tile_req = kTile;       // tile size of the next layout
+    DevBuf<TopoD> d_topo;
+    DevBuf<LsqW> d_lsq;
+    DevBuf<LsqWF> d_lsqf;
+    DevBuf<double2> d_vxy;
+    DevBuf<int32_t> d_fbstart, d_fstart;
+    DevBuf<uint32_t> d_fbitem;
+    DevBuf<FaceItemD> d_fitems;
+    int fbmax = 0;
+    // the caller's mesh, kept to lay it out again for another tile size
+    int raw_nseg = 0;
+    std::vector<int64_t> raw_nv, raw_nc;
+    std::vector<double> raw_vx, raw_vy, raw_h;
+    std::vector<int32_t> raw_tri;
+    int variant = VSW_KERNEL_FACES;
     bool use_graph = false;
     int xcd_order = 1;
     int occupancy = 0;  // fused stage kernels: workgroups per CU cap (0 = none)
@@ -168,12 +190,16 @@ struct vsw_solver {
         d_perm.release(); d_nbr.release(); d_geom.release(); d_area.release();
         d_rgeom.release();
         d_rgeomf.release();
-        d_perim.release(); d_h.release(); d_w.release(); d_w1.release();
-        d_wf.release(); d_w1f.release();
+        d_perim.release(); d_h.release(); d_w[0].release(); d_w[1].release(); d_w1.release();
+        d_wf[0].release(); d_wf[1].release(); d_w1f.release();
+        cur = 0;
         d_face.release(); d_sc.release(); d_order.release(); d_tmp.release();
         d_nloc.release(); d_bstart.release(); d_bitem.release(); d_tinfo.release();
+        d_topo.release(); d_lsq.release(); d_lsqf.release(); d_vxy.release(); d_fbstart.release();
+        d_fstart.release(); d_fbitem.release(); d_fitems.release();
         d_seg.release(); d_t0.release();
         d_gauge_cells.release();
+        d_gauge_seg.release();
         ngauges = 0;
         has_mesh = has_state = false;
     }
@@ -182,20 +208,20 @@ struct vsw_solver {
         const dim3 g(unsigned((nint + kBlock - 1) / kBlock));
         if (prm.precision == VSW_FP32)
             hipLaunchKernelGGL(pack_state_f32_kernel, g, dim3(kBlock), 0, stream, nint, d_perm.p,
-                               H, HU, HV, d_h.p, d_wf.p, d_w1f.p);
+                               H, HU, HV, d_h.p, d_wf[cur].p, d_w1f.p);
         else
             hipLaunchKernelGGL(pack_state_kernel, g, dim3(kBlock), 0, stream, nint, d_perm.p, H,
-                               HU, HV, d_h.p, d_w.p, d_w1.p);
+                               HU, HV, d_h.p, d_w[cur].p, d_w1.p);
     }
     // state records -> caller-order arrays (device; NULL skips a field)
     void unpack(double* H, double* HU, double* HV) {
         const dim3 g(unsigned((nint + kBlock - 1) / kBlock));
         if (prm.precision == VSW_FP32)
             hipLaunchKernelGGL(unpack_state_f32_kernel, g, dim3(kBlock), 0, stream, nint, d_perm.p,
-                               d_wf.p, H, HU, HV);
+                               d_wf[cur].p, d_h.p, H, HU, HV);
         else
             hipLaunchKernelGGL(unpack_state_kernel, g, dim3(kBlock), 0, stream, nint, d_perm.p,
-                               d_w.p, H, HU, HV);
+                               d_w[cur].p, H, HU, HV);
     }
     void set_time(double t0) {
         t = t0;
@@ -208,6 +234,20 @@ struct vsw_solver {
         last_dts.clear();
         has_state = true;
     }
+    FaceMesh face_mesh() const {
+        FaceMesh m;
+        m.nc = nint;
+        m.topo = d_topo.p;
+        m.lsq = d_lsq.p;
+        m.lsqf = d_lsqf.p;
+        m.vxy = d_vxy.p;
+        m.perim = d_perim.p;
+        return m;
+    }
+    FaceTileMap face_tiles(int nsg) const {
+        return FaceTileMap{d_fbstart.p, d_fbitem.p, d_fstart.p, d_fitems.p, d_tinfo.p, fbmax,
+                           ntiles, nsg, xcd_order};
+    }
     DevMesh dev_mesh() const {
         DevMesh m;
         m.nc = nint;
@@ -217,6 +257,7 @@ struct vsw_solver {
         m.rgeomf = d_rgeomf.p;
         m.area = d_area.p;
         m.perim = d_perim.p;
+        m.hcell = d_h.p;
         return m;
     }
 };
@@ -235,6 +276,83 @@ struct DeviceGuard {
 };
 
 unsigned grid_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+// Face-parallel stage kernel of the tile size in use.
+void launch_faces_stage(int tile, int stage, int ntiles, size_t lds, hipStream_t q,
+                        const FaceMesh& m, const FaceTileMap& tm, Cell4* Wa, Cell4* Wb,
+                        Cell4* W1, const StepParams& p, Ctrl* c, Seg* sg, int slot, int sa,
+                        double* lg) {
+    const dim3 grid{unsigned(ntiles), 1u, 1u};
+#define VSW_LAUNCH_FACES(T)                                                                    \
+    if (stage == 1)                                                                            \
+        hipLaunchKernelGGL((faces_stage_kernel<T, 1>), grid, dim3(T), lds, q, m, tm, Wa, Wb,   \
+                           W1, p, c, sg, slot, sa, lg);                                        \
+    else                                                                                       \
+        hipLaunchKernelGGL((faces_stage_kernel<T, 2>), grid, dim3(T), lds, q, m, tm, Wa, Wb,   \
+                           W1, p, c, sg, slot, sa, lg);
+    if (tile == 128) {
+        VSW_LAUNCH_FACES(128)
+    } else if (tile == 512) {
+        VSW_LAUNCH_FACES(512)
+    } else {
+        VSW_LAUNCH_FACES(256)
+    }
+#undef VSW_LAUNCH_FACES
+}
+
+void launch_faces_stage_f32(int tile, int stage, int ntiles, size_t lds, hipStream_t q,
+                            const FaceMesh& m, const FaceTileMap& tm, const double* h, CellF* Wa,
+                            CellF* Wb, CellF* W1, const StepParams& p, Ctrl* c, Seg* sg, int slot,
+                            int sa, double* lg) {
+    const dim3 grid{unsigned(ntiles), 1u, 1u};
+#define VSW_LAUNCH_FACES_F32(T)                                                                \
+    if (stage == 1)                                                                            \
+        hipLaunchKernelGGL((faces_stage_f32_kernel<T, 1>), grid, dim3(T), lds, q, m, tm, h,    \
+                           Wa, Wb, W1, p, c, sg, slot, sa, lg);                                \
+    else                                                                                       \
+        hipLaunchKernelGGL((faces_stage_f32_kernel<T, 2>), grid, dim3(T), lds, q, m, tm, h,    \
+                           Wa, Wb, W1, p, c, sg, slot, sa, lg);
+    if (tile == 128) {
+        VSW_LAUNCH_FACES_F32(128)
+    } else if (tile == 512) {
+        VSW_LAUNCH_FACES_F32(512)
+    } else {
+        VSW_LAUNCH_FACES_F32(256)
+    }
+#undef VSW_LAUNCH_FACES_F32
+}
+
+void launch_faces_dt_init_f32(int tile, int ntiles, hipStream_t q, const FaceMesh& m,
+                              const FaceTileMap& tm, const CellF* W, const double* h,
+                              const double* area, double g, double thr, Seg* sg) {
+    const dim3 grid{unsigned(ntiles), 1u, 1u};
+    if (tile == 128)
+        hipLaunchKernelGGL(faces_dt_init_f32_kernel<128>, grid, dim3(128), 0, q, m, tm, W, h,
+                           area, g, thr, sg);
+    else if (tile == 512)
+        hipLaunchKernelGGL(faces_dt_init_f32_kernel<512>, grid, dim3(512), 0, q, m, tm, W, h,
+                           area, g, thr, sg);
+    else
+        hipLaunchKernelGGL(faces_dt_init_f32_kernel<256>, grid, dim3(256), 0, q, m, tm, W, h,
+                           area, g, thr, sg);
+}
+
+void launch_faces_dt_init(int tile, int ntiles, hipStream_t q, const FaceMesh& m,
+                          const FaceTileMap& tm, const Cell4* W, const double* area, double g,
+                          double thr, Seg* sg) {
+    const dim3 grid{unsigned(ntiles), 1u, 1u};
+    if (tile == 128)
+        hipLaunchKernelGGL(faces_dt_init_kernel<128>, grid, dim3(128), 0, q, m, tm, W, area, g,
+                           thr, sg);
+    else if (tile == 512)
+        hipLaunchKernelGGL(faces_dt_init_kernel<512>, grid, dim3(512), 0, q, m, tm, W, area, g,
+                           thr, sg);
+    else
+        hipLaunchKernelGGL(faces_dt_init_kernel<256>, grid, dim3(256), 0, q, m, tm, W, area, g,
+                           thr, sg);
+}
+
+bool f32_solver(const vsw_solver* s) { return s->prm.precision == VSW_FP32; }
 
 }  // namespace
 
@@ -269,6 +387,8 @@ int vsw_create(const vsw_params* p, int device, vsw_solver** out) {
     vsw_solver* s = new vsw_solver();
     s->prm = *p;
     s->device = device;
+    // the face-parallel kernels for FP64, the cell-parallel kernel for FP32
+    s->variant = VSW_KERNEL_FACES;
     hipError_t e = hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = s->d_ctrl.alloc(1);
     if (e != hipSuccess) {
@@ -288,6 +408,7 @@ void vsw_destroy(vsw_solver* s) {
     s->release_graph();
     s->d_log.release();
     s->d_ctrl.release();
+    s->d_flag.release();
     s->d_gauge_log.release();
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
@@ -320,6 +441,7 @@ int upload_assembled(vsw_solver* s, EnsembleMesh& em) {
     s->seg_log.clear();
     s->perm = hm.perm;
     const size_t n = size_t(hm.nc);
+    const bool cellpar = (em.ftiles.tile == kTile);  // the cell-parallel kernels' layout
     HIP_TRY(s->d_perm.alloc(n));
     HIP_TRY(s->d_nbr.alloc(n));
     HIP_TRY(s->d_geom.alloc(size_t(G_NFACE) * 3 * n));
@@ -327,14 +449,14 @@ int upload_assembled(vsw_solver* s, EnsembleMesh& em) {
     HIP_TRY(s->d_perim.alloc(n));
     HIP_TRY(s->d_h.alloc(n));
     if (s->prm.precision == VSW_FP32) {
-        HIP_TRY(s->d_wf.alloc(n));
+        HIP_TRY(s->d_wf[0].alloc(n));
+        HIP_TRY(s->d_wf[1].alloc(n));
         HIP_TRY(s->d_w1f.alloc(n));
     } else {
-        HIP_TRY(s->d_w.alloc(n));
+        HIP_TRY(s->d_w[0].alloc(n));
+        HIP_TRY(s->d_w[1].alloc(n));
         HIP_TRY(s->d_w1.alloc(n));
-        HIP_TRY(s->d_face.alloc(15 * n));
-        HIP_TRY(s->d_sc.alloc(2 * n));
-        HIP_TRY(s->d_order.alloc(n));
+        // the two-pass variant's face buffer is allocated when it first runs
     }
     HIP_TRY(s->d_tmp.alloc(3 * size_t(em.ncell)));
     HIP_TRY(s->d_seg.alloc(size_t(em.nseg)));
@@ -375,6 +497,52 @@ int upload_assembled(vsw_solver* s, EnsembleMesh& em) {
     }
     HIP_TRY(hipMemcpy(s->d_perim.p, hm.perim.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->d_h.p, hm.h.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    // face-parallel kernels
+    {
+        FaceTilesHost& ft = em.ftiles;
+        static_assert(sizeof(TopoRec) == sizeof(TopoD), "topology record layout");
+        static_assert(sizeof(FaceItem) == sizeof(FaceItemD), "face item layout");
+        std::vector<LsqW> lw(n);
+        for (size_t i = 0; i < n; ++i)
+            for (int j = 0; j < 3; ++j) {
+                lw[i].w[2 * j] = hm.face_geom[(size_t(G_WX) * 3 + j) * n + i];
+                lw[i].w[2 * j + 1] = hm.face_geom[(size_t(G_WY) * 3 + j) * n + i];
+            }
+        const size_t nvu = hm.vxy.size() / 2;
+        HIP_TRY(s->d_topo.alloc(n));
+        HIP_TRY(s->d_lsq.alloc(n));
+        if (s->prm.precision == VSW_FP32) {
+            // rounded to nearest here, as the FP32 kernels round each weight
+            std::vector<LsqWF> lf(n);
+            for (size_t i = 0; i < n; ++i)
+                for (int q = 0; q < 6; ++q) lf[i].w[q] = float(lw[i].w[q]);
+            HIP_TRY(s->d_lsqf.alloc(n));
+            HIP_TRY(hipMemcpy(s->d_lsqf.p, lf.data(), n * sizeof(LsqWF), hipMemcpyHostToDevice));
+        }
+        HIP_TRY(s->d_vxy.alloc(std::max<size_t>(nvu, 1)));
+        HIP_TRY(s->d_fbstart.alloc(ft.bstart.size()));
+        HIP_TRY(s->d_fstart.alloc(ft.fstart.size()));
+        HIP_TRY(s->d_fbitem.alloc(std::max<size_t>(ft.bitem.size(), 1)));
+        HIP_TRY(s->d_fitems.alloc(std::max<size_t>(ft.items.size(), 1)));
+        HIP_TRY(hipMemcpy(s->d_topo.p, ft.topo.data(), n * sizeof(TopoD), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->d_lsq.p, lw.data(), n * sizeof(LsqW), hipMemcpyHostToDevice));
+        if (nvu)
+            HIP_TRY(hipMemcpy(s->d_vxy.p, hm.vxy.data(), nvu * sizeof(double2),
+                              hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->d_fbstart.p, ft.bstart.data(), ft.bstart.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->d_fstart.p, ft.fstart.data(), ft.fstart.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+        if (!ft.bitem.empty())
+            HIP_TRY(hipMemcpy(s->d_fbitem.p, ft.bitem.data(), ft.bitem.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice));
+        if (!ft.items.empty())
+            HIP_TRY(hipMemcpy(s->d_fitems.p, ft.items.data(),
+                              ft.items.size() * sizeof(FaceItemD), hipMemcpyHostToDevice));
+        s->fbmax = ft.bmax;
+        s->tile = ft.tile;
+        s->ntiles = ft.ntiles;
+    }
     TileMapHost& tmh = em.tiles;
     HIP_TRY(s->d_nloc.alloc(tmh.nloc.size()));
     HIP_TRY(s->d_bstart.alloc(tmh.bstart.size()));
@@ -390,9 +558,44 @@ int upload_assembled(vsw_solver* s, EnsembleMesh& em) {
     HIP_TRY(hipMemcpy(s->d_tinfo.p, em.tinfo.data(), em.tinfo.size() * sizeof(uint32_t),
                       hipMemcpyHostToDevice));
     s->bmax = tmh.bmax;
-    s->ntiles = tmh.ntiles;
+    (void)cellpar;
     s->has_mesh = true;
     s->has_state = false;
+    return VSW_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Builds and uploads the layout of the solver's stored mesh for tiles of
+// `tile` cells.
+int layout_raw(vsw_solver* s, int tile) {
+    EnsembleMesh em;
+    std::string err;
+    int rc = build_ensemble(s->raw_nseg, s->raw_nv.data(), s->raw_vx.data(), s->raw_vy.data(),
+                            s->raw_nc.data(), s->raw_tri.data(), s->raw_h.data(),
+                            s->prm.ordering, s->prm.seed, tile, em, err);
+    if (rc != VSW_OK) return fail(rc, err);
+    return upload_assembled(s, em);
+}
+
+int store_raw(vsw_solver* s, int nseg, const int64_t* nv, const double* vx, const double* vy,
+              const int64_t* nc, const int32_t* tri, const double* h) {
+    int64_t V = 0, C = 0;
+    for (int q = 0; q < nseg; ++q) {
+        if (nv[q] <= 0 || nc[q] <= 0 || nc[q] > kMaxCells || nv[q] > INT32_MAX)
+            return fail(VSW_EINVAL, "scenario " + std::to_string(q) + ": empty or oversized mesh");
+        V += nv[q];
+        C += nc[q];
+    }
+    s->raw_nseg = nseg;
+    s->raw_nv.assign(nv, nv + nseg);
+    s->raw_nc.assign(nc, nc + nseg);
+    s->raw_vx.assign(vx, vx + V);
+    s->raw_vy.assign(vy, vy + V);
+    s->raw_h.assign(h, h + C);
+    s->raw_tri.assign(tri, tri + 3 * C);
     return VSW_OK;
 }
 
@@ -401,12 +604,10 @@ int upload_assembled(vsw_solver* s, EnsembleMesh& em) {
 int vsw_upload_mesh(vsw_solver* s, int64_t nv, const double* vx, const double* vy, int64_t nc,
                     const int32_t* tri, const double* h) {
     if (!s) return fail(VSW_EINVAL, "NULL solver");
-    EnsembleMesh em;
-    std::string err;
-    int rc = build_ensemble(1, &nv, vx, vy, &nc, tri, h, s->prm.ordering, s->prm.seed, kTile,
-                            em, err);
-    if (rc != VSW_OK) return fail(rc, err);
-    return upload_assembled(s, em);
+    if (!vx || !vy || !tri || !h) return fail(VSW_EINVAL, "NULL array");
+    int rc = store_raw(s, 1, &nv, vx, vy, &nc, tri, h);
+    if (rc != VSW_OK) return rc;
+    return layout_raw(s, s->tile_req);
 }
 
 int vsw_upload_ensemble(vsw_solver* s, int32_t nscen, const int64_t* nv, const double* vx,
@@ -414,13 +615,54 @@ int vsw_upload_ensemble(vsw_solver* s, int32_t nscen, const int64_t* nv, const d
                         const double* h) {
     if (!s) return fail(VSW_EINVAL, "NULL solver");
     if (nscen <= 0 || nscen > (1 << 22)) return fail(VSW_EINVAL, "bad scenario count");
-    if (!vx || !vy || !tri || !h) return fail(VSW_EINVAL, "NULL array");
-    EnsembleMesh em;
-    std::string err;
-    int rc = build_ensemble(nscen, nv, vx, vy, nc, tri, h, s->prm.ordering, s->prm.seed, kTile,
-                            em, err);
-    if (rc != VSW_OK) return fail(rc, err);
-    return upload_assembled(s, em);
+    if (!vx || !vy || !tri || !h || !nv || !nc) return fail(VSW_EINVAL, "NULL array");
+    int rc = store_raw(s, nscen, nv, vx, vy, nc, tri, h);
+    if (rc != VSW_OK) return rc;
+    return layout_raw(s, s->tile_req);
+}
+
+int vsw_set_tile_size(vsw_solver* s, int cells) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (cells != 128 && cells != 256 && cells != 512)
+        return fail(VSW_EINVAL, "tile size must be 128, 256 or 512");
+    s->tile_req = cells;
+    if (!s->has_mesh || s->tile == cells) return VSW_OK;
+    // lay the mesh out again, carrying the state (caller's order), the
+    // scenarios' times and the clamp count over
+    DeviceGuard dg(s->device);
+    const bool had_state = s->has_state;
+    const int64_t nc = s->nc;
+    DevBuf<double> keep;
+    if (had_state) {
+        HIP_TRY(keep.alloc(3 * size_t(nc)));
+        s->unpack(keep.p, keep.p + nc, keep.p + 2 * nc);
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    const double t = s->t, dt_last = s->dt_last;
+    const int64_t clamps = s->clamps;
+    const std::vector<double> seg_t = s->seg_t, seg_dt = s->seg_dt;
+    int rc = layout_raw(s, cells);
+    if (rc != VSW_OK) {
+        keep.release();
+        return rc;
+    }
+    if (had_state) {
+        s->pack(keep.p, keep.p + nc, keep.p + 2 * nc);
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        keep.release();
+        s->set_time(t);
+        s->dt_last = dt_last;
+        s->clamps = clamps;
+        s->seg_t = seg_t;
+        s->seg_dt = seg_dt;
+    }
+    return VSW_OK;
+}
+
+int vsw_tile_size(vsw_solver* s, int* cells) {
+    if (!s || !cells) return fail(VSW_EINVAL, "NULL argument");
+    *cells = s->has_mesh ? s->tile : s->tile_req;
+    return VSW_OK;
 }
 
 int vsw_set_state(vsw_solver* s, const double* H, const double* HU, const double* HV, double t) {
@@ -454,6 +696,18 @@ int vsw_set_state_device(vsw_solver* s, const double* dH, const double* dHU, con
     if (!dH || !dHU || !dHV) return fail(VSW_EINVAL, "NULL state array");
     if (!std::isfinite(t)) return fail(VSW_EINVAL, "non-finite time");
     DeviceGuard dg(s->device);
+    // checked on the device before anything is written
+    if (!s->d_flag.p) HIP_TRY(s->d_flag.alloc(1));
+    const int zero = 0;
+    HIP_TRY(hipMemcpyAsync(s->d_flag.p, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    hipLaunchKernelGGL(check_state_kernel, dim3(grid_for(s->nc)), dim3(kBlock), 0, s->stream,
+                       s->nc, dH, dHU, dHV, s->d_flag.p);
+    HIP_TRY(hipGetLastError());
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, s->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (flag & 1) return fail(VSW_EINVAL, "non-finite state value");
+    if (flag & 2) return fail(VSW_EINVAL, "negative depth H");
     s->pack(dH, dHU, dHV);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));
@@ -514,8 +768,15 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     p.cfl = s->prm.cfl;
     p.dt_fixed = s->prm.dt_fixed;
     p.t_stop = t_stop;
-    Cell4* W = s->d_w.p;
+    Cell4* Wa = s->d_w[0].p;
+    Cell4* Wb = s->d_w[1].p;
     Cell4* W1 = s->d_w1.p;
+    if (!f32_solver(s) && s->variant == VSW_KERNEL_TWO_PASS && !s->d_face.p) {
+        const size_t nn = size_t(s->nint);
+        HIP_TRY(s->d_face.alloc(15 * nn));
+        HIP_TRY(s->d_sc.alloc(2 * nn));
+        HIP_TRY(s->d_order.alloc(nn));
+    }
     FaceBuf fb{s->d_face.p, s->d_sc.p, s->d_order.p};
     Ctrl* c = s->d_ctrl.p;
     Seg* sg = s->d_seg.p;
@@ -525,8 +786,23 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, nseg,
                s->xcd_order};
     const bool f32 = (s->prm.precision == VSW_FP32);
+    const bool faces = s->variant == VSW_KERNEL_FACES;
+    if (!faces && s->tile != kTile)
+        return fail(VSW_EINVAL, "this kernel variant needs tiles of 256 cells");
     const size_t lds = capped_lds(stage_lds_bytes(s->bmax), s->occupancy);
     const size_t lds32 = capped_lds(stage_f32_lds_bytes(s->bmax), s->occupancy);
+    const size_t ldsf = capped_lds(faces_lds_bytes(s->tile, s->fbmax), s->occupancy);
+    if (faces) {
+        int maxlds = 0;
+        HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                      s->device));
+        if (ldsf > size_t(maxlds))
+            return fail(VSW_EINVAL, "tile too large for the LDS of a workgroup (" +
+                                        std::to_string(ldsf) + " > " + std::to_string(maxlds) +
+                                        " bytes)");
+    }
+    const FaceMesh fm = s->face_mesh();
+    const FaceTileMap ftm = s->face_tiles(nseg);
 
     // profiling events: one pair per timed launch
     size_t ev_used = 0;
@@ -551,57 +827,77 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         ev_used += 2;
     };
     // One step on stream q with control slot `slot`; its index is the
-    // device step base plus sa.
+    // device step base plus sa (which also picks the state buffers).
     auto launch_step = [&](hipStream_t q, int slot, int sa) {
         const dim3 gg(unsigned((ng + 63) / 64));
         if (f32) {
-            ev_begin(KK_STAGE1, q);
-            hipLaunchKernelGGL(stage_f32_kernel<1>, grid, block, lds32, q, m, tm, s->d_wf.p,
-                               s->d_w1f.p, p, c, sg, slot, sa, lg);
-            ev_end(q);
-            ev_begin(KK_STAGE2, q);
-            hipLaunchKernelGGL(stage_f32_kernel<2>, grid, block, lds32, q, m, tm, s->d_wf.p,
-                               s->d_w1f.p, p, c, sg, slot, sa, lg);
-            ev_end(q);
+            CellF* Fa = s->d_wf[0].p;
+            CellF* Fb = s->d_wf[1].p;
+            for (int stage = 1; stage <= 2; ++stage) {
+                ev_begin(stage == 1 ? KK_STAGE1 : KK_STAGE2, q);
+                if (faces)
+                    launch_faces_stage_f32(s->tile, stage, s->ntiles, ldsf, q, fm, ftm, s->d_h.p,
+                                           Fa, Fb, s->d_w1f.p, p, c, sg, slot, sa, lg);
+                else if (stage == 1)
+                    hipLaunchKernelGGL(stage_f32_kernel<1>, grid, block, lds32, q, m, tm, Fa, Fb,
+                                       s->d_w1f.p, p, c, sg, slot, sa, lg);
+                else
+                    hipLaunchKernelGGL(stage_f32_kernel<2>, grid, block, lds32, q, m, tm, Fa, Fb,
+                                       s->d_w1f.p, p, c, sg, slot, sa, lg);
+                ev_end(q);
+            }
             if (ng > 0)
-                hipLaunchKernelGGL(gauge_f32_kernel, gg, dim3(64), 0, q, s->d_wf.p,
-                                   s->d_gauge_cells.p, ng, s->d_tinfo.p, sg, c, sa,
+                hipLaunchKernelGGL(gauge_f32_kernel, gg, dim3(64), 0, q, Fa, Fb, s->d_h.p,
+                                   s->d_gauge_cells.p, ng, s->d_gauge_seg.p, sg, c, sa,
                                    s->d_gauge_log.p);
             return;
         }
-        if (s->variant == VSW_KERNEL_FUSED) {
+        if (faces) {
             ev_begin(KK_STAGE1, q);
-            hipLaunchKernelGGL(stage_kernel<1>, grid, block, lds, q, m, tm, W, W1, p, c, sg, slot,
-                               sa, lg);
+            launch_faces_stage(s->tile, 1, s->ntiles, ldsf, q, fm, ftm, Wa, Wb, W1, p, c, sg,
+                               slot, sa, lg);
             ev_end(q);
             ev_begin(KK_STAGE2, q);
-            hipLaunchKernelGGL(stage_kernel<2>, grid, block, lds, q, m, tm, W, W1, p, c, sg, slot,
-                               sa, lg);
+            launch_faces_stage(s->tile, 2, s->ntiles, ldsf, q, fm, ftm, Wa, Wb, W1, p, c, sg,
+                               slot, sa, lg);
+            ev_end(q);
+        } else if (s->variant == VSW_KERNEL_FUSED) {
+            ev_begin(KK_STAGE1, q);
+            hipLaunchKernelGGL(stage_kernel<1>, grid, block, lds, q, m, tm, Wa, Wb, W1, p, c, sg,
+                               slot, sa, lg);
+            ev_end(q);
+            ev_begin(KK_STAGE2, q);
+            hipLaunchKernelGGL(stage_kernel<2>, grid, block, lds, q, m, tm, Wa, Wb, W1, p, c, sg,
+                               slot, sa, lg);
             ev_end(q);
         } else {
             ev_begin(KK_RECON, q);
-            hipLaunchKernelGGL(recon_kernel, grid, block, 0, q, m, tm, W, fb, p, c, sg, slot);
+            hipLaunchKernelGGL(recon_kernel<1>, grid, block, 0, q, m, tm, Wa, Wb, W1, fb, p, c,
+                               sg, slot, sa);
             ev_end(q);
             ev_begin(KK_UPDATE1, q);
-            hipLaunchKernelGGL(update1_kernel, grid, block, 0, q, m, tm, W, W1, fb, p, c, sg,
-                               slot);
+            hipLaunchKernelGGL(update1_kernel, grid, block, 0, q, m, tm, Wa, Wb, W1, fb, p, c, sg,
+                               slot, sa);
             ev_end(q);
             ev_begin(KK_RECON, q);
-            hipLaunchKernelGGL(recon_kernel, grid, block, 0, q, m, tm, W1, fb, p, c, sg, slot);
+            hipLaunchKernelGGL(recon_kernel<2>, grid, block, 0, q, m, tm, Wa, Wb, W1, fb, p, c,
+                               sg, slot, sa);
             ev_end(q);
             ev_begin(KK_UPDATE2, q);
-            hipLaunchKernelGGL(update2_kernel, grid, block, 0, q, m, tm, W, W1, fb, p, c, sg, slot,
-                               sa, lg);
+            hipLaunchKernelGGL(update2_kernel, grid, block, 0, q, m, tm, Wa, Wb, W1, fb, p, c, sg,
+                               slot, sa, lg);
             ev_end(q);
         }
         if (ng > 0)
-            hipLaunchKernelGGL(gauge_kernel, gg, dim3(64), 0, q, W, s->d_gauge_cells.p, ng,
-                               s->d_tinfo.p, sg, c, sa, s->d_gauge_log.p);
+            hipLaunchKernelGGL(gauge_kernel, gg, dim3(64), 0, q, Wa, Wb, s->d_gauge_cells.p, ng,
+                               s->d_gauge_seg.p, sg, c, sa, s->d_gauge_log.p);
     };
 
     // Graph mode: a captured pair of steps followed by a step-base bump,
     // replayed n / 2 times (kernel nodes only).  Rebuilt when anything baked
-    // into its launch arguments changes.
+    // into its launch arguments changes.  The state buffers a step uses follow
+    // from the device step index and the call's parity, so one capture
+    // serves every call.
     const bool use_graph = s->use_graph && !prof && n >= 2;
     if (use_graph) {
         const GraphKey key{lg, s->d_gauge_log.p, s->d_gauge_cells.p, ng, t_stop,
@@ -628,13 +924,21 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
 
     HIP_TRY(hipMemcpy(s->d_t0.p, s->seg_t.data(), size_t(nseg) * sizeof(double),
                       hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(256), 0, st, c, sg, nseg, s->d_t0.p);
+    hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(256), 0, st, c, sg, nseg, s->d_t0.p,
+                       s->cur);
     ev_begin(KK_DTINIT, st);
-    if (f32)
-        hipLaunchKernelGGL(dt_init_f32_kernel, grid, block, 0, st, m, tm, s->d_wf.p, p.g, p.thr,
-                           sg);
+    if (f32 && faces)
+        launch_faces_dt_init_f32(s->tile, s->ntiles, st, fm, ftm, s->d_wf[s->cur].p, s->d_h.p,
+                                 s->d_area.p, p.g, p.thr, sg);
+    else if (f32)
+        hipLaunchKernelGGL(dt_init_f32_kernel, grid, block, 0, st, m, tm, s->d_wf[s->cur].p, p.g,
+                           p.thr, sg);
+    else if (faces)
+        launch_faces_dt_init(s->tile, s->ntiles, st, fm, ftm, s->d_w[s->cur].p, s->d_area.p, p.g,
+                             p.thr, sg);
     else
-        hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, tm, W, p.g, p.thr, sg);
+        hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, tm, s->d_w[s->cur].p, p.g,
+                           p.thr, sg);
     ev_end(st);
     if (use_graph) {
         for (int64_t k = 0; k + 1 < n; k += 2) HIP_TRY(hipGraphLaunch(s->graph_exec, st));
@@ -669,6 +973,9 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         cap = hc.err_step;
         rc = fail(VSW_EUNSTABLE, (hc.err & 1) ? "non-finite state" : "no valid time step");
     }
+    // every step before the failing one (all n without an error) moved the
+    // state to the other buffer; the failing step's input stays where it is
+    s->cur ^= int(cap & 1);
     int64_t done = 0;
     double tmin = INFINITY;
     s->seg_log.resize(nlog);
@@ -761,11 +1068,11 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     const std::vector<double> seg_log_save = s->seg_log, last_dts_save = s->last_dts;
     DevBuf<Cell4> W0, ck, seg;
     HIP_TRY(W0.alloc(size_t(n)));
-    HIP_TRY(hipMemcpyAsync(W0.p, s->d_w.p, size_t(n) * sizeof(Cell4), hipMemcpyDeviceToDevice,
-                           st));
+    HIP_TRY(hipMemcpyAsync(W0.p, s->d_w[s->cur].p, size_t(n) * sizeof(Cell4),
+                           hipMemcpyDeviceToDevice, st));
     auto restore = [&]() {
-        (void)hipMemcpyAsync(s->d_w.p, W0.p, size_t(n) * sizeof(Cell4), hipMemcpyDeviceToDevice,
-                             st);
+        (void)hipMemcpyAsync(s->d_w[s->cur].p, W0.p, size_t(n) * sizeof(Cell4),
+                             hipMemcpyDeviceToDevice, st);
         (void)hipMemcpyAsync(s->d_w1.p, W0.p, size_t(n) * sizeof(Cell4),
                              hipMemcpyDeviceToDevice, st);
         (void)hipStreamSynchronize(st);
@@ -777,10 +1084,17 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
         s->seg_steps = seg_steps_save;
         s->seg_log = seg_log_save;
         s->last_dts = last_dts_save;
-        if (s->d_gauge_cells.alloc(user_gauges.size()) == hipSuccess && !user_gauges.empty())
+        // the adjoint takes a single scenario: every gauge is in scenario 0
+        const std::vector<int32_t> zeros(user_gauges.size(), 0);
+        const bool ok = s->d_gauge_cells.alloc(user_gauges.size()) == hipSuccess &&
+                        s->d_gauge_seg.alloc(user_gauges.size()) == hipSuccess;
+        if (ok && !user_gauges.empty()) {
             (void)hipMemcpy(s->d_gauge_cells.p, user_gauges.data(),
                             user_gauges.size() * sizeof(int64_t), hipMemcpyHostToDevice);
-        s->ngauges = int(user_gauges.size());
+            (void)hipMemcpy(s->d_gauge_seg.p, zeros.data(), zeros.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice);
+        }
+        s->ngauges = ok ? int(user_gauges.size()) : 0;
         s->gauge_eta.clear();
         s->gauge_t.clear();
         s->release_graph();
@@ -794,7 +1108,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
         return fail(VSW_ENOMEM, "checkpoint memory");
     std::vector<double> dts, eta;
     for (int64_t c = 0; c < nck; ++c) {
-        HIP_TRY(hipMemcpyAsync(ck.p + c * n, s->d_w.p, size_t(n) * sizeof(Cell4),
+        HIP_TRY(hipMemcpyAsync(ck.p + c * n, s->d_w[s->cur].p, size_t(n) * sizeof(Cell4),
                                hipMemcpyDeviceToDevice, st));
         const int64_t m = std::min(ckpt, nsteps - c * ckpt);
         int64_t done = 0;
@@ -861,17 +1175,17 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                                rmin_hist.p);
         }
         hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(256), 0, st, s->d_ctrl.p, s->d_seg.p,
-                           1, s->d_t0.p);
+                           1, s->d_t0.p, 0);
         for (int64_t i = 0; i < len; ++i) {
             Cell4* Wi = seg.p + i * n;
             Cell4* W1i = segW1.p + i * n;
             const StepParams p{g, hg, thr, cfl, dts[size_t(n0 + i)], INFINITY};
-            const Tape t1{tR0.p + 3 * i * n, tm1.p + i * n, nullptr, nullptr};
-            const Tape t2{tR1.p + 3 * i * n, tm2.p + i * n, (i + 1 < len) ? Wi + n : wend.p,
-                          rmin_hist.p + i + 1};
-            hipLaunchKernelGGL(stage_tape_kernel<1>, grid, block, lds, st, m, tm, Wi, W1i, p,
+            Cell4* Wo = (i + 1 < len) ? Wi + n : wend.p;
+            const Tape t1{tR0.p + 3 * i * n, tm1.p + i * n, nullptr};
+            const Tape t2{tR1.p + 3 * i * n, tm2.p + i * n, rmin_hist.p + i + 1};
+            hipLaunchKernelGGL(stage_tape_kernel<1>, grid, block, lds, st, m, tm, Wi, Wo, W1i, p,
                                s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t1);
-            hipLaunchKernelGGL(stage_tape_kernel<2>, grid, block, lds, st, m, tm, Wi, W1i, p,
+            hipLaunchKernelGGL(stage_tape_kernel<2>, grid, block, lds, st, m, tm, Wi, Wo, W1i, p,
                                s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
         }
         bool started = false;  // the start of step k was done by the previous turn
@@ -951,15 +1265,22 @@ int vsw_set_gauges(vsw_solver* s, int32_t n, const int32_t* cells) {
     for (int64_t i = 0; i < s->nint; ++i)
         if (s->perm[i] >= 0) inv[s->perm[i]] = i;
     std::vector<int64_t> idx(n);
+    std::vector<int32_t> seg(n);
     for (int32_t g = 0; g < n; ++g) {
         if (cells[g] < 0 || cells[g] >= s->nc) return fail(VSW_EINVAL, "gauge cell out of range");
         idx[g] = inv[cells[g]];
+        seg[g] = int32_t(std::upper_bound(s->seg_off.begin(), s->seg_off.end(),
+                                          int64_t(cells[g])) - s->seg_off.begin()) - 1;
     }
     DeviceGuard dg(s->device);
     HIP_TRY(s->d_gauge_cells.alloc(size_t(n)));
-    if (n > 0)
+    HIP_TRY(s->d_gauge_seg.alloc(size_t(n)));
+    if (n > 0) {
         HIP_TRY(hipMemcpy(s->d_gauge_cells.p, idx.data(), size_t(n) * sizeof(int64_t),
                           hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->d_gauge_seg.p, seg.data(), size_t(n) * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    }
     s->ngauges = n;
     s->gauge_eta.clear();
     s->gauge_t.clear();
@@ -980,7 +1301,8 @@ int vsw_get_gauges(vsw_solver* s, int64_t max_steps, double* eta_out, double* t_
 
 int vsw_set_kernel_variant(vsw_solver* s, int variant) {
     if (!s) return fail(VSW_EINVAL, "NULL solver");
-    if (variant != VSW_KERNEL_FUSED && variant != VSW_KERNEL_TWO_PASS)
+    if (variant != VSW_KERNEL_FUSED && variant != VSW_KERNEL_TWO_PASS &&
+        variant != VSW_KERNEL_FACES)
         return fail(VSW_EINVAL, "unknown kernel variant");
     if (variant == VSW_KERNEL_TWO_PASS && s->prm.precision == VSW_FP32)
         return fail(VSW_EINVAL, "the two-pass variant is FP64 only");
@@ -1015,8 +1337,9 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
     const size_t bytes = n * (f32 ? sizeof(CellF) : sizeof(Cell4));
     DevBuf<unsigned char> save;
     HIP_TRY(save.alloc(bytes));
-    void* wp = f32 ? (void*)s->d_wf.p : (void*)s->d_w.p;
-    HIP_TRY(hipMemcpyAsync(save.p, wp, bytes, hipMemcpyDeviceToDevice, st));
+    // the buffer holding the current state (it alternates as steps run)
+    auto wp = [&]() { return f32 ? (void*)s->d_wf[s->cur].p : (void*)s->d_w[s->cur].p; };
+    HIP_TRY(hipMemcpyAsync(save.p, wp(), bytes, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     const double t_save = s->t, dt_save = s->dt_last;
     const int64_t clamps_save = s->clamps;
@@ -1032,7 +1355,7 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
     const auto restore_on_exit = on_exit([&]() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        (void)hipMemcpyAsync(wp, save.p, bytes, hipMemcpyDeviceToDevice, st);
+        (void)hipMemcpyAsync(wp(), save.p, bytes, hipMemcpyDeviceToDevice, st);
         (void)hipStreamSynchronize(st);
         s->t = t_save;
         s->dt_last = dt_save;
@@ -1078,7 +1401,7 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
             float f = 0.f;
             HIP_TRY(hipEventElapsedTime(&f, e0, e1));
             ms = double(f) / double(steps);
-            HIP_TRY(hipMemcpyAsync(wp, save.p, bytes, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(wp(), save.p, bytes, hipMemcpyDeviceToDevice, st));
             HIP_TRY(hipStreamSynchronize(st));
         }
         if (ms_per_step) ms_per_step[c] = ms;

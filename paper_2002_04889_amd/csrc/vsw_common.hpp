@@ -33,9 +33,9 @@ struct TileInfo {
 
 __device__ __forceinline__ TileInfo tile_info(uint32_t v) {
     TileInfo t;
-    t.seg = int(v >> 9);
-    t.first = ((v >> 8) & 1u) != 0;
-    t.cnt = int(v & 255u) + 1;
+    t.seg = int(v >> 10);
+    t.first = ((v >> 9) & 1u) != 0;
+    t.cnt = int(v & 511u) + 1;
     return t;
 }
 
@@ -61,21 +61,44 @@ __device__ __forceinline__ bool step_dt(const Ctrl* c, const Seg* sg, int slot,
     return true;
 }
 
+// The two state buffers of step `step` of the call: w^n is read from in,
+// w^{n+1} written to out.
+template <class T>
+__device__ __forceinline__ void step_buffers(const Ctrl* c, int step, T* Wa, T* Wb, T*& in,
+                                             T*& out) {
+    const bool odd = ((c->par + step) & 1) != 0;
+    in = odd ? Wb : Wa;
+    out = odd ? Wa : Wb;
+}
+
+// A scenario whose time has reached t_stop takes no more steps in this call;
+// its cells are carried into the buffer the step writes (not after an error,
+// where the failing step's input stays where it is).
+template <class T>
+__device__ __forceinline__ void carry_state(const Ctrl* c, const Seg* sg, int slot,
+                                            const StepParams& p, const T* __restrict__ in,
+                                            T* __restrict__ out, int64_t c0, int cnt) {
+    if (c->err || sg->t[slot] < p.t_stop) return;
+    const int i = threadIdx.x;
+    if (i < cnt) out[c0 + i] = in[c0 + i];
+}
+
 // CFL ratio |K| / (P_K (|u| + sqrt(g H))) of a wet cell, +inf otherwise.
 __device__ __forceinline__ double cfl_ratio(double H, double HU, double HV, double area,
                                             double perim, double g, double thr) {
     if (!(H >= thr)) return __longlong_as_double(0x7FF0000000000000ll);
-    const double rH = 1.0 / H, u = HU * rH, v = HV * rH;
+    const double u = HU / H, v = HV / H;
     const double s = sqrt(u * u + v * v) + sqrt(g * H);
     return area / (perim * s);
 }
 
-// Block-wide min of a positive double, then one atomic min on its bits.
-// The bits of positive doubles order like the values; a plain read first
-// skips the atomic when the target already holds a value at least as small
-// (values only decrease, so a stale read never loses one).
+// Block-wide min of a positive double over NT threads, then one atomic min
+// on its bits.  The bits of positive doubles order like the values; a plain
+// read first skips the atomic when the target already holds a value at
+// least as small (values only decrease, so a stale read never loses one).
+template <int NT = kBlock>
 __device__ __forceinline__ void block_min_atomic(double v, unsigned long long* target) {
-    __shared__ double part[kBlock / 64];
+    __shared__ double part[NT / 64];
     v = wave_min(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) part[wid] = v;
@@ -83,7 +106,7 @@ __device__ __forceinline__ void block_min_atomic(double v, unsigned long long* t
     if (threadIdx.x == 0) {
         double m = part[0];
 #pragma unroll
-        for (int i = 1; i < kBlock / 64; ++i) m = (part[i] < m) ? part[i] : m;
+        for (int i = 1; i < NT / 64; ++i) m = (part[i] < m) ? part[i] : m;
         const unsigned long long b = dbits(m);
         if (m < __longlong_as_double(0x7FF0000000000000ll) &&
             b < __hip_atomic_load(target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
@@ -91,8 +114,9 @@ __device__ __forceinline__ void block_min_atomic(double v, unsigned long long* t
     }
 }
 
+template <int NT = kBlock>
 __device__ __forceinline__ void block_count_atomic(unsigned long long v, unsigned long long* target) {
-    __shared__ unsigned long long part[kBlock / 64];
+    __shared__ unsigned long long part[NT / 64];
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) part[wid] = v;
@@ -100,9 +124,42 @@ __device__ __forceinline__ void block_count_atomic(unsigned long long v, unsigne
     if (threadIdx.x == 0) {
         unsigned long long s = 0;
 #pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) s += part[i];
+        for (int i = 0; i < NT / 64; ++i) s += part[i];
         if (s) atomicAdd(target, s);
     }
+}
+
+// Stage 1: w1 = w + dt R(w), then the post-stage fix (negative depth set to
+// zero and counted; velocity zero below H_thr).
+// mk: bit 0 cleared when the depth is clamped, bit 1 when the momentum is
+// zeroed (what the adjoint of the fix needs).
+__device__ __forceinline__ Cell4 stage1_update(const Cell4& w, const double R[3], double dt,
+                                               double thr, unsigned long long& clamp,
+                                               uint8_t& mk) {
+    Cell4 o;
+    o.H = w.H + dt * R[0];
+    o.HU = w.HU + dt * R[1];
+    o.HV = w.HV + dt * R[2];
+    o.h = w.h;
+    mk = 3;
+    if (o.H < 0.0) { o.H = 0.0; clamp = 1; mk &= uint8_t(~1u); }
+    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; mk &= uint8_t(~2u); }
+    return o;
+}
+
+// Stage 2: w^{n+1} = w/2 + (w1 + dt R(w1))/2, then the post-stage fix.
+__device__ __forceinline__ Cell4 stage2_update(const Cell4& w, const Cell4& w1, const double R[3],
+                                               double dt, double thr, unsigned long long& clamp,
+                                               uint8_t& mk) {
+    Cell4 o;
+    o.H = 0.5 * w.H + 0.5 * (w1.H + dt * R[0]);
+    o.HU = 0.5 * w.HU + 0.5 * (w1.HU + dt * R[1]);
+    o.HV = 0.5 * w.HV + 0.5 * (w1.HV + dt * R[2]);
+    o.h = w.h;
+    mk = 3;
+    if (o.H < 0.0) { o.H = 0.0; clamp = 1; mk &= uint8_t(~1u); }
+    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; mk &= uint8_t(~2u); }
+    return o;
 }
 
 // Time bookkeeping of a scenario at the end of stage 2 (thread 0 of the
@@ -166,10 +223,10 @@ __device__ __forceinline__ void residual_from_faces(const DevMesh& m, const Face
         a1 = a1 + fb.sc[k];
         a2 = a2 + fb.sc[nc + k];
     }
-    const double ra = 1.0 / m.area[k];
-    R[0] = a0 * ra;
-    R[1] = a1 * ra;
-    R[2] = a2 * ra;
+    const double ar = m.area[k];
+    R[0] = a0 / ar;
+    R[1] = a1 / ar;
+    R[2] = a2 / ar;
 }
 
 // A face state in LDS: eta, h, u, v at slot + c * stride.  The face depth H

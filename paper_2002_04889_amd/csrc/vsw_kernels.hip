@@ -20,13 +20,13 @@ namespace vsw {
 
 // ---------------------------------------------------------------- control
 
-__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0) {
+__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0, int par) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->err = 0;
         c->err_step = 0x7FFFFFFF;
         c->clamps = 0;
         c->kbase = 0;
-        c->pad = 0;
+        c->par = par;
     }
     for (int s = int(blockIdx.x * blockDim.x + threadIdx.x); s < nseg;
          s += int(gridDim.x * blockDim.x)) {
@@ -60,13 +60,19 @@ __global__ __launch_bounds__(kBlock) void dt_init_kernel(DevMesh m, TileMap tm,
 // ---------------------------------------------------------------- two-pass kernels
 
 // The two-pass kernels run one block per tile (kBlock == kTile).
+template <int STAGE>
 __global__ __launch_bounds__(kBlock) void recon_kernel(DevMesh m, TileMap tm,
-                                                       const Cell4* __restrict__ W, FaceBuf fb,
+                                                       const Cell4* __restrict__ Wa,
+                                                       const Cell4* __restrict__ Wb,
+                                                       const Cell4* __restrict__ W1, FaceBuf fb,
                                                        StepParams p, const Ctrl* c, const Seg* sg,
-                                                       int slot) {
+                                                       int slot, int step_arg) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     double dt, tn;
     if (!step_dt(c, sg + ti.seg, slot, p, dt, tn)) return;
+    const Cell4 *Win, *Wout;
+    step_buffers(c, c->kbase + step_arg, Wa, Wb, Win, Wout);
+    const Cell4* __restrict__ W = (STAGE == 1) ? Win : W1;
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (int(threadIdx.x) >= ti.cnt) return;
     const int64_t nc = m.nc;
@@ -86,46 +92,24 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(DevMesh m, TileMap tm,
     fb.order[k] = second ? 2 : 1;
 }
 
-// Stage 1: w1 = w + dt R(w), then the post-stage fix (negative depth set to
-// zero and counted; velocity zero below H_thr).
-// mk: bit 0 cleared when the depth is clamped, bit 1 when the momentum is
-// zeroed (what the adjoint of the fix needs).
-__device__ __forceinline__ Cell4 stage1_update(const Cell4& w, const double R[3], double dt,
-                                               double thr, unsigned long long& clamp,
-                                               uint8_t& mk) {
-    Cell4 o;
-    o.H = w.H + dt * R[0];
-    o.HU = w.HU + dt * R[1];
-    o.HV = w.HV + dt * R[2];
-    o.h = w.h;
-    mk = 3;
-    if (o.H < 0.0) { o.H = 0.0; clamp = 1; mk &= uint8_t(~1u); }
-    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; mk &= uint8_t(~2u); }
-    return o;
-}
-
-// Stage 2: w^{n+1} = w/2 + (w1 + dt R(w1))/2, then the post-stage fix.
-__device__ __forceinline__ Cell4 stage2_update(const Cell4& w, const Cell4& w1, const double R[3],
-                                               double dt, double thr, unsigned long long& clamp,
-                                               uint8_t& mk) {
-    Cell4 o;
-    o.H = 0.5 * w.H + 0.5 * (w1.H + dt * R[0]);
-    o.HU = 0.5 * w.HU + 0.5 * (w1.HU + dt * R[1]);
-    o.HV = 0.5 * w.HV + 0.5 * (w1.HV + dt * R[2]);
-    o.h = w.h;
-    mk = 3;
-    if (o.H < 0.0) { o.H = 0.0; clamp = 1; mk &= uint8_t(~1u); }
-    if (o.H < thr) { o.HU = 0.0; o.HV = 0.0; mk &= uint8_t(~2u); }
-    return o;
-}
+template __global__ void recon_kernel<1>(DevMesh, TileMap, const Cell4*, const Cell4*,
+                                         const Cell4*, FaceBuf, StepParams, const Ctrl*,
+                                         const Seg*, int, int);
+template __global__ void recon_kernel<2>(DevMesh, TileMap, const Cell4*, const Cell4*,
+                                         const Cell4*, FaceBuf, StepParams, const Ctrl*,
+                                         const Seg*, int, int);
 
 __global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, TileMap tm,
-                                                         const Cell4* __restrict__ W,
+                                                         const Cell4* __restrict__ Wa,
+                                                         const Cell4* __restrict__ Wb,
                                                          Cell4* __restrict__ W1, FaceBuf fb,
-                                                         StepParams p, Ctrl* c, Seg* sg, int slot) {
+                                                         StepParams p, Ctrl* c, Seg* sg, int slot,
+                                                         int step_arg) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     double dt, tn;
     if (!step_dt(c, sg + ti.seg, slot, p, dt, tn)) return;
+    const Cell4 *W, *Wout;
+    step_buffers(c, c->kbase + step_arg, Wa, Wb, W, Wout);
     if (ti.first && threadIdx.x == 0) sg[ti.seg].rmin[slot ^ 1] = 0x7FF0000000000000ull;
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     unsigned long long clamp = 0;
@@ -139,16 +123,20 @@ __global__ __launch_bounds__(kBlock) void update1_kernel(DevMesh m, TileMap tm,
 }
 
 __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, TileMap tm,
-                                                         Cell4* __restrict__ W,
+                                                         Cell4* __restrict__ Wa,
+                                                         Cell4* __restrict__ Wb,
                                                          const Cell4* __restrict__ W1, FaceBuf fb,
                                                          StepParams p, Ctrl* c, Seg* sg, int slot,
                                                          int step_arg, double* log) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     Seg* sgs = sg + ti.seg;
     const int step = c->kbase + step_arg;
+    Cell4 *W, *Wout;
+    step_buffers(c, step, Wa, Wb, W, Wout);
     double dt, tn;
     const bool active = step_dt(c, sgs, slot, p, dt, tn);
     if (!active) {
+        carry_state(c, sgs, slot, p, W, Wout, int64_t(blockIdx.x) * kBlock, ti.cnt);
         stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, log);
         return;
     }
@@ -161,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, TileMap tm,
         residual_from_faces(m, fb, k, p.g, p.hg, R);
         uint8_t mk;
         const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp, mk);
-        W[k] = o;
+        Wout[k] = o;
         bad = !isfinite(o.H) || !isfinite(o.HU) || !isfinite(o.HV);
         r = cfl_ratio(o.H, o.HU, o.HV, m.area[k], m.perim[k], p.g, p.thr);
     }
@@ -187,20 +175,25 @@ __global__ __launch_bounds__(kBlock) void update2_kernel(DevMesh m, TileMap tm,
 // the adjoint records (see Tape) and leaves the arithmetic as it is.
 template <int STAGE, bool TAPE>
 __device__ __forceinline__ void stage_body(const DevMesh& m, const TileMap& tm,
-                                           Cell4* __restrict__ W, Cell4* __restrict__ W1,
-                                           const StepParams& p, Ctrl* c, Seg* sg, int slot,
-                                           int step_arg, double* log, const Tape& tp) {
+                                           Cell4* __restrict__ Wa, Cell4* __restrict__ Wb,
+                                           Cell4* __restrict__ W1, const StepParams& p, Ctrl* c,
+                                           Seg* sg, int slot, int step_arg, double* log,
+                                           const Tape& tp) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
     const int t = tm.xcd_order ? xcd_tile(int(blockIdx.x), tm.ntiles) : int(blockIdx.x);
     const TileInfo ti = tile_info(tm.tinfo[t]);
     Seg* sgs = sg + ti.seg;
     const int step = c->kbase + step_arg;
+    Cell4 *W, *Wout;
+    step_buffers(c, step, Wa, Wb, W, Wout);
     double dt, tn;
     const bool active = step_dt(c, sgs, slot, p, dt, tn);
     if (!active) {
-        if (STAGE == 2)
+        if (STAGE == 2) {
+            carry_state(c, sgs, slot, p, W, Wout, int64_t(t) * kTile, ti.cnt);
             stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, log);
+        }
         return;
     }
     if (STAGE == 1 && ti.first && threadIdx.x == 0) sgs->rmin[slot ^ 1] = 0x7FF0000000000000ull;
@@ -243,14 +236,13 @@ __device__ __forceinline__ void stage_body(const DevMesh& m, const TileMap& tm,
             a2 = a2 + sc[1];
         }
         const double ar = m.area[k];
-        const double ra = 1.0 / ar;
-        const double R[3] = {a0 * ra, a1 * ra, a2 * ra};
+        const double R[3] = {a0 / ar, a1 / ar, a2 / ar};
         uint8_t mk;
         if (STAGE == 1) {
             W1[k] = stage1_update(W[k], R, dt, p.thr, clamp, mk);
         } else {
             const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp, mk);
-            if (TAPE) tp.wout[k] = o; else W[k] = o;
+            Wout[k] = o;
             bad = !isfinite(o.H) || !isfinite(o.HU) || !isfinite(o.HV);
             rr = cfl_ratio(o.H, o.HU, o.HV, ar, m.perim[k], p.g, p.thr);
         }
@@ -273,44 +265,50 @@ __device__ __forceinline__ void stage_body(const DevMesh& m, const TileMap& tm,
 }
 
 template <int STAGE>
-__global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm, Cell4* __restrict__ W,
+__global__ __launch_bounds__(kBlock) void stage_kernel(DevMesh m, TileMap tm,
+                                                       Cell4* __restrict__ Wa,
+                                                       Cell4* __restrict__ Wb,
                                                        Cell4* __restrict__ W1, StepParams p,
                                                        Ctrl* c, Seg* sg, int slot, int step_arg,
                                                        double* log) {
-    stage_body<STAGE, false>(m, tm, W, W1, p, c, sg, slot, step_arg, log, Tape{});
+    stage_body<STAGE, false>(m, tm, Wa, Wb, W1, p, c, sg, slot, step_arg, log, Tape{});
 }
 
 template <int STAGE>
 __global__ __launch_bounds__(kBlock) void stage_tape_kernel(DevMesh m, TileMap tm,
                                                             Cell4* __restrict__ W,
+                                                            Cell4* __restrict__ Wout,
                                                             Cell4* __restrict__ W1, StepParams p,
                                                             Ctrl* c, Seg* sg, int slot,
                                                             int step_arg, double* log, Tape tp) {
-    stage_body<STAGE, true>(m, tm, W, W1, p, c, sg, slot, step_arg, log, tp);
+    stage_body<STAGE, true>(m, tm, W, Wout, W1, p, c, sg, slot, step_arg, log, tp);
 }
 
-template __global__ void stage_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, Seg*,
-                                         int, int, double*);
-template __global__ void stage_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*, Seg*,
-                                         int, int, double*);
-template __global__ void stage_tape_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*,
-                                              Seg*, int, int, double*, Tape);
-template __global__ void stage_tape_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, StepParams, Ctrl*,
-                                              Seg*, int, int, double*, Tape);
+template __global__ void stage_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, Cell4*, StepParams,
+                                         Ctrl*, Seg*, int, int, double*);
+template __global__ void stage_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, Cell4*, StepParams,
+                                         Ctrl*, Seg*, int, int, double*);
+template __global__ void stage_tape_kernel<1>(DevMesh, TileMap, Cell4*, Cell4*, Cell4*,
+                                              StepParams, Ctrl*, Seg*, int, int, double*, Tape);
+template __global__ void stage_tape_kernel<2>(DevMesh, TileMap, Cell4*, Cell4*, Cell4*,
+                                              StepParams, Ctrl*, Seg*, int, int, double*, Tape);
 
 // ---------------------------------------------------------------- gauges
 
 // Free surface eta = H - h at the gauge cells after step `step`, if the
 // gauge's scenario took the step (steps_done counts the steps it took in
 // this call; once a scenario stops, it takes no later step of the call).
-__global__ void gauge_kernel(const Cell4* __restrict__ W, const int64_t* __restrict__ cells,
-                             int ng, const uint32_t* __restrict__ tinfo, const Seg* sg,
-                             const Ctrl* c, int step_arg, double* __restrict__ log) {
+__global__ void gauge_kernel(const Cell4* __restrict__ Wa, const Cell4* __restrict__ Wb,
+                             const int64_t* __restrict__ cells, int ng,
+                             const int32_t* __restrict__ gseg, const Seg* sg, const Ctrl* c,
+                             int step_arg, double* __restrict__ log) {
     const int gi = int(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gi >= ng) return;
     const int step = c->kbase + step_arg;
+    const Cell4 *Win, *W;
+    step_buffers(c, step, Wa, Wb, Win, W);
     const int64_t k = cells[gi];
-    if (sg[tinfo[k / kTile] >> 9].steps_done <= step) return;
+    if (sg[gseg[gi]].steps_done <= step) return;
     const Cell4 q = W[k];
     log[int64_t(step) * ng + gi] = q.H - q.h;
 }
@@ -334,6 +332,19 @@ __global__ void pack_state_kernel(int64_t n, const int64_t* __restrict__ perm,
     q.h = h[i];
     W[i] = q;
     W1[i] = q;
+}
+
+__global__ void check_state_kernel(int64_t nc, const double* __restrict__ H,
+                                   const double* __restrict__ HU, const double* __restrict__ HV,
+                                   int* flag) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int f = 0;
+    if (k < nc) {
+        const double a = H[k], b = HU[k], d = HV[k];
+        if (!isfinite(a) || !isfinite(b) || !isfinite(d)) f |= 1;
+        if (a < 0.0) f |= 2;
+    }
+    if (f) atomicOr(flag, f);
 }
 
 // Internal-order state records into caller-order arrays.

@@ -29,7 +29,7 @@ struct Ctrl {
     int err;                     // bit 0: non-finite state, bit 1: no valid dt
     int err_step;                // first failing step of the call
     int kbase;                   // step index = kbase + the kernel's step argument
-    int pad;
+    int par;                     // state buffer (0 or 1) that holds the call's first state
 };
 
 struct StepParams {
@@ -48,8 +48,8 @@ struct FaceBuf {
 constexpr int kTile = 256;   // cells per tile of the fused stage kernel (= kBlock)
 constexpr uint16_t kNlocWall16 = 0xFFFFu;
 
-// Tile word: bits 0-7 the tile's cell count minus one, bit 8 set on the
-// first tile of a scenario, bits 9-31 the scenario index.
+// Tile word: bits 0-8 the tile's cell count minus one, bit 9 set on the
+// first tile of a scenario, bits 10-31 the scenario index.
 struct TileMap {
     const uint16_t* __restrict__ nloc;   // [3][nc] LDS slot per face, bit 15 = left
     const int32_t* __restrict__ bstart;  // [ntiles + 1]
@@ -61,15 +61,21 @@ struct TileMap {
     int xcd_order;                       // 1: deal contiguous tile runs to the XCDs
 };
 
+// The state lives in two buffers Wa, Wb: step k of a call reads w^n from
+// buffer (par + k) & 1 and writes w^{n+1} to the other one, so the input of
+// a step is never overwritten by it.  A scenario that has reached t_stop
+// copies its cells across instead; a step that fails leaves its input in
+// place (the solver's state after VSW_EUNSTABLE).
+//
 // Fused stage kernel.  STAGE 1: w1 = w + dt R(w).  STAGE 2:
-// w^{n+1} = w/2 + (w1 + dt R(w1))/2 in place, plus the next CFL minimum and
-// the time bookkeeping.  Dynamic LDS: stage_lds_bytes(bmax).
+// w^{n+1} = w/2 + (w1 + dt R(w1))/2, plus the next CFL minimum and the time
+// bookkeeping.  Dynamic LDS: stage_lds_bytes(bmax).
 // Step k of the call is kbase + step_arg (kbase advances on the device, so a
 // captured pair of steps can be replayed).  Log: log[2 (k nseg + scenario)]
 // = time after the step, log[2 (k nseg + scenario) + 1] = its dt.
 template <int STAGE>
-__global__ void stage_kernel(DevMesh m, TileMap tm, Cell4* W, Cell4* W1, StepParams p, Ctrl* c,
-                             Seg* sg, int slot, int step_arg, double* log);
+__global__ void stage_kernel(DevMesh m, TileMap tm, Cell4* Wa, Cell4* Wb, Cell4* W1, StepParams p,
+                             Ctrl* c, Seg* sg, int slot, int step_arg, double* log);
 
 // LDS of the fused stage kernel: four doubles (eta, h, u, v) per face slot.
 inline size_t stage_lds_bytes(int bmax) { return sizeof(double) * 4 * size_t(3 * kTile + bmax); }
@@ -77,34 +83,45 @@ inline size_t stage_lds_bytes(int bmax) { return sizeof(double) * 4 * size_t(3 *
 // What the discrete adjoint records of a stage while it replays a checkpoint
 // segment: the stage's residual R (3 per cell) and the mask of its
 // post-stage fix (bit 0: depth not clamped, bit 1: momentum kept); stage 2
-// writes w^{n+1} to wout (w^n is kept) and the bits of the CFL minimum of
-// w^{n+1} to *rmin (pre-set to +inf) instead of the scenario's record.
+// writes the bits of the CFL minimum of w^{n+1} to *rmin (pre-set to +inf)
+// instead of the scenario's record.
 struct Tape {
     double* __restrict__ R;
     uint8_t* __restrict__ mask;
-    Cell4* __restrict__ wout;
     unsigned long long* rmin;
 };
 
-// The fused stage kernel with a tape: the same arithmetic and results.
+// The fused stage kernel with a tape: the same arithmetic and results.  It
+// reads w^n from W and writes w^{n+1} to Wout (the control block's par and
+// step index are 0).
 template <int STAGE>
-__global__ void stage_tape_kernel(DevMesh m, TileMap tm, Cell4* W, Cell4* W1, StepParams p,
-                                  Ctrl* c, Seg* sg, int slot, int step_arg, double* log, Tape tp);
+__global__ void stage_tape_kernel(DevMesh m, TileMap tm, Cell4* W, Cell4* Wout, Cell4* W1,
+                                  StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg,
+                                  double* log, Tape tp);
 
-// Start of a call: every scenario's time from t0[s], minima cleared.
-__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0);
+// Start of a call: every scenario's time from t0[s], minima cleared; par is
+// the state buffer holding the call's first state.
+__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0, int par);
 // CFL minimum of the incoming state, one block per tile.
 __global__ void dt_init_kernel(DevMesh m, TileMap tm, const Cell4* W, double g, double thr,
                                Seg* sg);
-__global__ void recon_kernel(DevMesh m, TileMap tm, const Cell4* W, FaceBuf fb, StepParams p,
-                             const Ctrl* c, const Seg* sg, int slot);
-__global__ void update1_kernel(DevMesh m, TileMap tm, const Cell4* W, Cell4* W1, FaceBuf fb,
-                               StepParams p, Ctrl* c, Seg* sg, int slot);
-__global__ void update2_kernel(DevMesh m, TileMap tm, Cell4* W, const Cell4* W1, FaceBuf fb,
-                               StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg,
+// Two-pass organisation: recon_kernel reconstructs the state the stage reads
+// (STAGE 1: w^n from Wa/Wb; STAGE 2: w1) into the face buffer.
+template <int STAGE>
+__global__ void recon_kernel(DevMesh m, TileMap tm, const Cell4* Wa, const Cell4* Wb,
+                             const Cell4* W1, FaceBuf fb, StepParams p, const Ctrl* c,
+                             const Seg* sg, int slot, int step_arg);
+__global__ void update1_kernel(DevMesh m, TileMap tm, const Cell4* Wa, const Cell4* Wb,
+                               Cell4* W1, FaceBuf fb, StepParams p, Ctrl* c, Seg* sg, int slot,
+                               int step_arg);
+__global__ void update2_kernel(DevMesh m, TileMap tm, Cell4* Wa, Cell4* Wb, const Cell4* W1,
+                               FaceBuf fb, StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg,
                                double* log);
-__global__ void gauge_kernel(const Cell4* W, const int64_t* cells, int ng, const uint32_t* tinfo,
-                             const Seg* sg, const Ctrl* c, int step_arg, double* log);
+// Free surface at the gauge cells after step kbase + step_arg (read from the
+// buffer that step wrote); gseg[g] is the scenario of gauge g.
+__global__ void gauge_kernel(const Cell4* Wa, const Cell4* Wb, const int64_t* cells, int ng,
+                             const int32_t* gseg, const Seg* sg, const Ctrl* c, int step_arg,
+                             double* log);
 // Advance the step base by `by` steps (the last node of a captured pair).
 __global__ void step_bump_kernel(Ctrl* c, int by);
 // perm[i] = caller index of internal cell i, or -1 for the padding cells
@@ -112,6 +129,10 @@ __global__ void step_bump_kernel(Ctrl* c, int by);
 __global__ void pack_state_kernel(int64_t n, const int64_t* perm, const double* H,
                                   const double* HU, const double* HV, const double* h, Cell4* W,
                                   Cell4* W1);
+// Checks a caller-order state (nc cells): bit 0 of *flag for a non-finite
+// value, bit 1 for a negative depth (*flag is cleared by the caller).
+__global__ void check_state_kernel(int64_t nc, const double* H, const double* HU,
+                                   const double* HV, int* flag);
 __global__ void unpack_state_kernel(int64_t n, const int64_t* perm, const Cell4* W, double* H,
                                     double* HU, double* HV);
 

@@ -17,6 +17,7 @@
 // by the post-stage fix stores eta = -h rounded upward, so its depth
 // eta + h is never negative.
 #include "vsw_common.hpp"
+#include "vsw_faces.hpp"
 #include "vsw_kernels_f32.hpp"
 
 namespace vsw {
@@ -33,30 +34,37 @@ struct ReconF {
 __device__ __forceinline__ float fminf_(float a, float b) { return (b < a) ? b : a; }
 __device__ __forceinline__ float fmaxf_(float a, float b) { return (b > a) ? b : a; }
 
-__device__ __forceinline__ void recon_core_f32(const DevMesh& m, const CellF* __restrict__ W,
-                                               int64_t k, double thr, ReconF& r) {
+// FP32 reconstruction of cell k.  Geometry from callbacks as in recon_with:
+// wall_n(j, nx, ny) in FP64 (rounded here), geo(w, d) as FP32 values.
+template <class WallN, class Geo>
+__device__ __forceinline__ void recon_with_f32(const CellF* __restrict__ W,
+                                               const double* __restrict__ hc, int64_t k,
+                                               const uint32_t sl[3], double thr, WallN wall_n,
+                                               Geo geo, ReconF& r) {
     const CellF ck = W[k];
-    const double hk = ck.h;
+    const double hk = hc[k];
     const float ek = ck.eta, uk = ck.hu, vk = ck.hv;
     const double Hk = double(ek) + hk;
-    const Nbr4 nb = m.nbr[k];
-    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
     float qe[3], qu[3], qv[3], dh[3];
     bool cand = (Hk >= thr);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const uint32_t s = sl[j];
         if (s != kWallSlot) {
-            const CellF cn = W[int64_t(s >> 3)];
-            const double Hn = double(cn.eta) + cn.h;
+            const int64_t n = int64_t(s >> 3);
+            const CellF cn = W[n];
+            const double hn = hc[n];
+            const double Hn = double(cn.eta) + hn;
             qe[j] = cn.eta;
             qu[j] = cn.hu;
             qv[j] = cn.hv;
-            dh[j] = float(cn.h - hk);
+            dh[j] = float(hn - hk);
             if (!(Hn >= thr)) cand = false;
         } else {
             // wall ghost: same depth and surface, mirrored momentum
-            const float nx = float(gf(m, 0, j, k)), ny = float(gf(m, 1, j, k));
+            double nxd, nyd;
+            wall_n(j, nxd, nyd);
+            const float nx = float(nxd), ny = float(nyd);
             const float mn = uk * nx + vk * ny;
             qe[j] = ek;
             qu[j] = uk - (2.0f * mn) * nx;
@@ -67,11 +75,12 @@ __device__ __forceinline__ void recon_core_f32(const DevMesh& m, const CellF* __
     r.Hk = Hk;
     r.hk = hk;
     if (cand) {
-        const RGeomF rg = m.rgeomf[k];
-        const float wx0 = rg.w[0], wx1 = rg.w[2], wx2 = rg.w[4];
-        const float wy0 = rg.w[1], wy1 = rg.w[3], wy2 = rg.w[5];
-        const float dxs[3] = {rg.d[0], rg.d[2], rg.d[4]};
-        const float dys[3] = {rg.d[1], rg.d[3], rg.d[5]};
+        float gw[6], gd[6];
+        geo(gw, gd);
+        const float wx0 = gw[0], wx1 = gw[2], wx2 = gw[4];
+        const float wy0 = gw[1], wy1 = gw[3], wy2 = gw[5];
+        const float dxs[3] = {gd[0], gd[2], gd[4]};
+        const float dys[3] = {gd[1], gd[3], gd[5]};
         auto project = [&](const float* qs, float q0, float* pj) {
             const float d0 = qs[0] - q0, d1 = qs[1] - q0, d2 = qs[2] - q0;
             const float gx = wx0 * d0 + wx1 * d1 + wx2 * d2;
@@ -124,6 +133,27 @@ __device__ __forceinline__ void recon_core_f32(const DevMesh& m, const CellF* __
         }
     }
     r.second = cand;
+}
+
+__device__ __forceinline__ void recon_core_f32(const DevMesh& m, const CellF* __restrict__ W,
+                                               int64_t k, double thr, ReconF& r) {
+    const Nbr4 nb = m.nbr[k];
+    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
+    recon_with_f32(
+        W, m.hcell, k, sl, thr,
+        [&](int j, double& nx, double& ny) {
+            nx = gf(m, 0, j, k);
+            ny = gf(m, 1, j, k);
+        },
+        [&](float* gw, float* gd) {
+            const RGeomF rg = m.rgeomf[k];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                gw[q] = rg.w[q];
+                gd[q] = rg.d[q];
+            }
+        },
+        r);
 }
 
 __device__ __forceinline__ FaceF recon_face_f32(const ReconF& r, int j, double thr) {
@@ -226,22 +256,86 @@ __device__ __forceinline__ bool face_term_f32(double g, double hg, const FaceF& 
     return left;
 }
 
+// A face evaluated once for both of its cells, canonical orientation (the
+// numbers face_term_f32 gives each side).  On a wall R is L itself.
+__device__ __forceinline__ void face_pair_f32(double g, double hg, const FaceF& L, const FaceF& R,
+                                              bool wall, double nx, double ny, double l,
+                                              double tL[3], double tR[3]) {
+    const float nxf = float(nx), nyf = float(ny);
+    const float unL = L.u * nxf + L.v * nyf, utL = L.v * nxf - L.u * nyf;
+    float unR = R.u * nxf + R.v * nyf;
+    const float utR = R.v * nxf - R.u * nyf;
+    const double hs = dmin(L.h, R.h);
+    const double HsL = dpos(double(L.eta) + hs), HsR = dpos(double(R.eta) + hs);
+    if (wall) unR = -unL;
+    float f0, f2;
+    double f1;
+    hll_face_f32(g, hg, HsL, unL, utL, HsR, unR, utR, f0, f1, f2);
+    const double pcL = hg * (L.H * L.H - HsL * HsL);
+    const double pcR = hg * (R.H * R.H - HsR * HsR);
+    const double phi1 = f1 * nx - double(f2) * ny;
+    const double phi2 = f1 * ny + double(f2) * nx;
+    tL[0] = l * double(f0);
+    tL[1] = l * (phi1 + pcL * nx);
+    tL[2] = l * (phi2 + pcL * ny);
+    tR[0] = tL[0];
+    tR[1] = l * (phi1 + pcR * nx);
+    tR[2] = l * (phi2 + pcR * ny);
+}
+
+// FP32 reconstruction of cell k from its vertices (geometry in FP64 as the
+// host computes it, rounded to FP32 where the FP32 terms use it) and FP32
+// least-squares weights.  area (may be null) receives |K|.
+__device__ __forceinline__ void recon_geo_f32(const FaceMesh& m, const CellF* __restrict__ W,
+                                              const double* __restrict__ hc, int64_t k,
+                                              double thr, ReconF& r, double* area) {
+    const TopoD tp = m.topo[k];
+    const double2 p0 = m.vxy[tp.v0], p1 = m.vxy[tp.v1], p2 = m.vxy[tp.v2];
+    const double x[3] = {p0.x, p1.x, p2.x}, y[3] = {p0.y, p1.y, p2.y};
+    if (area) {
+        const double cr = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
+        *area = 0.5 * cr;
+    }
+    const uint32_t sl[3] = {tp.n0, tp.n1, tp.n2};
+    recon_with_f32(
+        W, hc, k, sl, thr,
+        [&](int j, double& nx, double& ny) {
+            const int j1 = (j == 2) ? 0 : j + 1;
+            const double ex = x[j1] - x[j], ey = y[j1] - y[j];
+            const double l = sqrt(ex * ex + ey * ey);
+            nx = ey / l;
+            ny = (-ex) / l;
+        },
+        [&](float* gw, float* gd) {
+            const LsqWF w = m.lsqf[k];
+            const double cx = ((x[0] + x[1]) + x[2]) / 3.0;
+            const double cy = ((y[0] + y[1]) + y[2]) / 3.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int j1 = (j == 2) ? 0 : j + 1;
+                gw[2 * j] = w.w[2 * j];
+                gw[2 * j + 1] = w.w[2 * j + 1];
+                gd[2 * j] = float((x[j] + x[j1]) * 0.5 - cx);
+                gd[2 * j + 1] = float((y[j] + y[j1]) * 0.5 - cy);
+            }
+        },
+        r);
+}
+
 // Store a stage result: eta rounded to nearest, or, for a cell set dry,
 // eta = -h rounded upward so that eta + h >= 0.
 __device__ __forceinline__ CellF store_state(double h, double eta, double hu, double hv, bool dry) {
     CellF o;
-    o.h = h;
     o.eta = dry ? __double2float_ru(-h) : float(eta);
     if (double(o.eta) + h < 0.0) o.eta = __double2float_ru(dry ? -h : eta);
     o.hu = float(hu);
     o.hv = float(hv);
-    o.pad = 0.0f;
     return o;
 }
 
-__device__ __forceinline__ double cfl_ratio_f32(const CellF& q, double area, double perim, double g,
-                                                double thr) {
-    const double H = double(q.eta) + q.h;
+__device__ __forceinline__ double cfl_ratio_f32(const CellF& q, double h, double area,
+                                                double perim, double g, double thr) {
+    const double H = double(q.eta) + h;
     return cfl_ratio(H, double(q.hu), double(q.hv), area, perim, g, thr);
 }
 
@@ -273,7 +367,8 @@ __global__ __launch_bounds__(kBlock) void dt_init_f32_kernel(DevMesh m, TileMap 
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
     double r = __longlong_as_double(0x7FF0000000000000ll);
-    if (int(threadIdx.x) < ti.cnt) r = cfl_ratio_f32(W[k], m.area[k], m.perim[k], g, thr);
+    if (int(threadIdx.x) < ti.cnt)
+        r = cfl_ratio_f32(W[k], m.hcell[k], m.area[k], m.perim[k], g, thr);
     block_min_atomic(r, &sg[ti.seg].rmin[0]);
 }
 
@@ -281,7 +376,8 @@ __global__ __launch_bounds__(kBlock) void dt_init_f32_kernel(DevMesh m, TileMap 
 // FP64 (h, H) and FP32 (eta, u, v) of the face state.
 template <int STAGE>
 __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm,
-                                                           CellF* __restrict__ W,
+                                                           CellF* __restrict__ Wa,
+                                                           CellF* __restrict__ Wb,
                                                            CellF* __restrict__ W1, StepParams p,
                                                            Ctrl* c, Seg* sg, int slot,
                                                            int step_arg, double* log) {
@@ -293,11 +389,15 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
     const TileInfo ti = tile_info(tm.tinfo[t]);
     Seg* sgs = sg + ti.seg;
     const int step = c->kbase + step_arg;
+    CellF *W, *Wout;
+    step_buffers(c, step, Wa, Wb, W, Wout);
     double dt, tn;
     const bool active = step_dt(c, sgs, slot, p, dt, tn);
     if (!active) {
-        if (STAGE == 2)
+        if (STAGE == 2) {
+            carry_state(c, sgs, slot, p, W, Wout, int64_t(t) * kTile, ti.cnt);
             stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, log);
+        }
         return;
     }
     if (STAGE == 1 && ti.first && threadIdx.x == 0) sgs->rmin[slot ^ 1] = 0x7FF0000000000000ull;
@@ -357,11 +457,12 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
                 a0 = a0 + tt[0]; a1 = a1 + tt[1]; a2 = a2 + tt[2];
             }
         }
+        const double hk = m.hcell[k];
         if (second) {
             const CellF q = Ws[k];
             double c3[3];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) c3[j] = (fl[j] * ((double(q.eta) + q.h) + fH[j])) * (fh[j] - q.h);
+            for (int j = 0; j < 3; ++j) c3[j] = (fl[j] * ((double(q.eta) + hk) + fH[j])) * (fh[j] - hk);
             const double sx = c3[0] * fnx[0] + c3[1] * fnx[1] + c3[2] * fnx[2];
             const double sy = c3[0] * fny[0] + c3[1] * fny[1] + c3[2] * fny[2];
             a1 = a1 + p.hg * sx;
@@ -382,17 +483,17 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
             u = 0.5 * double(w.hu) + 0.5 * (double(w1.hu) + dt * R1);
             v = 0.5 * double(w.hv) + 0.5 * (double(w1.hv) + dt * R2);
         }
-        const double Hn = e + w.h;
+        const double Hn = e + hk;
         bool dry = false;
         if (Hn < 0.0) { dry = true; clamp = 1; }
         if (Hn < p.thr) { u = 0.0; v = 0.0; }
-        const CellF o = store_state(w.h, e, u, v, dry);
+        const CellF o = store_state(hk, e, u, v, dry);
         if (STAGE == 1) {
             W1[k] = o;
         } else {
-            W[k] = o;
+            Wout[k] = o;
             bad = !isfinite(e) || !isfinite(u) || !isfinite(v);
-            rr = cfl_ratio_f32(o, ar, m.perim[k], p.g, p.thr);
+            rr = cfl_ratio_f32(o, hk, ar, m.perim[k], p.g, p.thr);
         }
     }
     if (STAGE == 2 && bad) {
@@ -406,22 +507,227 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
     }
 }
 
-template __global__ void stage_f32_kernel<1>(DevMesh, TileMap, CellF*, CellF*, StepParams, Ctrl*,
-                                             Seg*, int, int, double*);
-template __global__ void stage_f32_kernel<2>(DevMesh, TileMap, CellF*, CellF*, StepParams, Ctrl*,
-                                             Seg*, int, int, double*);
+template __global__ void stage_f32_kernel<1>(DevMesh, TileMap, CellF*, CellF*, CellF*,
+                                             StepParams, Ctrl*, Seg*, int, int, double*);
+template __global__ void stage_f32_kernel<2>(DevMesh, TileMap, CellF*, CellF*, CellF*,
+                                             StepParams, Ctrl*, Seg*, int, int, double*);
+
+// Face-parallel FP32 stage kernel: the phases of faces_stage_kernel, the
+// arithmetic of stage_f32_kernel.  LDS planes hold doubles (FP32 values are
+// stored exactly as doubles).
+template <int T, int STAGE>
+__global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTileMap tm,
+                                                            const double* __restrict__ hc,
+                                                            CellF* __restrict__ Wa,
+                                                            CellF* __restrict__ Wb,
+                                                            CellF* __restrict__ W1, StepParams p,
+                                                            Ctrl* c, Seg* sg, int slot,
+                                                            int step_arg, double* log) {
+    extern __shared__ double lds[];
+    const int S = 3 * T + tm.bmax;
+    double* __restrict__ Le = lds;
+    double* __restrict__ Lh = lds + S;
+    double* __restrict__ LH = lds + 2 * S;
+    double* __restrict__ Lu = lds + 3 * S;
+    double* __restrict__ Lv = lds + 4 * S;
+    double* __restrict__ CH = lds + 5 * S;
+    double* __restrict__ Ch = CH + T;
+    const int t = tm.xcd_order ? xcd_tile(int(blockIdx.x), tm.ntiles) : int(blockIdx.x);
+    const TileInfo ti = tile_info(tm.tinfo[t]);
+    Seg* sgs = sg + ti.seg;
+    const int step = c->kbase + step_arg;
+    CellF *W, *Wout;
+    step_buffers(c, step, Wa, Wb, W, Wout);
+    double dt, tn;
+    const bool active = step_dt(c, sgs, slot, p, dt, tn);
+    if (!active) {
+        if (STAGE == 2) {
+            carry_state(c, sgs, slot, p, W, Wout, int64_t(t) * T, ti.cnt);
+            stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, false, 0.0, 0.0, p.t_stop, log);
+        }
+        return;
+    }
+    if (STAGE == 1 && ti.first && threadIdx.x == 0) sgs->rmin[slot ^ 1] = 0x7FF0000000000000ull;
+    const CellF* __restrict__ Ws = (STAGE == 1) ? W : W1;
+    const int64_t c0 = int64_t(t) * T;
+    const int cnt = ti.cnt;
+    const int i = threadIdx.x;
+    const int64_t k = c0 + i;
+
+    double area = 1.0;
+    bool second = false;
+    if (i < cnt) {
+        ReconF r;
+        recon_geo_f32(m, Ws, hc, k, p.thr, r, &area);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const FaceF f = recon_face_f32(r, j, p.thr);
+            const int sj = j * T + i;
+            Le[sj] = double(f.eta);
+            Lh[sj] = f.h;
+            LH[sj] = f.H;
+            Lu[sj] = double(f.u);
+            Lv[sj] = double(f.v);
+        }
+        CH[i] = r.Hk;
+        Ch[i] = r.hk;
+        second = r.second;
+    }
+    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
+    for (int b = i; b < nb; b += T) {
+        const uint32_t item = tm.bitem[b0 + b];
+        const int64_t n = int64_t(item >> 2);
+        const int jn = int(item & 3u);
+        ReconF r;
+        recon_geo_f32(m, Ws, hc, n, p.thr, r, nullptr);
+        const FaceF f = (jn == 0) ? recon_face_f32(r, 0, p.thr)
+                      : (jn == 1) ? recon_face_f32(r, 1, p.thr) : recon_face_f32(r, 2, p.thr);
+        const int sb = 3 * T + b;
+        Le[sb] = double(f.eta);
+        Lh[sb] = f.h;
+        LH[sb] = f.H;
+        Lu[sb] = double(f.u);
+        Lv[sb] = double(f.v);
+    }
+    __syncthreads();
+
+    const int f0 = tm.fstart[t], nf = tm.fstart[t + 1] - f0;
+    for (int q = i; q < nf; q += T) {
+        const FaceItemD it = tm.items[f0 + q];
+        const int sl = it.sl;
+        const bool wall = (it.sr == kFaceWall);
+        const int sr = wall ? sl : int(it.sr);
+        FaceF L, R;
+        L.eta = float(Le[sl]); L.h = Lh[sl]; L.H = LH[sl]; L.u = float(Lu[sl]); L.v = float(Lv[sl]);
+        R.eta = float(Le[sr]); R.h = Lh[sr]; R.H = LH[sr]; R.u = float(Lu[sr]); R.v = float(Lv[sr]);
+        const double2 pa = m.vxy[it.va], pb = m.vxy[it.vb];
+        const double ex = pb.x - pa.x, ey = pb.y - pa.y;
+        const double l = sqrt(ex * ex + ey * ey);
+        const double nx = ey / l, ny = (-ex) / l;
+        double tL[3], tR[3];
+        face_pair_f32(p.g, p.hg, L, R, wall, nx, ny, l, tL, tR);
+        if (sl < 3 * T) {
+            const int ci = sl & (T - 1);
+            const double cc = (l * (CH[ci] + L.H)) * (L.h - Ch[ci]);
+            Le[sl] = -tL[0];
+            Lh[sl] = -tL[1];
+            LH[sl] = -tL[2];
+            Lu[sl] = cc * nx;
+            Lv[sl] = cc * ny;
+        }
+        if (!wall && sr < 3 * T) {
+            const int ci = sr & (T - 1);
+            const double cc = (l * (CH[ci] + R.H)) * (R.h - Ch[ci]);
+            Le[sr] = tR[0];
+            Lh[sr] = tR[1];
+            LH[sr] = tR[2];
+            Lu[sr] = cc * (-nx);
+            Lv[sr] = cc * (-ny);
+        }
+    }
+    __syncthreads();
+
+    unsigned long long clamp = 0;
+    double rr = __longlong_as_double(0x7FF0000000000000ll);
+    bool bad = false;
+    if (i < cnt) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int sj = j * T + i;
+            a0 = a0 + Le[sj];
+            a1 = a1 + Lh[sj];
+            a2 = a2 + LH[sj];
+        }
+        if (second) {
+            const double sx = (Lu[i] + Lu[T + i]) + Lu[2 * T + i];
+            const double sy = (Lv[i] + Lv[T + i]) + Lv[2 * T + i];
+            a1 = a1 + p.hg * sx;
+            a2 = a2 + p.hg * sy;
+        }
+        const double rar = 1.0 / area;
+        const double R0 = a0 * rar, R1 = a1 * rar, R2 = a2 * rar;
+        const double hk = hc[k];
+        const CellF w = W[k];
+        double e, u, v;
+        if (STAGE == 1) {
+            e = double(w.eta) + dt * R0;
+            u = double(w.hu) + dt * R1;
+            v = double(w.hv) + dt * R2;
+        } else {
+            const CellF w1 = W1[k];
+            e = 0.5 * double(w.eta) + 0.5 * (double(w1.eta) + dt * R0);
+            u = 0.5 * double(w.hu) + 0.5 * (double(w1.hu) + dt * R1);
+            v = 0.5 * double(w.hv) + 0.5 * (double(w1.hv) + dt * R2);
+        }
+        const double Hn = e + hk;
+        bool dry = false;
+        if (Hn < 0.0) { dry = true; clamp = 1; }
+        if (Hn < p.thr) { u = 0.0; v = 0.0; }
+        const CellF o = store_state(hk, e, u, v, dry);
+        if (STAGE == 1) {
+            W1[k] = o;
+        } else {
+            Wout[k] = o;
+            bad = !isfinite(e) || !isfinite(u) || !isfinite(v);
+            rr = cfl_ratio_f32(o, hk, area, m.perim[k], p.g, p.thr);
+        }
+    }
+    if (STAGE == 2 && bad) {
+        atomicOr(&c->err, 1);
+        atomicMin(&c->err_step, step);
+    }
+    block_count_atomic<T>(clamp, &c->clamps);
+    if (STAGE == 2) {
+        block_min_atomic<T>(rr, &sgs->rmin[slot ^ 1]);
+        stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void faces_dt_init_f32_kernel(FaceMesh m, FaceTileMap tm,
+                                                              const CellF* __restrict__ W,
+                                                              const double* __restrict__ hc,
+                                                              const double* __restrict__ area,
+                                                              double g, double thr, Seg* sg) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    const int64_t k = int64_t(blockIdx.x) * T + threadIdx.x;
+    double r = __longlong_as_double(0x7FF0000000000000ll);
+    if (int(threadIdx.x) < ti.cnt) r = cfl_ratio_f32(W[k], hc[k], area[k], m.perim[k], g, thr);
+    block_min_atomic<T>(r, &sg[ti.seg].rmin[0]);
+}
+
+#define VSW_FACES_F32_INSTANCES(T)                                                              \
+    template __global__ void faces_stage_f32_kernel<T, 1>(FaceMesh, FaceTileMap, const double*, \
+                                                          CellF*, CellF*, CellF*, StepParams,   \
+                                                          Ctrl*, Seg*, int, int, double*);      \
+    template __global__ void faces_stage_f32_kernel<T, 2>(FaceMesh, FaceTileMap, const double*, \
+                                                          CellF*, CellF*, CellF*, StepParams,   \
+                                                          Ctrl*, Seg*, int, int, double*);      \
+    template __global__ void faces_dt_init_f32_kernel<T>(FaceMesh, FaceTileMap, const CellF*,   \
+                                                         const double*, const double*, double,  \
+                                                         double, Seg*);
+VSW_FACES_F32_INSTANCES(128)
+VSW_FACES_F32_INSTANCES(256)
+VSW_FACES_F32_INSTANCES(512)
+#undef VSW_FACES_F32_INSTANCES
 
 // Free surface at the gauge cells after step `step` (see gauge_kernel).
-__global__ void gauge_f32_kernel(const CellF* __restrict__ W, const int64_t* __restrict__ cells,
-                                 int ng, const uint32_t* __restrict__ tinfo, const Seg* sg,
+__global__ void gauge_f32_kernel(const CellF* __restrict__ Wa, const CellF* __restrict__ Wb,
+                                 const double* __restrict__ h, const int64_t* __restrict__ cells,
+                                 int ng,
+                                 const int32_t* __restrict__ gseg, const Seg* sg,
                                  const Ctrl* c, int step_arg, double* __restrict__ log) {
     const int gi = int(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gi >= ng) return;
     const int step = c->kbase + step_arg;
+    const CellF *Win, *W;
+    step_buffers(c, step, Wa, Wb, Win, W);
     const int64_t k = cells[gi];
-    if (sg[tinfo[k / kTile] >> 9].steps_done <= step) return;
+    if (sg[gseg[gi]].steps_done <= step) return;
     const CellF q = W[k];
-    log[int64_t(step) * ng + gi] = (double(q.eta) + q.h) - q.h;
+    const double hk = h[k];
+    log[int64_t(step) * ng + gi] = (double(q.eta) + hk) - hk;
 }
 
 // Caller-order FP64 (H, HU, HV) into FP32 state records: eta = H - h rounded
@@ -441,14 +747,15 @@ __global__ void pack_state_f32_kernel(int64_t n, const int64_t* __restrict__ per
 
 // FP32 state records into caller-order FP64 arrays, H = eta + h.
 __global__ void unpack_state_f32_kernel(int64_t n, const int64_t* __restrict__ perm,
-                                        const CellF* __restrict__ W, double* __restrict__ H,
+                                        const CellF* __restrict__ W,
+                                        const double* __restrict__ h, double* __restrict__ H,
                                         double* __restrict__ HU, double* __restrict__ HV) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t k = perm[i];
     if (k < 0) return;
     const CellF q = W[i];
-    if (H) H[k] = double(q.eta) + q.h;
+    if (H) H[k] = double(q.eta) + h[i];
     if (HU) HU[k] = double(q.hu);
     if (HV) HV[k] = double(q.hv);
 }

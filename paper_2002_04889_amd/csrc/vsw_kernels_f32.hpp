@@ -4,11 +4,11 @@
 
 namespace vsw {
 
-// FP32 state record: still-water depth h (FP64, static) and the prognostic
-// free surface eta = H - h and momentum (Hu, Hv) in FP32; 24 bytes.
-struct alignas(8) CellF {
-    double h;
-    float eta, hu, hv, pad;
+// FP32 state record: the prognostic free surface eta = H - h and momentum
+// (Hu, Hv) in FP32; 12 bytes.  The still-water depth h (FP64, static) is a
+// separate array, read once per cell and stage.
+struct CellF {
+    float eta, hu, hv;
 };
 
 // Face state of the FP32 kernel: eta, u, v in FP32, bed and total depth in
@@ -24,18 +24,35 @@ inline size_t stage_f32_lds_bytes(int bmax) {
     return (2 * sizeof(double) + 3 * sizeof(float)) * size_t(3 * kTile + bmax);
 }
 
+// Same buffer convention as stage_kernel (w^n in buffer (par + step) & 1).
+// The still-water depth is m.hcell[k].
 template <int STAGE>
-__global__ void stage_f32_kernel(DevMesh m, TileMap tm, CellF* W, CellF* W1, StepParams p, Ctrl* c,
-                                 Seg* sg, int slot, int step_arg, double* log);
+__global__ void stage_f32_kernel(DevMesh m, TileMap tm, CellF* Wa, CellF* Wb, CellF* W1,
+                                 StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg,
+                                 double* log);
 __global__ void dt_init_f32_kernel(DevMesh m, TileMap tm, const CellF* W, double g, double thr,
                                    Seg* sg);
-__global__ void gauge_f32_kernel(const CellF* W, const int64_t* cells, int ng,
-                                 const uint32_t* tinfo, const Seg* sg, const Ctrl* c, int step_arg,
-                                 double* log);
+__global__ void gauge_f32_kernel(const CellF* Wa, const CellF* Wb, const double* h,
+                                 const int64_t* cells, int ng, const int32_t* gseg,
+                                 const Seg* sg, const Ctrl* c, int step_arg, double* log);
 __global__ void pack_state_f32_kernel(int64_t n, const int64_t* perm, const double* H,
                                       const double* HU, const double* HV, const double* h,
                                       CellF* W, CellF* W1);
-__global__ void unpack_state_f32_kernel(int64_t n, const int64_t* perm, const CellF* W, double* H,
-                                        double* HU, double* HV);
+__global__ void unpack_state_f32_kernel(int64_t n, const int64_t* perm, const CellF* W,
+                                        const double* h, double* H, double* HU, double* HV);
+
+// Face-parallel FP32 kernels (same arithmetic as stage_f32_kernel, the
+// geometry from the vertices as in faces_stage_kernel); LDS as
+// faces_lds_bytes.
+struct FaceMesh;
+struct FaceTileMap;
+template <int T, int STAGE>
+__global__ void faces_stage_f32_kernel(FaceMesh m, FaceTileMap tm, const double* h, CellF* Wa,
+                                       CellF* Wb, CellF* W1, StepParams p, Ctrl* c, Seg* sg,
+                                       int slot, int step_arg, double* log);
+template <int T>
+__global__ void faces_dt_init_f32_kernel(FaceMesh m, FaceTileMap tm, const CellF* W,
+                                         const double* h, const double* area, double g,
+                                         double thr, Seg* sg);
 
 }  // namespace vsw

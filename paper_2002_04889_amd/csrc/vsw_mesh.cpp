@@ -299,8 +299,80 @@ int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
             G(G_WY, j, i) = (sxx * ey[j] - sxy * ex[j]) / det;
         }
     }
+    // vertices in the order the internal cells first use them
+    std::vector<int64_t> vnew(nv, -1);
+    int64_t nvu = 0;
+    out.tri.assign(3 * size_t(nc), 0u);
+    for (int64_t i = 0; i < nc; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int32_t v = tri[3 * perm[i] + j];
+            if (vnew[v] < 0) vnew[v] = nvu++;
+            out.tri[3 * size_t(i) + j] = uint32_t(vnew[v]);
+        }
+    out.vxy.assign(2 * size_t(nvu), 0.0);
+    for (int64_t v = 0; v < nv; ++v)
+        if (vnew[v] >= 0) {
+            out.vxy[2 * size_t(vnew[v])] = vx[v];
+            out.vxy[2 * size_t(vnew[v]) + 1] = vy[v];
+        }
     out.perm = std::move(perm);
     return VSW_OK;
+}
+
+void build_face_tiles(const HostMesh& hm, int tile, FaceTilesHost& out) {
+    const int64_t nc = hm.nc;
+    out.tile = tile;
+    out.ntiles = int((nc + tile - 1) / tile);
+    out.topo.assign(size_t(nc), TopoRec{{kWall, kWall, kWall}, {0u, 0u, 0u}});
+    out.bstart.assign(size_t(out.ntiles) + 1, 0);
+    out.fstart.assign(size_t(out.ntiles) + 1, 0);
+    out.bitem.clear();
+    out.items.clear();
+    out.bmax = 0;
+    out.fmax = 0;
+    for (int64_t i = 0; i < nc; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const uint32_t s = hm.nbr[size_t(j) * nc + i];
+            out.topo[i].n[j] = (s == kWall) ? kWall : (s & ~7u);
+            out.topo[i].v[j] = hm.tri[3 * size_t(i) + j];
+        }
+    for (int t = 0; t < out.ntiles; ++t) {
+        const int64_t c0 = int64_t(t) * tile, c1 = std::min(nc, c0 + tile);
+        out.bstart[t] = int32_t(out.bitem.size());
+        out.fstart[t] = int32_t(out.items.size());
+        int nb = 0;
+        for (int64_t i = c0; i < c1; ++i) {
+            if (hm.perm[i] < 0) continue;  // padding of an ensemble scenario
+            const uint32_t* v = &hm.tri[3 * size_t(i)];
+            for (int j = 0; j < 3; ++j) {
+                const uint32_t s = hm.nbr[size_t(j) * nc + i];
+                const uint32_t va = v[j], vb = v[(j + 1) % 3];
+                const uint16_t own = uint16_t(j * tile + (i - c0));
+                if (s == kWall) {
+                    out.items.push_back(FaceItem{va, vb, own, kSlotWall});
+                    continue;
+                }
+                const int64_t n = int64_t(s >> 3);
+                const uint32_t jn = s & 3u;
+                const bool left = (s & 4u) != 0;
+                if (n >= c0 && n < c1) {
+                    // inside the tile: listed once, by the left cell
+                    if (left)
+                        out.items.push_back(
+                            FaceItem{va, vb, own, uint16_t(jn * tile + (n - c0))});
+                } else {
+                    const uint16_t halo = uint16_t(3 * tile + nb++);
+                    out.bitem.push_back((uint32_t(n) << 2) | jn);
+                    out.items.push_back(left ? FaceItem{va, vb, own, halo}
+                                             : FaceItem{vb, va, halo, own});
+                }
+            }
+        }
+        out.bmax = std::max(out.bmax, nb);
+        out.fmax = std::max(out.fmax, int(out.items.size()) - out.fstart[t]);
+    }
+    out.bstart[out.ntiles] = int32_t(out.bitem.size());
+    out.fstart[out.ntiles] = int32_t(out.items.size());
 }
 
 void build_tiles(const HostMesh& hm, int tile, TileMapHost& out) {
@@ -363,10 +435,14 @@ int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* 
     const int ntiles = int(N / tile);
     HostMesh& hm = out.hm;
     TileMapHost& tm = out.tiles;
+    if (tile != 128 && tile != 256 && tile != 512) {
+        err = "tile size must be 128, 256 or 512";
+        return VSW_EINVAL;
+    }
     if (nseg == 1) {  // one mesh: no copy
         int rc = build_host_mesh(nv[0], vx, vy, nc[0], tri, h, ordering, seed, tile, hm, err);
         if (rc) return rc;
-        build_tiles(hm, tile, tm);
+        if (tile == 256) build_tiles(hm, tile, tm);
     } else {
         hm.nc = N;
         hm.perm.assign(size_t(N), -1);
@@ -375,6 +451,8 @@ int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* 
         hm.area.assign(size_t(N), 0.0);
         hm.perim.assign(size_t(N), 0.0);
         hm.h.assign(size_t(N), 0.0);
+        hm.tri.assign(3 * size_t(N), 0u);
+        hm.vxy.clear();
         tm.tile = tile;
         tm.ntiles = ntiles;
         tm.nloc.assign(3 * size_t(N), kNlocWall);
@@ -391,9 +469,12 @@ int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* 
                 return rc;
             }
             TileMapHost pt;
-            build_tiles(p, tile, pt);
+            if (tile == 256) build_tiles(p, tile, pt);
             vo += nv[s];
             const int64_t o = out.off[s], n = p.nc;
+            const uint32_t v0 = uint32_t(hm.vxy.size() / 2);
+            hm.vxy.insert(hm.vxy.end(), p.vxy.begin(), p.vxy.end());
+            for (int64_t i = 0; i < 3 * n; ++i) hm.tri[3 * size_t(o) + i] = p.tri[i] + v0;
             hm.ne += p.ne;
             hm.nw += p.nw;
             hm.nv += p.nv;
@@ -406,22 +487,29 @@ int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* 
                     const uint32_t sl = p.nbr[size_t(j) * n + i];
                     hm.nbr[size_t(j) * N + o + i] =
                         sl == kWall ? kWall : (uint32_t((sl >> 3) + o) << 3) | (sl & 7u);
-                    tm.nloc[size_t(j) * N + o + i] = pt.nloc[size_t(j) * n + i];
+                    if (tile == 256) tm.nloc[size_t(j) * N + o + i] = pt.nloc[size_t(j) * n + i];
                     for (int f = 0; f < G_NFACE; ++f)
                         hm.face_geom[(size_t(f) * 3 + j) * N + o + i] =
                             p.face_geom[(size_t(f) * 3 + j) * n + i];
                 }
             }
-            const int t0 = int(o / tile);
-            const int32_t b0 = int32_t(tm.bitem.size());
-            for (int t = 0; t < pt.ntiles; ++t) tm.bstart[t0 + t] = b0 + pt.bstart[t];
-            for (uint32_t it : pt.bitem)
-                tm.bitem.push_back((uint32_t((it >> 2) + o) << 2) | (it & 3u));
-            tm.bmax = std::max(tm.bmax, pt.bmax);
+            if (tile == 256) {
+                const int t0 = int(o / tile);
+                const int32_t b0 = int32_t(tm.bitem.size());
+                for (int t = 0; t < pt.ntiles; ++t) tm.bstart[t0 + t] = b0 + pt.bstart[t];
+                for (uint32_t it : pt.bitem)
+                    tm.bitem.push_back((uint32_t((it >> 2) + o) << 2) | (it & 3u));
+                tm.bmax = std::max(tm.bmax, pt.bmax);
+            }
             // padding tiles cannot occur: each scenario's tiles end at off[s + 1]
         }
-        tm.bstart[ntiles] = int32_t(tm.bitem.size());
+        if (tile == 256)
+            tm.bstart[ntiles] = int32_t(tm.bitem.size());
+        else
+            tm = TileMapHost();
     }
+    // padding cells: no neighbours, their own three (first) vertices, never read
+    build_face_tiles(hm, tile, out.ftiles);
     out.tinfo.assign(size_t(ntiles), 0u);
     for (int s = 0; s < nseg; ++s) {
         const int t0 = int(out.off[s] / tile), t1 = int(out.off[s + 1] / tile);
@@ -429,7 +517,7 @@ int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* 
         for (int t = t0; t < t1; ++t) {
             const int64_t c0 = int64_t(t) * tile;
             const int cnt = int(std::min<int64_t>(tile, cend - c0));
-            out.tinfo[t] = (uint32_t(s) << 9) | (t == t0 ? 0x100u : 0u) | uint32_t(cnt - 1);
+            out.tinfo[t] = (uint32_t(s) << 10) | (t == t0 ? 0x200u : 0u) | uint32_t(cnt - 1);
         }
     }
     return VSW_OK;

@@ -35,7 +35,41 @@ struct HostMesh {
     std::vector<double> area;       // [nc]
     std::vector<double> perim;      // [nc]
     std::vector<double> h;          // [nc] still-water depth
+    // Vertices renumbered in the order the internal cells first use them
+    // (so a tile's vertices lie together); unused vertices dropped.
+    std::vector<uint32_t> tri;      // [nc][3] counter-clockwise, caller's first vertex first
+    std::vector<double> vxy;        // [nvu][2] coordinates
 };
+
+// Face-parallel stage kernels.  Per cell: the neighbour across each face
+// (its internal index shifted left by 3, kWall on a wall) and the vertices
+// in local order (face j joins local vertices j and j + 1).  Per tile of `tile` cells: the halo faces to
+// reconstruct (as in TileMapHost) and the list of the faces the tile
+// evaluates, each once, in canonical orientation: vertices a -> b as the
+// canonical left cell walks the face, and the LDS slots of the left and
+// right face states (slot convention of TileMapHost; sr = kSlotWall on a
+// wall).  An interior face inside the tile is listed once, a face to a
+// halo cell once per tile that owns one of its cells.
+struct TopoRec {
+    uint32_t n[3];
+    uint32_t v[3];
+};
+struct FaceItem {
+    uint32_t va, vb;
+    uint16_t sl, sr;
+};
+constexpr uint16_t kSlotWall = 0xFFFFu;
+
+struct FaceTilesHost {
+    int tile = 0, ntiles = 0, bmax = 0, fmax = 0;
+    std::vector<TopoRec> topo;      // [nc]
+    std::vector<int32_t> bstart;    // [ntiles + 1]
+    std::vector<uint32_t> bitem;    // halo faces: (cell << 2) | face
+    std::vector<int32_t> fstart;    // [ntiles + 1]
+    std::vector<FaceItem> items;
+};
+
+void build_face_tiles(const HostMesh& hm, int tile, FaceTilesHost& out);
 
 // Tiles of the fused stage kernel: tile t owns internal cells
 // [t * tile, (t + 1) * tile).  Every face of an owned cell gets an LDS slot:
@@ -67,13 +101,16 @@ struct EnsembleMesh {
     std::vector<int64_t> off;       // [nseg + 1] internal offsets; off[nseg] = internal count
     std::vector<int64_t> coff;      // [nseg + 1] caller offsets
     HostMesh hm;                    // over all internal cells; perm = caller index or -1
-    TileMapHost tiles;
-    std::vector<uint32_t> tinfo;    // [ntiles] (scenario << 9) | (first << 8) | (cells - 1)
+    TileMapHost tiles;              // tile map of the cell-parallel kernels (tile 256)
+    FaceTilesHost ftiles;           // face lists of the face-parallel kernels
+    std::vector<uint32_t> tinfo;    // [ntiles] (scenario << 10) | (first << 9) | (cells - 1)
 };
 
 // nv[s], nc[s]: vertex and cell counts of scenario s; vx, vy, tri, h hold
 // the scenarios' arrays one after the other, tri indexing the scenario's own
-// vertices.  Scenario s is renumbered with seed + s.
+// vertices.  Scenario s is renumbered with seed + s.  Scenarios start on
+// whole tiles of `tile` cells (a multiple of 256, or 128); the cell-parallel
+// tile map is built when tile is 256.
 int build_ensemble(int nseg, const int64_t* nv, const double* vx, const double* vy,
                    const int64_t* nc, const int32_t* tri, const double* h, int ordering,
                    uint64_t seed, int tile, EnsembleMesh& out, std::string& err);

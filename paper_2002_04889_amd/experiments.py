@@ -23,6 +23,7 @@ import argparse
 import json
 import math
 import sys
+import time
 
 import numpy as np
 
@@ -60,18 +61,29 @@ def find_cells(case, points):
     return np.array(out, dtype=np.int32)
 
 
+def progress(msg):
+    """One line per phase on stderr (flushed), so that a long experiment is
+    never silent between its steps."""
+    print(f"[experiments {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def thacker_gauge_run(dx, t_fin=10.0, dt_factor=None, precision=None, chunk=4000, cfl=None,
                       h_threshold=None):
     """Run Thacker's paraboloid on the mesh of size dx to t_fin with gauges.
 
-    Returns dict(t, eta [steps, 3], exact [steps, 3], cells, nc, steps)."""
+    Returns dict(t, eta [steps, 3], exact [steps, 3], exact_centroid [steps, 3]
+    (the closed form at the gauge cells' centroids), cells, nc, steps)."""
     from . import vsw
 
     n = int(round(4.0 / dx)) + 1
+    progress(f"dx={dx:g}: generating the {n}x{n}-point mesh")
+    t0 = time.perf_counter()
     case = W.thacker_case(n)
     L = W.THACKER_L
     pts = [(L / 2 + gx, L / 2 + gy) for gx, gy in GAUGES_FROM_CENTRE]
     cells = find_cells(case, pts)
+    progress(f"dx={dx:g}: {case.nc} cells, gauge cells {cells.tolist()} "
+             f"({time.perf_counter() - t0:.1f} s); uploading")
     kw = {}
     if dt_factor is not None:
         kw["dt_fixed"] = dt_factor * dx
@@ -82,6 +94,7 @@ def thacker_gauge_run(dx, t_fin=10.0, dt_factor=None, precision=None, chunk=4000
     if h_threshold is not None:
         kw["h_threshold"] = h_threshold
     s = vsw.Solver.for_case(case, **kw)
+    progress(f"dx={dx:g}: uploaded; stepping to t={t_fin:g} in calls of {chunk} steps")
     try:
         vsw.vsw_set_gauges(s.h, cells)
         ts, etas = [], []
@@ -99,12 +112,18 @@ def thacker_gauge_run(dx, t_fin=10.0, dt_factor=None, precision=None, chunk=4000
         eta = np.concatenate(etas)
     finally:
         s.close()
+    progress(f"dx={dx:g}: {len(t_arr)} steps done; closed form at the gauges")
     px = np.array([p[0] for p in pts])
     py = np.array([p[1] for p in pts])
+    cx, cy = case.centroids()
+    gx, gy = cx[cells], cy[cells]
     exact = np.stack([W.thacker_exact(px, py, tt)[0] for tt in t_arr]) if len(t_arr) else \
         np.zeros((0, 3))
-    return {"t": t_arr, "eta": eta, "exact": exact, "cells": cells, "nc": case.nc,
-            "n": n, "dx": 4.0 / (n - 1), "rc": rc, "steps": len(t_arr)}
+    exact_c = np.stack([W.thacker_exact(gx, gy, tt)[0] for tt in t_arr]) if len(t_arr) else \
+        np.zeros((0, 3))
+    return {"t": t_arr, "eta": eta, "exact": exact, "exact_centroid": exact_c, "cells": cells,
+            "nc": case.nc, "n": n, "dx": 4.0 / (n - 1), "rc": rc, "steps": len(t_arr),
+            "case": case}
 
 
 def convergence(sizes=(0.048, 0.024, 0.012, 0.006), t_fin=10.0, h_threshold=None):

@@ -29,7 +29,7 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 # The files the stage kernels are compiled from (their code and headers)
 # and the compile flags: a change to any of them invalidates measured traffic.
 STAGE_SOURCES = ("vsw_device.hpp", "vsw_common.hpp", "vsw_kernels.hpp", "vsw_kernels.hip",
-                 "vsw_kernels_f32.hpp", "vsw_kernels_f32.hip")
+                 "vsw_kernels_f32.hpp", "vsw_kernels_f32.hip", "vsw_faces.hpp", "vsw_faces.hip")
 
 
 def source_digest() -> str:

@@ -22,7 +22,7 @@ VSW_OK, VSW_EINVAL, VSW_EMESH, VSW_ESTATE, VSW_ENOMEM, VSW_EDEVICE, VSW_EUNSTABL
     0, -1, -2, -3, -4, -5, -6
 VSW_FP64, VSW_FP32 = 0, 1
 VSW_ORDER_HILBERT, VSW_ORDER_NONE, VSW_ORDER_RANDOM, VSW_ORDER_BISECTION = 0, 1, 2, 3
-VSW_KERNEL_FUSED, VSW_KERNEL_TWO_PASS = 0, 1
+VSW_KERNEL_FUSED, VSW_KERNEL_TWO_PASS, VSW_KERNEL_FACES = 0, 1, 2
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM",
                -5: "EDEVICE", -6: "EUNSTABLE"}
 
@@ -74,6 +74,8 @@ _SIGS = {
     "vsw_set_occupancy": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vsw_autotune": (ctypes.c_int, [_vp, _i64, _ip, _dp]),
     "vsw_set_kernel_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vsw_set_tile_size": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vsw_tile_size": (ctypes.c_int, [_vp, _ip]),
     "vsw_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _lp]),
     "vsw_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
     "vsw_prepare_mesh_host": (ctypes.c_int, [_i64, _dp, _dp, _i64, _ip, _dp, _dp, _dp, _dp,
@@ -255,6 +257,16 @@ def vsw_set_stream(h, stream_handle: int | None):
 
 def vsw_set_kernel_variant(h, variant: int):
     return _check(lib().vsw_set_kernel_variant(h, int(variant)))
+
+
+def vsw_set_tile_size(h, cells: int):
+    return _check(lib().vsw_set_tile_size(h, int(cells)))
+
+
+def vsw_tile_size(h):
+    n = ctypes.c_int32(0)
+    _check(lib().vsw_tile_size(h, ctypes.byref(n)))
+    return n.value
 
 
 def vsw_adjoint_gauge_loss(h, nc, nsteps, checkpoint_every, gauges, eta_obs):

@@ -2,9 +2,10 @@
 the same seeded inputs, element by element.
 
 Bar (FP64): per field q in (H, HU, HV), max_K |q_gpu - q_oracle| <= 1e-12
-max_K |q_oracle|, and the same for the time and every step's dt.  Both
-sides evaluate the same expressions in the same order without contraction,
-so the observed difference is normally exactly zero; the tests print it.
+max_K |q_oracle|, and the same for the time and every step's dt.  The
+kernels take a quotient by a value used more than once as one reciprocal
+and products, where the oracle divides as the scheme is written; the tests
+print the largest difference and the share of bitwise-equal values.
 """
 import math
 import sys
@@ -163,13 +164,49 @@ def test_fixed_dt_and_t_stop(orc):
     assert_parity(g, o, "dt_fixed")
 
 
-def test_unstable_run_reports_eunstable(orc):
+@pytest.mark.parametrize("mode", ["fused", "two_pass", "graph", "fp32"])
+def test_unstable_run_reports_eunstable(orc, mode):
+    """A fixed dt far above the stable one blows up.  The call returns
+    VSW_EUNSTABLE with the number of good steps, and the solver keeps the
+    state those steps reached: the input of the failing step (the oracle's
+    state after the same number of steps)."""
     c = W.thacker_case(23)
-    g = gpu_run(c, 400, dt_fixed=0.2)
     o = orc_run(orc, c, 400, dt_fixed=0.2)
     assert o["rc"] != 0
-    assert g["rc"] == vsw.VSW_EUNSTABLE
-    assert g["steps"] == o["steps"] < 400
+    done_o = o["steps"]
+    prec = vsw.VSW_FP32 if mode == "fp32" else vsw.VSW_FP64
+    s = vsw.Solver.for_case(c, precision=prec, dt_fixed=0.2)
+    try:
+        if mode == "two_pass":
+            vsw.vsw_set_kernel_variant(s.h, vsw.VSW_KERNEL_TWO_PASS)
+        if mode == "graph":
+            vsw.vsw_set_graph(s.h, True)
+        s.step(3)  # an odd count first: the next call starts from the other buffer
+        rc, done, t = s.step(400, check=False)
+        H, HU, HV, t = s.state()
+        assert rc == vsw.VSW_EUNSTABLE
+        say(mode, "EUNSTABLE after", 3 + done, "good steps; oracle", done_o)
+        if mode == "fp32":
+            assert 3 + done >= 1
+            ref = vsw.Solver.for_case(c, precision=prec, dt_fixed=0.2)
+            try:
+                ref.step(3 + done)
+                r = ref.state()
+            finally:
+                ref.close()
+            for a, b in zip((H, HU, HV), r[:3]):
+                assert np.array_equal(a, b)
+            return
+        assert 3 + done == done_o
+        ref = orc_run(orc, c, done_o, dt_fixed=0.2)
+        g = {"H": H, "HU": HU, "HV": HV, "t": t, "steps": done_o, "dts": ref["dts"]}
+        assert np.isfinite(H).all() and np.isfinite(HU).all() and np.isfinite(HV).all()
+        assert_parity(g, ref, f"eunstable-{mode}")
+        # the solver goes on from there: the same failing step again
+        rc2, done2, _ = s.step(5, check=False)
+        assert rc2 == vsw.VSW_EUNSTABLE and done2 == 0
+    finally:
+        s.close()
 
 
 def test_state_validation_and_order_errors():
@@ -189,6 +226,23 @@ def test_state_validation_and_order_errors():
         with pytest.raises(vsw.VswError, match="EINVAL"):
             s.set_state(bad, c.HU, c.HV)
         s.set_state(c.H, c.HU, c.HV)
+        # device arrays are checked on the device, and a rejected state
+        # leaves the solver's state as it was
+        import torch
+
+        dev = torch.device("cuda:0")
+        good = [torch.tensor(a, device=dev) for a in (c.H, c.HU, c.HV)]
+        for k, v, what in ((0, -1.0, "negative"), (1, np.nan, "non-finite"),
+                           (2, np.inf, "non-finite")):
+            arr = [g.clone() for g in good]
+            arr[k][7] = v
+            torch.cuda.synchronize()
+            with pytest.raises(vsw.VswError, match="EINVAL"):
+                vsw.vsw_set_state_device(s.h, *[a.data_ptr() for a in arr], 0.0)
+            assert what in vsw.vsw_last_error()
+            H, HU, HV, t = s.state()
+            assert np.array_equal(H, c.H) and np.array_equal(HU, c.HU)
+        vsw.vsw_set_state_device(s.h, *[a.data_ptr() for a in good], 0.0)
         rc, done, t = s.step(0)
         assert rc == 0 and done == 0 and t == 0.0
         nc, ne, nw = vsw.vsw_mesh_info(s.h)
@@ -227,30 +281,22 @@ def test_device_state_roundtrip_and_profiling():
         s.close()
 
 
-def test_basin_1m_bench_configuration(orc):
+def test_basin_1m_bench_configuration(orc, basin1m_oracle):
     """The benchmark's workload (1M-triangle basin, Hilbert order, the
-    launch configuration the benchmark times): full-field parity after 30
-    steps, then 2000 steps checked by properties that hold at any size."""
-    c = W.basin_case()
-    say("basin", c.nc, "cells: 30-step parity")
-    g = gpu_run(c, 30)
-    o = orc_run(orc, c, 30)
-    assert_parity(g, o, "basin-1M-30")
-    s = vsw.Solver.for_case(c)
-    try:
-        rc, done, t = s.step(2000)
-        assert done == 2000
-        H, HU, HV, t = s.state()
-        m = orc.Mesh.from_case(c)
-        area = m.geometry()["area"]
-        m0, m1 = (area * c.H).sum(), (area * H).sum()
-        say("basin 2000 steps: t", t, "mass rel change", (m1 - m0) / m0, "clamps",
-            vsw.vsw_clamp_count(s.h))
-        assert np.isfinite(H).all() and np.isfinite(HU).all() and np.isfinite(HV).all()
-        assert abs(m1 - m0) <= 1e-12 * m0
-        assert (H >= 0).all()
-    finally:
-        s.close()
+    launch configuration the benchmark times): full-field parity with the
+    oracle after all 2000 steps (the oracle on every host core, bitwise the
+    same as on one), every step's dt, mass and positivity."""
+    c, o = basin1m_oracle
+    say("basin", c.nc, "cells: 2000-step parity; oracle on", orc.max_threads(), "threads")
+    g = gpu_run(c, 2000)
+    assert_parity(g, o, "basin-1M-2000")
+    assert g["clamps"] == o["clamps"]
+    m = orc.Mesh.from_case(c)
+    area = m.geometry()["area"]
+    m0, m1 = (area * c.H).sum(), (area * g["H"]).sum()
+    say("basin 2000 steps: t", g["t"], "mass rel change", (m1 - m0) / m0, "clamps", g["clamps"])
+    assert abs(m1 - m0) <= 1e-12 * m0
+    assert (g["H"] >= 0).all()
 
 
 @pytest.mark.parametrize("precision", [vsw.VSW_FP64, vsw.VSW_FP32])
@@ -274,7 +320,8 @@ def test_gauges_record_each_step(orc, precision):
         s.close()
     if precision == vsw.VSW_FP64:
         o = orc_run(orc, c, 60)
-        assert np.array_equal(e2[-1], o["H"][cells] - c.h[cells])
+        ref = o["H"][cells] - c.h[cells]
+        assert np.abs(e2[-1] - ref).max() <= TOL * np.abs(o["H"]).max()
 
 
 @pytest.mark.parametrize("which", ["thacker", "basin"])
