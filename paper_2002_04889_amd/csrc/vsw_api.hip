@@ -1045,8 +1045,10 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                            double* gH, double* gHU, double* gHV, double* gh) {
     if (!s) return fail(VSW_EINVAL, "NULL solver");
     if (!s->has_mesh || !s->has_state) return fail(VSW_ESTATE, "mesh and state required");
-    if (s->prm.precision != VSW_FP64) return fail(VSW_EINVAL, "the adjoint is FP64 only");
     if (s->nseg != 1) return fail(VSW_EINVAL, "the adjoint takes a single scenario");
+    if (s->tile != kTile) return fail(VSW_EINVAL, "the adjoint needs tiles of 256 cells");
+    // FP32 solvers: FP32 forward and replay, FP64 adjoint on their trajectory
+    const bool f32 = (s->prm.precision == VSW_FP32);
     if (nsteps < 1 || nsteps > INT32_MAX || ckpt < 1)
         return fail(VSW_EINVAL, "bad step or checkpoint count");
     if (ng < 1 || !gauge_cells || !eta_obs || !loss) return fail(VSW_EINVAL, "NULL argument");
@@ -1066,15 +1068,17 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     const std::vector<double> seg_t_save = s->seg_t, seg_dt_save = s->seg_dt;
     const std::vector<int64_t> seg_steps_save = s->seg_steps;
     const std::vector<double> seg_log_save = s->seg_log, last_dts_save = s->last_dts;
-    DevBuf<Cell4> W0, ck, seg;
-    HIP_TRY(W0.alloc(size_t(n)));
-    HIP_TRY(hipMemcpyAsync(W0.p, s->d_w[s->cur].p, size_t(n) * sizeof(Cell4),
-                           hipMemcpyDeviceToDevice, st));
+    // state records of the solver's precision: the current one and stage 1
+    const size_t rec = f32 ? sizeof(CellF) : sizeof(Cell4);
+    auto wcur = [&]() { return f32 ? (void*)s->d_wf[s->cur].p : (void*)s->d_w[s->cur].p; };
+    void* const w1buf = f32 ? (void*)s->d_w1f.p : (void*)s->d_w1.p;
+    DevBuf<unsigned char> W0, ck;
+    DevBuf<Cell4> seg;
+    HIP_TRY(W0.alloc(size_t(n) * rec));
+    HIP_TRY(hipMemcpyAsync(W0.p, wcur(), size_t(n) * rec, hipMemcpyDeviceToDevice, st));
     auto restore = [&]() {
-        (void)hipMemcpyAsync(s->d_w[s->cur].p, W0.p, size_t(n) * sizeof(Cell4),
-                             hipMemcpyDeviceToDevice, st);
-        (void)hipMemcpyAsync(s->d_w1.p, W0.p, size_t(n) * sizeof(Cell4),
-                             hipMemcpyDeviceToDevice, st);
+        (void)hipMemcpyAsync(wcur(), W0.p, size_t(n) * rec, hipMemcpyDeviceToDevice, st);
+        (void)hipMemcpyAsync(w1buf, W0.p, size_t(n) * rec, hipMemcpyDeviceToDevice, st);
         (void)hipStreamSynchronize(st);
         s->t = t_save;
         s->dt_last = dt_save;
@@ -1104,11 +1108,11 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     int rc = vsw_set_gauges(s, ng, gauge_cells);
     if (rc != VSW_OK) return rc;
     // ---- forward with checkpoints and gauge records
-    if (ck.alloc(size_t(nck) * size_t(n)) != hipSuccess)
+    if (ck.alloc(size_t(nck) * size_t(n) * rec) != hipSuccess)
         return fail(VSW_ENOMEM, "checkpoint memory");
     std::vector<double> dts, eta;
     for (int64_t c = 0; c < nck; ++c) {
-        HIP_TRY(hipMemcpyAsync(ck.p + c * n, s->d_w[s->cur].p, size_t(n) * sizeof(Cell4),
+        HIP_TRY(hipMemcpyAsync(ck.p + size_t(c) * size_t(n) * rec, wcur(), size_t(n) * rec,
                                hipMemcpyDeviceToDevice, st));
         const int64_t m = std::min(ckpt, nsteps - c * ckpt);
         int64_t done = 0;
@@ -1139,8 +1143,13 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     DevBuf<Adj4> lam, lamn;
     DevBuf<unsigned long long> rmin_hist;
     hipError_t e = hipSuccess;
+    DevBuf<CellF> fA, fB, f1;  // FP32 replay buffers
+    if (f32) {
+        for (hipError_t x : {fA.alloc(N), fB.alloc(N), f1.alloc(N)})
+            if (x != hipSuccess) return fail(VSW_ENOMEM, "adjoint work memory");
+    }
     for (hipError_t x : {d_r.alloc(r.size()), seg.alloc(SL * N), segW1.alloc(SL * N),
-                         wend.alloc(N), tR0.alloc(3 * SL * N), tR1.alloc(3 * SL * N),
+                         wend.alloc(f32 ? 1 : N), tR0.alloc(3 * SL * N), tR1.alloc(3 * SL * N),
                          tm1.alloc(SL * N), tm2.alloc(SL * N), rmin_hist.alloc(SL + 1),
                          lam.alloc(N), lamn.alloc(N), mua.alloc(3 * N), C.alloc(16 * N),
                          hbar.alloc(N), part.alloc(size_t(s->ntiles)), lamdt.alloc(1),
@@ -1155,7 +1164,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                s->xcd_order};
     const dim3 grid(unsigned(s->ntiles)), block(kBlock);
     int64_t* cells = s->d_gauge_cells.p;
-    const size_t lds = stage_lds_bytes(s->bmax);
+    const size_t lds = stage_lds_bytes(s->bmax), lds32 = stage_f32_lds_bytes(s->bmax);
     const double zero_t = 0.0;
     HIP_TRY(hipMemcpy(s->d_t0.p, &zero_t, sizeof(double), hipMemcpyHostToDevice));
     if (s->d_log.n < 2) HIP_TRY(s->d_log.alloc(2));
@@ -1166,27 +1175,48 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     for (int64_t c = nck - 1; c >= 0; --c) {
         const int64_t n0 = c * ckpt, n1 = std::min(nsteps, n0 + ckpt);
         const int64_t len = n1 - n0;
-        HIP_TRY(hipMemcpyAsync(seg.p, ck.p + c * n, N * sizeof(Cell4), hipMemcpyDeviceToDevice,
-                               st));
-        if (cfl_dt) {
+        if (cfl_dt)
             HIP_TRY(hipMemcpyAsync(rmin_hist.p, inf_bits.data(), (SL + 1) * sizeof(inf_bits[0]),
                                    hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(adj_rmin_kernel, grid, block, 0, st, m, tm, seg.p, g, thr,
-                               rmin_hist.p);
-        }
         hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(256), 0, st, s->d_ctrl.p, s->d_seg.p,
                            1, s->d_t0.p, 0);
-        for (int64_t i = 0; i < len; ++i) {
-            Cell4* Wi = seg.p + i * n;
-            Cell4* W1i = segW1.p + i * n;
-            const StepParams p{g, hg, thr, cfl, dts[size_t(n0 + i)], INFINITY};
-            Cell4* Wo = (i + 1 < len) ? Wi + n : wend.p;
-            const Tape t1{tR0.p + 3 * i * n, tm1.p + i * n, nullptr};
-            const Tape t2{tR1.p + 3 * i * n, tm2.p + i * n, rmin_hist.p + i + 1};
-            hipLaunchKernelGGL(stage_tape_kernel<1>, grid, block, lds, st, m, tm, Wi, Wo, W1i, p,
-                               s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t1);
-            hipLaunchKernelGGL(stage_tape_kernel<2>, grid, block, lds, st, m, tm, Wi, Wo, W1i, p,
-                               s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
+        const unsigned char* ckc = ck.p + size_t(c) * N * rec;
+        if (!f32) {
+            HIP_TRY(hipMemcpyAsync(seg.p, ckc, N * sizeof(Cell4), hipMemcpyDeviceToDevice, st));
+            if (cfl_dt)
+                hipLaunchKernelGGL(adj_rmin_kernel, grid, block, 0, st, m, tm, seg.p, g, thr,
+                                   rmin_hist.p);
+            for (int64_t i = 0; i < len; ++i) {
+                Cell4* Wi = seg.p + i * n;
+                Cell4* W1i = segW1.p + i * n;
+                const StepParams p{g, hg, thr, cfl, dts[size_t(n0 + i)], INFINITY};
+                Cell4* Wo = (i + 1 < len) ? Wi + n : wend.p;
+                const Tape t1{tR0.p + 3 * i * n, tm1.p + i * n, nullptr};
+                const Tape t2{tR1.p + 3 * i * n, tm2.p + i * n, rmin_hist.p + i + 1};
+                hipLaunchKernelGGL(stage_tape_kernel<1>, grid, block, lds, st, m, tm, Wi, Wo, W1i,
+                                   p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t1);
+                hipLaunchKernelGGL(stage_tape_kernel<2>, grid, block, lds, st, m, tm, Wi, Wo, W1i,
+                                   p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
+            }
+        } else {
+            // the FP32 steps again from the FP32 checkpoint; the tape holds
+            // the states they reconstruct as FP64 records
+            HIP_TRY(hipMemcpyAsync(fA.p, ckc, N * sizeof(CellF), hipMemcpyDeviceToDevice, st));
+            for (int64_t i = 0; i < len; ++i) {
+                CellF* Fi = (i & 1) ? fB.p : fA.p;
+                CellF* Fo = (i & 1) ? fA.p : fB.p;
+                const StepParams p{g, hg, thr, cfl, dts[size_t(n0 + i)], INFINITY};
+                const TapeF t1{tR0.p + 3 * i * n, tm1.p + i * n, nullptr, seg.p + i * n};
+                const TapeF t2{tR1.p + 3 * i * n, tm2.p + i * n, rmin_hist.p + i + 1,
+                               segW1.p + i * n};
+                hipLaunchKernelGGL(stage_f32_tape_kernel<1>, grid, block, lds32, st, m, tm, Fi, Fo,
+                                   f1.p, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t1);
+                hipLaunchKernelGGL(stage_f32_tape_kernel<2>, grid, block, lds32, st, m, tm, Fi, Fo,
+                                   f1.p, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
+            }
+            if (cfl_dt)
+                hipLaunchKernelGGL(adj_rmin_kernel, grid, block, 0, st, m, tm, seg.p, g, thr,
+                                   rmin_hist.p);
         }
         bool started = false;  // the start of step k was done by the previous turn
         for (int64_t k = n1 - 1; k >= n0; --k) {

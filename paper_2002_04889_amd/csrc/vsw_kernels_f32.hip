@@ -373,14 +373,15 @@ __global__ __launch_bounds__(kBlock) void dt_init_f32_kernel(DevMesh m, TileMap 
 }
 
 // Same three phases as the FP64 stage kernel; LDS holds per face slot the
-// FP64 (h, H) and FP32 (eta, u, v) of the face state.
-template <int STAGE>
-__global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm,
-                                                           CellF* __restrict__ Wa,
-                                                           CellF* __restrict__ Wb,
-                                                           CellF* __restrict__ W1, StepParams p,
-                                                           Ctrl* c, Seg* sg, int slot,
-                                                           int step_arg, double* log) {
+// FP64 (h, H) and FP32 (eta, u, v) of the face state.  TAPE adds the
+// outputs the discrete adjoint records (TapeF) and leaves the arithmetic as
+// it is.
+template <int STAGE, bool TAPE>
+__device__ __forceinline__ void stage_f32_body(const DevMesh& m, const TileMap& tm,
+                                               CellF* __restrict__ Wa, CellF* __restrict__ Wb,
+                                               CellF* __restrict__ W1, const StepParams& p,
+                                               Ctrl* c, Seg* sg, int slot, int step_arg,
+                                               double* log, const TapeF& tp) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
     double* ld = lds;
@@ -485,8 +486,9 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
         }
         const double Hn = e + hk;
         bool dry = false;
-        if (Hn < 0.0) { dry = true; clamp = 1; }
-        if (Hn < p.thr) { u = 0.0; v = 0.0; }
+        uint8_t mk = 3;
+        if (Hn < 0.0) { dry = true; clamp = 1; mk &= uint8_t(~1u); }
+        if (Hn < p.thr) { u = 0.0; v = 0.0; mk &= uint8_t(~2u); }
         const CellF o = store_state(hk, e, u, v, dry);
         if (STAGE == 1) {
             W1[k] = o;
@@ -495,6 +497,16 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
             bad = !isfinite(e) || !isfinite(u) || !isfinite(v);
             rr = cfl_ratio_f32(o, hk, ar, m.perim[k], p.g, p.thr);
         }
+        if (TAPE) {
+            // the state this stage reconstructed, in FP64 as the FP32 terms
+            // of the stage see it (H = eta + h rounded once)
+            const CellF q = Ws[k];
+            tp.win[k] = Cell4{double(q.eta) + hk, double(q.hu), double(q.hv), hk};
+            tp.R[3 * k] = R0;
+            tp.R[3 * k + 1] = R1;
+            tp.R[3 * k + 2] = R2;
+            tp.mask[k] = mk;
+        }
     }
     if (STAGE == 2 && bad) {
         atomicOr(&c->err, 1);
@@ -502,15 +514,42 @@ __global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm
     }
     block_count_atomic(clamp, &c->clamps);
     if (STAGE == 2) {
-        block_min_atomic(rr, &sgs->rmin[slot ^ 1]);
+        block_min_atomic(rr, TAPE ? tp.rmin : &sgs->rmin[slot ^ 1]);
         stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
     }
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kBlock) void stage_f32_kernel(DevMesh m, TileMap tm,
+                                                           CellF* __restrict__ Wa,
+                                                           CellF* __restrict__ Wb,
+                                                           CellF* __restrict__ W1, StepParams p,
+                                                           Ctrl* c, Seg* sg, int slot,
+                                                           int step_arg, double* log) {
+    stage_f32_body<STAGE, false>(m, tm, Wa, Wb, W1, p, c, sg, slot, step_arg, log, TapeF{});
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kBlock) void stage_f32_tape_kernel(DevMesh m, TileMap tm,
+                                                                CellF* __restrict__ W,
+                                                                CellF* __restrict__ Wout,
+                                                                CellF* __restrict__ W1,
+                                                                StepParams p, Ctrl* c, Seg* sg,
+                                                                int slot, int step_arg,
+                                                                double* log, TapeF tp) {
+    stage_f32_body<STAGE, true>(m, tm, W, Wout, W1, p, c, sg, slot, step_arg, log, tp);
 }
 
 template __global__ void stage_f32_kernel<1>(DevMesh, TileMap, CellF*, CellF*, CellF*,
                                              StepParams, Ctrl*, Seg*, int, int, double*);
 template __global__ void stage_f32_kernel<2>(DevMesh, TileMap, CellF*, CellF*, CellF*,
                                              StepParams, Ctrl*, Seg*, int, int, double*);
+template __global__ void stage_f32_tape_kernel<1>(DevMesh, TileMap, CellF*, CellF*, CellF*,
+                                                  StepParams, Ctrl*, Seg*, int, int, double*,
+                                                  TapeF);
+template __global__ void stage_f32_tape_kernel<2>(DevMesh, TileMap, CellF*, CellF*, CellF*,
+                                                  StepParams, Ctrl*, Seg*, int, int, double*,
+                                                  TapeF);
 
 // Face-parallel FP32 stage kernel: the phases of faces_stage_kernel, the
 // arithmetic of stage_f32_kernel.  LDS planes hold doubles (FP32 values are

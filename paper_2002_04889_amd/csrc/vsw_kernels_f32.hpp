@@ -25,11 +25,30 @@ inline size_t stage_f32_lds_bytes(int bmax) {
 }
 
 // Same buffer convention as stage_kernel (w^n in buffer (par + step) & 1).
+// What the discrete adjoint records while an FP32 run replays a checkpoint
+// segment: the stage's residual R (3 per cell, FP64), the mask of its
+// post-stage fix (bit 0: depth not clamped, bit 1: momentum kept), the state
+// the stage reconstructs converted to FP64 records (H = eta + h), and in
+// stage 2 the bits of the CFL minimum of w^{n+1} into *rmin (pre-set to
+// +inf) instead of the scenario's record.
+struct TapeF {
+    double* __restrict__ R;
+    uint8_t* __restrict__ mask;
+    unsigned long long* rmin;
+    Cell4* __restrict__ win;
+};
+
 // The still-water depth is m.hcell[k].
 template <int STAGE>
 __global__ void stage_f32_kernel(DevMesh m, TileMap tm, CellF* Wa, CellF* Wb, CellF* W1,
                                  StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg,
                                  double* log);
+// stage_f32_kernel with a tape (same arithmetic and results): reads w^n
+// from W and writes w^{n+1} to Wout (control par and step index 0).
+template <int STAGE>
+__global__ void stage_f32_tape_kernel(DevMesh m, TileMap tm, CellF* W, CellF* Wout, CellF* W1,
+                                      StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg,
+                                      double* log, TapeF tp);
 __global__ void dt_init_f32_kernel(DevMesh m, TileMap tm, const CellF* W, double g, double thr,
                                    Seg* sg);
 __global__ void gauge_f32_kernel(const CellF* Wa, const CellF* Wb, const double* h,

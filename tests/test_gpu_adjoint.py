@@ -248,3 +248,40 @@ def test_adjoint_full_basin_finite_differences():
         say(f"direction {k} ({which}): adjoint {ad:.10e}, |FD - adjoint| / scale per step "
             f"{np.round(np.array(errs) / scale, 12)} (noise floor {noise:.1e})")
         assert min(errs) <= tol * scale + noise
+
+
+def fp32_adjoint(c, nsteps, ckpt, gauges, obs):
+    s = vsw.Solver.for_case(c, precision=vsw.VSW_FP32)
+    try:
+        return vsw.vsw_adjoint_gauge_loss(s.h, c.nc, nsteps, ckpt, gauges, obs)
+    finally:
+        s.close()
+
+
+def test_fp32_forward_adjoint():
+    """FP32 forward and checkpoint replay, FP64 adjoint accumulation on the
+    FP32 trajectory: the loss is the FP32 run's, the gradients are identical
+    for every checkpoint interval, and they differ from the FP64 adjoint's
+    only by the FP32 trajectory's departure from the FP64 one."""
+    c, gauges, rng = setup_case("basin")
+    nsteps = 30
+    obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
+    outs = [fp32_adjoint(c, nsteps, k, gauges, obs) for k in (1, 7, 30)]
+    for o in outs[1:]:
+        assert o[0] == outs[0][0]
+        for a, b in zip(o[1:], outs[0][1:]):
+            assert np.array_equal(a, b)
+    s = vsw.Solver.for_case(c, precision=vsw.VSW_FP32)
+    try:
+        vsw.vsw_set_gauges(s.h, gauges)
+        s.step(nsteps)
+        _, eta = vsw.vsw_get_gauges(s.h, len(gauges))
+    finally:
+        s.close()
+    r = eta - obs
+    assert outs[0][0] == float((r * r).sum())
+    g64 = gpu_adjoint(c, nsteps, 8, gauges, obs)
+    for name, a, b in zip(("H", "HU", "HV", "h"), outs[0][1:], g64[1:]):
+        rel = np.abs(a - b).max() / np.abs(b).max()
+        say(f"fp32-forward adjoint d/d{name}: max |g32 - g64| / max |g64| = {rel:.3e}")
+        assert rel <= 1e-3, name
