@@ -129,6 +129,37 @@ __device__ __forceinline__ void block_count_atomic(unsigned long long v, unsigne
     }
 }
 
+// block_count_atomic and block_min_atomic in one pass (one barrier).
+template <int NT>
+__device__ __forceinline__ void block_count_min_atomic(unsigned long long n,
+                                                       unsigned long long* count, double v,
+                                                       unsigned long long* target) {
+    __shared__ unsigned long long pn[NT / 64];
+    __shared__ double pv[NT / 64];
+    n = wave_sum(n);
+    v = wave_min(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        pn[wid] = n;
+        pv[wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        double m = pv[0];
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) {
+            s += pn[i];
+            m = (pv[i] < m) ? pv[i] : m;
+        }
+        if (s) atomicAdd(count, s);
+        const unsigned long long b = dbits(m);
+        if (m < __longlong_as_double(0x7FF0000000000000ll) &&
+            b < __hip_atomic_load(target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMin(target, b);
+    }
+}
+
 // Stage 1: w1 = w + dt R(w), then the post-stage fix (negative depth set to
 // zero and counted; velocity zero below H_thr).
 // mk: bit 0 cleared when the depth is clamped, bit 1 when the momentum is
@@ -286,9 +317,7 @@ __device__ __forceinline__ void tile_faces(const DevMesh& m, const TileMap& tm,
         const int jn = int(item & 3u);
         Recon r;
         recon_core(m, Ws, n, thr, r);
-        const Face f = (jn == 0) ? recon_face(r, 0, thr)
-                     : (jn == 1) ? recon_face(r, 1, thr) : recon_face(r, 2, thr);
-        lds_store_face(lds, stride, 3 * kTile + b, f);
+        lds_store_face(lds, stride, 3 * kTile + b, recon_face_sel(r, jn, thr));
     }
 }
 

@@ -27,47 +27,84 @@ namespace vsw {
 
 namespace {
 
-// Reconstruction of cell k from its vertices and least-squares weights.
-// area (may be null) receives |K|.
-__device__ __forceinline__ void recon_geo(const FaceMesh& m, const Cell4* __restrict__ W,
-                                          int64_t k, double thr, Recon& r, double* area) {
-    const TopoD tp = m.topo[k];
+// Vertex coordinates of a cell in local order.
+struct Tri {
+    double x[3], y[3];
+};
+
+__device__ __forceinline__ Tri load_tri(const FaceMesh& m, const TopoD& tp) {
     const double2 p0 = m.vxy[tp.v0], p1 = m.vxy[tp.v1], p2 = m.vxy[tp.v2];
-    const double x[3] = {p0.x, p1.x, p2.x}, y[3] = {p0.y, p1.y, p2.y};
-    if (area) {
-        const double cr = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
-        *area = 0.5 * cr;
-    }
+    return Tri{{p0.x, p1.x, p2.x}, {p0.y, p1.y, p2.y}};
+}
+
+// State records of the three neighbours of cell k (k itself across a wall,
+// where the record is not used): one load each, without branches.
+__device__ __forceinline__ void load_nbrs(const Cell4* __restrict__ W, const TopoD& tp, int64_t k,
+                                          Cell4 cn[3]) {
     const uint32_t sl[3] = {tp.n0, tp.n1, tp.n2};
-    recon_with(
-        W, k, sl, thr,
+#pragma unroll
+    for (int j = 0; j < 3; ++j) cn[j] = W[(sl[j] != kWallSlot) ? int64_t(sl[j] >> 3) : k];
+}
+
+__device__ __forceinline__ double tri_area(const Tri& g) {
+    const double cr = (g.x[1] - g.x[0]) * (g.y[2] - g.y[0]) - (g.x[2] - g.x[0]) * (g.y[1] - g.y[0]);
+    return 0.5 * cr;
+}
+
+// Reconstruction of a cell from its loaded state, neighbours, vertices and
+// least-squares weights; the wall normals and face-midpoint offsets are
+// computed from the vertices as the host computes its stored geometry.
+__device__ __forceinline__ void recon_tri(const Cell4& ck, const Cell4 cn[3], const TopoD& tp,
+                                          const Tri& g, const LsqW& w, double thr, Recon& r) {
+    const uint32_t sl[3] = {tp.n0, tp.n1, tp.n2};
+    recon_from(
+        ck, cn, sl, thr,
         [&](int j, double& nx, double& ny) {
             const int j1 = (j == 2) ? 0 : j + 1;
-            const double ex = x[j1] - x[j], ey = y[j1] - y[j];
+            const double ex = g.x[j1] - g.x[j], ey = g.y[j1] - g.y[j];
             const double l = sqrt(ex * ex + ey * ey);
             nx = ey / l;
             ny = (-ex) / l;
         },
         [&](double* gw, double* gd) {
-            const LsqW w = m.lsq[k];
-            const double cx = ((x[0] + x[1]) + x[2]) / 3.0;
-            const double cy = ((y[0] + y[1]) + y[2]) / 3.0;
+            const double cx = ((g.x[0] + g.x[1]) + g.x[2]) / 3.0;
+            const double cy = ((g.y[0] + g.y[1]) + g.y[2]) / 3.0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int j1 = (j == 2) ? 0 : j + 1;
                 gw[2 * j] = w.w[2 * j];
                 gw[2 * j + 1] = w.w[2 * j + 1];
-                gd[2 * j] = (x[j] + x[j1]) * 0.5 - cx;
-                gd[2 * j + 1] = (y[j] + y[j1]) * 0.5 - cy;
+                gd[2 * j] = (g.x[j] + g.x[j1]) * 0.5 - cx;
+                gd[2 * j + 1] = (g.y[j] + g.y[j1]) * 0.5 - cy;
             }
         },
         r);
 }
 
+// Unit normal (from vertex a to b, turned clockwise) and length of a face.
+struct FaceGeo {
+    double nx, ny, l;
+};
+
+__device__ __forceinline__ FaceGeo face_geo(const double2& pa, const double2& pb) {
+    const double ex = pb.x - pa.x, ey = pb.y - pa.y;
+    const double l = sqrt(ex * ex + ey * ey);
+    return FaceGeo{ey / l, (-ex) / l, l};
+}
+
+__device__ __forceinline__ void store_face(double* Le, double* Lh, double* LH, double* Lu,
+                                           double* Lv, int s, const Face& f) {
+    Le[s] = f.eta;
+    Lh[s] = f.h;
+    LH[s] = f.H;
+    Lu[s] = f.u;
+    Lv[s] = f.v;
+}
+
 }  // namespace
 
 template <int T, int STAGE>
-__global__ __launch_bounds__(T) void faces_stage_kernel(FaceMesh m, FaceTileMap tm,
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void faces_stage_kernel(FaceMesh m, FaceTileMap tm,
                                                         Cell4* __restrict__ Wa,
                                                         Cell4* __restrict__ Wb,
                                                         Cell4* __restrict__ W1, StepParams p,
@@ -106,58 +143,105 @@ __global__ __launch_bounds__(T) void faces_stage_kernel(FaceMesh m, FaceTileMap 
     const int cnt = ti.cnt;
     const int i = threadIdx.x;
     const int64_t k = c0 + i;
+    const bool own = i < cnt;
+    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
+    const int f0 = tm.fstart[t], nf = tm.fstart[t + 1] - f0;
+
+    // The loads are issued in dependency levels, each before the arithmetic
+    // that waits for the previous one: (1) the cell's topology, weights and
+    // state, the first halo item and the first two face records of the
+    // thread; (2) the cell's neighbours and vertices and the halo cell's
+    // topology; (3) after the cell's reconstruction, the halo cell's data;
+    // (4) after the halo, the faces' vertices and the records the
+    // Runge-Kutta stage reads, all before the first barrier.  (The faces'
+    // vertices held through the reconstructions would need more than the 128
+    // registers of four waves per SIMD.)
+    const int64_t ko = own ? k : c0;
+    const TopoD tp = m.topo[ko];
+    const LsqW lw = m.lsq[ko];
+    const Cell4 ck = Ws[ko];
+    uint32_t hitem = 0;
+    if (i < nb) hitem = tm.bitem[b0 + i];
+    const Tri tg = load_tri(m, tp);
+    Cell4 cn[3];
+    load_nbrs(Ws, tp, ko, cn);
+    TopoD htp{0u, 0u, 0u, 0u, 0u, 0u};
+    if (i < nb) htp = m.topo[hitem >> 2];
+    FaceItemD it0{0u, 0u, 0, 0}, it1{0u, 0u, 0, 0};
+    if (i < nf) it0 = tm.items[f0 + i];
+    if (i + T < nf) it1 = tm.items[f0 + i + T];
 
     // phase 1: the tile's cells and the halo faces
     double area = 1.0;
     bool second = false;
-    if (i < cnt) {
+    if (own) {
         Recon r;
-        recon_geo(m, Ws, k, p.thr, r, &area);
+        recon_tri(ck, cn, tp, tg, lw, p.thr, r);
+        area = tri_area(tg);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const Face f = recon_face(r, j, p.thr);
-            const int sj = j * T + i;
-            Le[sj] = f.eta;
-            Lh[sj] = f.h;
-            LH[sj] = f.H;
-            Lu[sj] = f.u;
-            Lv[sj] = f.v;
-        }
+        for (int j = 0; j < 3; ++j) store_face(Le, Lh, LH, Lu, Lv, j * T + i, recon_face(r, j, p.thr));
         CH[i] = r.Hk;
         Ch[i] = r.hk;
         second = r.second;
     }
-    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
     for (int b = i; b < nb; b += T) {
-        const uint32_t item = tm.bitem[b0 + b];
+        const bool pre = (b == i);
+        const uint32_t item = pre ? hitem : tm.bitem[b0 + b];
         const int64_t n = int64_t(item >> 2);
         const int jn = int(item & 3u);
+        const TopoD tq = pre ? htp : m.topo[n];
+        const LsqW lq = m.lsq[n];
+        const Cell4 cq = Ws[n];
+        const Tri gq = load_tri(m, tq);
+        Cell4 cnq[3];
+        load_nbrs(Ws, tq, n, cnq);
         Recon r;
-        recon_geo(m, Ws, n, p.thr, r, nullptr);
-        const Face f = (jn == 0) ? recon_face(r, 0, p.thr)
-                     : (jn == 1) ? recon_face(r, 1, p.thr) : recon_face(r, 2, p.thr);
-        const int sb = 3 * T + b;
-        Le[sb] = f.eta;
-        Lh[sb] = f.h;
-        LH[sb] = f.H;
-        Lu[sb] = f.u;
-        Lv[sb] = f.v;
+        recon_tri(cq, cnq, tq, gq, lq, p.thr, r);
+        store_face(Le, Lh, LH, Lu, Lv, 3 * T + b, recon_face_sel(r, jn, p.thr));
     }
+    double2 a0 = make_double2(0.0, 0.0), e0 = a0, a1 = a0, e1 = a0;
+    if (i < nf) {
+        a0 = m.vxy[it0.va];
+        e0 = m.vxy[it0.vb];
+    }
+    if (i + T < nf) {
+        a1 = m.vxy[it1.va];
+        e1 = m.vxy[it1.vb];
+    }
+    Cell4 wn{0.0, 0.0, 0.0, 0.0}, w1{0.0, 0.0, 0.0, 0.0};
+    double per = 1.0;
+    if (own) {
+        wn = W[k];
+        if (STAGE == 2) {
+            w1 = W1[k];
+            per = m.perim[k];
+        }
+    }
+    FaceGeo g0{0.0, 0.0, 0.0}, g1{0.0, 0.0, 0.0};
+    if (i < nf) g0 = face_geo(a0, e0);
+    if (i + T < nf) g1 = face_geo(a1, e1);
     __syncthreads();
 
     // phase 2: each face once
-    const int f0 = tm.fstart[t], nf = tm.fstart[t + 1] - f0;
     for (int q = i; q < nf; q += T) {
-        const FaceItemD it = tm.items[f0 + q];
+        FaceItemD it;
+        FaceGeo fg;
+        if (q == i) {
+            it = it0;
+            fg = g0;
+        } else if (q == i + T) {
+            it = it1;
+            fg = g1;
+        } else {
+            it = tm.items[f0 + q];
+            fg = face_geo(m.vxy[it.va], m.vxy[it.vb]);
+        }
         const int sl = it.sl;
         const bool wall = (it.sr == kFaceWall);
         const int sr = wall ? sl : int(it.sr);
         const Face L{Le[sl], Lh[sl], LH[sl], Lu[sl], Lv[sl]};
         const Face R{Le[sr], Lh[sr], LH[sr], Lu[sr], Lv[sr]};
-        const double2 pa = m.vxy[it.va], pb = m.vxy[it.vb];
-        const double ex = pb.x - pa.x, ey = pb.y - pa.y;
-        const double l = sqrt(ex * ex + ey * ey);
-        const double nx = ey / l, ny = (-ex) / l;
+        const double nx = fg.nx, ny = fg.ny, l = fg.l;
         double tL[3], tR[3];
         face_pair(p.g, p.hg, L, R, wall, nx, ny, l, tL, tR);
         // the left cell subtracts its term, the right cell adds its own;
@@ -188,40 +272,41 @@ __global__ __launch_bounds__(T) void faces_stage_kernel(FaceMesh m, FaceTileMap 
     unsigned long long clamp = 0;
     double rr = __longlong_as_double(0x7FF0000000000000ll);
     bool bad = false;
-    if (i < cnt) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (own) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int sj = j * T + i;
-            a0 = a0 + Le[sj];
-            a1 = a1 + Lh[sj];
-            a2 = a2 + LH[sj];
+            s0 = s0 + Le[sj];
+            s1 = s1 + Lh[sj];
+            s2 = s2 + LH[sj];
         }
         if (second) {
             const double sx = (Lu[i] + Lu[T + i]) + Lu[2 * T + i];
             const double sy = (Lv[i] + Lv[T + i]) + Lv[2 * T + i];
-            a1 = a1 + p.hg * sx;
-            a2 = a2 + p.hg * sy;
+            s1 = s1 + p.hg * sx;
+            s2 = s2 + p.hg * sy;
         }
-        const double R[3] = {a0 / area, a1 / area, a2 / area};
+        const double R[3] = {s0 / area, s1 / area, s2 / area};
         uint8_t mk;
         if (STAGE == 1) {
-            W1[k] = stage1_update(W[k], R, dt, p.thr, clamp, mk);
+            W1[k] = stage1_update(wn, R, dt, p.thr, clamp, mk);
         } else {
-            const Cell4 o = stage2_update(W[k], W1[k], R, dt, p.thr, clamp, mk);
+            const Cell4 o = stage2_update(wn, w1, R, dt, p.thr, clamp, mk);
             Wout[k] = o;
             bad = !isfinite(o.H) || !isfinite(o.HU) || !isfinite(o.HV);
-            rr = cfl_ratio(o.H, o.HU, o.HV, area, m.perim[k], p.g, p.thr);
+            rr = cfl_ratio(o.H, o.HU, o.HV, area, per, p.g, p.thr);
         }
     }
     if (STAGE == 2 && bad) {
         atomicOr(&c->err, 1);
         atomicMin(&c->err_step, step);
     }
-    block_count_atomic<T>(clamp, &c->clamps);
     if (STAGE == 2) {
-        block_min_atomic<T>(rr, &sgs->rmin[slot ^ 1]);
+        block_count_min_atomic<T>(clamp, &c->clamps, rr, &sgs->rmin[slot ^ 1]);
         stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
+    } else {
+        block_count_atomic<T>(clamp, &c->clamps);
     }
 }
 

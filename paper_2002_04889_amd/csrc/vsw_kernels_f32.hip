@@ -34,15 +34,25 @@ struct ReconF {
 __device__ __forceinline__ float fminf_(float a, float b) { return (b < a) ? b : a; }
 __device__ __forceinline__ float fmaxf_(float a, float b) { return (b > a) ? b : a; }
 
+// Reciprocal of a positive normal double to about one ulp: the hardware
+// estimate and two Newton steps e = 1 - b r, r = r + r e with fused
+// multiply-adds (quadratic convergence from the estimate).
+__device__ __forceinline__ double recip_f64(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-b, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
 // FP32 reconstruction of cell k.  Geometry from callbacks as in recon_with:
 // wall_n(j, nx, ny) in FP64 (rounded here), geo(w, d) as FP32 values.
+// recon_from_f32 takes the records already loaded: ck, hk of the cell,
+// cnb[j], hnb[j] of the neighbour across face j (not read on a wall).
 template <class WallN, class Geo>
-__device__ __forceinline__ void recon_with_f32(const CellF* __restrict__ W,
-                                               const double* __restrict__ hc, int64_t k,
-                                               const uint32_t sl[3], double thr, WallN wall_n,
-                                               Geo geo, ReconF& r) {
-    const CellF ck = W[k];
-    const double hk = hc[k];
+__device__ __forceinline__ void recon_from_f32(const CellF& ck, double hk, const CellF cnb[3],
+                                               const double hnb[3], const uint32_t sl[3],
+                                               double thr, WallN wall_n, Geo geo, ReconF& r) {
     const float ek = ck.eta, uk = ck.hu, vk = ck.hv;
     const double Hk = double(ek) + hk;
     float qe[3], qu[3], qv[3], dh[3];
@@ -51,9 +61,8 @@ __device__ __forceinline__ void recon_with_f32(const CellF* __restrict__ W,
     for (int j = 0; j < 3; ++j) {
         const uint32_t s = sl[j];
         if (s != kWallSlot) {
-            const int64_t n = int64_t(s >> 3);
-            const CellF cn = W[n];
-            const double hn = hc[n];
+            const CellF& cn = cnb[j];
+            const double hn = hnb[j];
             const double Hn = double(cn.eta) + hn;
             qe[j] = cn.eta;
             qu[j] = cn.hu;
@@ -93,7 +102,8 @@ __device__ __forceinline__ void recon_with_f32(const CellF* __restrict__ W,
         project(qu, uk, pu);
         project(qv, vk, pv);
         project(dh, 0.0f, ph);
-        // Barth-Jespersen, as in the FP64 kernel (at most two divisions)
+        // Barth-Jespersen, as in the FP64 kernel, with the two ratios taken
+        // by the hardware reciprocal (1 ulp) and capped at one
         auto limiter = [](float q0, const float* qs, const float* pj) -> float {
             float qmax = q0, qmin = q0;
 #pragma unroll
@@ -109,8 +119,10 @@ __device__ __forceinline__ void recon_with_f32(const CellF* __restrict__ W,
                 dneg_min = fminf_(dneg_min, pj[j]);
             }
             float a = 1.0f;
-            if (dpos_max > 0.0f && up < dpos_max) a = up / dpos_max;
-            if (dneg_min < 0.0f && dn > dneg_min) a = fminf_(a, dn / dneg_min);
+            if (dpos_max > 0.0f && up < dpos_max)
+                a = fminf_(1.0f, up * __builtin_amdgcn_rcpf(dpos_max));
+            if (dneg_min < 0.0f && dn > dneg_min)
+                a = fminf_(a, dn * __builtin_amdgcn_rcpf(dneg_min));
             return a;
         };
         const float ae = limiter(ek, qe, pe);
@@ -133,6 +145,24 @@ __device__ __forceinline__ void recon_with_f32(const CellF* __restrict__ W,
         }
     }
     r.second = cand;
+}
+
+template <class WallN, class Geo>
+__device__ __forceinline__ void recon_with_f32(const CellF* __restrict__ W,
+                                               const double* __restrict__ hc, int64_t k,
+                                               const uint32_t sl[3], double thr, WallN wall_n,
+                                               Geo geo, ReconF& r) {
+    const CellF ck = W[k];
+    const double hk = hc[k];
+    CellF cn[3];
+    double hn[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int64_t n = (sl[j] != kWallSlot) ? int64_t(sl[j] >> 3) : k;
+        cn[j] = W[n];
+        hn[j] = hc[n];
+    }
+    recon_from_f32(ck, hk, cn, hn, sl, thr, wall_n, geo, r);
 }
 
 __device__ __forceinline__ void recon_core_f32(const DevMesh& m, const CellF* __restrict__ W,
@@ -172,6 +202,18 @@ __device__ __forceinline__ FaceF recon_face_f32(const ReconF& r, int j, double t
         f.v = 0.0f;
     }
     return f;
+}
+
+// recon_face_f32(r, j) for a face index j known only at run time: the face
+// values are selected first, then one face state is formed.
+__device__ __forceinline__ FaceF recon_face_sel_f32(const ReconF& r, int j, double thr) {
+    ReconF s;
+    s.fe[0] = (j == 0) ? r.fe[0] : (j == 1) ? r.fe[1] : r.fe[2];
+    s.fu[0] = (j == 0) ? r.fu[0] : (j == 1) ? r.fu[1] : r.fu[2];
+    s.fv[0] = (j == 0) ? r.fv[0] : (j == 1) ? r.fv[1] : r.fv[2];
+    s.fh[0] = (j == 0) ? r.fh[0] : (j == 1) ? r.fh[1] : r.fh[2];
+    s.fH[0] = (j == 0) ? r.fH[0] : (j == 1) ? r.fH[1] : r.fH[2];
+    return recon_face_f32(s, 0, thr);
 }
 
 // HLL flux in the face frame (Section 2.2) with FP64 depths HL, HR: the
@@ -216,9 +258,9 @@ __device__ __forceinline__ void hll_face_f32(double g, double hg, double HL, flo
         // relative on every face).  Mass and normal-momentum star fluxes are
         // formed in FP64 from the FP32 terms; the tangential one in FP32.
         // One reciprocal for the three components (this path is held to a
-        // tolerance, not to the FP64 path's bits).
+        // tolerance, not to the FP64 path's bits); den > 0 here.
         const double dR = double(sR), dL = double(sL), den = dR - dL, sLR = dL * dR;
-        const double rden = 1.0 / den;
+        const double rden = recip_f64(den);
         f0 = float(((dR * double(fL0) - dL * double(fR0)) + sLR * (HR - HL)) * rden);
         f1 = ((dR * fL1 - dL * fR1) + sLR * (double(qR) - double(qL))) * rden;
         f2 = ((sR * fL2 - sL * fR2) + float(sLR) * (HRf * utR - HLf * utL)) * float(rden);
@@ -283,22 +325,16 @@ __device__ __forceinline__ void face_pair_f32(double g, double hg, const FaceF& 
     tR[2] = l * (phi2 + pcR * ny);
 }
 
-// FP32 reconstruction of cell k from its vertices (geometry in FP64 as the
-// host computes it, rounded to FP32 where the FP32 terms use it) and FP32
-// least-squares weights.  area (may be null) receives |K|.
-__device__ __forceinline__ void recon_geo_f32(const FaceMesh& m, const CellF* __restrict__ W,
-                                              const double* __restrict__ hc, int64_t k,
-                                              double thr, ReconF& r, double* area) {
-    const TopoD tp = m.topo[k];
-    const double2 p0 = m.vxy[tp.v0], p1 = m.vxy[tp.v1], p2 = m.vxy[tp.v2];
-    const double x[3] = {p0.x, p1.x, p2.x}, y[3] = {p0.y, p1.y, p2.y};
-    if (area) {
-        const double cr = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
-        *area = 0.5 * cr;
-    }
+// FP32 reconstruction of a cell from its loaded records, vertices (geometry
+// in FP64 as the host computes it, rounded to FP32 where the FP32 terms use
+// it) and FP32 least-squares weights.
+__device__ __forceinline__ void recon_tri_f32(const CellF& ck, double hk, const CellF cn[3],
+                                              const double hn[3], const TopoD& tp,
+                                              const double x[3], const double y[3],
+                                              const LsqWF& w, double thr, ReconF& r) {
     const uint32_t sl[3] = {tp.n0, tp.n1, tp.n2};
-    recon_with_f32(
-        W, hc, k, sl, thr,
+    recon_from_f32(
+        ck, hk, cn, hn, sl, thr,
         [&](int j, double& nx, double& ny) {
             const int j1 = (j == 2) ? 0 : j + 1;
             const double ex = x[j1] - x[j], ey = y[j1] - y[j];
@@ -307,7 +343,6 @@ __device__ __forceinline__ void recon_geo_f32(const FaceMesh& m, const CellF* __
             ny = (-ex) / l;
         },
         [&](float* gw, float* gd) {
-            const LsqWF w = m.lsqf[k];
             const double cx = ((x[0] + x[1]) + x[2]) / 3.0;
             const double cy = ((y[0] + y[1]) + y[2]) / 3.0;
 #pragma unroll
@@ -320,6 +355,33 @@ __device__ __forceinline__ void recon_geo_f32(const FaceMesh& m, const CellF* __
             }
         },
         r);
+}
+
+// The records recon_tri_f32 reads for cell k: state, still-water depth,
+// neighbours (k itself across a wall, not used), vertices.
+struct CellInF {
+    CellF ck;
+    double hk;
+    CellF cn[3];
+    double hn[3];
+    double x[3], y[3];
+};
+
+__device__ __forceinline__ void load_cell_f32(const FaceMesh& m, const CellF* __restrict__ W,
+                                              const double* __restrict__ hc, const TopoD& tp,
+                                              int64_t k, CellInF& in) {
+    const uint32_t sl[3] = {tp.n0, tp.n1, tp.n2};
+    in.ck = W[k];
+    in.hk = hc[k];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int64_t n = (sl[j] != kWallSlot) ? int64_t(sl[j] >> 3) : k;
+        in.cn[j] = W[n];
+        in.hn[j] = hc[n];
+    }
+    const double2 p0 = m.vxy[tp.v0], p1 = m.vxy[tp.v1], p2 = m.vxy[tp.v2];
+    in.x[0] = p0.x; in.x[1] = p1.x; in.x[2] = p2.x;
+    in.y[0] = p0.y; in.y[1] = p1.y; in.y[2] = p2.y;
 }
 
 // Store a stage result: eta rounded to nearest, or, for a cell set dry,
@@ -425,9 +487,7 @@ __device__ __forceinline__ void stage_f32_body(const DevMesh& m, const TileMap& 
         const int jn = int(item & 3u);
         ReconF r;
         recon_core_f32(m, Ws, n, p.thr, r);
-        const FaceF f = (jn == 0) ? recon_face_f32(r, 0, p.thr)
-                      : (jn == 1) ? recon_face_f32(r, 1, p.thr) : recon_face_f32(r, 2, p.thr);
-        lds_store_face_f32(ld, lf, stride, 3 * kTile + b, f);
+        lds_store_face_f32(ld, lf, stride, 3 * kTile + b, recon_face_sel_f32(r, jn, p.thr));
     }
     __syncthreads();
 
@@ -470,7 +530,7 @@ __device__ __forceinline__ void stage_f32_body(const DevMesh& m, const TileMap& 
             a2 = a2 + p.hg * sy;
         }
         const double ar = m.area[k];
-        const double rar = 1.0 / ar;
+        const double rar = recip_f64(ar);
         const double R0 = a0 * rar, R1 = a1 * rar, R2 = a2 * rar;
         const CellF w = W[k];
         double e, u, v;
@@ -593,11 +653,33 @@ __global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTile
     const int i = threadIdx.x;
     const int64_t k = c0 + i;
 
+    const bool own = i < cnt;
+    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
+    const int f0 = tm.fstart[t], nf = tm.fstart[t + 1] - f0;
+    // loads in dependency levels, as in faces_stage_kernel; the FP32 records
+    // leave the registers to fetch the thread's first two face records with
+    // the first level and their vertices after the cell's reconstruction
+    const int64_t ko = own ? k : c0;
+    const TopoD tp = m.topo[ko];
+    const LsqWF lw = m.lsqf[ko];
+    uint32_t hitem = 0;
+    if (i < nb) hitem = tm.bitem[b0 + i];
+    CellInF in;
+    load_cell_f32(m, Ws, hc, tp, ko, in);
+    TopoD htp{0u, 0u, 0u, 0u, 0u, 0u};
+    if (i < nb) htp = m.topo[hitem >> 2];
+    FaceItemD it0{0u, 0u, 0, 0}, it1{0u, 0u, 0, 0};
+    if (i < nf) it0 = tm.items[f0 + i];
+    if (i + T < nf) it1 = tm.items[f0 + i + T];
+
     double area = 1.0;
     bool second = false;
-    if (i < cnt) {
+    if (own) {
         ReconF r;
-        recon_geo_f32(m, Ws, hc, k, p.thr, r, &area);
+        recon_tri_f32(in.ck, in.hk, in.cn, in.hn, tp, in.x, in.y, lw, p.thr, r);
+        const double cr = (in.x[1] - in.x[0]) * (in.y[2] - in.y[0]) -
+                          (in.x[2] - in.x[0]) * (in.y[1] - in.y[0]);
+        area = 0.5 * cr;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const FaceF f = recon_face_f32(r, j, p.thr);
@@ -612,15 +694,27 @@ __global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTile
         Ch[i] = r.hk;
         second = r.second;
     }
-    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
+    double2 a0 = make_double2(0.0, 0.0), e0 = a0, a1 = a0, e1 = a0;
+    if (i < nf) {
+        a0 = m.vxy[it0.va];
+        e0 = m.vxy[it0.vb];
+    }
+    if (i + T < nf) {
+        a1 = m.vxy[it1.va];
+        e1 = m.vxy[it1.vb];
+    }
     for (int b = i; b < nb; b += T) {
-        const uint32_t item = tm.bitem[b0 + b];
+        const bool pre = (b == i);
+        const uint32_t item = pre ? hitem : tm.bitem[b0 + b];
         const int64_t n = int64_t(item >> 2);
         const int jn = int(item & 3u);
+        const TopoD tq = pre ? htp : m.topo[n];
+        const LsqWF lq = m.lsqf[n];
+        CellInF iq;
+        load_cell_f32(m, Ws, hc, tq, n, iq);
         ReconF r;
-        recon_geo_f32(m, Ws, hc, n, p.thr, r, nullptr);
-        const FaceF f = (jn == 0) ? recon_face_f32(r, 0, p.thr)
-                      : (jn == 1) ? recon_face_f32(r, 1, p.thr) : recon_face_f32(r, 2, p.thr);
+        recon_tri_f32(iq.ck, iq.hk, iq.cn, iq.hn, tq, iq.x, iq.y, lq, p.thr, r);
+        const FaceF f = recon_face_sel_f32(r, jn, p.thr);
         const int sb = 3 * T + b;
         Le[sb] = double(f.eta);
         Lh[sb] = f.h;
@@ -628,21 +722,48 @@ __global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTile
         Lu[sb] = double(f.u);
         Lv[sb] = double(f.v);
     }
+    CellF wn{0.0f, 0.0f, 0.0f}, w1{0.0f, 0.0f, 0.0f};
+    double hk = 0.0, per = 1.0;
+    if (own) {
+        wn = W[k];
+        hk = hc[k];
+        if (STAGE == 2) {
+            w1 = W1[k];
+            per = m.perim[k];
+        }
+    }
+    auto fgeo = [](const double2& pa, const double2& pb, double g[3]) {
+        const double ex = pb.x - pa.x, ey = pb.y - pa.y;
+        const double l = sqrt(ex * ex + ey * ey);
+        g[0] = ey / l;
+        g[1] = (-ex) / l;
+        g[2] = l;
+    };
+    double g0[3] = {0.0, 0.0, 0.0}, g1[3] = {0.0, 0.0, 0.0};
+    if (i < nf) fgeo(a0, e0, g0);
+    if (i + T < nf) fgeo(a1, e1, g1);
     __syncthreads();
 
-    const int f0 = tm.fstart[t], nf = tm.fstart[t + 1] - f0;
     for (int q = i; q < nf; q += T) {
-        const FaceItemD it = tm.items[f0 + q];
+        FaceItemD it;
+        double fg[3];
+        if (q == i) {
+            it = it0;
+            fg[0] = g0[0]; fg[1] = g0[1]; fg[2] = g0[2];
+        } else if (q == i + T) {
+            it = it1;
+            fg[0] = g1[0]; fg[1] = g1[1]; fg[2] = g1[2];
+        } else {
+            it = tm.items[f0 + q];
+            fgeo(m.vxy[it.va], m.vxy[it.vb], fg);
+        }
         const int sl = it.sl;
         const bool wall = (it.sr == kFaceWall);
         const int sr = wall ? sl : int(it.sr);
         FaceF L, R;
         L.eta = float(Le[sl]); L.h = Lh[sl]; L.H = LH[sl]; L.u = float(Lu[sl]); L.v = float(Lv[sl]);
         R.eta = float(Le[sr]); R.h = Lh[sr]; R.H = LH[sr]; R.u = float(Lu[sr]); R.v = float(Lv[sr]);
-        const double2 pa = m.vxy[it.va], pb = m.vxy[it.vb];
-        const double ex = pb.x - pa.x, ey = pb.y - pa.y;
-        const double l = sqrt(ex * ex + ey * ey);
-        const double nx = ey / l, ny = (-ex) / l;
+        const double nx = fg[0], ny = fg[1], l = fg[2];
         double tL[3], tR[3];
         face_pair_f32(p.g, p.hg, L, R, wall, nx, ny, l, tL, tR);
         if (sl < 3 * T) {
@@ -669,32 +790,30 @@ __global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTile
     unsigned long long clamp = 0;
     double rr = __longlong_as_double(0x7FF0000000000000ll);
     bool bad = false;
-    if (i < cnt) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (own) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int sj = j * T + i;
-            a0 = a0 + Le[sj];
-            a1 = a1 + Lh[sj];
-            a2 = a2 + LH[sj];
+            s0 = s0 + Le[sj];
+            s1 = s1 + Lh[sj];
+            s2 = s2 + LH[sj];
         }
         if (second) {
             const double sx = (Lu[i] + Lu[T + i]) + Lu[2 * T + i];
             const double sy = (Lv[i] + Lv[T + i]) + Lv[2 * T + i];
-            a1 = a1 + p.hg * sx;
-            a2 = a2 + p.hg * sy;
+            s1 = s1 + p.hg * sx;
+            s2 = s2 + p.hg * sy;
         }
-        const double rar = 1.0 / area;
-        const double R0 = a0 * rar, R1 = a1 * rar, R2 = a2 * rar;
-        const double hk = hc[k];
-        const CellF w = W[k];
+        const double rar = recip_f64(area);
+        const double R0 = s0 * rar, R1 = s1 * rar, R2 = s2 * rar;
+        const CellF w = wn;
         double e, u, v;
         if (STAGE == 1) {
             e = double(w.eta) + dt * R0;
             u = double(w.hu) + dt * R1;
             v = double(w.hv) + dt * R2;
         } else {
-            const CellF w1 = W1[k];
             e = 0.5 * double(w.eta) + 0.5 * (double(w1.eta) + dt * R0);
             u = 0.5 * double(w.hu) + 0.5 * (double(w1.hu) + dt * R1);
             v = 0.5 * double(w.hv) + 0.5 * (double(w1.hv) + dt * R2);
@@ -709,17 +828,18 @@ __global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTile
         } else {
             Wout[k] = o;
             bad = !isfinite(e) || !isfinite(u) || !isfinite(v);
-            rr = cfl_ratio_f32(o, hk, area, m.perim[k], p.g, p.thr);
+            rr = cfl_ratio_f32(o, hk, area, per, p.g, p.thr);
         }
     }
     if (STAGE == 2 && bad) {
         atomicOr(&c->err, 1);
         atomicMin(&c->err_step, step);
     }
-    block_count_atomic<T>(clamp, &c->clamps);
     if (STAGE == 2) {
-        block_min_atomic<T>(rr, &sgs->rmin[slot ^ 1]);
+        block_count_min_atomic<T>(clamp, &c->clamps, rr, &sgs->rmin[slot ^ 1]);
         stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
+    } else {
+        block_count_atomic<T>(clamp, &c->clamps);
     }
 }
 

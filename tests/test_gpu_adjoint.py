@@ -279,7 +279,9 @@ def test_fp32_forward_adjoint():
     finally:
         s.close()
     r = eta - obs
-    assert outs[0][0] == float((r * r).sum())
+    # same residuals; the sums differ only in their order of addition
+    ref = float((r * r).sum())
+    assert abs(outs[0][0] - ref) <= 1e-13 * ref
     g64 = gpu_adjoint(c, nsteps, 8, gauges, obs)
     for name, a, b in zip(("H", "HU", "HV", "h"), outs[0][1:], g64[1:]):
         rel = np.abs(a - b).max() / np.abs(b).max()
