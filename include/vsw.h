@@ -238,20 +238,24 @@ int vsw_set_kernel_variant(vsw_solver *s, int variant);
 
 /* Cells per tile (one workgroup, one thread per cell) of the layout of the
  * mesh on the device: 128, 256 (default) or 512.  With a mesh uploaded the
- * mesh is laid out again and its state and time carried over (results are
- * bitwise the same for every tile size); otherwise it applies to the next
- * upload.  The solver keeps a copy of the uploaded mesh for this.  EINVAL
+ * mesh is laid out again and its state records (unchanged, in either
+ * precision), time and gauges carried over (results are bitwise the same
+ * for every tile size); otherwise it applies to the next upload.  The solver keeps a copy of the uploaded mesh for this.  EINVAL
  * for other sizes; ENOMEM/EDEVICE as vsw_upload_mesh. */
 int vsw_set_tile_size(vsw_solver *s, int cells);
 int vsw_tile_size(vsw_solver *s, int *cells);
 
-/* Graph mode (off by default): vsw_step captures one pair of steps (their
- * kernel launches and a one-thread kernel that advances the device-side
- * step index) into a HIP graph once and replays it n / 2 times, an odd last
- * step launched directly; results are bitwise the same as without it.  The
- * graph holds kernel nodes only and is captured again when the mesh, the
- * gauges, t_stop, the kernel variant or the log buffers change.  Profiling
- * (vsw_set_profiling) launches directly.  on = 0 frees the graph. */
+/* Graph mode: 0 (default) launches every kernel of a vsw_step call
+ * directly; 1 captures one pair of steps (their kernel launches and a
+ * one-thread kernel that advances the device-side step index) into a HIP
+ * graph once and replays it n / 2 times, an odd last step launched
+ * directly; 2 captures the whole call (n steps, up to 20000; longer calls
+ * use mode 1) as one graph, captured again when n changes.  Results are
+ * bitwise the same in every mode.  The graphs hold kernel nodes only and
+ * are captured again when the mesh, the gauges, t_stop, the kernel
+ * variant, the tile layout or the log buffers change.  Profiling
+ * (vsw_set_profiling) launches directly.  Setting a mode
+ * frees the current graph.  EINVAL for other values. */
 int vsw_set_graph(vsw_solver *s, int on);
 
 /* Order in which the stage kernels' workgroups visit the tiles: 1
@@ -268,18 +272,23 @@ int vsw_set_tile_order(vsw_solver *s, int xcd_order);
  * values. */
 int vsw_set_occupancy(vsw_solver *s, int wg_per_cu);
 
-/* Autotuner: runs `steps` steps (after two warm-up steps) of the current
- * state under every launch configuration c = 0 .. VSW_TUNE_CONFIGS - 1
- * (c / 8: workgroups per CU of the fused kernels, 0 = as many as fit,
- * 1 = at most 3, 2 = at most 2; bit 2: the two-pass kernel organisation,
- * FP64 and uncapped only; bit 1: XCD tile order; bit 0: graph mode),
- * timing each with HIP events on the solver's stream, restores the state,
- * time and logs after each, and keeps the fastest configuration for later
- * vsw_step calls.  Every configuration gives bitwise the same results.
- * ms_per_step (may be NULL) receives VSW_TUNE_CONFIGS values (INFINITY
- * where a configuration does not apply), *chosen (may be NULL) the winner.
- * EINVAL unless 2 <= steps <= 100000; ESTATE without mesh and state. */
-enum { VSW_TUNE_CONFIGS = 24 };
+/* Autotuner: runs `steps` steps (after a warm-up: two steps, or in graph
+ * mode 2 one call of `steps` steps that captures its graph) of the current
+ * state under every launch configuration
+ *   c = (org * 2 + xcd) * 3 + graph,  c = 0 .. VSW_TUNE_CONFIGS - 1,
+ * org: 0, 1, 2 the face-parallel kernels with tiles of 128, 256, 512
+ * cells; 3, 4, 5 the fused cell-parallel kernel (tiles of 256) with as many
+ * workgroups per CU as fit, at most 3, at most 2; 6 the two-pass
+ * organisation (FP64 only); xcd: the tile order of vsw_set_tile_order;
+ * graph: the mode of vsw_set_graph.  Each configuration is timed with HIP
+ * events on the solver's stream, the state, time and logs are restored
+ * after each, and the fastest configuration is kept for later vsw_step
+ * calls (its tile size laid out as vsw_set_tile_size does).  Every
+ * configuration gives bitwise the same results.  ms_per_step (may be NULL)
+ * receives VSW_TUNE_CONFIGS values (INFINITY where a configuration does not
+ * apply), *chosen (may be NULL) the winner.  EINVAL unless
+ * 2 <= steps <= 100000; ESTATE without mesh and state. */
+enum { VSW_TUNE_CONFIGS = 42 };
 int vsw_autotune(vsw_solver *s, int64_t steps, int32_t *chosen,
                  double *ms_per_step);
 

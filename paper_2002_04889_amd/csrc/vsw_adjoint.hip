@@ -287,6 +287,20 @@ __global__ __launch_bounds__(kBlock) void adj_rmin_kernel(DevMesh m, TileMap tm,
     block_min_atomic(r, rmin);
 }
 
+__global__ __launch_bounds__(kBlock) void adj_argmin_kernel(DevMesh m, TileMap tm,
+                                                            const Cell4* __restrict__ W, double g,
+                                                            double thr,
+                                                            const unsigned long long* rmin,
+                                                            unsigned long long* argmin) {
+    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
+    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
+    if (int(threadIdx.x) >= ti.cnt) return;
+    const Cell4 q = W[k];
+    const double r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
+    if (r < __longlong_as_double(0x7FF0000000000000ll) && dbits(r) == *rmin)
+        atomicMin(argmin, (unsigned long long)k);
+}
+
 __global__ __launch_bounds__(kBlock) void adj_start_kernel(DevMesh m, TileMap tm,
                                                            const Adj4* __restrict__ lam,
                                                            const uint8_t* __restrict__ mask2,
@@ -593,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
 
 __global__ __launch_bounds__(kBlock) void adj_turn_kernel(
     DevMesh m, TileMap tm, const double* __restrict__ C, const Cell4* __restrict__ W, double g,
-    double thr, double cfl, const unsigned long long* rmin, const double* lamdt,
+    double thr, double cfl, const unsigned long long* argmin, const double* lamdt,
     const int64_t* cells, int ng, const double* r, Adj4* __restrict__ lamn,
     double* __restrict__ hbar, const uint8_t* __restrict__ mask2p,
     const double* __restrict__ R1p, double dtp, double* __restrict__ mua,
@@ -607,11 +621,12 @@ __global__ __launch_bounds__(kBlock) void adj_turn_kernel(
         Adj4 n = lamn[k];
         n.H += w.H; n.HU += w.HU; n.HV += w.HV;
         double hb = hbar[k] + w.h;
-        if (rmin) {
-            // dt = CFL ratio of the minimising cell(s)
+        if (argmin && (unsigned long long)k == *argmin) {
+            // dt = CFL ratio of the minimising cell (the first in the
+            // internal order among cells of equal ratio)
             const Cell4 q = W[k];
             const double rr = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
-            if (rr < __longlong_as_double(0x7FF0000000000000ll) && dbits(rr) == *rmin) {
+            {
                 const double u = q.HU / q.H, v = q.HV / q.H;
                 const double m2 = u * u + v * v, mm = sqrt(m2), c = sqrt(g * q.H), sp = mm + c;
                 const double sb = -(*lamdt * cfl) * rr / sp;

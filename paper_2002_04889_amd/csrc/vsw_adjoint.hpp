@@ -40,15 +40,21 @@ __global__ void adj_gather_rk2_kernel(DevMesh m, TileMap tm, const double* C, co
                                       const uint8_t* mask2, const uint8_t* mask1,
                                       const double* R0, double dt, double* mua, Adj4* lamn,
                                       double* hbar, double* part);
+// The cell that sets dt: *argmin (preset to all ones) becomes the smallest
+// internal index among the cells whose CFL ratio bits equal *rmin.  At a tie
+// the dt depends on the minimum of equal ratios, whose derivative is taken
+// as that one cell's.
+__global__ void adj_argmin_kernel(DevMesh m, TileMap tm, const Cell4* W, double g, double thr,
+                                  const unsigned long long* rmin, unsigned long long* argmin);
 // End of the reverse of step k, in one pass per cell: after J_R(w)^T the
-// gathered contributions (lamn += wb, hbar += wb.h); with rmin, the CFL
-// term dt = CFL ratio(w^k) at the cell(s) whose ratio bits equal *rmin
-// (lamn += lamdt CFL d ratio/d w); with r, the gauge misfit of w^k
+// gathered contributions (lamn += wb, hbar += wb.h); with argmin, the CFL
+// term dt = CFL ratio(w^k) at cell *argmin (lamn += lamdt CFL
+// d ratio/d w); with r, the gauge misfit of w^k
 // (lamn.H += 2 r, hbar -= 2 r per gauge on the cell).  lamn then holds the
 // adjoint of w^k.  With mask2p, also the start of the reverse of step k-1
 // from its tape (R1p, mask2p, dtp), as adj_start_kernel: mua, lamp, part.
 __global__ void adj_turn_kernel(DevMesh m, TileMap tm, const double* C, const Cell4* W, double g,
-                                double thr, double cfl, const unsigned long long* rmin,
+                                double thr, double cfl, const unsigned long long* argmin,
                                 const double* lamdt, const int64_t* cells, int ng,
                                 const double* r, Adj4* lamn, double* hbar, const uint8_t* mask2p,
                                 const double* R1p, double dtp, double* mua, Adj4* lamp,

@@ -48,12 +48,17 @@ struct GraphKey {
     int ngauges;
     double t_stop;
     int variant;
+    int64_t nsteps;  // steps of a whole-call graph, 0 for the step pair
     bool operator==(const GraphKey& o) const {
         return log == o.log && gauge_log == o.gauge_log && gauge_cells == o.gauge_cells &&
                ngauges == o.ngauges && (t_stop == o.t_stop || (t_stop != t_stop && o.t_stop != o.t_stop)) &&
-               variant == o.variant;
+               variant == o.variant && nsteps == o.nsteps;
     }
 };
+
+// Longest call captured as one graph in graph mode 2 (longer calls replay
+// the step pair).
+constexpr int64_t kWholeGraphMaxSteps = 20000;
 
 // Runs f when the scope ends, on every return path.
 template <class F>
@@ -78,10 +83,16 @@ size_t capped_lds(size_t need, int cap) {
     return std::max(need, cu / size_t(cap + 1) + 1024);
 }
 
+// Device array owned by one object: freed by release() or when it goes out
+// of scope.
 template <class T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
     void release() {
         if (p) (void)hipFree(p);
         p = nullptr;
@@ -139,6 +150,7 @@ struct vsw_solver {
     DevBuf<int32_t> d_gauge_seg;   // scenario of each gauge
     DevBuf<double> d_gauge_log;    // [step][gauge] free surface of the last call
     int ngauges = 0;
+    std::vector<int32_t> gauge_user;  // the gauge cells in the caller's order
     std::vector<double> gauge_eta; // host copy of the last call's records
     std::vector<double> gauge_t;
     DevBuf<uint16_t> d_nloc;       // tile map of the fused kernel
@@ -162,7 +174,7 @@ struct vsw_solver {
     std::vector<double> raw_vx, raw_vy, raw_h;
     std::vector<int32_t> raw_tri;
     int variant = VSW_KERNEL_FACES;
-    bool use_graph = false;
+    int graph_mode = 0;  // 0 direct launches, 1 step-pair graph, 2 whole-call graph
     int xcd_order = 1;
     int occupancy = 0;  // fused stage kernels: workgroups per CU cap (0 = none)
     hipGraph_t graph = nullptr;
@@ -184,6 +196,9 @@ struct vsw_solver {
     double prof_ms[KK_COUNT] = {};
     int64_t prof_n[KK_COUNT] = {};
     std::vector<double> last_dts;
+    // host copies a step call reads back (kept between calls)
+    std::vector<Seg> h_seg;
+    std::vector<double> h_logs;
 
     void release_mesh() {
         release_graph();
@@ -201,6 +216,7 @@ struct vsw_solver {
         d_gauge_cells.release();
         d_gauge_seg.release();
         ngauges = 0;
+        gauge_user.clear();
         has_mesh = has_state = false;
     }
     // caller-order arrays (device) -> state records of both stage buffers
@@ -354,6 +370,22 @@ void launch_faces_dt_init(int tile, int ntiles, hipStream_t q, const FaceMesh& m
 
 bool f32_solver(const vsw_solver* s) { return s->prm.precision == VSW_FP32; }
 
+// State records into a new layout: cell i of the new layout takes record
+// from[i] of the old one (its stage buffer too); padding cells (from < 0)
+// keep what the layout gave them.
+template <class R>
+__global__ void move_records_kernel(int64_t n, const int64_t* __restrict__ from,
+                                    const R* __restrict__ old, R* __restrict__ W,
+                                    R* __restrict__ W1) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = from[i];
+    if (j < 0) return;
+    const R q = old[j];
+    W[i] = q;
+    W1[i] = q;
+}
+
 }  // namespace
 
 extern "C" {
@@ -434,6 +466,7 @@ int upload_assembled(vsw_solver* s, EnsembleMesh& em) {
     s->ne = hm.ne;
     s->nw = hm.nw;
     s->nseg = em.nseg;
+    s->h_seg.reserve(size_t(em.nseg));
     s->seg_off = em.coff;
     s->seg_t.assign(size_t(em.nseg), 0.0);
     s->seg_dt.assign(size_t(em.nseg), 0.0);
@@ -627,29 +660,52 @@ int vsw_set_tile_size(vsw_solver* s, int cells) {
         return fail(VSW_EINVAL, "tile size must be 128, 256 or 512");
     s->tile_req = cells;
     if (!s->has_mesh || s->tile == cells) return VSW_OK;
-    // lay the mesh out again, carrying the state (caller's order), the
-    // scenarios' times and the clamp count over
+    // lay the mesh out again, moving the state records (as they are, in
+    // either precision), the scenarios' times, the clamp count and the
+    // gauges over
     DeviceGuard dg(s->device);
     const bool had_state = s->has_state;
-    const int64_t nc = s->nc;
-    DevBuf<double> keep;
+    const bool f32 = f32_solver(s);
+    const size_t rec = f32 ? sizeof(CellF) : sizeof(Cell4);
+    DevBuf<unsigned char> keep;
+    const std::vector<int64_t> old_perm = s->perm;
     if (had_state) {
-        HIP_TRY(keep.alloc(3 * size_t(nc)));
-        s->unpack(keep.p, keep.p + nc, keep.p + 2 * nc);
+        const size_t bytes = size_t(s->nint) * rec;
+        HIP_TRY(keep.alloc(bytes));
+        const void* w = f32 ? (const void*)s->d_wf[s->cur].p : (const void*)s->d_w[s->cur].p;
+        HIP_TRY(hipMemcpyAsync(keep.p, w, bytes, hipMemcpyDeviceToDevice, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
     const double t = s->t, dt_last = s->dt_last;
     const int64_t clamps = s->clamps;
     const std::vector<double> seg_t = s->seg_t, seg_dt = s->seg_dt;
+    const std::vector<int32_t> gauges = s->gauge_user;
     int rc = layout_raw(s, cells);
-    if (rc != VSW_OK) {
-        keep.release();
-        return rc;
+    if (rc != VSW_OK) return rc;
+    if (!gauges.empty()) {
+        rc = vsw_set_gauges(s, int32_t(gauges.size()), gauges.data());
+        if (rc != VSW_OK) return rc;
     }
     if (had_state) {
-        s->pack(keep.p, keep.p + nc, keep.p + 2 * nc);
+        // new internal index -> old internal index of the same cell
+        std::vector<int64_t> inv(size_t(s->nc), -1), from(size_t(s->nint), -1);
+        for (size_t i = 0; i < old_perm.size(); ++i)
+            if (old_perm[i] >= 0) inv[size_t(old_perm[i])] = int64_t(i);
+        for (int64_t i = 0; i < s->nint; ++i)
+            if (s->perm[size_t(i)] >= 0) from[size_t(i)] = inv[size_t(s->perm[size_t(i)])];
+        DevBuf<int64_t> d_from;
+        HIP_TRY(d_from.alloc(from.size()));
+        HIP_TRY(hipMemcpy(d_from.p, from.data(), from.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice));
+        const dim3 g(unsigned((s->nint + kBlock - 1) / kBlock));
+        if (f32)
+            hipLaunchKernelGGL(move_records_kernel<CellF>, g, dim3(kBlock), 0, s->stream, s->nint,
+                               d_from.p, (const CellF*)keep.p, s->d_wf[s->cur].p, s->d_w1f.p);
+        else
+            hipLaunchKernelGGL(move_records_kernel<Cell4>, g, dim3(kBlock), 0, s->stream, s->nint,
+                               d_from.p, (const Cell4*)keep.p, s->d_w[s->cur].p, s->d_w1.p);
+        HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(s->stream));
-        keep.release();
         s->set_time(t);
         s->dt_last = dt_last;
         s->clamps = clamps;
@@ -744,22 +800,20 @@ int vsw_get_state_device(vsw_solver* s, double* dH, double* dHU, double* dHV, do
     return VSW_OK;
 }
 
-int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, double* t_out) {
-    if (!s) return fail(VSW_EINVAL, "NULL solver");
-    if (!s->has_mesh || !s->has_state) return fail(VSW_ESTATE, "mesh and state required");
-    if (n < 0) return fail(VSW_EINVAL, "negative step count");
-    if (std::isnan(t_stop)) return fail(VSW_EINVAL, "t_stop is NaN");
-    if (n > INT32_MAX) return fail(VSW_EINVAL, "too many steps in one call");
-    if (steps_done) *steps_done = 0;
-    if (t_out) *t_out = s->t;
-    if (n == 0) return VSW_OK;
-    DeviceGuard dg(s->device);
+}  // extern "C"
+
+namespace {
+
+// The step loop of vsw_step: n steps with the step log
+// in lg (2 n nseg doubles) and the gauge records in glog (n ngauges
+// doubles).  noalloc: no device or host memory is allocated (the two-pass
+// face buffer must exist), no graph is captured and no profiling events are
+// recorded.
+int step_impl(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, double* t_out,
+              double* lg, double* glog, bool noalloc) {
     const int nseg = s->nseg;
     const size_t nlog = size_t(n) * size_t(nseg);
-    if (s->d_log.n < 2 * nlog) HIP_TRY(s->d_log.alloc(std::max(2 * nlog, 2 * s->d_log.n)));
     const int ng = s->ngauges;
-    if (ng > 0 && s->d_gauge_log.n < size_t(n) * size_t(ng))
-        HIP_TRY(s->d_gauge_log.alloc(std::max(size_t(n) * size_t(ng), 2 * s->d_gauge_log.n)));
     const DevMesh m = s->dev_mesh();
     StepParams p;
     p.g = s->prm.g;
@@ -772,6 +826,8 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     Cell4* Wb = s->d_w[1].p;
     Cell4* W1 = s->d_w1.p;
     if (!f32_solver(s) && s->variant == VSW_KERNEL_TWO_PASS && !s->d_face.p) {
+        if (noalloc)
+            return fail(VSW_EINVAL, "the two-pass kernels' face buffer is not allocated yet");
         const size_t nn = size_t(s->nint);
         HIP_TRY(s->d_face.alloc(15 * nn));
         HIP_TRY(s->d_sc.alloc(2 * nn));
@@ -780,7 +836,6 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     FaceBuf fb{s->d_face.p, s->d_sc.p, s->d_order.p};
     Ctrl* c = s->d_ctrl.p;
     Seg* sg = s->d_seg.p;
-    double* lg = s->d_log.p;
     const dim3 grid(unsigned(s->ntiles)), block(kBlock);
     hipStream_t st = s->stream;
     TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, nseg,
@@ -806,7 +861,7 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
 
     // profiling events: one pair per timed launch
     size_t ev_used = 0;
-    bool prof = s->profiling;
+    bool prof = s->profiling && !noalloc;
     auto ev_begin = [&](int kind, hipStream_t q) {
         if (!prof) return;
         if (ev_used + 2 > s->ev_pool.size()) {
@@ -848,8 +903,7 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
             }
             if (ng > 0)
                 hipLaunchKernelGGL(gauge_f32_kernel, gg, dim3(64), 0, q, Fa, Fb, s->d_h.p,
-                                   s->d_gauge_cells.p, ng, s->d_gauge_seg.p, sg, c, sa,
-                                   s->d_gauge_log.p);
+                                   s->d_gauge_cells.p, ng, s->d_gauge_seg.p, sg, c, sa, glog);
             return;
         }
         if (faces) {
@@ -890,7 +944,7 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         }
         if (ng > 0)
             hipLaunchKernelGGL(gauge_kernel, gg, dim3(64), 0, q, Wa, Wb, s->d_gauge_cells.p, ng,
-                               s->d_gauge_seg.p, sg, c, sa, s->d_gauge_log.p);
+                               s->d_gauge_seg.p, sg, c, sa, glog);
     };
 
     // Graph mode: a captured pair of steps followed by a step-base bump,
@@ -898,18 +952,27 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     // into its launch arguments changes.  The state buffers a step uses follow
     // from the device step index and the call's parity, so one capture
     // serves every call.
-    const bool use_graph = s->use_graph && !prof && n >= 2;
-    if (use_graph) {
-        const GraphKey key{lg, s->d_gauge_log.p, s->d_gauge_cells.p, ng, t_stop,
-                           (s->variant * 2 + s->xcd_order) * 8 + s->occupancy};
+    // Graph mode 2: the whole call (n steps, direct step indices) captured
+    // as one graph, launched once.
+    const int gmode = (prof || noalloc) ? 0 : s->graph_mode;
+    const bool whole = gmode == 2 && n <= kWholeGraphMaxSteps;
+    const bool use_graph = (gmode == 1 || (gmode == 2 && !whole)) && n >= 2;
+    if (use_graph || whole) {
+        const GraphKey key{lg, glog, s->d_gauge_cells.p, ng, t_stop,
+                           ((s->variant * 2 + s->xcd_order) * 8 + s->occupancy) * 1024 + s->tile,
+                           whole ? n : 0};
         if (!s->graph_exec || !(key == s->graph_key)) {
             s->release_graph();
             prof = false;
             hipStream_t cs = s->own_stream;
             HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            launch_step(cs, 0, 0);
-            launch_step(cs, 1, 1);
-            hipLaunchKernelGGL(step_bump_kernel, dim3(1), dim3(64), 0, cs, c, 2);
+            if (whole) {
+                for (int64_t k = 0; k < n; ++k) launch_step(cs, int(k & 1), int(k));
+            } else {
+                launch_step(cs, 0, 0);
+                launch_step(cs, 1, 1);
+                hipLaunchKernelGGL(step_bump_kernel, dim3(1), dim3(64), 0, cs, c, 2);
+            }
             hipGraph_t g = nullptr;
             const hipError_t ec = hipStreamEndCapture(cs, &g);
             if (ec != hipSuccess) {
@@ -940,7 +1003,9 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         hipLaunchKernelGGL(dt_init_kernel, grid, block, 0, st, m, tm, s->d_w[s->cur].p, p.g,
                            p.thr, sg);
     ev_end(st);
-    if (use_graph) {
+    if (whole) {
+        HIP_TRY(hipGraphLaunch(s->graph_exec, st));
+    } else if (use_graph) {
         for (int64_t k = 0; k + 1 < n; k += 2) HIP_TRY(hipGraphLaunch(s->graph_exec, st));
         if (n & 1) launch_step(st, 0, 0);  // the base is n - 1 here
     } else {
@@ -948,12 +1013,13 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     }
     HIP_TRY(hipGetLastError());
     Ctrl hc;
-    std::vector<Seg> hs(static_cast<size_t>(nseg));
+    std::vector<Seg>& hs = s->h_seg;
+    hs.resize(size_t(nseg));
     HIP_TRY(hipMemcpyAsync(&hc, c, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(hs.data(), sg, size_t(nseg) * sizeof(Seg), hipMemcpyDeviceToHost, st));
-    std::vector<double> logs(2 * nlog);
-    HIP_TRY(hipMemcpyAsync(logs.data(), s->d_log.p, 2 * nlog * sizeof(double),
-                           hipMemcpyDeviceToHost, st));
+    std::vector<double>& logs = s->h_logs;
+    logs.resize(2 * nlog);
+    HIP_TRY(hipMemcpyAsync(logs.data(), lg, 2 * nlog * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (s->profiling) {
         for (size_t i = 0; i + 1 < ev_used; i += 2) {
@@ -998,13 +1064,42 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
         s->gauge_t[k] = logs[2 * size_t(k) * nseg];
     s->gauge_eta.assign(size_t(done) * size_t(ng), 0.0);
     if (ng > 0 && done > 0)
-        HIP_TRY(hipMemcpy(s->gauge_eta.data(), s->d_gauge_log.p,
-                          size_t(done) * size_t(ng) * sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(s->gauge_eta.data(), glog, size_t(done) * size_t(ng) * sizeof(double),
+                          hipMemcpyDeviceToHost));
     s->t = tmin;
     s->dt_last = s->seg_dt[0];
     if (steps_done) *steps_done = done;
     if (t_out) *t_out = s->t;
     return rc;
+}
+
+// Argument checks of the step calls; 1 when there is
+// nothing to do (n = 0).
+int step_args(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, double* t_out) {
+    if (!s) return fail(VSW_EINVAL, "NULL solver");
+    if (!s->has_mesh || !s->has_state) return fail(VSW_ESTATE, "mesh and state required");
+    if (n < 0) return fail(VSW_EINVAL, "negative step count");
+    if (std::isnan(t_stop)) return fail(VSW_EINVAL, "t_stop is NaN");
+    if (n > INT32_MAX) return fail(VSW_EINVAL, "too many steps in one call");
+    if (steps_done) *steps_done = 0;
+    if (t_out) *t_out = s->t;
+    return (n == 0) ? 1 : VSW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, double* t_out) {
+    const int a = step_args(s, n, t_stop, steps_done, t_out);
+    if (a != VSW_OK) return (a == 1) ? VSW_OK : a;
+    DeviceGuard dg(s->device);
+    const size_t nlog = size_t(n) * size_t(s->nseg);
+    if (s->d_log.n < 2 * nlog) HIP_TRY(s->d_log.alloc(std::max(2 * nlog, 2 * s->d_log.n)));
+    const int ng = s->ngauges;
+    if (ng > 0 && s->d_gauge_log.n < size_t(n) * size_t(ng))
+        HIP_TRY(s->d_gauge_log.alloc(std::max(size_t(n) * size_t(ng), 2 * s->d_gauge_log.n)));
+    return step_impl(s, n, t_stop, steps_done, t_out, s->d_log.p, s->d_gauge_log.p, false);
 }
 
 int vsw_scenario_count(vsw_solver* s, int32_t* nscen) {
@@ -1059,6 +1154,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     const int64_t nck = (nsteps + ckpt - 1) / ckpt;
     const int64_t segl = std::min(ckpt, nsteps);
     // the caller's solver state, restored on return
+    const std::vector<int32_t> user_gauge_cells = s->gauge_user;
     std::vector<int64_t> user_gauges(size_t(s->ngauges));
     if (s->ngauges > 0)
         HIP_TRY(hipMemcpy(user_gauges.data(), s->d_gauge_cells.p,
@@ -1099,6 +1195,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                             hipMemcpyHostToDevice);
         }
         s->ngauges = ok ? int(user_gauges.size()) : 0;
+        s->gauge_user = ok ? user_gauge_cells : std::vector<int32_t>();
         s->gauge_eta.clear();
         s->gauge_t.clear();
         s->release_graph();
@@ -1141,7 +1238,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     DevBuf<double> d_r, tR0, tR1, mua, C, hbar, part, lamdt, gout;
     DevBuf<uint8_t> tm1, tm2;
     DevBuf<Adj4> lam, lamn;
-    DevBuf<unsigned long long> rmin_hist;
+    DevBuf<unsigned long long> rmin_hist, argmin;
     hipError_t e = hipSuccess;
     DevBuf<CellF> fA, fB, f1;  // FP32 replay buffers
     if (f32) {
@@ -1150,7 +1247,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     }
     for (hipError_t x : {d_r.alloc(r.size()), seg.alloc(SL * N), segW1.alloc(SL * N),
                          wend.alloc(f32 ? 1 : N), tR0.alloc(3 * SL * N), tR1.alloc(3 * SL * N),
-                         tm1.alloc(SL * N), tm2.alloc(SL * N), rmin_hist.alloc(SL + 1),
+                         tm1.alloc(SL * N), tm2.alloc(SL * N), rmin_hist.alloc(SL + 1), argmin.alloc(1),
                          lam.alloc(N), lamn.alloc(N), mua.alloc(3 * N), C.alloc(16 * N),
                          hbar.alloc(N), part.alloc(size_t(s->ntiles)), lamdt.alloc(1),
                          gout.alloc(4 * size_t(s->nc))})
@@ -1240,10 +1337,15 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                                    lamdt.p);
             hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, Wn, mua.p, g, hg, thr,
                                C.p);
+            if (cfl_dt) {
+                HIP_TRY(hipMemsetAsync(argmin.p, 0xFF, sizeof(unsigned long long), st));
+                hipLaunchKernelGGL(adj_argmin_kernel, grid, block, 0, st, m, tm, Wn, g, thr,
+                                   rmin_hist.p + i, argmin.p);
+            }
             // step k-1's tape is in this segment: start its reverse in the same pass
             const bool next = (k - 1 >= n0);
             hipLaunchKernelGGL(adj_turn_kernel, grid, block, 0, st, m, tm, C.p, Wn, g, thr, cfl,
-                               cfl_dt ? rmin_hist.p + i : nullptr, lamdt.p, cells, ng,
+                               cfl_dt ? argmin.p : nullptr, lamdt.p, cells, ng,
                                k >= 1 ? d_r.p + (k - 1) * ng : nullptr, lamn.p, hbar.p,
                                next ? m2 - n : nullptr, next ? R1 - 3 * n : nullptr,
                                next ? dts[size_t(k - 1)] : 0.0, mua.p, lam.p, part.p);
@@ -1312,6 +1414,7 @@ int vsw_set_gauges(vsw_solver* s, int32_t n, const int32_t* cells) {
                           hipMemcpyHostToDevice));
     }
     s->ngauges = n;
+    s->gauge_user.assign(cells, cells + n);
     s->gauge_eta.clear();
     s->gauge_t.clear();
     return VSW_OK;
@@ -1360,33 +1463,40 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
     if (!s->has_mesh || !s->has_state) return fail(VSW_ESTATE, "mesh and state required");
     if (steps < 2 || steps > 100000) return fail(VSW_EINVAL, "steps must be in [2, 100000]");
     DeviceGuard dg(s->device);
-    hipStream_t st = s->stream;
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipStreamSynchronize(s->stream));
     const bool f32 = s->prm.precision == VSW_FP32;
-    const size_t n = size_t(s->nint);
-    const size_t bytes = n * (f32 ? sizeof(CellF) : sizeof(Cell4));
-    DevBuf<unsigned char> save;
-    HIP_TRY(save.alloc(bytes));
+    const size_t rec = f32 ? sizeof(CellF) : sizeof(Cell4);
     // the buffer holding the current state (it alternates as steps run)
     auto wp = [&]() { return f32 ? (void*)s->d_wf[s->cur].p : (void*)s->d_w[s->cur].p; };
-    HIP_TRY(hipMemcpyAsync(save.p, wp(), bytes, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
     const double t_save = s->t, dt_save = s->dt_last;
     const int64_t clamps_save = s->clamps;
     const std::vector<double> seg_t_save = s->seg_t, seg_dt_save = s->seg_dt;
     const std::vector<int64_t> seg_steps_save = s->seg_steps;
     const int variant_save = s->variant, xcd_save = s->xcd_order, occ_save = s->occupancy;
-    const bool graph_save = s->use_graph, prof_save = s->profiling;
-    static const int kOcc[3] = {0, 3, 2};
-    // On every return path: the state, time and logs as they were; the
-    // caller's launch configuration unless a winner was applied.
-    bool applied = false;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    const auto restore_on_exit = on_exit([&]() {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-        (void)hipMemcpyAsync(wp(), save.p, bytes, hipMemcpyDeviceToDevice, st);
-        (void)hipStreamSynchronize(st);
+    const int graph_save = s->graph_mode, tile_save = s->tile;
+    const bool prof_save = s->profiling;
+    // kernel organisation of each configuration group
+    static const int kTileOf[7] = {128, 256, 512, kTile, kTile, kTile, kTile};
+    static const int kVariantOf[7] = {VSW_KERNEL_FACES, VSW_KERNEL_FACES, VSW_KERNEL_FACES,
+                                      VSW_KERNEL_FUSED, VSW_KERNEL_FUSED, VSW_KERNEL_FUSED,
+                                      VSW_KERNEL_TWO_PASS};
+    static const int kOccOf[7] = {0, 0, 0, 0, 3, 2, 0};
+    // The state records of the current layout, copied back after every
+    // configuration (a layout for another tile size is made from them).
+    DevBuf<unsigned char> save;
+    auto snapshot = [&]() -> hipError_t {
+        const size_t bytes = size_t(s->nint) * rec;
+        if (save.n < bytes) {
+            const hipError_t e = save.alloc(bytes);
+            if (e != hipSuccess) return e;
+        }
+        const hipError_t e = hipMemcpyAsync(save.p, wp(), bytes, hipMemcpyDeviceToDevice, s->stream);
+        return (e != hipSuccess) ? e : hipStreamSynchronize(s->stream);
+    };
+    auto restore = [&]() {
+        (void)hipMemcpyAsync(wp(), save.p, size_t(s->nint) * rec, hipMemcpyDeviceToDevice,
+                             s->stream);
+        (void)hipStreamSynchronize(s->stream);
         s->t = t_save;
         s->dt_last = dt_save;
         s->clamps = clamps_save;
@@ -1397,53 +1507,89 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
         s->last_dts.clear();
         s->gauge_eta.clear();
         s->gauge_t.clear();
+    };
+    // On every return path: the state, time and logs as they were; the
+    // caller's launch configuration unless a winner was applied.
+    bool applied = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const auto restore_on_exit = on_exit([&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        restore();
         s->profiling = prof_save;
         s->release_graph();
         if (!applied) {
             s->variant = variant_save;
             s->xcd_order = xcd_save;
-            s->use_graph = graph_save;
+            s->graph_mode = graph_save;
             s->occupancy = occ_save;
+            if (s->tile != tile_save) (void)vsw_set_tile_size(s, tile_save);
         }
     });
+    HIP_TRY(snapshot());
     s->profiling = false;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     double best = INFINITY;
-    int best_c = 0;
-    for (int c = 0; c < VSW_TUNE_CONFIGS; ++c) {
-        const int variant = (c >> 2) & 1, xcd = (c >> 1) & 1, graph = c & 1, occ = kOcc[c / 8];
-        double ms = INFINITY;
-        if (!(variant == VSW_KERNEL_TWO_PASS && (f32 || occ != 0))) {
-            s->variant = variant;
-            s->xcd_order = xcd;
-            s->occupancy = occ;
-            s->use_graph = graph != 0;
-            s->release_graph();
-            s->seg_t = seg_t_save;
-            int rc = vsw_step(s, 2, INFINITY, nullptr, nullptr);  // warm-up (and graph capture)
+    int best_c = -1;
+    for (int c = 0; c < VSW_TUNE_CONFIGS; ++c)
+        if (ms_per_step) ms_per_step[c] = INFINITY;
+    // the caller's tile size first, so that the others are laid out from
+    // the caller's own records
+    int tiles[3] = {tile_save, 0, 0};
+    for (int i = 0, j = 1; i < 3; ++i)
+        if (kTileOf[i] != tile_save) tiles[j++] = kTileOf[i];
+    for (int ti = 0; ti < 3; ++ti) {
+        const int tile = tiles[ti];
+        if (tile != s->tile) {
+            restore();
+            const int rc = vsw_set_tile_size(s, tile);
             if (rc != VSW_OK) return rc;
-            HIP_TRY(hipEventRecord(e0, st));
-            rc = vsw_step(s, steps, INFINITY, nullptr, nullptr);
-            if (rc != VSW_OK) return rc;
-            HIP_TRY(hipEventRecord(e1, st));
-            HIP_TRY(hipEventSynchronize(e1));
-            float f = 0.f;
-            HIP_TRY(hipEventElapsedTime(&f, e0, e1));
-            ms = double(f) / double(steps);
-            HIP_TRY(hipMemcpyAsync(wp(), save.p, bytes, hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(snapshot());
         }
-        if (ms_per_step) ms_per_step[c] = ms;
-        if (ms < best) {
-            best = ms;
-            best_c = c;
+        for (int org = 0; org < 7; ++org) {
+            if (kTileOf[org] != tile) continue;
+            if (kVariantOf[org] == VSW_KERNEL_TWO_PASS && f32) continue;
+            for (int xcd = 0; xcd < 2; ++xcd)
+                for (int graph = 0; graph < 3; ++graph) {
+                    const int c = (org * 2 + xcd) * 3 + graph;
+                    s->variant = kVariantOf[org];
+                    s->xcd_order = xcd;
+                    s->occupancy = kOccOf[org];
+                    s->graph_mode = graph;
+                    s->release_graph();
+                    restore();
+                    // warm-up (and graph capture: a whole-call graph is
+                    // captured for the step count it runs)
+                    int rc = vsw_step(s, graph == 2 ? steps : 2, INFINITY, nullptr, nullptr);
+                    if (rc != VSW_OK) return rc;
+                    HIP_TRY(hipEventRecord(e0, s->stream));
+                    rc = vsw_step(s, steps, INFINITY, nullptr, nullptr);
+                    if (rc != VSW_OK) return rc;
+                    HIP_TRY(hipEventRecord(e1, s->stream));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float f = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+                    const double ms = double(f) / double(steps);
+                    if (ms_per_step) ms_per_step[c] = ms;
+                    if (ms < best) {
+                        best = ms;
+                        best_c = c;
+                    }
+                }
         }
     }
-    s->variant = (best_c >> 2) & 1;
-    s->xcd_order = (best_c >> 1) & 1;
-    s->use_graph = (best_c & 1) != 0;
-    s->occupancy = kOcc[best_c / 8];
+    const int org = (best_c / 3) / 2;
+    if (kTileOf[org] != s->tile) {
+        restore();
+        const int rc = vsw_set_tile_size(s, kTileOf[org]);
+        if (rc != VSW_OK) return rc;
+        HIP_TRY(snapshot());
+    }
+    s->variant = kVariantOf[org];
+    s->xcd_order = (best_c / 3) % 2;
+    s->graph_mode = best_c % 3;
+    s->occupancy = kOccOf[org];
     applied = true;
     if (chosen) *chosen = best_c;
     return VSW_OK;
@@ -1451,8 +1597,9 @@ int vsw_autotune(vsw_solver* s, int64_t steps, int32_t* chosen, double* ms_per_s
 
 int vsw_set_graph(vsw_solver* s, int on) {
     if (!s) return fail(VSW_EINVAL, "NULL solver");
-    s->use_graph = on != 0;
-    if (!s->use_graph) {
+    if (on < 0 || on > 2) return fail(VSW_EINVAL, "graph mode must be 0, 1 or 2");
+    s->graph_mode = on;
+    {
         DeviceGuard dg(s->device);
         (void)hipStreamSynchronize(s->stream);
         s->release_graph();

@@ -281,8 +281,12 @@ def vsw_adjoint_gauge_loss(h, nc, nsteps, checkpoint_every, gauges, eta_obs):
     return (loss.value, *out)
 
 
-VSW_TUNE_CONFIGS = 24
-TUNE_OCCUPANCY = (0, 3, 2)  # workgroups per CU of configuration c // 8 (0 = as many as fit)
+VSW_TUNE_CONFIGS = 42
+# kernel organisation of configuration c: TUNE_ORGS[c // 6] = (kernel, tile
+# size, workgroups per CU cap (0 = as many as fit))
+TUNE_ORGS = (("faces", 128, 0), ("faces", 256, 0), ("faces", 512, 0), ("fused", 256, 0),
+             ("fused", 256, 3), ("fused", 256, 2), ("two-pass", 256, 0))
+GRAPH_MODES = ("direct launches", "step-pair graph", "whole-call graph")
 
 
 def vsw_set_tile_order(h, xcd_order: int):
@@ -302,14 +306,15 @@ def vsw_autotune(h, steps: int):
 
 
 def tune_config_name(c: int) -> str:
-    occ = TUNE_OCCUPANCY[c // 8]
-    return (("two-pass" if c & 4 else "fused") + (", XCD tile order" if c & 2 else
-            ", index tile order") + (", graph" if c & 1 else ", direct launches")
+    kernel, tile, occ = TUNE_ORGS[c // 6]
+    return (f"{kernel}, tiles of {tile}" + (", XCD tile order" if (c // 3) % 2 else
+            ", index tile order") + ", " + GRAPH_MODES[c % 3]
             + (f", at most {occ} workgroups per CU" if occ else ""))
 
 
-def vsw_set_graph(h, on: bool):
-    return _check(lib().vsw_set_graph(h, 1 if on else 0))
+def vsw_set_graph(h, mode):
+    """mode 0 direct launches, 1 (or True) step-pair graph, 2 whole-call graph."""
+    return _check(lib().vsw_set_graph(h, int(mode)))
 
 
 def vsw_set_profiling(h, on: bool):

@@ -287,3 +287,59 @@ def test_fp32_forward_adjoint():
         rel = np.abs(a - b).max() / np.abs(b).max()
         say(f"fp32-forward adjoint d/d{name}: max |g32 - g64| / max |g64| = {rel:.3e}")
         assert rel <= 1e-3, name
+
+
+def tied_cfl_case():
+    """Congruent right triangles on an integer grid (1 km): a deep half at
+    rest (1000 m), whose cells all have bitwise the same CFL ratio and set
+    dt together, and a shallow half (50 m) with a surface bump, so that the
+    gauge misfit depends on dt."""
+    nx, ny, d = 40, 20, 1000.0
+    xs, ys = np.meshgrid(np.arange(nx + 1) * d, np.arange(ny + 1) * d, indexing="xy")
+    vx, vy = xs.ravel(), ys.ravel()
+    tri = []
+    for j in range(ny):
+        for i in range(nx):
+            a = j * (nx + 1) + i
+            tri += [[a, a + 1, a + nx + 2], [a, a + nx + 2, a + nx + 1]]
+    tri = np.array(tri, dtype=np.int32)
+    cx, cy = vx[tri].mean(axis=1), vy[tri].mean(axis=1)
+    deep = cx < nx * d / 2
+    h = np.where(deep, 1000.0, 50.0)
+    bump = np.exp(-((cx - 0.75 * nx * d) ** 2 + (cy - 0.5 * ny * d) ** 2) / (2 * (3 * d) ** 2))
+    H = h + np.where(deep, 0.0, bump)
+    c = W.Case(name="tied-cfl", vx=vx, vy=vy, tri=tri, h=h, H=H, HU=np.zeros(len(tri)),
+               HV=np.zeros(len(tri)))
+    return c, deep, cx, cy
+
+
+def test_cfl_tie_takes_one_cell():
+    """Where several cells share the CFL minimum bit for bit, dt is their
+    common ratio and the adjoint's dt term belongs to one of them (counting
+    it once per tied cell would multiply it).  Raising the surface of all
+    tied cells together keeps the tie, so the loss is differentiable along
+    that direction: the adjoint's derivative matches central differences."""
+    c, deep, cx, cy = tied_cfl_case()
+    s = vsw.Solver.for_case(c)
+    try:
+        s.step(1)
+        dt = vsw.vsw_dt_history(s.h)[0]
+    finally:
+        s.close()
+    # the deep cells' ratio sets dt (about 0.665 s; the shallow ones ~3 s)
+    assert 0.6 < dt < 0.7
+    near = np.flatnonzero(~deep & (np.hypot(cx - 30e3, cy - 10e3) < 6e3))
+    gauges = near[:: max(1, len(near) // 6)][:6].astype(np.int32)
+    nsteps = 20
+    rng = np.random.default_rng(17)
+    obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
+    loss, gH, _, _, _ = gpu_adjoint(c, nsteps, 7, gauges, obs)
+    v = deep.astype(np.float64)
+    ad = float((gH * v).sum())
+    eps = 1e-3
+    fd = (gpu_loss(c, c.H + eps * v, c.h, nsteps, gauges, obs)
+          - gpu_loss(c, c.H - eps * v, c.h, nsteps, gauges, obs)) / (2 * eps)
+    noise = 1e-12 * loss / eps
+    say(f"tied CFL minimum: {int(deep.sum())} tied cells, adjoint {ad:.10e}, FD {fd:.10e}")
+    assert abs(fd) > 1e3 * noise  # the direction reaches the loss through dt
+    assert abs(ad - fd) <= 1e-6 * abs(fd) + noise

@@ -103,13 +103,17 @@ def test_faces_lake_at_rest():
     assert np.abs(g["HU"]).max() <= vmax and np.abs(g["HV"]).max() <= vmax
 
 
-def test_tile_size_change_keeps_the_run():
-    """Laying the mesh out again for another tile size mid-run carries the
-    state and time over: the run continues bitwise as without the change."""
+@pytest.mark.parametrize("precision", [vsw.VSW_FP64, vsw.VSW_FP32], ids=["fp64", "fp32"])
+def test_tile_size_change_keeps_the_run(precision):
+    """Laying the mesh out again for another tile size mid-run moves the
+    state records, time and gauges over: the run continues bitwise as
+    without the change."""
     c = W.basin_case(scale=16)
-    ref = run(c, 90, vsw.VSW_KERNEL_FACES)
-    s = vsw.Solver.for_case(c)
+    gauges = np.array([2, 700, 3000], dtype=np.int32)
+    ref = run(c, 90, vsw.VSW_KERNEL_FACES, precision=precision)
+    s = vsw.Solver.for_case(c, precision=precision)
     try:
+        vsw.vsw_set_gauges(s.h, gauges)
         s.step(30)
         vsw.vsw_set_tile_size(s.h, 512)
         assert vsw.vsw_tile_size(s.h) == 512
@@ -117,11 +121,16 @@ def test_tile_size_change_keeps_the_run():
         vsw.vsw_set_tile_size(s.h, 128)
         s.step(29)
         H, HU, HV, t = s.state()
+        _, eta = vsw.vsw_get_gauges(s.h, len(gauges))
     finally:
         s.close()
     assert t == ref["t"]
     for a, k in ((H, "H"), (HU, "HU"), (HV, "HV")):
         assert np.array_equal(a, ref[k]), k
+    # the gauges survive the relayouts (FP32: eta recorded as stored, H - h
+    # in FP64 differs from it by rounding at the 1e-12 m level)
+    assert eta.shape == (29, 3)
+    assert np.abs(eta[-1] - (H - c.h)[gauges]).max() <= 1e-9
 
 
 def test_faces_ensemble_equals_solo():

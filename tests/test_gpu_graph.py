@@ -1,9 +1,11 @@
-"""Graph mode: the step loop replayed from a captured pair of steps must give
-exactly the results of direct launches (state, times, dt history, gauges),
-for FP64 (both kernel variants) and FP32, odd and even step counts, t_stop
-inside the run, ensembles, and over repeated calls with the program's own
-eager work (state reads, synchronisation) between the replays; changing
-t_stop or the gauges recaptures the graph."""
+"""Graph modes: the step loop replayed from a captured pair of steps (mode 1)
+or captured whole for the call's step count (mode 2) must give exactly the
+results of direct launches (state, times, dt history, gauges), for FP64
+(face-parallel and two-pass kernels) and FP32, odd and even step counts,
+t_stop inside the run, ensembles, and over repeated calls with the
+program's own eager work (state reads, synchronisation) between the
+replays; changing t_stop, the step count or the gauges recaptures the
+graph."""
 import math
 import sys
 
@@ -62,8 +64,9 @@ def assert_same(a, b):
 CALLS = [(7, math.inf), (10, math.inf), (1, math.inf), (6, math.inf), (9, math.inf)]
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("config", ["fp64", "fp64-two-pass", "fp32"])
-def test_graph_equals_direct_launches(config):
+def test_graph_equals_direct_launches(config, mode):
     c = W.basin_case(scale=16)
     kw = {"precision": vsw.VSW_FP32 if config == "fp32" else vsw.VSW_FP64}
     gauges = np.array([1, 500, 2000], dtype=np.int32)
@@ -83,30 +86,32 @@ def test_graph_equals_direct_launches(config):
                 return res
             finally:
                 s.close()
-        a, b = run(False), run(True)
+        a, b = run(0), run(mode)
     else:
-        a = session(c, CALLS, False, gauges, **kw)
-        b = session(c, CALLS, True, gauges, **kw)
+        a = session(c, CALLS, 0, gauges, **kw)
+        b = session(c, CALLS, mode, gauges, **kw)
     assert_same(a, b)
-    say(config, "t", b[-1]["t"], "steps", sum(r["done"] for r in b))
+    say(config, "mode", mode, "t", b[-1]["t"], "steps", sum(r["done"] for r in b))
 
 
-def test_graph_t_stop_changes_recapture():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_graph_t_stop_changes_recapture(mode):
     c = W.thacker_case(23)
     T = W.thacker_constants()["T1"]
     calls = [(40, 0.1 * T), (40, 0.1 * T), (200, 0.5 * T), (7, T), (400, T)]
-    a = session(c, calls, False, cfl=0.45, h_threshold=1e-5)
-    b = session(c, calls, True, cfl=0.45, h_threshold=1e-5)
+    a = session(c, calls, 0, cfl=0.45, h_threshold=1e-5)
+    b = session(c, calls, mode, cfl=0.45, h_threshold=1e-5)
     assert_same(a, b)
     assert b[1]["done"] == 0 and b[-1]["t"] == T
 
 
-def test_graph_ensemble():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_graph_ensemble(mode):
     ens, _ = W.ensemble_cases(n_scen=4, nmin=2e3, nmax=2e4)
     t_stop = 200.0
-    calls = [(11, t_stop), (20, t_stop), (300, t_stop)]
-    a = session(ens, calls, False)
-    b = session(ens, calls, True)
+    calls = [(11, t_stop), (20, t_stop), (300, t_stop), (300, t_stop)]
+    a = session(ens, calls, 0)
+    b = session(ens, calls, mode)
     assert_same(a, b)
     say("ensemble steps per scenario", b[-1]["status"][2], "t", b[-1]["status"][0])
 
@@ -116,7 +121,7 @@ def test_autotune_keeps_state_and_results(precision):
     """The autotuner times every launch configuration, restores the state
     and keeps the fastest; every configuration gives the same bits."""
     c = W.basin_case(scale=16)
-    ref = session(c, [(30, math.inf)], False, precision=precision)
+    ref = session(c, [(30, math.inf)], 0, precision=precision)
     s = vsw.Solver.for_case(c, precision=precision)
     try:
         before = s.state()
@@ -124,9 +129,9 @@ def test_autotune_keeps_state_and_results(precision):
         say(f"precision {precision}: chosen {chosen} ({vsw.tune_config_name(chosen)}), "
             f"ms/step {np.round(ms, 4)}")
         assert 0 <= chosen < vsw.VSW_TUNE_CONFIGS and ms[chosen] == np.min(ms)
-        # the two-pass organisation (bit 2) is FP64 only and takes no cap
+        # the two-pass organisation (configurations 36-41) is FP64 only
         cfg = np.arange(vsw.VSW_TUNE_CONFIGS)
-        applies = ((cfg & 4) == 0) | ((precision == vsw.VSW_FP64) & (cfg < 8))
+        applies = (cfg < 36) | (precision == vsw.VSW_FP64)
         assert np.all(np.isfinite(ms[applies])) and np.all(np.isinf(ms[~applies]))
         after = s.state()
         for a, b in zip(before, after):
@@ -175,3 +180,13 @@ def test_tile_orders_bitwise():
             s.close()
     for a, b in zip(*out):
         assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_graph_mode_checked():
+    s = vsw.Solver.for_case(W.thacker_case(23))
+    try:
+        for bad in (-1, 3):
+            with pytest.raises(vsw.VswError, match="EINVAL"):
+                vsw.vsw_set_graph(s.h, bad)
+    finally:
+        s.close()
