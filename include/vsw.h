@@ -184,6 +184,24 @@ int vsw_set_state_device(vsw_solver *s, const double *dev_H,
 int vsw_step(vsw_solver *s, int64_t n, double t_stop, int64_t *steps_done,
              double *t_out);
 
+/* vsw_step for callers that cannot allocate memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc): the same steps with the
+ * same results and error behaviour, but the per-call step log (time and dt
+ * of every step and scenario) and the gauge records are kept in a fixed
+ * device array of the library, VSW_NOALLOC_BYTES per device (set up by
+ * vsw_create, held until the process ends), instead of buffers the solver
+ * grows.  It allocates no device or host memory, captures no graph
+ * (vsw_set_graph is ignored) and records no profiling events.  The call must
+ * fit the array: n * (2 * scenarios + gauges) doubles <= VSW_NOALLOC_BYTES /
+ * 8, else EINVAL; with VSW_KERNEL_TWO_PASS its face buffer must already
+ * exist (after one vsw_step), else EINVAL.  Every call on a device uses
+ * that device's one array and overwrites what the previous call left there
+ * (nothing in it needs to start at zero): calls that overlap on one device,
+ * from several host threads or solvers on different streams, race. */
+#define VSW_NOALLOC_BYTES (1u << 20)
+int vsw_step_noalloc(vsw_solver *s, int64_t n, double t_stop,
+                     int64_t *steps_done, double *t_out);
+
 /* Copy the state to host arrays (caller's order); *t (may be NULL) gets the
  * time. */
 int vsw_get_state(vsw_solver *s, double *H, double *HU, double *HV, double *t);
@@ -254,7 +272,7 @@ int vsw_tile_size(vsw_solver *s, int *cells);
  * bitwise the same in every mode.  The graphs hold kernel nodes only and
  * are captured again when the mesh, the gauges, t_stop, the kernel
  * variant, the tile layout or the log buffers change.  Profiling
- * (vsw_set_profiling) launches directly.  Setting a mode
+ * (vsw_set_profiling) and vsw_step_noalloc launch directly.  Setting a mode
  * frees the current graph.  EINVAL for other values. */
 int vsw_set_graph(vsw_solver *s, int on);
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -107,6 +108,34 @@ struct DevBuf {
     }
 };
 
+// Device memory of vsw_step_noalloc: the step log (time and dt of each step
+// and scenario) and the gauge records of a call, in one array per device
+// that lives until the process ends.  Host code never passes the array's
+// name to a kernel or a copy: it uses the device address resolved for each
+// device by resolve_scratch (called from vsw_create with the device current).
+constexpr size_t kScratchDoubles = VSW_NOALLOC_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;  // per device; null until resolved
+
+int resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.size() <= size_t(device)) g_scratch_ptr.resize(size_t(device) + 1, nullptr);
+    if (g_scratch_ptr[size_t(device)]) return VSW_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(VSW_EDEVICE, std::string("no-allocation scratch array: ") + hipGetErrorString(e));
+    g_scratch_ptr[size_t(device)] = static_cast<double*>(ptr);
+    return VSW_OK;
+}
+
+double* scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (size_t(device) < g_scratch_ptr.size()) ? g_scratch_ptr[size_t(device)] : nullptr;
+}
+
 }  // namespace
 
 struct vsw_solver {
@@ -196,7 +225,8 @@ struct vsw_solver {
     double prof_ms[KK_COUNT] = {};
     int64_t prof_n[KK_COUNT] = {};
     std::vector<double> last_dts;
-    // host copies a step call reads back (kept between calls)
+    // host copies a step call reads back (kept between calls so that a call
+    // within the sizes of vsw_step_noalloc allocates no host memory)
     std::vector<Seg> h_seg;
     std::vector<double> h_logs;
 
@@ -428,6 +458,17 @@ int vsw_create(const vsw_params* p, int device, vsw_solver** out) {
         return fail(VSW_EDEVICE, std::string("device setup: ") + hipGetErrorString(e));
     }
     s->stream = s->own_stream;
+    const int rs = resolve_scratch(device);
+    if (rs != VSW_OK) {
+        vsw_destroy(s);
+        return rs;
+    }
+    // host side of the largest vsw_step_noalloc call
+    s->h_logs.reserve(kScratchDoubles);
+    s->seg_log.reserve(kScratchDoubles / 2);
+    s->last_dts.reserve(kScratchDoubles / 2);
+    s->gauge_t.reserve(kScratchDoubles / 2);
+    s->gauge_eta.reserve(kScratchDoubles);
     *out = s;
     return VSW_OK;
 }
@@ -804,7 +845,7 @@ int vsw_get_state_device(vsw_solver* s, double* dH, double* dHU, double* dHV, do
 
 namespace {
 
-// The step loop of vsw_step: n steps with the step log
+// The step loop of vsw_step and vsw_step_noalloc: n steps with the step log
 // in lg (2 n nseg doubles) and the gauge records in glog (n ngauges
 // doubles).  noalloc: no device or host memory is allocated (the two-pass
 // face buffer must exist), no graph is captured and no profiling events are
@@ -1073,7 +1114,7 @@ int step_impl(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doub
     return rc;
 }
 
-// Argument checks of the step calls; 1 when there is
+// Argument checks shared by vsw_step and vsw_step_noalloc; 1 when there is
 // nothing to do (n = 0).
 int step_args(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, double* t_out) {
     if (!s) return fail(VSW_EINVAL, "NULL solver");
@@ -1100,6 +1141,23 @@ int vsw_step(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done, doubl
     if (ng > 0 && s->d_gauge_log.n < size_t(n) * size_t(ng))
         HIP_TRY(s->d_gauge_log.alloc(std::max(size_t(n) * size_t(ng), 2 * s->d_gauge_log.n)));
     return step_impl(s, n, t_stop, steps_done, t_out, s->d_log.p, s->d_gauge_log.p, false);
+}
+
+int vsw_step_noalloc(vsw_solver* s, int64_t n, double t_stop, int64_t* steps_done,
+                     double* t_out) {
+    const int a = step_args(s, n, t_stop, steps_done, t_out);
+    if (a != VSW_OK) return (a == 1) ? VSW_OK : a;
+    const size_t need = size_t(n) * (2 * size_t(s->nseg) + size_t(s->ngauges));
+    if (need > kScratchDoubles)
+        return fail(VSW_EINVAL, "vsw_step_noalloc: n * (2 scenarios + gauges) = " +
+                                    std::to_string(need) + " doubles exceeds its " +
+                                    std::to_string(kScratchDoubles) + "-double array");
+    DeviceGuard dg(s->device);
+    double* sp = scratch_ptr(s->device);
+    if (!sp) return fail(VSW_EDEVICE, "no-allocation scratch array not resolved");
+    // the step log first, the gauge records after it
+    return step_impl(s, n, t_stop, steps_done, t_out, sp, sp + 2 * size_t(n) * size_t(s->nseg),
+                     true);
 }
 
 int vsw_scenario_count(vsw_solver* s, int32_t* nscen) {

@@ -58,6 +58,7 @@ _SIGS = {
     "vsw_set_state": (ctypes.c_int, [_vp, _dp, _dp, _dp, _d]),
     "vsw_set_state_device": (ctypes.c_int, [_vp, _vp, _vp, _vp, _d]),
     "vsw_step": (ctypes.c_int, [_vp, _i64, _d, _lp, _dp]),
+    "vsw_step_noalloc": (ctypes.c_int, [_vp, _i64, _d, _lp, _dp]),
     "vsw_get_state": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "vsw_get_state_device": (ctypes.c_int, [_vp, _vp, _vp, _vp, _dp]),
     "vsw_last_dt": (ctypes.c_int, [_vp, _dp]),
@@ -199,6 +200,20 @@ def vsw_step(h, n, t_stop=math.inf, check=True):
     done = ctypes.c_int64(0)
     t = ctypes.c_double(0.0)
     rc = lib().vsw_step(h, int(n), float(t_stop), ctypes.byref(done), ctypes.byref(t))
+    if check:
+        _check(rc)
+    return rc, done.value, t.value
+
+
+VSW_NOALLOC_BYTES = 1 << 20
+
+
+def vsw_step_noalloc(h, n, t_stop=math.inf, check=True):
+    """vsw_step without allocation: logs in the library's fixed device array
+    (n * (2 scenarios + gauges) doubles at most VSW_NOALLOC_BYTES / 8)."""
+    done = ctypes.c_int64(0)
+    t = ctypes.c_double(0.0)
+    rc = lib().vsw_step_noalloc(h, int(n), float(t_stop), ctypes.byref(done), ctypes.byref(t))
     if check:
         _check(rc)
     return rc, done.value, t.value
