@@ -12,6 +12,7 @@
 python -m paper_2002_04889_amd.experiments convergence [--sizes 0.048 0.024 ...]
 python -m paper_2002_04889_amd.experiments dtstudy
 python -m paper_2002_04889_amd.experiments decompose
+python -m paper_2002_04889_amd.experiments floor [--sizes ...] [--h-threshold H]
 
 The mesh for size dx is the seeded jittered grid of the Thacker case with
 round(4 / dx) + 1 points per side.  Time steps follow the CFL rule of the
@@ -110,6 +111,7 @@ def thacker_gauge_run(dx, t_fin=10.0, dt_factor=None, precision=None, chunk=4000
                 break
         t_arr = np.concatenate(ts)
         eta = np.concatenate(etas)
+        H_fin = s.state()[0]
     finally:
         s.close()
     progress(f"dx={dx:g}: {len(t_arr)} steps done; closed form at the gauges")
@@ -123,7 +125,7 @@ def thacker_gauge_run(dx, t_fin=10.0, dt_factor=None, precision=None, chunk=4000
         np.zeros((0, 3))
     return {"t": t_arr, "eta": eta, "exact": exact, "exact_centroid": exact_c, "cells": cells,
             "nc": case.nc, "n": n, "dx": 4.0 / (n - 1), "rc": rc, "steps": len(t_arr),
-            "case": case}
+            "case": case, "H_final": H_fin}
 
 
 def convergence(sizes=(0.048, 0.024, 0.012, 0.006), t_fin=10.0, h_threshold=None):
@@ -141,6 +143,49 @@ def convergence(sizes=(0.048, 0.024, 0.012, 0.006), t_fin=10.0, h_threshold=None
     for a, b in zip(rows, rows[1:]):
         b["order_centre"] = math.log(a["linf_centre"] / b["linf_centre"]) / math.log(a["dx"] / b["dx"])
         b["order_mid"] = math.log(a["linf_mid"] / b["linf_mid"]) / math.log(a["dx"] / b["dx"])
+    return rows
+
+
+def floor_study(sizes=(0.048, 0.024, 0.012, 0.006), t_fin=10.0, band=0.02, h_threshold=None):
+    """Where the error floor of the convergence study comes from.  At t_fin
+    the free surface of every cell is compared with the closed form at its
+    centroid, in three classes: the interior of the wet region (exact depth
+    at least `band` m, about 0.1 m from the shoreline), the shoreline band
+    (exact depth below `band`, or wet in the model where the closed form is
+    dry), and the centre gauge cell; the gauge series are compared with the
+    closed form at the gauge cells' centroids (not at the gauge points, which
+    lie up to half a cell away where eta has a slope).  L-infinity and
+    area-weighted mean errors per class, with observed orders."""
+    rows = []
+    for dx in sizes:
+        r = thacker_gauge_run(dx, t_fin, h_threshold=h_threshold)
+        c = r["case"]
+        cx, cy = c.centroids()
+        eta_ex, H_ex, _, _ = W.thacker_exact(cx, cy, float(r["t"][-1]))
+        H = r["H_final"]
+        err = np.abs((H - c.h) - eta_ex)
+        t = c.tri
+        area = 0.5 * np.abs((c.vx[t[:, 1]] - c.vx[t[:, 0]]) * (c.vy[t[:, 2]] - c.vy[t[:, 0]])
+                            - (c.vx[t[:, 2]] - c.vx[t[:, 0]]) * (c.vy[t[:, 1]] - c.vy[t[:, 0]]))
+        interior = H_ex >= band
+        shore = ((H_ex > 0.0) & (H_ex < band)) | ((H_ex == 0.0) & (H > 0.0))
+        row = {"dx": r["dx"], "cells": r["nc"], "steps": r["steps"],
+               "interior_linf": float(err[interior].max()),
+               "interior_mean": float((err * area)[interior].sum() / area[interior].sum()),
+               "shore_linf": float(err[shore].max()),
+               "shore_mean": float((err * area)[shore].sum() / area[shore].sum()),
+               "centre_cell": float(err[r["cells"][0]])}
+        ge = np.abs(r["eta"] - r["exact_centroid"]).max(axis=0)
+        row.update({"gauge_centre_linf": float(ge[0]), "gauge_mid_linf": float(ge[1]),
+                    "gauge_edge_linf": float(ge[2])})
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    keys = [k for k in rows[0] if k.endswith("_linf") or k.endswith("_mean")
+            or k == "centre_cell"]
+    for a, b in zip(rows, rows[1:]):
+        for k in keys:
+            if a[k] > 0.0 and b[k] > 0.0:
+                b["order_" + k] = math.log(a[k] / b[k]) / math.log(a["dx"] / b["dx"])
     return rows
 
 
@@ -191,7 +236,7 @@ def decompose(h=0.024, t_fin=10.0):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["convergence", "dtstudy", "decompose"])
+    ap.add_argument("what", choices=["convergence", "dtstudy", "decompose", "floor"])
     ap.add_argument("--sizes", type=float, nargs="*", default=[0.048, 0.024, 0.012, 0.006])
     ap.add_argument("--t-fin", type=float, default=None)
     ap.add_argument("--h-threshold", type=float, default=None)
@@ -199,6 +244,8 @@ def main(argv=None):
     if a.what == "convergence":
         rows = convergence(a.sizes, a.t_fin or 10.0, a.h_threshold)
         print(json.dumps(rows))
+    elif a.what == "floor":
+        print(json.dumps(floor_study(a.sizes, a.t_fin or 10.0, h_threshold=a.h_threshold)))
     elif a.what == "dtstudy":
         print(json.dumps(dt_study(t_fin=a.t_fin or 10.0)))
     else:
