@@ -136,26 +136,67 @@ def copy_bandwidth(torch, dev):
     return round(2 * n * 8 / (best / 1e3) / 1e9, 1)
 
 
-def measured_traffic(workload, ordering, precision_name, kernel, cells):
-    """HBM bytes per launch of `kernel` from the committed PMC summary
-    (profiles/traffic_<workload>_<ordering>.json: FETCH_SIZE + WRITE_SIZE,
-    scaled by a plain copy kernel), or None when there is none or the kernel
-    sources have changed since the counters were taken."""
+def kernel_symbol(kind, precision_name, variant, tile):
+    """The device kernel behind a timed kind ("stage1_kernel", ...) of the
+    given kernel organisation, as rocprofv3 names it; None for kinds that
+    are not one kernel."""
+    stage = kind[5]  # "stage1_kernel" -> "1"
+    if variant == "faces":
+        return (f"vsw::faces_stage_kernel<{tile}, {stage}>" if precision_name == "fp64"
+                else f"vsw::faces_stage_f32_kernel<{tile}, {stage}>")
+    if variant == "fused":
+        return (f"vsw::stage_kernel<{stage}>" if precision_name == "fp64"
+                else f"vsw::stage_f32_kernel<{stage}>")
+    return None
+
+
+# Vector issue rate of the chip: 256 CUs x 4 SIMDs, each issuing one
+# wave instruction over 16 lanes per clock (a wave64 instruction in four
+# clocks, FP64 and FP32 alike without packed math), at 2.4 GHz: lane
+# operations per second.
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def measured_counters(workload, ordering, symbol, cells):
+    """The committed PMC record of kernel `symbol` (see measured_traffic),
+    or None."""
     from paper_2002_04889_amd import profsum
 
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{ordering}.json")
-    if not os.path.exists(path):
+    if symbol is None or not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("digest") != profsum.source_digest():
+    if d.get("digest") != profsum.source_digest() or d.get("cells") not in (None, cells):
         return None
-    stage = kernel[5]  # "stage1_kernel" -> "1"
-    name = (f"vsw::stage_kernel<{stage}>" if precision_name == "fp64"
-            else f"vsw::stage_f32_kernel<{stage}>")
-    k = d["kernels"].get(name)
-    if not k or d.get("cells") not in (None, cells):
+    return d["kernels"].get(symbol)
+
+
+def measured_traffic(workload, ordering, symbol, cells):
+    """HBM bytes per launch of kernel `symbol` from the committed PMC summary
+    (profiles/traffic_<workload>_<ordering>.json: FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy kernel), or None when there is none or the kernel
+    sources or the mesh layout code have changed since the counters were
+    taken."""
+    k = measured_counters(workload, ordering, symbol, cells)
+    if not k or "fetch_bytes" not in k or "write_bytes" not in k:
         return None
     return round(k["fetch_bytes"] + k["write_bytes"])
+
+
+def add_measured(rf, workload, ordering, cells):
+    """Measured HBM traffic and vector issue rate of the roofline's kernel."""
+    tr = measured_traffic(workload, ordering, rf["kernel_symbol"], cells)
+    rf["traffic"] = tr
+    if tr is not None:
+        rf["traffic_bytes_per_cell"] = round(tr / cells, 1)
+        rf["traffic_GBps"] = round(tr / (rf["avg_launch_us"] * 1e-6) / 1e9, 1)
+    k = measured_counters(workload, ordering, rf["kernel_symbol"], cells)
+    if k and "sq_insts_valu" in k:
+        ops = k["sq_insts_valu"] * 64 / (rf["avg_launch_us"] * 1e-6)
+        rf["valu_issue"] = {"achieved": round(ops / 1e12, 2), "peak": VALU_PEAK_LANE_OPS / 1e12,
+                            "unit": "T lane-ops/s",
+                            "frac": round(ops / VALU_PEAK_LANE_OPS, 3),
+                            "wave_insts_per_launch": round(k["sq_insts_valu"])}
 
 
 def time_steps(torch, stream, s, steps):
@@ -197,7 +238,8 @@ def run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, precision, ordering, st
         f"{value:.3e} cell-updates/s")
     leg = {"value": value, "unit": "cell-updates/s", "ms_per_step": ms / steps,
            "roofline": kernel_roofline(vsw, s, steps, nc, bytes1, bytes2),
-           "mesh": {"cells": nc, "edges": ne, "walls": nw}}
+           "mesh": {"cells": nc, "edges": ne, "walls": nw},
+           "tile": vsw.vsw_tile_size(s.h)}
     return leg, s
 
 
@@ -487,12 +529,9 @@ def main():
                         "f32 state and fluxes, f64 depths/pressure/accumulation")
         leg["ordering"] = "hilbert" if order == vsw.VSW_ORDER_HILBERT else "random"
         rf = leg["roofline"]
-        tr = measured_traffic(args.workload + ("" if args.scale == 1.0 else f"x{args.scale:g}"),
-                              leg["ordering"], name[:4], rf["kernel"], leg["mesh"]["cells"])
-        rf["traffic"] = tr
-        if tr is not None:
-            rf["traffic_bytes_per_cell"] = round(tr / leg["mesh"]["cells"], 1)
-            rf["traffic_GBps"] = round(tr / (rf["avg_launch_us"] * 1e-6) / 1e9, 1)
+        rf["kernel_symbol"] = kernel_symbol(rf["kernel"], name[:4], args.kernel, leg["tile"])
+        add_measured(rf, args.workload + ("" if args.scale == 1.0 else f"x{args.scale:g}"),
+                     leg["ordering"], leg["mesh"]["cells"])
         res[name] = leg
         torch.cuda.synchronize()
 
@@ -550,12 +589,9 @@ def main():
         del cH, cU, cV
         torch.cuda.empty_cache()
         rf = leg["roofline"]
-        tr = measured_traffic("coastal" + ("" if args.scale == 1.0 else f"x{args.scale:g}"),
-                              "hilbert", "fp64", rf["kernel"], leg["mesh"]["cells"])
-        rf["traffic"] = tr
-        if tr is not None:
-            rf["traffic_bytes_per_cell"] = round(tr / leg["mesh"]["cells"], 1)
-            rf["traffic_GBps"] = round(tr / (rf["avg_launch_us"] * 1e-6) / 1e9, 1)
+        rf["kernel_symbol"] = kernel_symbol(rf["kernel"], "fp64", args.kernel, leg["tile"])
+        add_measured(rf, "coastal" + ("" if args.scale == 1.0 else f"x{args.scale:g}"),
+                     "hilbert", leg["mesh"]["cells"])
         rf["copy_GBps"] = out["roofline"].get("copy_GBps")
         mesh = leg.pop("mesh")
         leg["dtype"] = "f64"

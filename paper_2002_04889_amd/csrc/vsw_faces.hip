@@ -55,7 +55,8 @@ __device__ __forceinline__ double tri_area(const Tri& g) {
 // least-squares weights; the wall normals and face-midpoint offsets are
 // computed from the vertices as the host computes its stored geometry.
 __device__ __forceinline__ void recon_tri(const Cell4& ck, const Cell4 cn[3], const TopoD& tp,
-                                          const Tri& g, const LsqW& w, double thr, Recon& r) {
+                                          const Tri& g, const LsqW& w, double thr, Recon& r,
+                                          int sel = -1) {
     const uint32_t sl[3] = {tp.n0, tp.n1, tp.n2};
     recon_from(
         ck, cn, sl, thr,
@@ -78,7 +79,7 @@ __device__ __forceinline__ void recon_tri(const Cell4& ck, const Cell4 cn[3], co
                 gd[2 * j + 1] = (g.y[j] + g.y[j1]) * 0.5 - cy;
             }
         },
-        r);
+        r, sel);
 }
 
 // Unit normal (from vertex a to b, turned clockwise) and length of a face.
@@ -149,12 +150,12 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void fac
 
     // The loads are issued in dependency levels, each before the arithmetic
     // that waits for the previous one: (1) the cell's topology, weights and
-    // state, the first halo item and the first two face records of the
-    // thread; (2) the cell's neighbours and vertices and the halo cell's
-    // topology; (3) after the cell's reconstruction, the halo cell's data;
-    // (4) after the halo, the faces' vertices and the records the
-    // Runge-Kutta stage reads, all before the first barrier.  (The faces'
-    // vertices held through the reconstructions would need more than the 128
+    // state and the first halo item of the thread; (2) the cell's neighbours
+    // and vertices and the halo cell's topology; (3) after the cell's
+    // reconstruction, the halo cell's data; (4) after the halo, the first
+    // two face records of the thread, their vertices and the records the
+    // Runge-Kutta stage reads, all before the first barrier.  (Face records
+    // held through the reconstructions would need more than the 128
     // registers of four waves per SIMD.)
     const int64_t ko = own ? k : c0;
     const TopoD tp = m.topo[ko];
@@ -167,9 +168,6 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void fac
     load_nbrs(Ws, tp, ko, cn);
     TopoD htp{0u, 0u, 0u, 0u, 0u, 0u};
     if (i < nb) htp = m.topo[hitem >> 2];
-    FaceItemD it0{0u, 0u, 0, 0}, it1{0u, 0u, 0, 0};
-    if (i < nf) it0 = tm.items[f0 + i];
-    if (i + T < nf) it1 = tm.items[f0 + i + T];
 
     // phase 1: the tile's cells and the halo faces
     double area = 1.0;
@@ -196,9 +194,12 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void fac
         Cell4 cnq[3];
         load_nbrs(Ws, tq, n, cnq);
         Recon r;
-        recon_tri(cq, cnq, tq, gq, lq, p.thr, r);
-        store_face(Le, Lh, LH, Lu, Lv, 3 * T + b, recon_face_sel(r, jn, p.thr));
+        recon_tri(cq, cnq, tq, gq, lq, p.thr, r, jn);
+        store_face(Le, Lh, LH, Lu, Lv, 3 * T + b, recon_face(r, 0, p.thr));
     }
+    FaceItemD it0{0u, 0u, 0, 0}, it1{0u, 0u, 0, 0};
+    if (i < nf) it0 = tm.items[f0 + i];
+    if (i + T < nf) it1 = tm.items[f0 + i + T];
     double2 a0 = make_double2(0.0, 0.0), e0 = a0, a1 = a0, e1 = a0;
     if (i < nf) {
         a0 = m.vxy[it0.va];

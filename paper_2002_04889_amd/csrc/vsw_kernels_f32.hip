@@ -34,6 +34,12 @@ struct ReconF {
 __device__ __forceinline__ float fminf_(float a, float b) { return (b < a) ? b : a; }
 __device__ __forceinline__ float fmaxf_(float a, float b) { return (b > a) ? b : a; }
 
+// pick3 of the FP64 kernel for FP32 values.
+__device__ __forceinline__ float pick3f(int j, float a, float b, float c) {
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
+    return (j == 0) ? a : (j == 1) ? b : c;
+}
+
 // Reciprocal of a positive normal double to about one ulp: the hardware
 // estimate and two Newton steps e = 1 - b r, r = r + r e with fused
 // multiply-adds (quadratic convergence from the estimate).
@@ -52,7 +58,8 @@ __device__ __forceinline__ double recip_f64(double b) {
 template <class WallN, class Geo>
 __device__ __forceinline__ void recon_from_f32(const CellF& ck, double hk, const CellF cnb[3],
                                                const double hnb[3], const uint32_t sl[3],
-                                               double thr, WallN wall_n, Geo geo, ReconF& r) {
+                                               double thr, WallN wall_n, Geo geo, ReconF& r,
+                                               int sel = -1) {
     const float ek = ck.eta, uk = ck.hu, vk = ck.hv;
     const double Hk = double(ek) + hk;
     float qe[3], qu[3], qv[3], dh[3];
@@ -131,11 +138,23 @@ __device__ __forceinline__ void recon_from_f32(const CellF& ck, double hk, const
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             r.fe[j] = ek + ae * pe[j];
-            r.fu[j] = uk + au * pu[j];
-            r.fv[j] = vk + av * pv[j];
             r.fh[j] = hk + double(ph[j]);
             r.fH[j] = double(r.fe[j]) + r.fh[j];
             if (r.fH[j] < thr) cand = false;
+        }
+        if (sel < 0) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                r.fu[j] = uk + au * pu[j];
+                r.fv[j] = vk + av * pv[j];
+            }
+        } else {
+            // one face in slot 0 (see recon_from)
+            r.fu[0] = uk + au * pick3f(sel, pu[0], pu[1], pu[2]);
+            r.fv[0] = vk + av * pick3f(sel, pv[0], pv[1], pv[2]);
+            r.fe[0] = pick3f(sel, r.fe[0], r.fe[1], r.fe[2]);
+            r.fh[0] = pick3(sel, r.fh[0], r.fh[1], r.fh[2]);
+            r.fH[0] = pick3(sel, r.fH[0], r.fH[1], r.fH[2]);
         }
     }
     if (!cand) {
@@ -205,14 +224,15 @@ __device__ __forceinline__ FaceF recon_face_f32(const ReconF& r, int j, double t
 }
 
 // recon_face_f32(r, j) for a face index j known only at run time: the face
-// values are selected first, then one face state is formed.
+// values are selected first (among registers, see pick3), then one face
+// state is formed.
 __device__ __forceinline__ FaceF recon_face_sel_f32(const ReconF& r, int j, double thr) {
     ReconF s;
-    s.fe[0] = (j == 0) ? r.fe[0] : (j == 1) ? r.fe[1] : r.fe[2];
-    s.fu[0] = (j == 0) ? r.fu[0] : (j == 1) ? r.fu[1] : r.fu[2];
-    s.fv[0] = (j == 0) ? r.fv[0] : (j == 1) ? r.fv[1] : r.fv[2];
-    s.fh[0] = (j == 0) ? r.fh[0] : (j == 1) ? r.fh[1] : r.fh[2];
-    s.fH[0] = (j == 0) ? r.fH[0] : (j == 1) ? r.fH[1] : r.fH[2];
+    s.fe[0] = pick3f(j, r.fe[0], r.fe[1], r.fe[2]);
+    s.fu[0] = pick3f(j, r.fu[0], r.fu[1], r.fu[2]);
+    s.fv[0] = pick3f(j, r.fv[0], r.fv[1], r.fv[2]);
+    s.fh[0] = pick3(j, r.fh[0], r.fh[1], r.fh[2]);
+    s.fH[0] = pick3(j, r.fH[0], r.fH[1], r.fH[2]);
     return recon_face_f32(s, 0, thr);
 }
 
@@ -331,7 +351,8 @@ __device__ __forceinline__ void face_pair_f32(double g, double hg, const FaceF& 
 __device__ __forceinline__ void recon_tri_f32(const CellF& ck, double hk, const CellF cn[3],
                                               const double hn[3], const TopoD& tp,
                                               const double x[3], const double y[3],
-                                              const LsqWF& w, double thr, ReconF& r) {
+                                              const LsqWF& w, double thr, ReconF& r,
+                                              int sel = -1) {
     const uint32_t sl[3] = {tp.n0, tp.n1, tp.n2};
     recon_from_f32(
         ck, hk, cn, hn, sl, thr,
@@ -354,7 +375,7 @@ __device__ __forceinline__ void recon_tri_f32(const CellF& ck, double hk, const 
                 gd[2 * j + 1] = float((y[j] + y[j1]) * 0.5 - cy);
             }
         },
-        r);
+        r, sel);
 }
 
 // The records recon_tri_f32 reads for cell k: state, still-water depth,
@@ -713,8 +734,8 @@ __global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTile
         CellInF iq;
         load_cell_f32(m, Ws, hc, tq, n, iq);
         ReconF r;
-        recon_tri_f32(iq.ck, iq.hk, iq.cn, iq.hn, tq, iq.x, iq.y, lq, p.thr, r);
-        const FaceF f = recon_face_sel_f32(r, jn, p.thr);
+        recon_tri_f32(iq.ck, iq.hk, iq.cn, iq.hn, tq, iq.x, iq.y, lq, p.thr, r, jn);
+        const FaceF f = recon_face_f32(r, 0, p.thr);
         const int sb = 3 * T + b;
         Le[sb] = double(f.eta);
         Lh[sb] = f.h;

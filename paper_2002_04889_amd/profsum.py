@@ -9,9 +9,10 @@ counter value that the copy kernel (rocclr copyBuffer) reports for its
 largest dispatch gives the scale factor from counter units to bytes.
 
 --traffic-json OUT --workload NAME: also write the scaled FETCH_SIZE and
-WRITE_SIZE per launch of every kernel, in bytes, with a digest of the
-kernel sources; the benchmark reports these as the measured HBM traffic
-only while the digest matches the sources it runs.
+WRITE_SIZE per launch of every kernel, in bytes (and SQ_INSTS_VALU, SQ_WAVES
+per launch where a pass holds them), with a digest of the kernel sources;
+the benchmark reports these as the measured HBM traffic and vector issue
+rate only while the digest matches the sources it runs.
 """
 from __future__ import annotations
 
@@ -26,10 +27,12 @@ import re
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
-# The files the stage kernels are compiled from (their code and headers)
-# and the compile flags: a change to any of them invalidates measured traffic.
+# The files the stage kernels are compiled from (their code and headers),
+# the host code that lays the mesh out in memory, and the compile flags: a
+# change to any of them invalidates measured traffic.
 STAGE_SOURCES = ("vsw_device.hpp", "vsw_common.hpp", "vsw_kernels.hpp", "vsw_kernels.hip",
-                 "vsw_kernels_f32.hpp", "vsw_kernels_f32.hip", "vsw_faces.hpp", "vsw_faces.hip")
+                 "vsw_kernels_f32.hpp", "vsw_kernels_f32.hip", "vsw_faces.hpp", "vsw_faces.hip",
+                 "vsw_mesh.hpp", "vsw_mesh.cpp")
 
 
 def source_digest() -> str:
@@ -91,6 +94,11 @@ def traffic(paths, copy_bytes: float, workload: str) -> dict:
                 if c in v and c in scale:
                     out["kernels"].setdefault(k, {})[c.lower().replace("_size", "_bytes")] = \
                         sum(v[c]) / len(v[c]) * scale[c] * 1024.0
+            # vector instructions issued per launch (wave instructions: one
+            # per wavefront of 64 lanes), when that pass was taken
+            for c in ("SQ_INSTS_VALU", "SQ_WAVES"):
+                if c in v:
+                    out["kernels"].setdefault(k, {})[c.lower()] = sum(v[c]) / len(v[c])
     return out
 
 

@@ -15,7 +15,8 @@ import re
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvsw.so")
+# VSW_LIB names another build of the library (to compare builds)
+LIB_PATH = os.environ.get("VSW_LIB") or os.path.join(_HERE, "libvsw.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "vsw.h")
 
 VSW_OK, VSW_EINVAL, VSW_EMESH, VSW_ESTATE, VSW_ENOMEM, VSW_EDEVICE, VSW_EUNSTABLE = \
