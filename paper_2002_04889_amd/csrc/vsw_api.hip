@@ -1320,6 +1320,12 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     const dim3 grid(unsigned(s->ntiles)), block(kBlock);
     int64_t* cells = s->d_gauge_cells.p;
     const size_t lds = stage_lds_bytes(s->bmax), lds32 = stage_f32_lds_bytes(s->bmax);
+    // the replay of an FP64 run uses the face-parallel kernels unless the
+    // solver runs the cell-parallel ones (both record the same tape)
+    const bool faces = (s->variant == VSW_KERNEL_FACES);
+    const FaceMesh fm = s->face_mesh();
+    const FaceTileMap ftm = s->face_tiles(1);
+    const size_t ldsf = faces_lds_bytes(kTile, s->fbmax);
     const double zero_t = 0.0;
     HIP_TRY(hipMemcpy(s->d_t0.p, &zero_t, sizeof(double), hipMemcpyHostToDevice));
     if (s->d_log.n < 2) HIP_TRY(s->d_log.alloc(2));
@@ -1348,10 +1354,19 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                 Cell4* Wo = (i + 1 < len) ? Wi + n : wend.p;
                 const Tape t1{tR0.p + 3 * i * n, tm1.p + i * n, nullptr};
                 const Tape t2{tR1.p + 3 * i * n, tm2.p + i * n, rmin_hist.p + i + 1};
-                hipLaunchKernelGGL(stage_tape_kernel<1>, grid, block, lds, st, m, tm, Wi, Wo, W1i,
-                                   p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t1);
-                hipLaunchKernelGGL(stage_tape_kernel<2>, grid, block, lds, st, m, tm, Wi, Wo, W1i,
-                                   p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
+                if (faces) {
+                    hipLaunchKernelGGL((faces_tape_kernel<256, 1>), grid, block, ldsf, st, fm, ftm,
+                                       Wi, Wo, W1i, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p,
+                                       t1);
+                    hipLaunchKernelGGL((faces_tape_kernel<256, 2>), grid, block, ldsf, st, fm, ftm,
+                                       Wi, Wo, W1i, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p,
+                                       t2);
+                } else {
+                    hipLaunchKernelGGL(stage_tape_kernel<1>, grid, block, lds, st, m, tm, Wi, Wo,
+                                       W1i, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t1);
+                    hipLaunchKernelGGL(stage_tape_kernel<2>, grid, block, lds, st, m, tm, Wi, Wo,
+                                       W1i, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
+                }
             }
         } else {
             // the FP32 steps again from the FP32 checkpoint; the tape holds

@@ -104,13 +104,12 @@ __device__ __forceinline__ void store_face(double* Le, double* Lh, double* LH, d
 
 }  // namespace
 
-template <int T, int STAGE>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void faces_stage_kernel(FaceMesh m, FaceTileMap tm,
-                                                        Cell4* __restrict__ Wa,
-                                                        Cell4* __restrict__ Wb,
-                                                        Cell4* __restrict__ W1, StepParams p,
-                                                        Ctrl* c, Seg* sg, int slot, int step_arg,
-                                                        double* log) {
+template <int T, int STAGE, bool TAPE>
+__device__ __forceinline__ void faces_stage_body(const FaceMesh& m, const FaceTileMap& tm,
+                                                 Cell4* __restrict__ Wa, Cell4* __restrict__ Wb,
+                                                 Cell4* __restrict__ W1, const StepParams& p,
+                                                 Ctrl* c, Seg* sg, int slot, int step_arg,
+                                                 double* log, const Tape& tape) {
     extern __shared__ double lds[];
     const int S = 3 * T + tm.bmax;
     // face slots: eta, h, H, u, v of a face state; after phase 2 the face's
@@ -298,17 +297,38 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void fac
             bad = !isfinite(o.H) || !isfinite(o.HU) || !isfinite(o.HV);
             rr = cfl_ratio(o.H, o.HU, o.HV, area, per, p.g, p.thr);
         }
+        if (TAPE) {
+            tape.R[3 * k] = R[0];
+            tape.R[3 * k + 1] = R[1];
+            tape.R[3 * k + 2] = R[2];
+            tape.mask[k] = mk;
+        }
     }
     if (STAGE == 2 && bad) {
         atomicOr(&c->err, 1);
         atomicMin(&c->err_step, step);
     }
     if (STAGE == 2) {
-        block_count_min_atomic<T>(clamp, &c->clamps, rr, &sgs->rmin[slot ^ 1]);
+        block_count_min_atomic<T>(clamp, &c->clamps, rr, TAPE ? tape.rmin : &sgs->rmin[slot ^ 1]);
         stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
     } else {
         block_count_atomic<T>(clamp, &c->clamps);
     }
+}
+
+template <int T, int STAGE>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void faces_stage_kernel(
+    FaceMesh m, FaceTileMap tm, Cell4* __restrict__ Wa, Cell4* __restrict__ Wb,
+    Cell4* __restrict__ W1, StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg, double* log) {
+    faces_stage_body<T, STAGE, false>(m, tm, Wa, Wb, W1, p, c, sg, slot, step_arg, log, Tape{});
+}
+
+template <int T, int STAGE>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void faces_tape_kernel(
+    FaceMesh m, FaceTileMap tm, Cell4* __restrict__ W, Cell4* __restrict__ Wout,
+    Cell4* __restrict__ W1, StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg, double* log,
+    Tape tp) {
+    faces_stage_body<T, STAGE, true>(m, tm, W, Wout, W1, p, c, sg, slot, step_arg, log, tp);
 }
 
 template <int T>
@@ -339,5 +359,13 @@ VSW_FACES_INSTANCES(128)
 VSW_FACES_INSTANCES(256)
 VSW_FACES_INSTANCES(512)
 #undef VSW_FACES_INSTANCES
+
+// the adjoint replays tiles of 256 cells
+template __global__ void faces_tape_kernel<256, 1>(FaceMesh, FaceTileMap, Cell4*, Cell4*, Cell4*,
+                                                   StepParams, Ctrl*, Seg*, int, int, double*,
+                                                   Tape);
+template __global__ void faces_tape_kernel<256, 2>(FaceMesh, FaceTileMap, Cell4*, Cell4*, Cell4*,
+                                                   StepParams, Ctrl*, Seg*, int, int, double*,
+                                                   Tape);
 
 }  // namespace vsw

@@ -65,6 +65,14 @@ __global__ void faces_stage_kernel(FaceMesh m, FaceTileMap tm, Cell4* Wa, Cell4*
                                    StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg,
                                    double* log);
 
+// faces_stage_kernel with a tape (same arithmetic and results, the tape of
+// stage_tape_kernel): reads w^n from W and writes w^{n+1} to Wout (control
+// par and step index 0).
+template <int T, int STAGE>
+__global__ void faces_tape_kernel(FaceMesh m, FaceTileMap tm, Cell4* W, Cell4* Wout, Cell4* W1,
+                                  StepParams p, Ctrl* c, Seg* sg, int slot, int step_arg,
+                                  double* log, Tape tp);
+
 // CFL minimum of the incoming state for tiles of T cells.
 template <int T>
 __global__ void faces_dt_init_kernel(FaceMesh m, FaceTileMap tm, const Cell4* W, const double* area,
