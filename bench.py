@@ -376,8 +376,8 @@ def bench_adjoint(args, torch, vsw, W):
     h_true = case.h - Phi @ a_true
     log(f"[bench] adjoint: {nc} cells, {steps} steps, 20 gauges, checkpoints every {ckpt}")
 
-    def forward(h, timed):
-        s = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold)
+    def forward(h, timed, precision=vsw.VSW_FP64):
+        s = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold, precision=precision)
         try:
             s.upload_mesh(case.vx, case.vy, case.tri, h)
             s.set_state(case.H, case.HU, case.HV, 0.0)
@@ -403,6 +403,19 @@ def bench_adjoint(args, torch, vsw, W):
     ga = -(Phi.T @ gh)
     log(f"[bench] forward {t_fwd * 1e3:.1f} ms, adjoint (forward + reverse) {t_adj * 1e3:.1f} ms, "
         f"ratio {t_adj / t_fwd:.2f}; loss {loss:.6e}, |dL/da| {np.abs(ga).max():.3e}")
+    # the FP32 solver: FP32 forward and replay, FP64 reverse sweep
+    _, t_fwd32 = forward(case.h, True, vsw.VSW_FP32)
+    s = vsw.Solver.for_case(case, precision=vsw.VSW_FP32)
+    try:
+        t0 = time.perf_counter()
+        loss32, gH32, _, _, gh32 = vsw.vsw_adjoint_gauge_loss(s.h, nc, steps, ckpt, gauges, obs)
+        t_adj32 = time.perf_counter() - t0
+    finally:
+        s.close()
+    ga32 = -(Phi.T @ gh32)
+    rel = float(np.abs(ga32 - ga).max() / np.abs(ga).max())
+    log(f"[bench] fp32 forward {t_fwd32 * 1e3:.1f} ms, adjoint {t_adj32 * 1e3:.1f} ms, ratio "
+        f"{t_adj32 / t_fwd32:.2f}; max |dL/da fp32-forward - fp64| / max |dL/da| {rel:.2e}")
     out = {"metric": "adjoint/forward time", "value": t_adj / t_fwd, "unit": "ratio",
            "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": t_adj * 1e3 / steps,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -414,7 +427,11 @@ def bench_adjoint(args, torch, vsw, W):
                       "cells": nc, "precision": "fp64 forward and adjoint",
                       "global_batch": nc, "parallelism": "single-gpu"},
            "forward_ms": t_fwd * 1e3, "adjoint_ms": t_adj * 1e3, "loss": loss,
-           "grad_amplitudes_max": float(np.abs(ga).max())}
+           "grad_amplitudes_max": float(np.abs(ga).max()),
+           "fp32_forward": {"value": t_adj32 / t_fwd32, "unit": "ratio",
+                            "forward_ms": t_fwd32 * 1e3, "adjoint_ms": t_adj32 * 1e3,
+                            "loss": loss32, "grad_amplitudes_rel_diff_vs_fp64": rel,
+                            "precision": "fp32 forward and replay, fp64 reverse sweep"}}
     print(json.dumps(out), flush=True)
 
 

@@ -1,6 +1,7 @@
 """Summarise rocprofv3 CSV output (kernel stats, PMC counters) as markdown.
 
 python -m paper_2002_04889_amd.profsum --stats DIR/run_kernel_stats.csv
+python -m paper_2002_04889_amd.profsum --trace DIR/run_kernel_trace.csv
 python -m paper_2002_04889_amd.profsum --pmc DIR/run_counter_collection.csv \
        [--copy-bytes N]
 
@@ -59,6 +60,32 @@ def stats(path: str) -> str:
         out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                    f"{float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
+def trace(path: str) -> str:
+    """Per-dispatch kernel trace grouped by run and kernel: a run starts at
+    each state upload (a pack_state kernel), so that the legs of one
+    benchmark (meshes, precisions, cell orders) are averaged separately."""
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    agg = collections.OrderedDict()
+    run = 0
+    for r in rows:
+        name = short(r["Kernel_Name"])
+        if name.startswith("vsw::pack_state"):
+            run += 1
+        wg = int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"])
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        agg.setdefault((run, name, grid // max(wg, 1)), []).append(dur)
+    total = sum(sum(v) for v in agg.values())
+    out = ["| run | kernel | workgroups | calls | avg us | min us | max us | share % |",
+           "|---|---|---|---|---|---|---|---|"]
+    for (rn, k, wgs), v in agg.items():
+        if not k.startswith("vsw::") or 100.0 * sum(v) / total < 0.05:
+            continue
+        out.append(f"| {rn} | {k} | {wgs} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | "
+                   f"{max(v):.2f} | {100.0 * sum(v) / total:.1f} |")
     return "\n".join(out)
 
 
@@ -124,6 +151,7 @@ def pmc(path: str, copy_bytes: float | None) -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats")
+    ap.add_argument("--trace")
     ap.add_argument("--pmc", action="append", default=[])
     ap.add_argument("--copy-bytes", type=float)
     ap.add_argument("--traffic-json")
@@ -131,6 +159,8 @@ def main():
     a = ap.parse_args()
     if a.stats:
         print(stats(a.stats))
+    if a.trace:
+        print(trace(a.trace))
     for p in a.pmc:
         print()
         print(pmc(p, a.copy_bytes))
