@@ -20,7 +20,8 @@ namespace vsw {
 
 // ---------------------------------------------------------------- control
 
-__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0, int par) {
+__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0, int par,
+                                 int keep) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->err = 0;
         c->err_step = 0x7FFFFFFF;
@@ -31,7 +32,8 @@ __global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0, i
     for (int s = int(blockIdx.x * blockDim.x + threadIdx.x); s < nseg;
          s += int(gridDim.x * blockDim.x)) {
         Seg q;
-        q.rmin[0] = q.rmin[1] = 0x7FF0000000000000ull;
+        q.rmin[0] = (keep >= 0) ? sg[s].rmin[keep] : 0x7FF0000000000000ull;
+        q.rmin[1] = 0x7FF0000000000000ull;
         q.t[0] = q.t[1] = t0[s];
         q.dt_last = 0.0;
         q.steps_done = 0;

@@ -100,8 +100,11 @@ __global__ void stage_tape_kernel(DevMesh m, TileMap tm, Cell4* W, Cell4* Wout, 
                                   double* log, Tape tp);
 
 // Start of a call: every scenario's time from t0[s], minima cleared; par is
-// the state buffer holding the call's first state.
-__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0, int par);
+// the state buffer holding the call's first state.  keep >= 0: the CFL
+// minimum of that state is already in slot `keep` of every scenario's record
+// (the previous call's last step computed it) and moves to slot 0.
+__global__ void ctrl_init_kernel(Ctrl* c, Seg* sg, int nseg, const double* t0, int par,
+                                 int keep);
 // CFL minimum of the incoming state, one block per tile.
 __global__ void dt_init_kernel(DevMesh m, TileMap tm, const Cell4* W, double g, double thr,
                                Seg* sg);
