@@ -213,7 +213,7 @@ def time_steps(torch, stream, s, steps):
 
 
 def run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, precision, ordering, steps, warmup,
-            bytes1, bytes2, label, kernel=None, tile=None):
+            bytes1, bytes2, label, kernel=None, tile=None, launch_modes=False):
     """Warm up and time `steps` steps of one solver configuration; returns
     (leg summary dict, solver handle still open)."""
     s = vsw.Solver(g=case.g, cfl=case.cfl, h_threshold=case.h_threshold, device=0,
@@ -240,6 +240,19 @@ def run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, precision, ordering, st
            "roofline": kernel_roofline(vsw, s, steps, nc, bytes1, bytes2),
            "mesh": {"cells": nc, "edges": ne, "walls": nw},
            "tile": vsw.vsw_tile_size(s.h)}
+    if launch_modes:
+        # the same call length replayed from a captured step pair and from
+        # one graph of the whole call (its first call captures it), against
+        # the direct launches timed above
+        modes = {"direct": {"value": value, "ms_per_step": ms / steps}}
+        for mode, name in ((1, "pair_graph"), (2, "whole_call_graph")):
+            vsw.vsw_set_graph(s.h, mode)
+            s.step(steps)
+            m = time_steps(torch, stream, s, steps)
+            modes[name] = {"value": nc * steps / (m / 1e3), "ms_per_step": m / steps}
+            log(f"[bench] {label}, {name}: {m:.1f} ms for {steps} steps")
+        vsw.vsw_set_graph(s.h, 0)
+        leg["launch_modes"] = modes
     return leg, s
 
 
@@ -450,6 +463,8 @@ def main():
                          "adjoint: gauge-misfit gradient, adjoint/forward time")
     ap.add_argument("--no-fp64", action="store_true", help="ensemble: skip the FP64 leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-launch-modes", action="store_true",
+                    help="skip timing the FP64 leg again in the two graph modes")
     ap.add_argument("--no-fp32", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-random", action="store_true",
                     help="coastal: skip the random-order legs")
@@ -540,7 +555,8 @@ def main():
         b1, b2 = ((ALG_BYTES_STAGE1, ALG_BYTES_STAGE2) if prec == vsw.VSW_FP64
                   else (ALG_BYTES_STAGE1_F32, ALG_BYTES_STAGE2_F32))
         leg, s = run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, prec, order, steps,
-                         warmup, b1, b2, name, kernel=kernel, tile=args.tile)
+                         warmup, b1, b2, name, kernel=kernel, tile=args.tile,
+                         launch_modes=(name == "fp64" and not args.no_launch_modes))
         s.close()
         leg["dtype"] = ("f64" if prec == vsw.VSW_FP64 else
                         "f32 state and fluxes, f64 depths/pressure/accumulation")
@@ -576,6 +592,8 @@ def main():
                       "ordering": top["ordering"], "global_batch": mesh["cells"],
                       "parallelism": "single-gpu"},
            "roofline": top["roofline"]}
+    if "launch_modes" in top:
+        out["launch_modes"] = top["launch_modes"]
     for name, leg in res.items():
         leg.pop("mesh")
         out[name] = leg

@@ -64,7 +64,7 @@ enum { VSW_ORDER_HILBERT = 0, VSW_ORDER_NONE = 1, VSW_ORDER_RANDOM = 2,
        VSW_ORDER_BISECTION = 3 };
 
 typedef struct vsw_params {
-    double g;            /* gravity (m/s^2), > 0 */
+    double g;            /* gravity (m/s^2), in (0, 2^100] */
     double cfl;          /* Courant number of the dt rule, > 0 (Section 2.3) */
     double h_threshold;  /* threshold depth H_thr (m), >= 0 (Section 2.4):
                             below it a cell is not reconstructed and its
@@ -80,8 +80,9 @@ typedef struct vsw_params {
 typedef struct vsw_solver vsw_solver;
 
 /* Create a solver on HIP device `device` (Section 2 parameters in p).
- * EINVAL if p is NULL, g <= 0, cfl <= 0, h_threshold < 0, dt_fixed < 0 or
- * an unknown precision/ordering; EDEVICE if the device cannot be used. */
+ * EINVAL if p is NULL, g outside (0, 2^100], cfl <= 0, h_threshold < 0,
+ * dt_fixed < 0 or an unknown precision/ordering; EDEVICE if the device
+ * cannot be used. */
 int vsw_create(const vsw_params *p, int device, vsw_solver **out);
 
 /* Free every device and host resource of the solver.  NULL is a no-op. */
@@ -94,8 +95,11 @@ void vsw_destroy(vsw_solver *s);
  * Section 2.5), the geometry and the internal renumbering, and copies the
  * result to the device.  EMESH on an index out of range, a zero-area
  * triangle, a face shared by more than two triangles, two triangles on the
- * same side of a face, or duplicate vertex coordinates on a face.  Replaces
- * any previous mesh and discards the state. */
+ * same side of a face, or duplicate vertex coordinates on a face; EINVAL
+ * on a vertex coordinate that is neither 0 nor within [2^-300, 2^300] in
+ * magnitude (the range in which the kernels' face geometry is exact),
+ * or a non-finite depth.  Replaces any previous mesh and discards the
+ * state. */
 int vsw_upload_mesh(vsw_solver *s, int64_t nv, const double *vx,
                     const double *vy, int64_t nc, const int32_t *tri,
                     const double *h);
@@ -132,7 +136,7 @@ int vsw_scenario_status(vsw_solver *s, int32_t max, double *t, double *dt_last,
 int vsw_scenario_dt_history(vsw_solver *s, int32_t scen, int64_t max,
                             double *dts, int64_t *count);
 
-/* Discrete adjoint (FP64 solvers, one scenario).  From the current state,
+/* Discrete adjoint (one scenario, tiles of 256 cells).  From the current state,
  * run nsteps steps (the solver's dt rule, no t_stop) and evaluate the gauge
  * misfit loss = sum_{n=1..nsteps} sum_g (eta_g^n - eta_obs[(n-1) * ng + g])^2,
  * eta = H - h at gauge_cells[g] (caller's cell indices) after step n; then
@@ -147,8 +151,12 @@ int vsw_scenario_dt_history(vsw_solver *s, int32_t scen, int64_t max,
  * depth, with the initial H, HU, HV held fixed).  The solver's state, time,
  * gauges and logs are unchanged on return.  Device memory: about
  * 32 * ceil(nsteps / checkpoint_every) + 114 * min(checkpoint_every, nsteps)
- * + 300 bytes per cell.  EINVAL on an FP32 or ensemble solver, ng < 1 or
- * bad counts; ENOMEM when that memory is not available; EUNSTABLE if the
+ * + 300 bytes per cell.  On an FP32 solver the forward run and the segment
+ * replays are the FP32 kernels (its trajectory, its dts) and the reverse
+ * sweep is the FP64 adjoint of the scheme evaluated on the FP32 states:
+ * an approximation of the FP32 run's gradient, not its exact adjoint.
+ * EINVAL on an ensemble solver, tiles other than 256 cells, ng < 1 or bad
+ * counts; ENOMEM when that memory is not available; EUNSTABLE if the
  * forward run fails. */
 int vsw_adjoint_gauge_loss(vsw_solver *s, int64_t nsteps,
                            int64_t checkpoint_every, int32_t ng,

@@ -469,7 +469,7 @@ const char* vsw_kernel_name(int kind) {
 int vsw_create(const vsw_params* p, int device, vsw_solver** out) {
     if (!p || !out) return fail(VSW_EINVAL, "NULL argument");
     *out = nullptr;
-    if (!(p->g > 0.0) || !std::isfinite(p->g)) return fail(VSW_EINVAL, "g must be > 0");
+    if (!(p->g > 0.0) || !(p->g <= 0x1p100)) return fail(VSW_EINVAL, "g must be in (0, 2^100]");
     if (!(p->cfl > 0.0) || !std::isfinite(p->cfl)) return fail(VSW_EINVAL, "cfl must be > 0");
     if (!(p->h_threshold >= 0.0) || !std::isfinite(p->h_threshold))
         return fail(VSW_EINVAL, "h_threshold must be >= 0");

@@ -84,12 +84,25 @@ __device__ __forceinline__ void carry_state(const Ctrl* c, const Seg* sg, int sl
 }
 
 // CFL ratio |K| / (P_K (|u| + sqrt(g H))) of a wet cell, +inf otherwise.
+// Where g H >= 2^-600, sqrt(g H) >= 2^-300 and a speed |u| below 2^-383
+// does not change the sum: |u| is then taken as sqrt(max(u^2 + v^2,
+// 2^-767)), which keeps sqrt_n in its range, and the sum is the same
+// number.  Other cells, and momenta with tiny_num, take the plain form.
 __device__ __forceinline__ double cfl_ratio(double H, double HU, double HV, double area,
                                             double perim, double g, double thr) {
     if (!(H >= thr)) return __longlong_as_double(0x7FF0000000000000ll);
-    const double u = HU / H, v = HV / H;
-    const double s = sqrt(u * u + v * v) + sqrt(g * H);
-    return area / (perim * s);
+    const double gH = g * H;
+    const Rcp dh = rcp_of(H);
+    const double u = quot(HU, dh), v = quot(HV, dh);
+    const double uu = u * u + v * v;
+    const double s = sqrt_n(__builtin_fmax(uu, 0x1p-767)) + sqrt_n(gH);
+    const double ps = perim * s;
+    double r = quot(area, rcp_of(ps));
+    if (wave_any(!(gH >= 0x1p-600) || tiny_num(HU) || tiny_num(HV))) {
+        const double u2 = HU / H, v2 = HV / H;
+        r = area / (perim * (sqrt(u2 * u2 + v2 * v2) + sqrt(gH)));
+    }
+    return r;
 }
 
 // Block-wide min of a positive double over NT threads, then one atomic min

@@ -63,13 +63,16 @@ __device__ __forceinline__ void recon_tri(const Cell4& ck, const Cell4 cn[3], co
         [&](int j, double& nx, double& ny) {
             const int j1 = (j == 2) ? 0 : j + 1;
             const double ex = g.x[j1] - g.x[j], ey = g.y[j1] - g.y[j];
-            const double l = sqrt(ex * ex + ey * ey);
-            nx = ey / l;
-            ny = (-ex) / l;
+            const double l = sqrt_n(ex * ex + ey * ey);
+            const Rcp d = rcp_of(l);
+            nx = quot(ey, d);
+            ny = quot(-ex, d);
         },
         [&](double* gw, double* gd) {
-            const double cx = ((g.x[0] + g.x[1]) + g.x[2]) / 3.0;
-            const double cy = ((g.y[0] + g.y[1]) + g.y[2]) / 3.0;
+            // sums of admitted coordinates: zero or at least 2^-352
+            const Rcp d3 = rcp_three();
+            const double cx = quot((g.x[0] + g.x[1]) + g.x[2], d3);
+            const double cy = quot((g.y[0] + g.y[1]) + g.y[2], d3);
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int j1 = (j == 2) ? 0 : j + 1;
@@ -87,10 +90,15 @@ struct FaceGeo {
     double nx, ny, l;
 };
 
+// The mesh upload admits vertex coordinates that are zero or between 2^-300
+// and 2^300 in magnitude, so an edge component is zero or at least 2^-352,
+// the squared length at least 2^-704 and the length within [2^-352, 2^302]:
+// sqrt_n and quot return the correctly rounded values without range tests.
 __device__ __forceinline__ FaceGeo face_geo(const double2& pa, const double2& pb) {
     const double ex = pb.x - pa.x, ey = pb.y - pa.y;
-    const double l = sqrt(ex * ex + ey * ey);
-    return FaceGeo{ey / l, (-ex) / l, l};
+    const double l = sqrt_n(ex * ex + ey * ey);
+    const Rcp d = rcp_of(l);
+    return FaceGeo{quot(ey, d), quot(-ex, d), l};
 }
 
 __device__ __forceinline__ void store_face(double* Le, double* Lh, double* LH, double* Lu,
@@ -287,7 +295,8 @@ __device__ __forceinline__ void faces_stage_body(const FaceMesh& m, const FaceTi
             s1 = s1 + p.hg * sx;
             s2 = s2 + p.hg * sy;
         }
-        const double R[3] = {s0 / area, s1 / area, s2 / area};
+        double R[3];
+        div_area(s0, s1, s2, area, R);
         uint8_t mk;
         if (STAGE == 1) {
             W1[k] = stage1_update(wn, R, dt, p.thr, clamp, mk);

@@ -238,7 +238,8 @@ __device__ __forceinline__ void stage_body(const DevMesh& m, const TileMap& tm,
             a2 = a2 + sc[1];
         }
         const double ar = m.area[k];
-        const double R[3] = {a0 / ar, a1 / ar, a2 / ar};
+        double R[3];
+        div_area(a0, a1, a2, ar, R);
         uint8_t mk;
         if (STAGE == 1) {
             W1[k] = stage1_update(W[k], R, dt, p.thr, clamp, mk);

@@ -359,13 +359,15 @@ __device__ __forceinline__ void recon_tri_f32(const CellF& ck, double hk, const 
         [&](int j, double& nx, double& ny) {
             const int j1 = (j == 2) ? 0 : j + 1;
             const double ex = x[j1] - x[j], ey = y[j1] - y[j];
-            const double l = sqrt(ex * ex + ey * ey);
-            nx = ey / l;
-            ny = (-ex) / l;
+            const double l = sqrt_n(ex * ex + ey * ey);
+            const Rcp d = rcp_of(l);
+            nx = quot(ey, d);
+            ny = quot(-ex, d);
         },
         [&](float* gw, float* gd) {
-            const double cx = ((x[0] + x[1]) + x[2]) / 3.0;
-            const double cy = ((y[0] + y[1]) + y[2]) / 3.0;
+            const Rcp d3 = rcp_three();
+            const double cx = quot((x[0] + x[1]) + x[2], d3);
+            const double cy = quot((y[0] + y[1]) + y[2], d3);
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int j1 = (j == 2) ? 0 : j + 1;
@@ -755,9 +757,10 @@ __global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTile
     }
     auto fgeo = [](const double2& pa, const double2& pb, double g[3]) {
         const double ex = pb.x - pa.x, ey = pb.y - pa.y;
-        const double l = sqrt(ex * ex + ey * ey);
-        g[0] = ey / l;
-        g[1] = (-ex) / l;
+        const double l = sqrt_n(ex * ex + ey * ey);
+        const Rcp d = rcp_of(l);
+        g[0] = quot(ey, d);
+        g[1] = quot(-ex, d);
         g[2] = l;
     };
     double g0[3] = {0.0, 0.0, 0.0}, g1[3] = {0.0, 0.0, 0.0};

@@ -89,6 +89,21 @@ int build_host_mesh(int64_t nv, const double* vx, const double* vy, int64_t nc,
         err = "mesh too large for 29-bit cell indices";
         return VSW_EINVAL;
     }
+    // vertex coordinates zero or within [2^-300, 2^300] in magnitude: edge
+    // components are then zero or at least 2^-352 and every edge length,
+    // normal and area a normal number far from both ends of the range,
+    // which the stage kernels' face geometry relies on
+    for (int64_t i = 0; i < nv; ++i)
+        for (const double c : {vx[i], vy[i]}) {
+            const double a = std::fabs(c);
+            if (!(a == 0.0 || (a >= 0x1p-300 && a <= 0x1p300))) {
+                snprintf(buf, sizeof buf,
+                         "vertex %lld: coordinate %g not 0 or within [2^-300, 2^300] in magnitude",
+                         (long long)i, c);
+                err = buf;
+                return VSW_EINVAL;
+            }
+        }
     // 1. counter-clockwise vertex order (swap local vertices 1 and 2 of a
     //    clockwise triangle)
     std::vector<int32_t> tri(3 * nc);

@@ -269,6 +269,78 @@ def test_adjoint_full_basin_finite_differences():
         assert err <= tol * scale + noise
 
 
+@pytest.mark.skip(reason="not met over 2000 steps: with steps fixed in advance (1e-3 m surface, "
+                         "1e-2 m bed) |FD - adjoint| / |adjoint| measured 9e-6 to 1.7e-4 "
+                         "(surface) and 5.6e-4 to 4.1e-3 (bed) on the 1M-triangle basin; the "
+                         "finite step crosses limiter, wave-speed and CFL switches of the "
+                         "piecewise smooth scheme, so the quotient's error falls about linearly "
+                         "with the step and a step small enough for 1e-6 sinks into the loss's "
+                         "round-off; the exact derivative is held to the tape gradient at 1e-10 "
+                         "and the full-length differences to sum |g v| in "
+                         "test_adjoint_full_basin_finite_differences")
+def test_adjoint_full_basin_fd_relative_to_adjoint():
+    c = generic_basin(scale=1, rough_bed=20.0)
+    rng = np.random.default_rng(11)
+    wet = np.flatnonzero(c.H > 100.0)
+    gauges = np.sort(rng.choice(wet, 20, replace=False)).astype(np.int32)
+    nsteps = 2000
+    obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
+    loss, gH, gU, gV, gh = gpu_adjoint(c, nsteps, 50, gauges, obs)
+    cx, cy = c.centroids()
+    for k in range(10):
+        gk = gauges[(2 * k) % len(gauges)]
+        x0, y0 = cx[gk] + rng.uniform(-30e3, 30e3), cy[gk] + rng.uniform(-30e3, 30e3)
+        v = np.exp(-((cx - x0) ** 2 + (cy - y0) ** 2) / (2 * 40e3 ** 2)) * (c.H > 10.0)
+        if k % 2 == 0:
+            g, eps = gH, 1e-3
+            f = lambda e: gpu_loss(c, c.H + e * v, c.h, nsteps, gauges, obs)
+        else:
+            g, eps = gH + gh, 1e-2
+            f = lambda e: gpu_loss(c, c.H + e * v, c.h + e * v, nsteps, gauges, obs)
+        ad = float((g * v).sum())
+        err = abs((f(eps) - f(-eps)) / (2 * eps) - ad)
+        assert err <= 1e-6 * abs(ad)
+
+
+def fp32_adjoint(c, nsteps, ckpt, gauges, obs):
+    s = vsw.Solver.for_case(c, precision=vsw.VSW_FP32)
+    try:
+        return vsw.vsw_adjoint_gauge_loss(s.h, c.nc, nsteps, ckpt, gauges, obs)
+    finally:
+        s.close()
+
+
+def test_fp32_forward_adjoint():
+    """FP32 forward and checkpoint replay, FP64 adjoint accumulation on the
+    FP32 trajectory: the loss is the FP32 run's, the gradients are identical
+    for every checkpoint interval, and they differ from the FP64 adjoint's
+    only by the FP32 trajectory's departure from the FP64 one."""
+    c, gauges, rng = setup_case("basin")
+    nsteps = 30
+    obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
+    outs = [fp32_adjoint(c, nsteps, k, gauges, obs) for k in (1, 7, 30)]
+    for o in outs[1:]:
+        assert o[0] == outs[0][0]
+        for a, b in zip(o[1:], outs[0][1:]):
+            assert np.array_equal(a, b)
+    s = vsw.Solver.for_case(c, precision=vsw.VSW_FP32)
+    try:
+        vsw.vsw_set_gauges(s.h, gauges)
+        s.step(nsteps)
+        _, eta = vsw.vsw_get_gauges(s.h, len(gauges))
+    finally:
+        s.close()
+    r = eta - obs
+    # same residuals; the sums differ only in their order of addition
+    ref = float((r * r).sum())
+    assert abs(outs[0][0] - ref) <= 1e-13 * ref
+    g64 = gpu_adjoint(c, nsteps, 8, gauges, obs)
+    for name, a, b in zip(("H", "HU", "HV", "h"), outs[0][1:], g64[1:]):
+        rel = np.abs(a - b).max() / np.abs(b).max()
+        say(f"fp32-forward adjoint d/d{name}: max |g32 - g64| / max |g64| = {rel:.3e}")
+        assert rel <= 1e-3, name
+
+
 def tied_cfl_case():
     """Congruent right triangles on an integer grid (1 km): a deep half at
     rest (1000 m), whose cells all have bitwise the same CFL ratio and set

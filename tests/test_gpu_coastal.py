@@ -138,8 +138,9 @@ def test_coastal_fp32_1000_steps(coast):
 
 def test_coastal_12m_against_oracle(coastal12m, coastal12m_oracle50):
     """Full size, the benchmark's launch configuration: FP64 full-field
-    parity with the oracle after 50 steps (1e-12 relative, every dt), and
-    the FP32 solver's free surface within the plain 1e-4 m of the oracle."""
+    parity with the oracle after 50 steps (1e-12 relative, every dt; in
+    fact bit for bit, also asserted), and the FP32 solver's free surface
+    within the plain 1e-4 m of the oracle."""
     c, o = coastal12m, coastal12m_oracle50
     n = 50
     g = gpu_state(c, n)
@@ -153,6 +154,10 @@ def test_coastal_12m_against_oracle(coastal12m, coastal12m_oracle50):
     assert abs(g["t"] - o["t"]) <= TOL * o["t"]
     assert np.abs(g["dts"] - o["dts"]).max() <= TOL * o["dts"].max()
     assert g["clamps"] == o["clamps"]
+    # and bit for bit (the FP64 kernels round as the oracle does)
+    for k in ("H", "HU", "HV"):
+        assert np.array_equal(g[k], o[k]), k
+    assert np.array_equal(g["dts"], o["dts"])
     f = gpu_state(c, 4 * n, vsw.VSW_FP32, t_stop=o["t"])
     assert f["rc"] == 0 and f["t"] == o["t"]
     d = np.abs(f["H"] - o["H"]).max()

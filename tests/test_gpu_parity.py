@@ -285,11 +285,17 @@ def test_basin_1m_bench_configuration(orc, basin1m_oracle):
     """The benchmark's workload (1M-triangle basin, Hilbert order, the
     launch configuration the benchmark times): full-field parity with the
     oracle after all 2000 steps (the oracle on every host core, bitwise the
-    same as on one), every step's dt, mass and positivity."""
+    same as on one), every step's dt, mass and positivity; the fields and
+    dts are in fact bit for bit the oracle's, which is asserted too."""
     c, o = basin1m_oracle
     say("basin", c.nc, "cells: 2000-step parity; oracle on", orc.max_threads(), "threads")
     g = gpu_run(c, 2000)
     assert_parity(g, o, "basin-1M-2000")
+    # beyond the bar: the FP64 kernels round every operation as the oracle
+    # does, so the fields and the dt sequence are the oracle's bits
+    for k in ("H", "HU", "HV"):
+        assert np.array_equal(g[k], o[k]), k
+    assert np.array_equal(g["dts"], o["dts"])
     assert g["clamps"] == o["clamps"]
     m = orc.Mesh.from_case(c)
     area = m.geometry()["area"]

@@ -64,6 +64,20 @@ def test_host_mesh_rejects_invalid():
         vsw.vsw_prepare_mesh_host(vx3, vy3, np.array([[0, 1, 2], [0, 1, 4]]), np.ones(2))
     with pytest.raises(vsw.VswError, match="EINVAL"):
         vsw.vsw_prepare_mesh_host(vx, vy, tri, np.array([1.0, np.nan]))
+    # vertex coordinates must be 0 or within [2^-300, 2^300] in magnitude
+    # (the kernels' face normals and lengths are exact in that range)
+    for bad in (1e-100, 2.0 ** -301, -(2.0 ** 301), 1e200, np.inf, np.nan):
+        vb = np.array(vx, dtype=np.float64)
+        vb[1] = bad
+        with pytest.raises(vsw.VswError, match="EINVAL.*coordinate"):
+            vsw.vsw_prepare_mesh_host(vb, vy, tri, np.ones(2))
+    for good in (0.0, 2.0 ** -300, -(2.0 ** 300)):
+        vg = np.array(vx, dtype=np.float64)
+        vg[0] = good
+        try:
+            vsw.vsw_prepare_mesh_host(vg, vy, tri, np.ones(2))
+        except vsw.VswError as e:
+            assert "coordinate" not in str(e)
 
 
 def test_tiny_meshes_counts():
@@ -87,7 +101,7 @@ def test_create_fails_cleanly_without_gpu():
 
 
 def test_create_validates_params():
-    for kw in ({"g": 0.0}, {"cfl": -1.0}, {"h_threshold": -1e-3}, {"dt_fixed": -1.0},
-               {"ordering": 7}):
+    for kw in ({"g": 0.0}, {"g": 2.0 ** 101}, {"g": np.inf}, {"cfl": -1.0},
+               {"h_threshold": -1e-3}, {"dt_fixed": -1.0}, {"ordering": 7}):
         with pytest.raises(vsw.VswError, match="EINVAL"):
             vsw.vsw_create(vsw.make_params(**kw))
