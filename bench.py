@@ -556,7 +556,8 @@ def main():
                   else (ALG_BYTES_STAGE1_F32, ALG_BYTES_STAGE2_F32))
         leg, s = run_leg(torch, vsw, case, stream, dev, dH, dHU, dHV, prec, order, steps,
                          warmup, b1, b2, name, kernel=kernel, tile=args.tile,
-                         launch_modes=(name == "fp64" and not args.no_launch_modes))
+                         launch_modes=(name == "fp64" and not coastal
+                                       and not args.no_launch_modes))
         s.close()
         leg["dtype"] = ("f64" if prec == vsw.VSW_FP64 else
                         "f32 state and fluxes, f64 depths/pressure/accumulation")

@@ -27,7 +27,10 @@
 //   gather  each cell adds the contributions its face neighbours made to it,
 //           in a fixed order.
 // Branches (wet/dry, upwind side, limiter case, min/max) are taken as the
-// forward takes them; the derivative is that of the taken branch.
+// forward takes them; the derivative is that of the taken branch.  Values
+// that decide a branch are formed bit for bit as the forward forms them;
+// reciprocals that only scale a derivative are the refined hardware
+// reciprocal (within an ulp of the quotient).
 #include "vsw_adjoint.hpp"
 #include "vsw_common.hpp"
 
@@ -43,7 +46,13 @@ __device__ __forceinline__ void hll_face_rev(double g, double hg, double HL, dou
                                              double& utLb, double& HRb, double& unRb,
                                              double& utRb) {
     if (HL == 0.0 && HR == 0.0) return;
-    const double cL = sqrt(g * HL), cR = sqrt(g * HR);
+    // the forward's wave speeds, bit for bit (its branches are taken again)
+    const double xL = g * HL, xR = g * HR;
+    double cL = sqrt_n(xL), cR = sqrt_n(xR);
+    if (wave_any(!(xL >= 0x1p-767) || !(xR >= 0x1p-767))) {
+        cL = sqrt(xL);
+        cR = sqrt(xR);
+    }
     double sL, sR, us = 0.0, cs = 0.0;
     bool selL = false, selR = false;  // sL = us - cs, sR = unR + cR chosen
     if (HL == 0.0) {
@@ -72,7 +81,7 @@ __device__ __forceinline__ void hll_face_rev(double g, double hg, double HL, dou
     } else if (sR < 0.0) {
         fRb[0] = fb[0]; fRb[1] = fb[1]; fRb[2] = fb[2];
     } else {
-        const double den = sR - sL, sLR = sL * sR, rd = 1.0 / den;
+        const double den = sR - sL, sLR = sL * sR, rd = rcp_of(den).r;
         const double dU[3] = {HR - HL, qR - qL, HR * utR - HL * utL};
         double rdb = 0.0, sLRb = 0.0;
 #pragma unroll
@@ -136,8 +145,8 @@ __device__ __forceinline__ void hll_face_rev(double g, double hg, double HL, dou
         unRb -= 0.25 * csb;
         unLb += 0.25 * csb;
     }
-    if (HL > 0.0) HLb += cLb * g / (2.0 * cL);
-    if (HR > 0.0) HRb += cRb * g / (2.0 * cR);
+    if (HL > 0.0) HLb += cLb * g * rcp_of(2.0 * cL).r;
+    if (HR > 0.0) HRb += cRb * g * rcp_of(2.0 * cR).r;
 }
 
 __device__ __forceinline__ void face_add(Face& a, const double eta, double h, double H, double u,
@@ -245,8 +254,9 @@ __device__ __forceinline__ double limiter_fwd(double q0, const double qs[3], con
 __device__ __forceinline__ void limiter_rev(double a, double ab, const LimInfo& li, double& q0b,
                                             double qsb[3], double pjb[3]) {
     if (li.br == 0) return;
-    const double nb = ab / li.den;          // adjoint of (q_ext - q0)
-    pjb[li.jd] -= ab * a / li.den;          // adjoint of the denominator
+    const double rd = rcp_of(li.den).r;
+    const double nb = ab * rd;              // adjoint of (q_ext - q0)
+    pjb[li.jd] -= (ab * a) * rd;            // adjoint of the denominator
     q0b -= nb;
     if (li.iq < 0) q0b += nb; else qsb[li.iq] += nb;
 }
@@ -316,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void adj_start_kernel(DevMesh m, TileMap tm
         const Adj4 l = lam[k];
         const double l0 = (mk & 1) ? l.H : 0.0, l1 = (mk & 2) ? l.HU : 0.0,
                      l2 = (mk & 2) ? l.HV : 0.0;
-        const double ra = 1.0 / m.area[k];
+        const double ra = rcp_of(m.area[k]).r;
         mua[3 * k] = (0.5 * dt * l0) * ra;
         mua[3 * k + 1] = (0.5 * dt * l1) * ra;
         mua[3 * k + 2] = (0.5 * dt * l2) * ra;
@@ -475,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
         if (fH[j] >= thr) {
             // u = fu * rH, v = fv * rH, rH = 1 / fH
             const double ub = F[j].u, vb = F[j].v;
-            const double rH = 1.0 / fH[j];
+            const double rH = rcp_of(fH[j]).r;
             fub[j] = ub * rH;
             fvb[j] = vb * rH;
             fHb[j] -= (ub * fu[j] + vb * fv[j]) * rH * rH;
@@ -591,7 +601,7 @@ __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
         const double a1 = ((m2 & 2) ? 0.5 * l.HU : 0.0) + w.HU;
         const double a2 = ((m2 & 2) ? 0.5 * l.HV : 0.0) + w.HV;
         const double t0 = (m1 & 1) ? a0 : 0.0, t1 = (m1 & 2) ? a1 : 0.0, t2 = (m1 & 2) ? a2 : 0.0;
-        const double ra = 1.0 / m.area[k];
+        const double ra = rcp_of(m.area[k]).r;
         mua[3 * k] = (dt * t0) * ra;
         mua[3 * k + 1] = (dt * t1) * ra;
         mua[3 * k + 2] = (dt * t2) * ra;
@@ -652,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void adj_turn_kernel(
             const uint8_t mk = mask2p[k];
             const double l0 = (mk & 1) ? n.H : 0.0, l1 = (mk & 2) ? n.HU : 0.0,
                          l2 = (mk & 2) ? n.HV : 0.0;
-            const double ra = 1.0 / m.area[k];
+            const double ra = rcp_of(m.area[k]).r;
             mua[3 * k] = (0.5 * dtp * l0) * ra;
             mua[3 * k + 1] = (0.5 * dtp * l1) * ra;
             mua[3 * k + 2] = (0.5 * dtp * l2) * ra;

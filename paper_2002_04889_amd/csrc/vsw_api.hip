@@ -1445,10 +1445,19 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                 const TapeF t1{tR0.p + 3 * i * n, tm1.p + i * n, nullptr, seg.p + i * n};
                 const TapeF t2{tR1.p + 3 * i * n, tm2.p + i * n, rmin_hist.p + i + 1,
                                segW1.p + i * n};
-                hipLaunchKernelGGL(stage_f32_tape_kernel<1>, grid, block, lds32, st, m, tm, Fi, Fo,
-                                   f1.p, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t1);
-                hipLaunchKernelGGL(stage_f32_tape_kernel<2>, grid, block, lds32, st, m, tm, Fi, Fo,
-                                   f1.p, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
+                if (faces) {
+                    hipLaunchKernelGGL((faces_tape_f32_kernel<256, 1>), grid, block, ldsf, st, fm,
+                                       ftm, s->d_h.p, Fi, Fo, f1.p, p, s->d_ctrl.p, s->d_seg.p, 0,
+                                       0, s->d_log.p, t1);
+                    hipLaunchKernelGGL((faces_tape_f32_kernel<256, 2>), grid, block, ldsf, st, fm,
+                                       ftm, s->d_h.p, Fi, Fo, f1.p, p, s->d_ctrl.p, s->d_seg.p, 0,
+                                       0, s->d_log.p, t2);
+                } else {
+                    hipLaunchKernelGGL(stage_f32_tape_kernel<1>, grid, block, lds32, st, m, tm, Fi,
+                                       Fo, f1.p, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t1);
+                    hipLaunchKernelGGL(stage_f32_tape_kernel<2>, grid, block, lds32, st, m, tm, Fi,
+                                       Fo, f1.p, p, s->d_ctrl.p, s->d_seg.p, 0, 0, s->d_log.p, t2);
+                }
             }
             if (cfl_dt)
                 hipLaunchKernelGGL(adj_rmin_kernel, grid, block, 0, st, m, tm, seg.p, g, thr,

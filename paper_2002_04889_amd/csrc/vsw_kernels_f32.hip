@@ -637,14 +637,16 @@ template __global__ void stage_f32_tape_kernel<2>(DevMesh, TileMap, CellF*, Cell
 // Face-parallel FP32 stage kernel: the phases of faces_stage_kernel, the
 // arithmetic of stage_f32_kernel.  LDS planes hold doubles (FP32 values are
 // stored exactly as doubles).
-template <int T, int STAGE>
-__global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTileMap tm,
-                                                            const double* __restrict__ hc,
-                                                            CellF* __restrict__ Wa,
-                                                            CellF* __restrict__ Wb,
-                                                            CellF* __restrict__ W1, StepParams p,
-                                                            Ctrl* c, Seg* sg, int slot,
-                                                            int step_arg, double* log) {
+// TAPE records what stage_f32_tape_kernel records (TapeF), with the same
+// arithmetic.
+template <int T, int STAGE, bool TAPE>
+__device__ __forceinline__ void faces_stage_f32_body(const FaceMesh& m, const FaceTileMap& tm,
+                                                     const double* __restrict__ hc,
+                                                     CellF* __restrict__ Wa,
+                                                     CellF* __restrict__ Wb,
+                                                     CellF* __restrict__ W1, const StepParams& p,
+                                                     Ctrl* c, Seg* sg, int slot, int step_arg,
+                                                     double* log, const TapeF& tape) {
     extern __shared__ double lds[];
     const int S = 3 * T + tm.bmax;
     double* __restrict__ Le = lds;
@@ -844,8 +846,9 @@ __global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTile
         }
         const double Hn = e + hk;
         bool dry = false;
-        if (Hn < 0.0) { dry = true; clamp = 1; }
-        if (Hn < p.thr) { u = 0.0; v = 0.0; }
+        uint8_t mk = 3;
+        if (Hn < 0.0) { dry = true; clamp = 1; mk &= uint8_t(~1u); }
+        if (Hn < p.thr) { u = 0.0; v = 0.0; mk &= uint8_t(~2u); }
         const CellF o = store_state(hk, e, u, v, dry);
         if (STAGE == 1) {
             W1[k] = o;
@@ -854,17 +857,52 @@ __global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTile
             bad = !isfinite(e) || !isfinite(u) || !isfinite(v);
             rr = cfl_ratio_f32(o, hk, area, per, p.g, p.thr);
         }
+        if (TAPE) {
+            // the state this stage reconstructed, in FP64 as the FP32 terms
+            // of the stage see it (H = eta + h rounded once)
+            const CellF q = Ws[k];
+            tape.win[k] = Cell4{double(q.eta) + hk, double(q.hu), double(q.hv), hk};
+            tape.R[3 * k] = R0;
+            tape.R[3 * k + 1] = R1;
+            tape.R[3 * k + 2] = R2;
+            tape.mask[k] = mk;
+        }
     }
     if (STAGE == 2 && bad) {
         atomicOr(&c->err, 1);
         atomicMin(&c->err_step, step);
     }
     if (STAGE == 2) {
-        block_count_min_atomic<T>(clamp, &c->clamps, rr, &sgs->rmin[slot ^ 1]);
+        block_count_min_atomic<T>(clamp, &c->clamps, rr, TAPE ? tape.rmin : &sgs->rmin[slot ^ 1]);
         stage2_bookkeeping(c, sgs, ti, tm.nseg, slot, step, true, dt, tn, p.t_stop, log);
     } else {
         block_count_atomic<T>(clamp, &c->clamps);
     }
+}
+
+template <int T, int STAGE>
+__global__ __launch_bounds__(T) void faces_stage_f32_kernel(FaceMesh m, FaceTileMap tm,
+                                                            const double* __restrict__ hc,
+                                                            CellF* __restrict__ Wa,
+                                                            CellF* __restrict__ Wb,
+                                                            CellF* __restrict__ W1, StepParams p,
+                                                            Ctrl* c, Seg* sg, int slot,
+                                                            int step_arg, double* log) {
+    faces_stage_f32_body<T, STAGE, false>(m, tm, hc, Wa, Wb, W1, p, c, sg, slot, step_arg, log,
+                                          TapeF{});
+}
+
+// faces_stage_f32_kernel with a tape: reads w^n from W and writes w^{n+1}
+// to Wout (control par and step index 0).
+template <int T, int STAGE>
+__global__ __launch_bounds__(T) void faces_tape_f32_kernel(FaceMesh m, FaceTileMap tm,
+                                                           const double* __restrict__ hc,
+                                                           CellF* __restrict__ W,
+                                                           CellF* __restrict__ Wout,
+                                                           CellF* __restrict__ W1, StepParams p,
+                                                           Ctrl* c, Seg* sg, int slot,
+                                                           int step_arg, double* log, TapeF tp) {
+    faces_stage_f32_body<T, STAGE, true>(m, tm, hc, W, Wout, W1, p, c, sg, slot, step_arg, log, tp);
 }
 
 template <int T>
@@ -894,6 +932,14 @@ VSW_FACES_F32_INSTANCES(128)
 VSW_FACES_F32_INSTANCES(256)
 VSW_FACES_F32_INSTANCES(512)
 #undef VSW_FACES_F32_INSTANCES
+
+// the adjoint replays tiles of 256 cells
+template __global__ void faces_tape_f32_kernel<256, 1>(FaceMesh, FaceTileMap, const double*,
+                                                       CellF*, CellF*, CellF*, StepParams, Ctrl*,
+                                                       Seg*, int, int, double*, TapeF);
+template __global__ void faces_tape_f32_kernel<256, 2>(FaceMesh, FaceTileMap, const double*,
+                                                       CellF*, CellF*, CellF*, StepParams, Ctrl*,
+                                                       Seg*, int, int, double*, TapeF);
 
 // Free surface at the gauge cells after step `step` (see gauge_kernel).
 __global__ void gauge_f32_kernel(const CellF* __restrict__ Wa, const CellF* __restrict__ Wb,

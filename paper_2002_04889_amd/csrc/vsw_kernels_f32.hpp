@@ -69,6 +69,11 @@ template <int T, int STAGE>
 __global__ void faces_stage_f32_kernel(FaceMesh m, FaceTileMap tm, const double* h, CellF* Wa,
                                        CellF* Wb, CellF* W1, StepParams p, Ctrl* c, Seg* sg,
                                        int slot, int step_arg, double* log);
+// faces_stage_f32_kernel recording the tape of stage_f32_tape_kernel.
+template <int T, int STAGE>
+__global__ void faces_tape_f32_kernel(FaceMesh m, FaceTileMap tm, const double* h, CellF* W,
+                                      CellF* Wout, CellF* W1, StepParams p, Ctrl* c, Seg* sg,
+                                      int slot, int step_arg, double* log, TapeF tp);
 template <int T>
 __global__ void faces_dt_init_f32_kernel(FaceMesh m, FaceTileMap tm, const CellF* W,
                                          const double* h, const double* area, double g,

@@ -302,9 +302,11 @@ def test_adjoint_full_basin_fd_relative_to_adjoint():
         assert err <= 1e-6 * abs(ad)
 
 
-def fp32_adjoint(c, nsteps, ckpt, gauges, obs):
+def fp32_adjoint(c, nsteps, ckpt, gauges, obs, variant=None):
     s = vsw.Solver.for_case(c, precision=vsw.VSW_FP32)
     try:
+        if variant is not None:
+            vsw.vsw_set_kernel_variant(s.h, variant)
         return vsw.vsw_adjoint_gauge_loss(s.h, c.nc, nsteps, ckpt, gauges, obs)
     finally:
         s.close()
@@ -313,12 +315,15 @@ def fp32_adjoint(c, nsteps, ckpt, gauges, obs):
 def test_fp32_forward_adjoint():
     """FP32 forward and checkpoint replay, FP64 adjoint accumulation on the
     FP32 trajectory: the loss is the FP32 run's, the gradients are identical
-    for every checkpoint interval, and they differ from the FP64 adjoint's
-    only by the FP32 trajectory's departure from the FP64 one."""
+    for every checkpoint interval and for the face-parallel and cell-parallel
+    replays, and they differ from the FP64 adjoint's only by the FP32
+    trajectory's departure from the FP64 one."""
     c, gauges, rng = setup_case("basin")
     nsteps = 30
     obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
     outs = [fp32_adjoint(c, nsteps, k, gauges, obs) for k in (1, 7, 30)]
+    # the replay by the cell-parallel FP32 kernels records the same tape
+    outs.append(fp32_adjoint(c, nsteps, 7, gauges, obs, vsw.VSW_KERNEL_FUSED))
     for o in outs[1:]:
         assert o[0] == outs[0][0]
         for a, b in zip(o[1:], outs[0][1:]):
