@@ -48,9 +48,11 @@ def setup_case(which):
     return c, gauges, rng
 
 
-def gpu_adjoint(c, nsteps, ckpt, gauges, obs, dt_fixed=0.0):
+def gpu_adjoint(c, nsteps, ckpt, gauges, obs, dt_fixed=0.0, variant=None):
     s = vsw.Solver.for_case(c, dt_fixed=dt_fixed)
     try:
+        if variant is not None:
+            vsw.vsw_set_kernel_variant(s.h, variant)
         return vsw.vsw_adjoint_gauge_loss(s.h, c.nc, nsteps, ckpt, gauges, obs)
     finally:
         s.close()
@@ -139,6 +141,10 @@ def test_adjoint_deterministic_over_checkpoints_and_leaves_state():
     nsteps = 13
     obs = rng.normal(0.0, 0.05, (nsteps, len(gauges)))
     outs = [gpu_adjoint(c, nsteps, k, gauges, obs) for k in (1, 4, 13, 50)]
+    # the cell-parallel organisation (each interior face reversed from both
+    # of its cells) gives the same numbers as the face-parallel one
+    outs += [gpu_adjoint(c, nsteps, 4, gauges, obs, variant=v)
+             for v in (vsw.VSW_KERNEL_FUSED, vsw.VSW_KERNEL_TWO_PASS)]
     for o in outs[1:]:
         assert o[0] == outs[0][0]
         for a, b in zip(o[1:], outs[0][1:]):
