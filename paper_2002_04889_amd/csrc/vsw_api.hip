@@ -460,7 +460,7 @@ extern "C" {
 
 const char* vsw_last_error(void) { return g_last_error.c_str(); }
 
-const char* vsw_version(void) { return "vsw 0.1 gfx950 fp64"; }
+const char* vsw_version(void) { return "vsw 0.2 gfx950 fp64 fp32"; }
 
 const char* vsw_kernel_name(int kind) {
     return (kind >= 0 && kind < KK_COUNT) ? kKernelNames[kind] : "";
