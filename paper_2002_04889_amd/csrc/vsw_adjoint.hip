@@ -15,7 +15,9 @@
 //
 // The stages' residuals, fix masks and intermediate states are recorded by
 // the stage kernels while they replay a checkpoint segment (Tape).  J_R^T mu
-// is taken in two passes, each cell-centric and free of atomics:
+// is taken in two passes, each cell-centric and free of atomics (the
+// contributions between cells of one tile handed over through LDS in the
+// first, those between tiles through memory to the second):
 //   vjp     per tile, the face states reconstructed into LDS as in the
 //           forward; per cell, the adjoint of its face states from the face
 //           terms of both cells that share each face (the forward evaluates
@@ -24,8 +26,10 @@
 //           reconstruction (least-squares gradient, Barth-Jespersen limiter
 //           with its branch recomputed, eq. (3), face velocity), giving the
 //           cell's own adjoint and one contribution per stencil member;
-//   gather  each cell adds the contributions its face neighbours made to it,
-//           in a fixed order.
+//           a member in the same tile adds it to its own adjoint, in face
+//           order, after a barrier;
+//   gather  each cell adds the contributions its face neighbours in other
+//           tiles made to it, in face order.
 // Branches (wet/dry, upwind side, limiter case, min/max) are taken as the
 // forward takes them; the derivative is that of the taken branch.  Values
 // that decide a branch are formed bit for bit as the forward forms them;
@@ -364,12 +368,19 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
     bool second;
     tile_faces(m, tm, W, t, c0, ti.cnt, thr, hg, lds, stride, ownH, sc, second);
     __syncthreads();
-    if (i >= ti.cnt) return;
-
+    const bool own = i < ti.cnt;
+    // the cell's own adjoint and its contribution to the stencil member
+    // across each face (zero on a wall)
+    double ownv[4] = {0.0, 0.0, 0.0, 0.0};
+    double con[3][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    uint32_t sl[3] = {kWallSlot, kWallSlot, kWallSlot};
+    if (own) {
     // ---- a. face-state adjoints
     const double ab[3] = {mua[3 * k], mua[3 * k + 1], mua[3 * k + 2]};
     const Nbr4 nb = m.nbr[k];
-    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
+    sl[0] = nb.s0;
+    sl[1] = nb.s1;
+    sl[2] = nb.s2;
     Face F[3];
     double fhs[3];
 #pragma unroll
@@ -534,15 +545,14 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
         project_rev(pvb, vkb, qvb);
         project_rev(phb, hkb, qhb);
     }
-    double* out = C + 16 * k;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const uint32_t s = sl[j];
         if (s != kWallSlot) {
-            out[4 + 4 * j + 0] = qeb[j];
-            out[4 + 4 * j + 1] = qub[j];
-            out[4 + 4 * j + 2] = qvb[j];
-            out[4 + 4 * j + 3] = qhb[j] - qeb[j];
+            con[j][0] = qeb[j];
+            con[j][1] = qub[j];
+            con[j][2] = qvb[j];
+            con[j][3] = qhb[j] - qeb[j];
         } else {
             const double nx = gf(m, 0, j, k), ny = gf(m, 1, j, k);
             ekb += qeb[j];
@@ -552,21 +562,56 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
             ukb += mnb * nx;
             vkb += mnb * ny;
             hkb += qhb[j];
-            out[4 + 4 * j + 0] = 0.0;
-            out[4 + 4 * j + 1] = 0.0;
-            out[4 + 4 * j + 2] = 0.0;
-            out[4 + 4 * j + 3] = 0.0;
         }
     }
-    out[0] = Hkb + ekb;
-    out[1] = ukb;
-    out[2] = vkb;
-    out[3] = hkb - ekb;
+    ownv[0] = Hkb + ekb;
+    ownv[1] = ukb;
+    ownv[2] = vkb;
+    ownv[3] = hkb - ekb;
+    }
+    // Hand the contributions over: to a stencil member in this tile through
+    // the LDS slot of its face state (the slot of the face it shares with
+    // this cell; every reader of face states is past the barrier), to one in
+    // another tile through C for the gather kernels.
+    __syncthreads();
+    if (own) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const uint32_t s = sl[j];
+            if (s == kWallSlot) continue;
+            if (int64_t(s >> 3) / kTile == int64_t(t)) {
+                const int slot = int(tm.nloc[j * nc + k] & 0x7FFFu);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) lds[q * stride + slot] = con[j][q];
+            } else {
+                double* out = C + 16 * k + 4 + 4 * j;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) out[q] = con[j][q];
+            }
+        }
+    }
+    __syncthreads();
+    if (own) {
+        // own + the contributions of the stencil members in this tile, in
+        // face order; those from other tiles follow in the gather
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const uint32_t s = sl[j];
+            if (s == kWallSlot || int64_t(s >> 3) / kTile != int64_t(t)) continue;
+            const int slot = j * kTile + i;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ownv[q] += lds[q * stride + slot];
+        }
+        double* out = C + 16 * k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = ownv[q];
+    }
 }
 
 namespace {
 
-// own + the stencil contributions the face neighbours made to cell k
+// own (with the contributions from its own tile) + the stencil contributions
+// the face neighbours in other tiles made to cell k
 __device__ __forceinline__ Adj4 gather_cell(const DevMesh& m, const double* __restrict__ C,
                                             int64_t k) {
     const double* o = C + 16 * k;
@@ -576,7 +621,8 @@ __device__ __forceinline__ Adj4 gather_cell(const DevMesh& m, const double* __re
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const uint32_t s = sl[j];
-        if (s == kWallSlot) continue;
+        // a stencil member in the same tile was added by the product itself
+        if (s == kWallSlot || int64_t(s >> 3) / kTile == k / kTile) continue;
         const double* c = C + 16 * int64_t(s >> 3) + 4 + 4 * int(s & 3u);
         a0 += c[0]; a1 += c[1]; a2 += c[2]; a3 += c[3];
     }

@@ -24,16 +24,20 @@ __global__ void adj_start_kernel(DevMesh m, TileMap tm, const Adj4* lam, const u
                                  const double* R1, double dt, double* mua, Adj4* lamn,
                                  double* part);
 // Vector-Jacobian product of R at W with weights mua = mu / |K| (3 per
-// cell), one workgroup per tile (dynamic LDS: stage_lds_bytes(bmax)), up to
-// the per-cell contributions: own (H, HU, HV, h) in C[16 k + 0..3], stencil
-// member j in C[16 k + 4 + 4 j + 0..3].  Each cell reverses its own term and
-// its neighbour's term of each face (the forward evaluates a face from both
-// sides) and keeps the part for its own face state, so no adjoint is handed
-// between cells before the gather.
+// cell), one workgroup per tile (dynamic LDS: stage_lds_bytes(bmax)).  Each
+// cell reverses its own term and its neighbour's term of each face (the
+// forward evaluates a face from both sides) and keeps the part for its own
+// face state, then reverses its reconstruction into its own adjoint and one
+// contribution per stencil member.  A contribution to a member in the same
+// tile is handed over through LDS and added to that member's own adjoint in
+// face order; C[16 k + 0..3] receives the own adjoint with those, and
+// C[16 k + 4 + 4 j + 0..3] the contribution to stencil member j when that
+// member is in another tile (for the gather).
 __global__ void adj_vjp_kernel(DevMesh m, TileMap tm, const Cell4* W, const double* mua,
                                double g, double hg, double thr, double* C);
-// Gather: own + the stencil contributions of the face neighbours, in fixed
-// order (no atomics), then the Runge-Kutta reverse that follows J_R(w1)^T:
+// Gather: own (with its tile's contributions) + the stencil contributions of
+// the face neighbours in other tiles, in fixed order (no atomics), then the
+// Runge-Kutta reverse that follows J_R(w1)^T:
 //   lam1 = lt2/2 + wb, hbar += wb.h, lt1 = mask1 (.) lam1,
 //   mua = dt lt1 / |K|, lamn += lt1, part[tile] += lt1 . R0.
 __global__ void adj_gather_rk2_kernel(DevMesh m, TileMap tm, const double* C, const Adj4* lam,
