@@ -288,6 +288,16 @@ __device__ __forceinline__ double block_sum(double v) {
 
 // ---------------------------------------------------------------- forward pieces
 
+__global__ __launch_bounds__(kBlock) void adj_xin_kernel(TileMap tm, int64_t nc,
+                                                         int32_t* __restrict__ xin) {
+    const int t = int(blockIdx.x);
+    const int b0 = tm.bstart[t], nb = tm.bstart[t + 1] - b0;
+    for (int b = int(threadIdx.x); b < nb; b += kBlock) {
+        const uint32_t item = tm.bitem[b0 + b];
+        xin[int64_t(item & 3u) * nc + int64_t(item >> 2)] = b0 + b;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void adj_rmin_kernel(DevMesh m, TileMap tm,
                                                           const Cell4* __restrict__ W, double g,
                                                           double thr, unsigned long long* rmin) {
@@ -351,12 +361,12 @@ __global__ __launch_bounds__(kBlock) void adj_start_kernel(DevMesh m, TileMap tm
 //     plus the bed source of a second-order cell;
 //  b. the reverse of k's reconstruction, its branches recomputed: the
 //     adjoint of k's own variables and one contribution per stencil member,
-//     written to C.
+//     handed to the member through LDS (same tile) or AdjC (other tiles).
 __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
                                                          const Cell4* __restrict__ W,
                                                          const double* __restrict__ mua,
                                                          double g, double hg, double thr,
-                                                         double* __restrict__ C) {
+                                                         AdjC c) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
     const int t = int(blockIdx.x);
@@ -584,9 +594,9 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
 #pragma unroll
                 for (int q = 0; q < 4; ++q) lds[q * stride + slot] = con[j][q];
             } else {
-                double* out = C + 16 * k + 4 + 4 * j;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) out[q] = con[j][q];
+                // slot 3 kTile + b: halo item b of this tile names the member
+                const int b = int(tm.nloc[j * nc + k] & 0x7FFFu) - 3 * kTile;
+                c.x[tm.bstart[t] + b] = Adj4{con[j][0], con[j][1], con[j][2], con[j][3]};
             }
         }
     }
@@ -602,37 +612,30 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
 #pragma unroll
             for (int q = 0; q < 4; ++q) ownv[q] += lds[q * stride + slot];
         }
-        double* out = C + 16 * k;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) out[q] = ownv[q];
+        c.own[k] = Adj4{ownv[0], ownv[1], ownv[2], ownv[3]};
     }
 }
 
 namespace {
 
 // own (with the contributions from its own tile) + the stencil contributions
-// the face neighbours in other tiles made to cell k
-__device__ __forceinline__ Adj4 gather_cell(const DevMesh& m, const double* __restrict__ C,
-                                            int64_t k) {
-    const double* o = C + 16 * k;
-    double a0 = o[0], a1 = o[1], a2 = o[2], a3 = o[3];
-    const Nbr4 nb = m.nbr[k];
-    const uint32_t sl[3] = {nb.s0, nb.s1, nb.s2};
+// the face neighbours in other tiles made to cell k, in face order
+__device__ __forceinline__ Adj4 gather_cell(const DevMesh& m, const AdjC& c, int64_t k) {
+    Adj4 a = c.own[k];
+    const int32_t x[3] = {c.xin[k], c.xin[m.nc + k], c.xin[2 * m.nc + k]};
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        const uint32_t s = sl[j];
-        // a stencil member in the same tile was added by the product itself
-        if (s == kWallSlot || int64_t(s >> 3) / kTile == k / kTile) continue;
-        const double* c = C + 16 * int64_t(s >> 3) + 4 + 4 * int(s & 3u);
-        a0 += c[0]; a1 += c[1]; a2 += c[2]; a3 += c[3];
+        if (x[j] < 0) continue;
+        const Adj4 v = c.x[x[j]];
+        a.H += v.H; a.HU += v.HU; a.HV += v.HV; a.h += v.h;
     }
-    return Adj4{a0, a1, a2, a3};
+    return a;
 }
 
 }  // namespace
 
 __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
-    DevMesh m, TileMap tm, const double* __restrict__ C, const Adj4* __restrict__ lam,
+    DevMesh m, TileMap tm, AdjC c, const Adj4* __restrict__ lam,
     const uint8_t* __restrict__ mask2, const uint8_t* __restrict__ mask1,
     const double* __restrict__ R0, double dt, double* __restrict__ mua, Adj4* __restrict__ lamn,
     double* __restrict__ hbar, double* __restrict__ part) {
@@ -640,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
     const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
     double d = 0.0;
     if (int(threadIdx.x) < ti.cnt) {
-        const Adj4 w = gather_cell(m, C, k);
+        const Adj4 w = gather_cell(m, c, k);
         const uint8_t m2 = mask2[k], m1 = mask1[k];
         const Adj4 l = lam[k];
         const double a0 = ((m2 & 1) ? 0.5 * l.H : 0.0) + w.H;
@@ -662,7 +665,7 @@ __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
 }
 
 __global__ __launch_bounds__(kBlock) void adj_turn_kernel(
-    DevMesh m, TileMap tm, const double* __restrict__ C, const Cell4* __restrict__ W, double g,
+    DevMesh m, TileMap tm, AdjC c, const Cell4* __restrict__ W, double g,
     double thr, double cfl, const unsigned long long* argmin, const double* lamdt,
     const int64_t* cells, int ng, const double* r, Adj4* __restrict__ lamn,
     double* __restrict__ hbar, const uint8_t* __restrict__ mask2p,
@@ -673,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void adj_turn_kernel(
     double d = 0.0;
     if (int(threadIdx.x) < ti.cnt) {
         // after J_R(w)^T: the contributions gathered in fixed order
-        const Adj4 w = gather_cell(m, C, k);
+        const Adj4 w = gather_cell(m, c, k);
         Adj4 n = lamn[k];
         n.H += w.H; n.HU += w.HU; n.HV += w.HV;
         double hb = hbar[k] + w.h;

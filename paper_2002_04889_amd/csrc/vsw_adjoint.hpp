@@ -13,6 +13,22 @@ struct alignas(32) Adj4 {
     double H, HU, HV, h;
 };
 
+// Where the vector-Jacobian product leaves its results for the gathers: the
+// own adjoint of each cell (with the contributions of the stencil members in
+// its tile), and the contributions to stencil members in other tiles, one
+// per halo item of the contributing cell's tile (the tile map's halo list,
+// in its order).  xin[j nc + k] is the index in x of the contribution cell k
+// receives across its face j, or -1 when none comes through x (a wall or a
+// neighbour in k's own tile).
+struct AdjC {
+    Adj4* __restrict__ own;          // [nc]
+    Adj4* __restrict__ x;            // [halo items]
+    const int32_t* __restrict__ xin; // [3][nc]
+};
+
+// xin of the tile map (preset to -1): for halo item b of tile t, the cell
+// outside t and its face that item names receive x index bstart[t] + b.
+__global__ void adj_xin_kernel(TileMap tm, int64_t nc, int32_t* xin);
 // Bits of the CFL minimum of W into *rmin (pre-set to +inf).
 __global__ void adj_rmin_kernel(DevMesh m, TileMap tm, const Cell4* W, double g, double thr,
                                 unsigned long long* rmin);
@@ -30,17 +46,17 @@ __global__ void adj_start_kernel(DevMesh m, TileMap tm, const Adj4* lam, const u
 // face state, then reverses its reconstruction into its own adjoint and one
 // contribution per stencil member.  A contribution to a member in the same
 // tile is handed over through LDS and added to that member's own adjoint in
-// face order; C[16 k + 0..3] receives the own adjoint with those, and
-// C[16 k + 4 + 4 j + 0..3] the contribution to stencil member j when that
-// member is in another tile (for the gather).
+// face order; c.own[k] receives the own adjoint with those, and c.x the
+// contribution to each stencil member in another tile, at the index of the
+// halo item of this tile that names the member (for the gathers).
 __global__ void adj_vjp_kernel(DevMesh m, TileMap tm, const Cell4* W, const double* mua,
-                               double g, double hg, double thr, double* C);
+                               double g, double hg, double thr, AdjC c);
 // Gather: own (with its tile's contributions) + the stencil contributions of
 // the face neighbours in other tiles, in fixed order (no atomics), then the
 // Runge-Kutta reverse that follows J_R(w1)^T:
 //   lam1 = lt2/2 + wb, hbar += wb.h, lt1 = mask1 (.) lam1,
 //   mua = dt lt1 / |K|, lamn += lt1, part[tile] += lt1 . R0.
-__global__ void adj_gather_rk2_kernel(DevMesh m, TileMap tm, const double* C, const Adj4* lam,
+__global__ void adj_gather_rk2_kernel(DevMesh m, TileMap tm, AdjC c, const Adj4* lam,
                                       const uint8_t* mask2, const uint8_t* mask1,
                                       const double* R0, double dt, double* mua, Adj4* lamn,
                                       double* hbar, double* part);
@@ -57,7 +73,7 @@ __global__ void adj_argmin_kernel(DevMesh m, TileMap tm, const Cell4* W, double 
 // (lamn.H += 2 r, hbar -= 2 r per gauge on the cell).  lamn then holds the
 // adjoint of w^k.  With mask2p, also the start of the reverse of step k-1
 // from its tape (R1p, mask2p, dtp), as adj_start_kernel: mua, lamp, part.
-__global__ void adj_turn_kernel(DevMesh m, TileMap tm, const double* C, const Cell4* W, double g,
+__global__ void adj_turn_kernel(DevMesh m, TileMap tm, AdjC c, const Cell4* W, double g,
                                 double thr, double cfl, const unsigned long long* argmin,
                                 const double* lamdt, const int64_t* cells, int ng,
                                 const double* r, Adj4* lamn, double* hbar, const uint8_t* mask2p,

@@ -1359,9 +1359,10 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     // fix masks, and the CFL minimum of each state.
     const size_t N = size_t(n), SL = size_t(segl);
     DevBuf<Cell4> segW1, wend;
-    DevBuf<double> d_r, tR0, tR1, mua, C, hbar, part, lamdt, gout;
+    DevBuf<double> d_r, tR0, tR1, mua, hbar, part, lamdt, gout;
     DevBuf<uint8_t> tm1, tm2;
-    DevBuf<Adj4> lam, lamn;
+    DevBuf<Adj4> lam, lamn, cown, cx;
+    DevBuf<int32_t> xin;
     DevBuf<unsigned long long> rmin_hist, argmin;
     hipError_t e = hipSuccess;
     DevBuf<CellF> fA, fB, f1;  // FP32 replay buffers
@@ -1372,7 +1373,8 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     for (hipError_t x : {d_r.alloc(r.size()), seg.alloc(SL * N), segW1.alloc(SL * N),
                          wend.alloc(f32 ? 1 : N), tR0.alloc(3 * SL * N), tR1.alloc(3 * SL * N),
                          tm1.alloc(SL * N), tm2.alloc(SL * N), rmin_hist.alloc(SL + 1), argmin.alloc(1),
-                         lam.alloc(N), lamn.alloc(N), mua.alloc(3 * N), C.alloc(16 * N),
+                         lam.alloc(N), lamn.alloc(N), mua.alloc(3 * N), cown.alloc(N),
+                         cx.alloc(s->d_bitem.n), xin.alloc(3 * N),
                          hbar.alloc(N), part.alloc(size_t(s->ntiles)), lamdt.alloc(1),
                          gout.alloc(4 * size_t(s->nc))})
         if (x != hipSuccess) e = x;
@@ -1384,6 +1386,9 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, 1,
                s->xcd_order};
     const dim3 grid(unsigned(s->ntiles)), block(kBlock);
+    HIP_TRY(hipMemsetAsync(xin.p, 0xFF, 3 * N * sizeof(int32_t), st));
+    hipLaunchKernelGGL(adj_xin_kernel, grid, block, 0, st, tm, int64_t(N), xin.p);
+    const AdjC cc{cown.p, cx.p, xin.p};
     int64_t* cells = s->d_gauge_cells.p;
     const size_t lds = stage_lds_bytes(s->bmax), lds32 = stage_f32_lds_bytes(s->bmax);
     // the replay of an FP64 run uses the face-parallel kernels unless the
@@ -1477,14 +1482,14 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                 hipLaunchKernelGGL(adj_start_kernel, grid, block, 0, st, m, tm, lam.p, m2, R1, dt,
                                    mua.p, lamn.p, part.p);
             hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, W1, mua.p, g, hg, thr,
-                               C.p);
-            hipLaunchKernelGGL(adj_gather_rk2_kernel, grid, block, 0, st, m, tm, C.p, lam.p, m2,
+                               cc);
+            hipLaunchKernelGGL(adj_gather_rk2_kernel, grid, block, 0, st, m, tm, cc, lam.p, m2,
                                m1, R0, dt, mua.p, lamn.p, hbar.p, part.p);
             if (cfl_dt)
                 hipLaunchKernelGGL(adj_sum_kernel, dim3(1), block, 0, st, part.p, s->ntiles,
                                    lamdt.p);
             hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, Wn, mua.p, g, hg, thr,
-                               C.p);
+                               cc);
             if (cfl_dt) {
                 HIP_TRY(hipMemsetAsync(argmin.p, 0xFF, sizeof(unsigned long long), st));
                 hipLaunchKernelGGL(adj_argmin_kernel, grid, block, 0, st, m, tm, Wn, g, thr,
@@ -1492,7 +1497,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
             }
             // step k-1's tape is in this segment: start its reverse in the same pass
             const bool next = (k - 1 >= n0);
-            hipLaunchKernelGGL(adj_turn_kernel, grid, block, 0, st, m, tm, C.p, Wn, g, thr, cfl,
+            hipLaunchKernelGGL(adj_turn_kernel, grid, block, 0, st, m, tm, cc, Wn, g, thr, cfl,
                                cfl_dt ? argmin.p : nullptr, lamdt.p, cells, ng,
                                k >= 1 ? d_r.p + (k - 1) * ng : nullptr, lamn.p, hbar.p,
                                next ? m2 - n : nullptr, next ? R1 - 3 * n : nullptr,
