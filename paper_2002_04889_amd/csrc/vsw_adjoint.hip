@@ -311,20 +311,6 @@ __global__ __launch_bounds__(kBlock) void adj_rmin_kernel(DevMesh m, TileMap tm,
     block_min_atomic(r, rmin);
 }
 
-__global__ __launch_bounds__(kBlock) void adj_argmin_kernel(DevMesh m, TileMap tm,
-                                                            const Cell4* __restrict__ W, double g,
-                                                            double thr,
-                                                            const unsigned long long* rmin,
-                                                            unsigned long long* argmin) {
-    const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
-    const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
-    if (int(threadIdx.x) >= ti.cnt) return;
-    const Cell4 q = W[k];
-    const double r = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
-    if (r < __longlong_as_double(0x7FF0000000000000ll) && dbits(r) == *rmin)
-        atomicMin(argmin, (unsigned long long)k);
-}
-
 __global__ __launch_bounds__(kBlock) void adj_start_kernel(DevMesh m, TileMap tm,
                                                            const Adj4* __restrict__ lam,
                                                            const uint8_t* __restrict__ mask2,
@@ -344,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void adj_start_kernel(DevMesh m, TileMap tm
         mua[3 * k] = (0.5 * dt * l0) * ra;
         mua[3 * k + 1] = (0.5 * dt * l1) * ra;
         mua[3 * k + 2] = (0.5 * dt * l2) * ra;
-        lamn[k] = Adj4{0.5 * l0, 0.5 * l1, 0.5 * l2, 0.0};
+        lamn[k] = Adj4{0.5 * l0, 0.5 * l1, 0.5 * l2, l.h};
         d = 0.5 * (l0 * R1[3 * k] + l1 * R1[3 * k + 1] + l2 * R1[3 * k + 2]);
     }
     const double s = block_sum(d);
@@ -366,7 +352,8 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
                                                          const Cell4* __restrict__ W,
                                                          const double* __restrict__ mua,
                                                          double g, double hg, double thr,
-                                                         AdjC c) {
+                                                         AdjC c,
+                                                         unsigned long long* argmin_reset) {
     extern __shared__ double lds[];
     const int stride = 3 * kTile + tm.bmax;
     const int t = int(blockIdx.x);
@@ -376,6 +363,9 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
     const int64_t k = c0 + i;
     double sc[2], ownH[3];
     bool second;
+    // clears the minimising-cell word the next gather fills (the previous
+    // step's turn kernel, its last reader, has finished)
+    if (argmin_reset && t == 0 && i == 0) *argmin_reset = ~0ull;
     tile_faces(m, tm, W, t, c0, ti.cnt, thr, hg, lds, stride, ownH, sc, second);
     __syncthreads();
     const bool own = i < ti.cnt;
@@ -638,11 +628,20 @@ __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
     DevMesh m, TileMap tm, AdjC c, const Adj4* __restrict__ lam,
     const uint8_t* __restrict__ mask2, const uint8_t* __restrict__ mask1,
     const double* __restrict__ R0, double dt, double* __restrict__ mua, Adj4* __restrict__ lamn,
-    double* __restrict__ hbar, double* __restrict__ part) {
+    double* __restrict__ part, const Cell4* __restrict__ W, double g, double thr,
+    const unsigned long long* rmin, unsigned long long* argmin) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
     double d = 0.0;
     if (int(threadIdx.x) < ti.cnt) {
+        if (argmin) {
+            // the cell that set dt: the lowest index whose CFL ratio has the
+            // bits of the minimum
+            const Cell4 q = W[k];
+            const double rr = cfl_ratio(q.H, q.HU, q.HV, m.area[k], m.perim[k], g, thr);
+            if (rr < __longlong_as_double(0x7FF0000000000000ll) && dbits(rr) == *rmin)
+                atomicMin(argmin, (unsigned long long)k);
+        }
         const Adj4 w = gather_cell(m, c, k);
         const uint8_t m2 = mask2[k], m1 = mask1[k];
         const Adj4 l = lam[k];
@@ -656,8 +655,8 @@ __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
         mua[3 * k + 2] = (dt * t2) * ra;
         Adj4 n = lamn[k];
         n.H += t0; n.HU += t1; n.HV += t2;
+        n.h += w.h;
         lamn[k] = n;
-        hbar[k] += w.h;
         d = t0 * R0[3 * k] + t1 * R0[3 * k + 1] + t2 * R0[3 * k + 2];
     }
     const double s = block_sum(d);
@@ -666,20 +665,32 @@ __global__ __launch_bounds__(kBlock) void adj_gather_rk2_kernel(
 
 __global__ __launch_bounds__(kBlock) void adj_turn_kernel(
     DevMesh m, TileMap tm, AdjC c, const Cell4* __restrict__ W, double g,
-    double thr, double cfl, const unsigned long long* argmin, const double* lamdt,
+    double thr, double cfl, const unsigned long long* argmin, const double* __restrict__ part,
     const int64_t* cells, int ng, const double* r, Adj4* __restrict__ lamn,
-    double* __restrict__ hbar, const uint8_t* __restrict__ mask2p,
+    const uint8_t* __restrict__ mask2p,
     const double* __restrict__ R1p, double dtp, double* __restrict__ mua,
-    Adj4* __restrict__ lamp, double* __restrict__ part) {
+    Adj4* __restrict__ lamp, double* __restrict__ partp) {
     const TileInfo ti = tile_info(tm.tinfo[blockIdx.x]);
     const int64_t k = int64_t(blockIdx.x) * kTile + threadIdx.x;
     double d = 0.0;
+    // the adjoint of dt, sum of part[] in fixed order, formed by the block
+    // that holds the minimising cell
+    double lamdt = 0.0;
+    if (argmin && *argmin / kTile == (unsigned long long)blockIdx.x) {
+        __shared__ double tot;
+        double sp = 0.0;
+        for (int i = threadIdx.x; i < int(gridDim.x); i += kBlock) sp += part[i];
+        const double t = block_sum(sp);
+        if (threadIdx.x == 0) tot = t;
+        __syncthreads();
+        lamdt = tot;
+    }
     if (int(threadIdx.x) < ti.cnt) {
         // after J_R(w)^T: the contributions gathered in fixed order
         const Adj4 w = gather_cell(m, c, k);
         Adj4 n = lamn[k];
         n.H += w.H; n.HU += w.HU; n.HV += w.HV;
-        double hb = hbar[k] + w.h;
+        double hb = n.h + w.h;
         if (argmin && (unsigned long long)k == *argmin) {
             // dt = CFL ratio of the minimising cell (the first in the
             // internal order among cells of equal ratio)
@@ -688,7 +699,7 @@ __global__ __launch_bounds__(kBlock) void adj_turn_kernel(
             {
                 const double u = q.HU / q.H, v = q.HV / q.H;
                 const double m2 = u * u + v * v, mm = sqrt(m2), c = sqrt(g * q.H), sp = mm + c;
-                const double sb = -(*lamdt * cfl) * rr / sp;
+                const double sb = -(lamdt * cfl) * rr / sp;
                 const double ub = (m2 > 0.0) ? sb * u / mm : 0.0;
                 const double vb = (m2 > 0.0) ? sb * v / mm : 0.0;
                 n.H += sb * g / (2.0 * c) - (ub * u + vb * v) / q.H;
@@ -704,8 +715,8 @@ __global__ __launch_bounds__(kBlock) void adj_turn_kernel(
                     hb -= 2.0 * r[gi];
                 }
         }
+        n.h = hb;
         lamn[k] = n;
-        hbar[k] = hb;
         if (mask2p) {
             // the start of the reverse of step k-1 (as adj_start_kernel)
             const uint8_t mk = mask2p[k];
@@ -715,40 +726,30 @@ __global__ __launch_bounds__(kBlock) void adj_turn_kernel(
             mua[3 * k] = (0.5 * dtp * l0) * ra;
             mua[3 * k + 1] = (0.5 * dtp * l1) * ra;
             mua[3 * k + 2] = (0.5 * dtp * l2) * ra;
-            lamp[k] = Adj4{0.5 * l0, 0.5 * l1, 0.5 * l2, 0.0};
+            lamp[k] = Adj4{0.5 * l0, 0.5 * l1, 0.5 * l2, hb};
             d = 0.5 * (l0 * R1p[3 * k] + l1 * R1p[3 * k + 1] + l2 * R1p[3 * k + 2]);
         }
     }
     if (mask2p) {
         const double s = block_sum(d);
-        if (threadIdx.x == 0) part[blockIdx.x] = s;
+        if (threadIdx.x == 0) partp[blockIdx.x] = s;
     }
 }
 
-// ---------------------------------------------------------------- time step
-
-__global__ void adj_sum_kernel(const double* part, int n, double* out) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
-    const double t = block_sum(s);
-    if (threadIdx.x == 0) *out = t;
-}
 
 // ---------------------------------------------------------------- loss and output
 
-__global__ void adj_gauge_kernel(const int64_t* cells, int ng, const double* r, Adj4* lam,
-                                 double* hbar) {
+__global__ void adj_gauge_kernel(const int64_t* cells, int ng, const double* r, Adj4* lam) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     for (int i = 0; i < ng; ++i) {  // one thread: gauges may share a cell
         const int64_t k = cells[i];
         lam[k].H += 2.0 * r[i];
-        hbar[k] -= 2.0 * r[i];
+        lam[k].h -= 2.0 * r[i];
     }
 }
 
-__global__ void adj_unpack_kernel(int64_t n, const int64_t* perm, const Adj4* lam,
-                                  const double* hbar, double* gH, double* gHU, double* gHV,
-                                  double* gh) {
+__global__ void adj_unpack_kernel(int64_t n, const int64_t* perm, const Adj4* lam, double* gH,
+                                  double* gHU, double* gHV, double* gh) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t k = perm[i];
@@ -756,7 +757,7 @@ __global__ void adj_unpack_kernel(int64_t n, const int64_t* perm, const Adj4* la
     gH[k] = lam[i].H;
     gHU[k] = lam[i].HU;
     gHV[k] = lam[i].HV;
-    gh[k] = hbar[i];
+    gh[k] = lam[i].h;
 }
 
 }  // namespace vsw

@@ -8,7 +8,9 @@
 
 namespace vsw {
 
-// Adjoint of one cell's variables (H, HU, HV, h).
+// Adjoint of one cell's variables (H, HU, HV, h).  In the records of the
+// state adjoints lam the h field carries the running adjoint of the bed
+// depth (the bed is the same in every state).
 struct alignas(32) Adj4 {
     double H, HU, HV, h;
 };
@@ -34,7 +36,7 @@ __global__ void adj_rmin_kernel(DevMesh m, TileMap tm, const Cell4* W, double g,
                                 unsigned long long* rmin);
 // Start of the reverse of a step from its tape (R1 = R(w1), mask2 of
 // w^{n+1} = fix(w/2 + (w1 + dt R1)/2)) with lam the adjoint of w^{n+1}:
-// lt2 = mask2 (.) lam, mua = dt/2 lt2 / |K|, lamn = lt2/2,
+// lt2 = mask2 (.) lam, mua = dt/2 lt2 / |K|, lamn = (lt2/2, lam.h),
 // part[tile] = sum lt2/2 . R1.
 __global__ void adj_start_kernel(DevMesh m, TileMap tm, const Adj4* lam, const uint8_t* mask2,
                                  const double* R1, double dt, double* mua, Adj4* lamn,
@@ -48,45 +50,45 @@ __global__ void adj_start_kernel(DevMesh m, TileMap tm, const Adj4* lam, const u
 // tile is handed over through LDS and added to that member's own adjoint in
 // face order; c.own[k] receives the own adjoint with those, and c.x the
 // contribution to each stencil member in another tile, at the index of the
-// halo item of this tile that names the member (for the gathers).
+// halo item of this tile that names the member (for the gathers).  With
+// argmin_reset, also sets that word to all ones for adj_gather_rk2_kernel.
 __global__ void adj_vjp_kernel(DevMesh m, TileMap tm, const Cell4* W, const double* mua,
-                               double g, double hg, double thr, AdjC c);
+                               double g, double hg, double thr, AdjC c,
+                               unsigned long long* argmin_reset);
 // Gather: own (with its tile's contributions) + the stencil contributions of
 // the face neighbours in other tiles, in fixed order (no atomics), then the
 // Runge-Kutta reverse that follows J_R(w1)^T:
-//   lam1 = lt2/2 + wb, hbar += wb.h, lt1 = mask1 (.) lam1,
+//   lam1 = lt2/2 + wb, lamn.h += wb.h (bed), lt1 = mask1 (.) lam1,
 //   mua = dt lt1 / |K|, lamn += lt1, part[tile] += lt1 . R0.
+// With argmin (preset to all ones), also the cell that sets the step's dt:
+// *argmin becomes the smallest internal index among the cells of W = w^k
+// whose CFL ratio bits equal *rmin.  At a tie the dt depends on the minimum
+// of equal ratios, whose derivative is taken as that one cell's.
 __global__ void adj_gather_rk2_kernel(DevMesh m, TileMap tm, AdjC c, const Adj4* lam,
                                       const uint8_t* mask2, const uint8_t* mask1,
                                       const double* R0, double dt, double* mua, Adj4* lamn,
-                                      double* hbar, double* part);
-// The cell that sets dt: *argmin (preset to all ones) becomes the smallest
-// internal index among the cells whose CFL ratio bits equal *rmin.  At a tie
-// the dt depends on the minimum of equal ratios, whose derivative is taken
-// as that one cell's.
-__global__ void adj_argmin_kernel(DevMesh m, TileMap tm, const Cell4* W, double g, double thr,
-                                  const unsigned long long* rmin, unsigned long long* argmin);
+                                      double* part, const Cell4* W, double g, double thr,
+                                      const unsigned long long* rmin,
+                                      unsigned long long* argmin);
 // End of the reverse of step k, in one pass per cell: after J_R(w)^T the
-// gathered contributions (lamn += wb, hbar += wb.h); with argmin, the CFL
-// term dt = CFL ratio(w^k) at cell *argmin (lamn += lamdt CFL
-// d ratio/d w); with r, the gauge misfit of w^k
-// (lamn.H += 2 r, hbar -= 2 r per gauge on the cell).  lamn then holds the
+// gathered contributions (lamn += wb, the bed's wb.h into lamn.h); with
+// argmin, the CFL term dt = CFL ratio(w^k) at cell *argmin (lamn += lamdt
+// CFL d ratio/d w, lamdt = the sum of part[0 .. tiles) in fixed order,
+// formed by that cell's workgroup); with r, the gauge misfit of w^k
+// (lamn.H += 2 r, lamn.h -= 2 r per gauge on the cell).  lamn then holds the
 // adjoint of w^k.  With mask2p, also the start of the reverse of step k-1
-// from its tape (R1p, mask2p, dtp), as adj_start_kernel: mua, lamp, part.
+// from its tape (R1p, mask2p, dtp), as adj_start_kernel: mua, lamp and
+// partp (a second array, as part is read during the pass).
 __global__ void adj_turn_kernel(DevMesh m, TileMap tm, AdjC c, const Cell4* W, double g,
                                 double thr, double cfl, const unsigned long long* argmin,
-                                const double* lamdt, const int64_t* cells, int ng,
-                                const double* r, Adj4* lamn, double* hbar, const uint8_t* mask2p,
+                                const double* part, const int64_t* cells, int ng,
+                                const double* r, Adj4* lamn, const uint8_t* mask2p,
                                 const double* R1p, double dtp, double* mua, Adj4* lamp,
-                                double* part);
-// Sum of part[0 .. n) in fixed order into *out (one block).
-__global__ void adj_sum_kernel(const double* part, int n, double* out);
-// Gauge misfit of the state after a step: lam[cell].H += 2 r, hbar[cell] -= 2 r.
-__global__ void adj_gauge_kernel(const int64_t* cells, int ng, const double* r, Adj4* lam,
-                                 double* hbar);
+                                double* partp);
+// Gauge misfit of the state after a step: lam[cell].H += 2 r, lam[cell].h -= 2 r.
+__global__ void adj_gauge_kernel(const int64_t* cells, int ng, const double* r, Adj4* lam);
 // Caller-order gradient arrays from internal-order adjoints.
-__global__ void adj_unpack_kernel(int64_t n, const int64_t* perm, const Adj4* lam,
-                                  const double* hbar, double* gH, double* gHU, double* gHV,
-                                  double* gh);
+__global__ void adj_unpack_kernel(int64_t n, const int64_t* perm, const Adj4* lam, double* gH,
+                                  double* gHU, double* gHV, double* gh);
 
 }  // namespace vsw

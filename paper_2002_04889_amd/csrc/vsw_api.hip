@@ -1359,7 +1359,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     // fix masks, and the CFL minimum of each state.
     const size_t N = size_t(n), SL = size_t(segl);
     DevBuf<Cell4> segW1, wend;
-    DevBuf<double> d_r, tR0, tR1, mua, hbar, part, lamdt, gout;
+    DevBuf<double> d_r, tR0, tR1, mua, partA, partB, gout;
     DevBuf<uint8_t> tm1, tm2;
     DevBuf<Adj4> lam, lamn, cown, cx;
     DevBuf<int32_t> xin;
@@ -1375,13 +1375,12 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                          tm1.alloc(SL * N), tm2.alloc(SL * N), rmin_hist.alloc(SL + 1), argmin.alloc(1),
                          lam.alloc(N), lamn.alloc(N), mua.alloc(3 * N), cown.alloc(N),
                          cx.alloc(s->d_bitem.n), xin.alloc(3 * N),
-                         hbar.alloc(N), part.alloc(size_t(s->ntiles)), lamdt.alloc(1),
+                         partA.alloc(size_t(s->ntiles)), partB.alloc(size_t(s->ntiles)),
                          gout.alloc(4 * size_t(s->nc))})
         if (x != hipSuccess) e = x;
     if (e != hipSuccess) return fail(VSW_ENOMEM, "adjoint work memory");
     HIP_TRY(hipMemcpy(d_r.p, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemsetAsync(lam.p, 0, N * sizeof(Adj4), st));
-    HIP_TRY(hipMemsetAsync(hbar.p, 0, N * sizeof(double), st));
     const DevMesh m = s->dev_mesh();
     TileMap tm{s->d_nloc.p, s->d_bstart.p, s->d_bitem.p, s->d_tinfo.p, s->bmax, s->ntiles, 1,
                s->xcd_order};
@@ -1403,7 +1402,7 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
     const std::vector<unsigned long long> inf_bits(SL + 1, 0x7FF0000000000000ull);
     // the misfit of the last state
     hipLaunchKernelGGL(adj_gauge_kernel, dim3(1), dim3(64), 0, st, cells, ng,
-                       d_r.p + (nsteps - 1) * ng, lam.p, hbar.p);
+                       d_r.p + (nsteps - 1) * ng, lam.p);
     for (int64_t c = nck - 1; c >= 0; --c) {
         const int64_t n0 = c * ckpt, n1 = std::min(nsteps, n0 + ckpt);
         const int64_t len = n1 - n0;
@@ -1469,6 +1468,8 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
                                    rmin_hist.p);
         }
         bool started = false;  // the start of step k was done by the previous turn
+        // per-tile dt adjoint terms of step k (part) and of step k-1 (partn)
+        double *part = partA.p, *partn = partB.p;
         for (int64_t k = n1 - 1; k >= n0; --k) {
             const int64_t i = k - n0;
             const Cell4* Wn = seg.p + i * n;
@@ -1480,36 +1481,31 @@ int vsw_adjoint_gauge_loss(vsw_solver* s, int64_t nsteps, int64_t ckpt, int32_t 
             const double dt = dts[size_t(k)];
             if (!started)
                 hipLaunchKernelGGL(adj_start_kernel, grid, block, 0, st, m, tm, lam.p, m2, R1, dt,
-                                   mua.p, lamn.p, part.p);
+                                   mua.p, lamn.p, part);
+            // the first product also clears the minimising-cell word, which
+            // the gather fills from w^k and the turn kernel reads
+            unsigned long long* const am = cfl_dt ? argmin.p : nullptr;
             hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, W1, mua.p, g, hg, thr,
-                               cc);
+                               cc, am);
             hipLaunchKernelGGL(adj_gather_rk2_kernel, grid, block, 0, st, m, tm, cc, lam.p, m2,
-                               m1, R0, dt, mua.p, lamn.p, hbar.p, part.p);
-            if (cfl_dt)
-                hipLaunchKernelGGL(adj_sum_kernel, dim3(1), block, 0, st, part.p, s->ntiles,
-                                   lamdt.p);
+                               m1, R0, dt, mua.p, lamn.p, part, Wn, g, thr, rmin_hist.p + i, am);
             hipLaunchKernelGGL(adj_vjp_kernel, grid, block, lds, st, m, tm, Wn, mua.p, g, hg, thr,
-                               cc);
-            if (cfl_dt) {
-                HIP_TRY(hipMemsetAsync(argmin.p, 0xFF, sizeof(unsigned long long), st));
-                hipLaunchKernelGGL(adj_argmin_kernel, grid, block, 0, st, m, tm, Wn, g, thr,
-                                   rmin_hist.p + i, argmin.p);
-            }
+                               cc, (unsigned long long*)nullptr);
             // step k-1's tape is in this segment: start its reverse in the same pass
             const bool next = (k - 1 >= n0);
             hipLaunchKernelGGL(adj_turn_kernel, grid, block, 0, st, m, tm, cc, Wn, g, thr, cfl,
-                               cfl_dt ? argmin.p : nullptr, lamdt.p, cells, ng,
-                               k >= 1 ? d_r.p + (k - 1) * ng : nullptr, lamn.p, hbar.p,
-                               next ? m2 - n : nullptr, next ? R1 - 3 * n : nullptr,
-                               next ? dts[size_t(k - 1)] : 0.0, mua.p, lam.p, part.p);
+                               am, part, cells, ng, k >= 1 ? d_r.p + (k - 1) * ng : nullptr,
+                               lamn.p, next ? m2 - n : nullptr, next ? R1 - 3 * n : nullptr,
+                               next ? dts[size_t(k - 1)] : 0.0, mua.p, lam.p, partn);
             std::swap(lam.p, lamn.p);
+            std::swap(part, partn);
             started = next;
         }
         HIP_TRY(hipGetLastError());
     }
     const int64_t nc = s->nc;
     hipLaunchKernelGGL(adj_unpack_kernel, dim3(unsigned((n + kBlock - 1) / kBlock)), block, 0, st,
-                       n, s->d_perm.p, lam.p, hbar.p, gout.p, gout.p + nc, gout.p + 2 * nc,
+                       n, s->d_perm.p, lam.p, gout.p, gout.p + nc, gout.p + 2 * nc,
                        gout.p + 3 * nc);
     HIP_TRY(hipGetLastError());
     double* outs[4] = {gH, gHU, gHV, gh};
