@@ -2,7 +2,8 @@
 (a) the tape gradient of the differentiable oracle (oracle/torch_scheme.py,
     torch.autograd, FP64): every gradient field within 1e-10 of the largest
     entry, with the CFL and the fixed time step, on the basin and on
-    Thacker's bowl (moving wet/dry front);
+    Thacker's bowl (moving wet/dry front), also on a bowl of 242 triangles,
+    one tile with no halo;
 (b) central finite differences of the GPU FP64 forward on 10 smooth
     directions of the initial surface and the bed (tie-free state, one
     step per kind fixed in advance): 20 steps on the small basin within
@@ -41,7 +42,7 @@ def setup_case(which):
         c = generic_basin()
         wet = np.flatnonzero(c.H > 10.0)
     else:
-        c = W.thacker_case(23)
+        c = W.thacker_case(23 if which == "thacker" else 12)
         wet = np.flatnonzero(c.H > 0.02)
     rng = np.random.default_rng(5)
     gauges = rng.choice(wet, 5, replace=False).astype(np.int32)
@@ -74,7 +75,7 @@ def gpu_loss(c, H0, h, nsteps, gauges, obs, dt_fixed=0.0):
 
 
 @pytest.mark.parametrize("which,dt_mode", [("basin", "cfl"), ("basin", "fixed"),
-                                           ("thacker", "cfl")])
+                                           ("thacker", "cfl"), ("thacker_one_tile", "cfl")])
 def test_adjoint_matches_tape_gradient(orc, which, dt_mode):
     c, gauges, rng = setup_case(which)
     nsteps = 12
