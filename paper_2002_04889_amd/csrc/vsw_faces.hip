@@ -164,6 +164,10 @@ __device__ __forceinline__ void faces_stage_body(const FaceMesh& m, const FaceTi
     // Runge-Kutta stage reads, all before the first barrier.  (Face records
     // held through the reconstructions would need more than the 128
     // registers of four waves per SIMD.)
+    // each level's loads are issued at raised wave priority, so that a wave
+    // that reaches them is not held behind the arithmetic of the other waves
+    // on its SIMD before its requests are in flight
+    __builtin_amdgcn_s_setprio(2);
     const int64_t ko = own ? k : c0;
     const TopoD tp = m.topo[ko];
     const LsqW lw = m.lsq[ko];
@@ -175,6 +179,7 @@ __device__ __forceinline__ void faces_stage_body(const FaceMesh& m, const FaceTi
     load_nbrs(Ws, tp, ko, cn);
     TopoD htp{0u, 0u, 0u, 0u, 0u, 0u};
     if (i < nb) htp = m.topo[hitem >> 2];
+    __builtin_amdgcn_s_setprio(0);
 
     // phase 1: the tile's cells and the halo faces
     double area = 1.0;
@@ -204,6 +209,7 @@ __device__ __forceinline__ void faces_stage_body(const FaceMesh& m, const FaceTi
         recon_tri(cq, cnq, tq, gq, lq, p.thr, r, jn);
         store_face(Le, Lh, LH, Lu, Lv, 3 * T + b, recon_face(r, 0, p.thr));
     }
+    __builtin_amdgcn_s_setprio(2);
     FaceItemD it0{0u, 0u, 0, 0}, it1{0u, 0u, 0, 0};
     if (i < nf) it0 = tm.items[f0 + i];
     if (i + T < nf) it1 = tm.items[f0 + i + T];
@@ -225,6 +231,7 @@ __device__ __forceinline__ void faces_stage_body(const FaceMesh& m, const FaceTi
             per = m.perim[k];
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     FaceGeo g0{0.0, 0.0, 0.0}, g1{0.0, 0.0, 0.0};
     if (i < nf) g0 = face_geo(a0, e0);
     if (i + T < nf) g1 = face_geo(a1, e1);
