@@ -366,7 +366,11 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
     // clears the minimising-cell word the next gather fills (the previous
     // step's turn kernel, its last reader, has finished)
     if (argmin_reset && t == 0 && i == 0) *argmin_reset = ~0ull;
+    // phase 1, mostly dependent gathers, at raised wave priority: a wave in
+    // it issues its loads ahead of waves in the arithmetic of phase 2
+    __builtin_amdgcn_s_setprio(2);
     tile_faces(m, tm, W, t, c0, ti.cnt, thr, hg, lds, stride, ownH, sc, second);
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     const bool own = i < ti.cnt;
     // the cell's own adjoint and its contribution to the stencil member
