@@ -151,7 +151,7 @@ int vsw_scenario_dt_history(vsw_solver *s, int32_t scen, int64_t max,
  * depth, with the initial H, HU, HV held fixed).  The solver's state, time,
  * gauges and logs are unchanged on return.  Device memory: about
  * 32 * ceil(nsteps / checkpoint_every) + 114 * min(checkpoint_every, nsteps)
- * + 300 bytes per cell.  On an FP32 solver the forward run and the segment
+ * + 250 bytes per cell.  On an FP32 solver the forward run and the segment
  * replays are the FP32 kernels (its trajectory, its dts) and the reverse
  * sweep is the FP64 adjoint of the scheme evaluated on the FP32 states:
  * an approximation of the FP32 run's gradient, not its exact adjoint.

@@ -576,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void adj_vjp_kernel(DevMesh m, TileMap tm,
     // Hand the contributions over: to a stencil member in this tile through
     // the LDS slot of its face state (the slot of the face it shares with
     // this cell; every reader of face states is past the barrier), to one in
-    // another tile through C for the gather kernels.
+    // another tile through c.x for the gather kernels.
     __syncthreads();
     if (own) {
 #pragma unroll
